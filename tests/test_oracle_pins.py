@@ -1,0 +1,392 @@
+"""Pins of the CPU FP64 oracle against facts fixed by the paper and by
+mathematics (closed forms, invariants, library routines, convergence).
+
+Each test names the passage it pins.  None of them compares the oracle with
+itself or with the GPU library.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from chorus_inputs import box_mesh, cubed_sphere_shell, two_element_mesh, uniform_noise
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# --------------------------------------------------------------------------
+# 1D operators (Section 3: solution points, Legendre recursion, Lagrange bases)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6, 8])
+def test_points_closed_forms(oracle_mod, N):
+    xs, xf, I, D, w = oracle_mod.basis(N)
+    s = np.arange(1, N + 1)
+    np.testing.assert_allclose(xs, 0.5 * (1 - np.cos((2 * s - 1) / (2 * N) * np.pi)), atol=1e-15)
+    # Legendre-Gauss nodes from numpy's own routine, mapped to [0, 1]
+    if N >= 2:
+        g, _ = np.polynomial.legendre.leggauss(N - 1)
+        np.testing.assert_allclose(xf[1:-1], np.sort(0.5 * (g + 1)), atol=1e-14)
+    assert xf[0] == 0.0 and xf[-1] == 1.0
+
+
+def test_points_survey_values(oracle_mod):
+    xs, xf, *_ = oracle_mod.basis(3)
+    np.testing.assert_allclose(xs, [0.0669873, 0.5, 0.9330127], atol=1e-7)
+    np.testing.assert_allclose(xf, [0, 0.2113249, 0.7886751, 1], atol=1e-7)
+    xs, xf, *_ = oracle_mod.basis(4)
+    np.testing.assert_allclose(xs, [0.0380602, 0.3086583, 0.6913417, 0.9619398], atol=1e-7)
+    np.testing.assert_allclose(xf, [0, 0.1127017, 0.5, 0.8872983, 1], atol=1e-7)
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 6])
+def test_operator_exactness(oracle_mod, N):
+    xs, xf, I, D, w = oracle_mod.basis(N)
+    for deg in range(N):          # interpolation exact up to degree N-1
+        c = np.random.default_rng(deg).normal(size=deg + 1)
+        np.testing.assert_allclose(I @ np.polyval(c, xs), np.polyval(c, xf), atol=1e-13)
+    c = np.ones(N + 1)            # ... and not for degree N
+    assert np.abs(I @ np.polyval(c, xs) - np.polyval(c, xf)).max() > 1e-6
+    for deg in range(N + 1):      # flux derivative exact up to degree N
+        c = np.random.default_rng(10 + deg).normal(size=deg + 1)
+        np.testing.assert_allclose(D @ np.polyval(c, xf), np.polyval(np.polyder(c), xs),
+                                   atol=1e-11)
+    # quadrature exact up to degree N-1, hence w^T D = e_N - e_0
+    for deg in range(N):
+        assert abs(w @ xs ** deg - 1.0 / (deg + 1)) < 1e-14
+    e = np.zeros(N + 1)
+    e[0], e[-1] = -1, 1
+    np.testing.assert_allclose(w @ D, e, atol=2e-15 * np.abs(D).max() * (N + 1))
+
+
+def test_paper_counts_golden(oracle_mod):
+    """Counts printed in the paper (tests/golden/paper_counts.txt)."""
+    vals = {}
+    with open(os.path.join(HERE, "golden", "paper_counts.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()[:2]
+                vals[k] = int(v)
+    N = 3
+    xs, xf, *_ = oracle_mod.basis(N)
+    assert len(xs) ** 2 == vals["sd2d_order3_solution_points"]
+    assert 2 * len(xs) * len(xf) == vals["sd2d_order3_flux_points"]
+    # DOFs = N_element x N^3 at N = 4
+    for t in ("test1", "test2", "sun"):
+        assert vals["dofs_%s_elements" % t] * 4 ** 3 == vals["dofs_%s" % t]
+
+
+# --------------------------------------------------------------------------
+# geometry (Section 3 mapping; Section 5 curved walls via the 20-node map)
+# --------------------------------------------------------------------------
+def test_affine_box_metrics_exact(oracle_mod):
+    m = box_mesh(3, 2, 2, lengths=(3.0, 1.0, 2.0))
+    om = oracle_mod.OracleMesh(m, 3)
+    jac, met, metf = om.geometry()
+    h = np.array([1.0, 0.5, 1.0])
+    np.testing.assert_allclose(jac, np.prod(h), rtol=1e-13)
+    want = np.diag([h[1] * h[2], h[0] * h[2], h[0] * h[1]])
+    np.testing.assert_allclose(met, np.broadcast_to(want, met.shape), atol=1e-13)
+    for d in range(3):
+        np.testing.assert_allclose(metf[:, d], np.broadcast_to(want[d], metf[:, d].shape),
+                                   atol=1e-13)
+
+
+def test_shell_volume_converges(oracle_mod):
+    ri, ro = 7.0 / 3.0, 10.0 / 3.0
+    exact = 4.0 / 3.0 * math.pi * (ro ** 3 - ri ** 3)
+    errs = []
+    for n in (2, 4):
+        om = oracle_mod.OracleMesh(cubed_sphere_shell(n, 1, ri, ro), 3)
+        _, wJ = om.solpts()
+        errs.append(abs(wJ.sum() - exact) / exact)
+        jac, _, _ = om.geometry()
+        assert (jac > 0).all()
+    assert errs[1] < errs[0] / 10.0   # quadratic serendipity geometry: ~h^3-4
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_metric_identity_and_watertight(oracle_mod, N):
+    """Discrete free-stream metric identity sum_d D_d (|J| grad xi_d) = 0 and
+    matching area vectors from both sides of every interior face."""
+    om = oracle_mod.OracleMesh(cubed_sphere_shell(3, 2, 2.0, 3.0), N)
+    xs, xf, I, D, w = oracle_mod.basis(N)
+    jac, met, metf = om.geometry()
+    E = om.E
+    mf = metf.reshape(E, 3, N, N, N + 1, 3)  # [e][d][t2][t1][a][c]
+    div = np.zeros((E, N, N, N, 3))          # [e][k][j][i][c]
+    div += np.einsum("ia,ekjac->ekjic", D, mf[:, 0])
+    div += np.einsum("ja,ekiac->ekjic", D, mf[:, 1])
+    div += np.einsum("ka,ejiac->ekjic", D, mf[:, 2])
+    scale = np.abs(metf).max() * np.abs(D).max() * (N + 1)
+    assert np.abs(div).max() < 1e-13 * scale * 10
+    ne, nf, npnt = om.faces()
+    worst = 0.0
+    for e in range(E):
+        for f in range(6):
+            e2 = ne[e, f]
+            if e2 < 0:
+                continue
+            f2 = nf[e, f]
+            for p in range(N * N):
+                t1, t2 = p % N, p // N
+                a = (f % 2) * N + (N + 1) * (t1 + N * t2)
+                p2 = npnt[e, f, p]
+                b = (f2 % 2) * N + (N + 1) * (p2 % N + N * (p2 // N))
+                Sa = (1 if f % 2 else -1) * metf[e, f // 2, a]
+                Sb = (1 if f2 % 2 else -1) * metf[e2, f2 // 2, b]
+                worst = max(worst, np.abs(Sa + Sb).max() / np.abs(Sa).max())
+    assert worst < 1e-12
+
+
+# --------------------------------------------------------------------------
+# residual invariants
+# --------------------------------------------------------------------------
+Q_UNIFORM = np.array([1.2, 0.3, -0.2, 0.1, 2.5])
+
+
+def _uniform(om, q=Q_UNIFORM):
+    return np.tile(np.asarray(q)[:, None, None], (1, om.E, om.np))
+
+
+def _residual_scale(om, oracle_mod, q=Q_UNIFORM):
+    """Rounding scale of a residual: |flux| * max|D| / min|J| at unit area."""
+    N = om.N
+    _, _, _, D, _ = oracle_mod.basis(N)
+    jac, _, metf = om.geometry()
+    return (np.abs(q).max() * 2 * np.abs(metf).max() * np.abs(D).max() * (N + 1)
+            / jac.min() * 3)
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_free_stream_curved_periodic_box(oracle_mod, N):
+    om = oracle_mod.OracleMesh(box_mesh(3, 3, 3, periodic=(True,) * 3, curve=0.03), N)
+    ph = oracle_mod.phys(nu=1e-2, kappa=1e-2, kappa_r=1e-3)
+    R = om.residual(ph, _uniform(om))
+    assert np.abs(R).max() < 1e-14 * _residual_scale(om, oracle_mod)
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_free_stream_curved_shell(oracle_mod, N):
+    m = cubed_sphere_shell(3, 2, 2.0, 3.0)
+    m.face_bc[m.face_bc > 0] = 3
+    om = oracle_mod.OracleMesh(m, N)
+    ph = oracle_mod.phys(nu=1e-2, kappa=1e-2, bc_state=tuple(Q_UNIFORM))
+    R = om.residual(ph, _uniform(om))
+    assert np.abs(R).max() < 1e-14 * _residual_scale(om, oracle_mod)
+
+
+def test_gravity_and_coriolis_signs(oracle_mod):
+    """At uniform rho, p the residual is -M: gravity pulls toward the origin
+    (Eq. 2: rho g with g = -GM/r^2 r_hat) and Coriolis is -2 Omega x (rho u)."""
+    m = box_mesh(3, 3, 3, periodic=(True,) * 3, curve=0.03, origin=(2.0, 1.0, 0.5))
+    om = oracle_mod.OracleMesh(m, 3)
+    GM, Om = 3.0, 0.7
+    ph = oracle_mod.phys(GM=GM, omega=Om)
+    Q = _uniform(om)
+    R = om.residual(ph, Q).reshape(5, -1)
+    xyz, _ = om.solpts()
+    r = np.linalg.norm(xyz, axis=0)
+    rho, mom = Q_UNIFORM[0], Q_UNIFORM[1:4]
+    g_phys = -GM * xyz / r ** 3
+    cor = -2.0 * np.cross(np.array([0, 0, Om]), mom)
+    want_m = rho * g_phys + cor[:, None]
+    tol = 1e-14 * _residual_scale(om, oracle_mod)
+    np.testing.assert_allclose(R[1:4], want_m, atol=tol)
+    np.testing.assert_allclose(R[4], (mom[:, None] * g_phys).sum(0), atol=tol)
+    np.testing.assert_allclose(R[0], 0.0, atol=tol)
+
+
+@pytest.mark.parametrize("rot", range(24))
+def test_orientation_invariance(oracle_mod, rot):
+    """The same two physical hexes, with the second one's local numbering in
+    each of the 24 proper rotations of the reference cube, give the same
+    residual at every physical solution point."""
+    out = []
+    for r in (0, rot):
+        om = oracle_mod.OracleMesh(two_element_mesh(r), 3)
+        xyz, _ = om.solpts()
+        x, y, z = xyz
+        Q = np.stack([1 + 0.1 * np.sin(x + 2 * y), 0.1 * np.cos(z), 0.05 * x, -0.02 * y * z,
+                      2.5 + 0.1 * np.cos(x * y)])
+        ph = oracle_mod.phys(nu=1e-2, kappa=1e-2, GM=0.5, omega=0.3, bc_state=(1, 0, 0, 0, 2.5))
+        R = om.residual(ph, Q).reshape(5, -1)
+        order = np.lexsort(np.round(xyz, 9)[::-1])
+        out.append(R[:, order])
+    np.testing.assert_allclose(out[1], out[0], atol=1e-10 * np.abs(out[0]).max())
+
+
+def test_linear_velocity_viscous_exact(oracle_mod):
+    """u = U + A x, uniform rho and p-part, kappa = 0: tau is constant, so the
+    viscous momentum residual is 0 and the viscous energy residual is the
+    dissipation tau:grad u, exactly, on curved elements two layers inside
+    the boundary (BR1 is compact).  Pins the chain rule, the metric
+    transposition and the viscous averaging."""
+    m = box_mesh(5, 5, 5, lengths=(1.0, 1.0, 1.0), curve=0.02)
+    om = oracle_mod.OracleMesh(m, 3)
+    xyz, _ = om.solpts()
+    A = np.array([[0.3, -0.2, 0.5], [0.1, -0.4, 0.25], [-0.3, 0.2, 0.15]])
+    U = np.array([0.2, -0.1, 0.05])
+    rho, p, nu, gam = 1.3, 2.0, 0.05, 5.0 / 3.0
+    u = U[:, None] + A @ xyz
+    Q = np.concatenate([np.full((1, xyz.shape[1]), rho), rho * u,
+                        (p / (gam - 1) + 0.5 * rho * (u ** 2).sum(0))[None]]).reshape(5, om.E, om.np)
+    R_v = om.residual(oracle_mod.phys(nu=nu), Q) - om.residual(oracle_mod.phys(nu=0.0), Q)
+    mu = rho * nu
+    tau = mu * (A + A.T - 2.0 / 3.0 * np.trace(A) * np.eye(3))
+    diss = (tau * A).sum()
+    centre = 2 + 5 * (2 + 5 * 2)
+    assert np.abs(R_v[1:4, centre]).max() < 1e-12
+    np.testing.assert_allclose(R_v[4, centre], diss, rtol=1e-11)
+    # and it is not identically zero outside (the boundary state differs)
+    assert np.abs(R_v[1:4]).max() > 1e-8
+
+
+def _density_wave(om, t, amp=0.2, u=(0.5, 0.3, 0.2), p=1.0, gam=5.0 / 3.0):
+    xyz, _ = om.solpts()
+    k = 2 * np.pi * np.ones(3)
+    ph = (k[:, None] * (xyz - np.asarray(u)[:, None] * t)).sum(0)
+    rho = 1.0 + amp * np.sin(ph)
+    uu = np.asarray(u)
+    Q = np.stack([rho, rho * uu[0], rho * uu[1], rho * uu[2],
+                  p / (gam - 1) + 0.5 * rho * (uu ** 2).sum()])
+    return Q.reshape(5, om.E, om.np)
+
+
+@pytest.mark.parametrize("N", [2, 4])
+def test_design_order_density_wave(oracle_mod, N):
+    """Advected density wave (exact Euler solution) on curved periodic boxes:
+    over one period the L2 error falls at about order N, the scheme's design
+    order (Section 3: N solution points give an N-th order scheme)."""
+    errs = []
+    for n in (4, 8):
+        mesh = box_mesh(n, 3, 3, lengths=(1.0, 0.3, 0.3), periodic=(True,) * 3, curve=0.01)
+        om = oracle_mod.OracleMesh(mesh, N)
+        xyz, wJ = om.solpts()
+
+        def wave(t):
+            rho = 1.0 + 0.2 * np.sin(2 * np.pi * (xyz[0] - t))
+            z = np.zeros_like(rho)
+            return np.stack([rho, rho, z, z, 1.5 + 0.5 * rho]).reshape(5, om.E, om.np)
+
+        steps = 20 * n * N
+        Q = om.rk3(oracle_mod.phys(), wave(0.0), 1.0 / steps, steps)
+        err = (Q[0] - wave(1.0)[0]).reshape(-1)
+        errs.append(math.sqrt((wJ * err ** 2).sum() / wJ.sum()))
+    rate = math.log(errs[0] / errs[1]) / math.log(2.0)
+    assert rate > N - 0.5, (errs, rate)
+
+
+def test_rusanov_dissipates(oracle_mod):
+    """With the Rusanov flux the discrete L2 norm of an advected density
+    perturbation does not grow (a wrong-signed dissipation term grows it)."""
+    om = oracle_mod.OracleMesh(box_mesh(3, 3, 3, periodic=(True,) * 3, curve=0.02), 3)
+    _, wJ = om.solpts()
+    Q = _density_wave(om, 0.0)
+    norms = []
+    for _ in range(4):
+        norms.append(math.sqrt((wJ * (Q[0].reshape(-1) - 1.0) ** 2).sum()))
+        Q = om.rk3(oracle_mod.phys(), Q, 0.01, 5)
+    assert all(b < a for a, b in zip(norms, norms[1:])), norms
+
+
+def test_rk3_linear_amplification(oracle_mod):
+    """Uniform state with only Coriolis: a linear ODE whose exact SSP-RK3
+    update is the polynomial 1 + z + z^2/2 + z^3/6 of dt L."""
+    om = oracle_mod.OracleMesh(box_mesh(3, 3, 3, periodic=(True,) * 3), 3)
+    Om, dt = 0.8, 0.05
+    Q = om.rk3(oracle_mod.phys(omega=Om), _uniform(om), dt, 1)
+    L = np.array([[0.0, 2 * Om], [-2 * Om, 0.0]])   # d(mx,my)/dt
+    Z = dt * L
+    P = np.eye(2) + Z + Z @ Z / 2 + Z @ Z @ Z / 6
+    want = P @ Q_UNIFORM[1:3]
+    np.testing.assert_allclose(Q[1], want[0], rtol=1e-12)
+    np.testing.assert_allclose(Q[2], want[1], rtol=1e-12)
+    np.testing.assert_allclose(Q[0], Q_UNIFORM[0], rtol=1e-12)
+
+
+def test_mass_conserved_shell_walls(oracle_mod):
+    """Section 6: conservative form + shared interface fluxes conserve mass;
+    walls carry no mass flux.  Exact to rounding, also after RK3 steps."""
+    om = oracle_mod.OracleMesh(cubed_sphere_shell(3, 2, 7.0 / 3.0, 10.0 / 3.0), 3)
+    Q, pars = om.polytrope(0.7, 1.0, noise=uniform_noise(om.n_solpts, 3), amp=1e-2)
+    ph = oracle_mod.phys(GM=pars["GM"], omega=1.0, nu=1e-3, kappa=1e-3, T_top=pars["chi_o"])
+    _, wJ = om.solpts()
+    R = om.residual(ph, Q)
+    assert abs((wJ * R[0].reshape(-1)).sum()) < 1e-15 * (wJ * np.abs(R[0].reshape(-1))).sum() * 100
+    m0 = om.sums(Q)[0]
+    Q2 = om.rk3(ph, Q, 0.02, 3)
+    assert abs(om.sums(Q2)[0] - m0) < 1e-14 * m0
+
+
+def test_periodic_box_conserves_everything(oracle_mod):
+    om = oracle_mod.OracleMesh(box_mesh(3, 3, 3, periodic=(True,) * 3, curve=0.03), 3)
+    Q = _density_wave(om, 0.0)
+    s0 = om.sums(Q)
+    s1 = om.sums(om.rk3(oracle_mod.phys(nu=1e-2, kappa=1e-2), Q, 0.01, 3))
+    np.testing.assert_allclose(s1, s0, rtol=1e-13, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# polytropic background (Section 4.2)
+# --------------------------------------------------------------------------
+def test_polytrope_closed_forms(oracle_mod):
+    beta, n_rho, n = 0.7, 1.0, 1.5
+    ri, ro = beta / (1 - beta), 1 / (1 - beta)
+    om = oracle_mod.OracleMesh(cubed_sphere_shell(2, 1, ri, ro), 3)
+    _, pars = om.polytrope(beta, n_rho, poly_n=n)
+    chi = lambda r: pars["c"] + pars["alpha"] / r
+    assert abs(chi(0.5 * (ri + ro)) - 1.0) < 1e-14           # mid-layer chi = 1
+    assert abs((chi(ri) / chi(ro)) ** n - math.exp(n_rho)) < 1e-12  # N_rho
+    # hydrostatic dp/dr = -rho GM / r^2, checked by central differences
+    r, h = 2.9, 1e-5
+    dp = (chi(r + h) ** (n + 1) - chi(r - h) ** (n + 1)) / (2 * h)
+    assert abs(dp + chi(r) ** n * pars["GM"] / r ** 2) < 1e-8
+    # the survey's listed constants for the 288-hex shell
+    assert abs(pars["chi_o"] - 0.719298) < 1e-6 and abs(pars["GM"] - 13.2553) < 1e-4
+
+
+@pytest.mark.slow
+def test_hydrostatic_balance_converges(oracle_mod):
+    """The polytrope at rest is a continuous steady state, so the discrete
+    residual of the inviscid shell vanishes under refinement (Section 4.1)."""
+    beta, n_rho = 0.7, 1.0
+    ri, ro = beta / (1 - beta), 1 / (1 - beta)
+    errs = []
+    for n in (2, 4):
+        om = oracle_mod.OracleMesh(cubed_sphere_shell(n, n, ri, ro), 3)
+        Q, pars = om.polytrope(beta, n_rho)
+        R = om.residual(oracle_mod.phys(GM=pars["GM"]), Q)
+        _, wJ = om.solpts()
+        errs.append(math.sqrt((wJ * (R[1:4] ** 2).sum(0).reshape(-1)).sum()))
+    rate = math.log(errs[0] / errs[1]) / math.log(2.0)
+    assert rate > 2.0, (errs, rate)
+
+
+@pytest.mark.parametrize("which", ["kappa", "kappa_r"])
+def test_entropy_diffusion_converges(oracle_mod, which):
+    """At rest with uniform p and varying rho, the diffusive energy flux of
+    Eq. 3, f = -kappa rho T grad S - kappa_r rho c_p grad T, gives
+    dE/dt = -k c_p (p/R) lap(ln rho) for either coefficient k.  The discrete
+    diffusion residual converges to it (sign, factor and BR1 chain pinned)."""
+    gam, R_gas, p, k = 5.0 / 3.0, 1.0, 1.7, 0.01
+    cp = gam * R_gas / (gam - 1.0)
+    errs = []
+    for n in (3, 6):
+        om = oracle_mod.OracleMesh(box_mesh(n, n, 3, periodic=(True,) * 3, curve=0.02), 4)
+        xyz, wJ = om.solpts()
+        a, kk = 0.2, 2 * np.pi
+        sx, sy = np.sin(kk * xyz[0]), np.sin(kk * xyz[1])
+        cx, cy = np.cos(kk * xyz[0]), np.cos(kk * xyz[1])
+        rho = 1.0 + a * sx * sy
+        grad2 = (a * kk) ** 2 * ((cx * sy) ** 2 + (sx * cy) ** 2)
+        lap_ln = -2 * kk ** 2 * a * sx * sy / rho - grad2 / rho ** 2
+        want = -k * cp * (p / R_gas) * lap_ln
+        z = np.zeros_like(rho)
+        Q = np.stack([rho, z, z, z, np.full_like(rho, p / (gam - 1))]).reshape(5, om.E, om.np)
+        kw = {which: k}
+        Rd = om.residual(oracle_mod.phys(**kw), Q) - om.residual(oracle_mod.phys(), Q)
+        err = Rd[4].reshape(-1) - want
+        errs.append(math.sqrt((wJ * err ** 2).sum() / (wJ * want ** 2).sum()))
+        assert np.abs(Rd[:4]).max() < 1e-12
+    assert errs[1] < 0.05 and errs[1] < errs[0] / 2.0, errs
