@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Benchmark: SD DOF-updates/s of the SSP-RK3 spectral-difference solver on
+one MI355X, with the per-kernel HBM roofline and the CPU oracle beside it.
+
+One step = one full SSP-RK3 step (three residual evaluations with the fused
+stage update) over every solution point of the workload; DOFs = E N^3.
+Inputs are synthetic and seeded: a cubed-sphere shell, the polytropic
+background and a seeded entropy perturbation (see the design notes).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SD DOF-updates/s, mixed vs FP64 plain at ≤1e-6 rel err; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def alg_bytes_per_stage_point(N, precision):
+    """Algorithmic bytes per solution point and residual stage.
+
+    FP64 state: 5 reads + 3 writes of 40 B per point per SSP-RK3 step, i.e.
+    320/3 B per stage; geometry from the 20 element nodes (480 B) and the
+    face connectivity (48 B) once per element and stage."""
+    NP = N ** 3
+    per = 320.0 / 3.0 + (480.0 + 48.0) / NP
+    if precision == "mixed":
+        # FP32 background residual (20 B), rho0, p0 (8 B) per point, and the
+        # FP32 background face jump + wave speed (12 B per face point)
+        per += 28.0 + 12.0 * 6 * N * N / NP
+    return per
+
+
+def cpu_baseline(cfg, budget_s=15.0):
+    """The CPU oracle on the same workload for a bounded number of steps."""
+    import oracle
+    from chorus_inputs import cubed_sphere_shell, shell_params_from_config, uniform_noise
+    oracle.build(force=False)
+    ri, ro = shell_params_from_config(cfg)
+    m = cubed_sphere_shell(cfg["panel_n"], cfg["radial_n"], ri, ro)
+    om = oracle.OracleMesh(m, cfg["order"])
+    Q, pars = om.polytrope(cfg["beta"], cfg["n_rho"], poly_n=cfg["poly_n"],
+                           noise=uniform_noise(om.n_solpts, cfg["seed"]), amp=1e-4)
+    ph = oracle.phys(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"],
+                     T_top=pars["chi_o"])
+    dt = 1e-3
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        Q = om.rk3(ph, Q, dt, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 20:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": om.n_solpts * steps / el, "unit": "DOF-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d SSP-RK3 step(s) of the full workload (%d hexes, N=%d), %.1f s" % (
+                steps, om.E, cfg["order"], el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="jupiter_41k_N4")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1503_00834_amd as ch
+    from chorus_inputs import CONFIGS, shell_params_from_config, uniform_noise
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    cfg = CONFIGS[args.workload]
+    N = cfg["order"]
+    ri, ro = shell_params_from_config(cfg)
+    log("workload %s: building mesh" % args.workload)
+    mesh = ch.chorus_mesh_create(cfg["panel_n"], cfg["radial_n"], N, ri, ro).upload()
+    noise = uniform_noise(mesh.n_solpts, cfg["seed"])
+    Qh, pars = mesh.init_polytrope(cfg["beta"], cfg["n_rho"], poly_n=cfg["poly_n"], noise=noise, amp=1e-4)
+    prec = ch.CHORUS_MIXED if args.precision == "mixed" else ch.CHORUS_FP64
+    phys = ch.physics(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"],
+                      T_top=pars["chi_o"], precision=prec)
+    dt = mesh.stable_dt(phys, Qh, cfg["cfl"])
+    Q = torch.from_numpy(Qh).cuda()
+    ws = mesh.workspace(phys)
+    if prec == ch.CHORUS_MIXED:
+        Q0 = Q.clone()
+        ch.chorus_set_background(mesh, phys, Q0, ws)
+    log("E=%d N=%d DOFs=%d dt=%.3e; warmup %d" % (mesh.n_elems, N, mesh.n_solpts, dt, args.warmup))
+    stream = torch.cuda.current_stream()
+    ch.chorus_rk_step(mesh, phys, Q, dt, args.warmup, ws, stream)
+    torch.cuda.synchronize()
+
+    log("timing %d steps" % args.steps)
+    ch.chorus_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.chorus_rk_step(mesh, phys, Q, dt, args.steps, ws, stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ch.chorus_kernel_timing(False)
+    ktimes = ch.chorus_kernel_times()
+    log("kernel times: %s" % ktimes)
+
+    # sanity outside the timed region
+    Qc = Q.cpu().numpy()
+    if not np.isfinite(Qc).all() or (Qc[0] <= 0).any():
+        print("state became non-finite or non-positive", file=sys.stderr)
+        sys.exit(3)
+
+    dof_updates = mesh.n_solpts * args.steps
+    value = dof_updates / wall
+    ms_resid, n_resid = ktimes["k_resid"]
+    avg_s = ms_resid / max(n_resid, 1) * 1e-3
+    alg = alg_bytes_per_stage_point(N, args.precision) * mesh.n_solpts
+    achieved = alg / avg_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "hexes": mesh.n_elems, "order": N, "dofs": mesh.n_solpts,
+                   "precision": args.precision, "integrator": "SSP-RK3", "dt": dt},
+        "roofline": {"bound": "hbm", "kernel": "k_resid", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg, "avg_launch_ms": avg_s * 1e3},
+        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in ktimes.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * chorus.h -- C ABI of the MI355X spectral-difference (SD) library.
+ *
+ * The library evaluates the SD residual and the explicit SSP-RK3 update of
+ * the compressible Navier-Stokes equations in a rotating frame with radial
+ * 1/r^2 gravity (Wang, Liang & Miesch, "A Compressible High-Order
+ * Unstructured Spectral Difference Code for Stratified Convection in
+ * Rotating Spherical Shells": Section 2, Eqs. 1-9; Section 3, the SD
+ * discretisation on 20-node hexahedra; Section 5, wall conditions) on GPU
+ * (gfx950, HIP).  Every call below that touches device memory is
+ * asynchronous on the given stream unless stated otherwise.
+ *
+ * Conventions
+ *   Status: every function returns 0 (CHORUS_OK) or a negative CHORUS_E*
+ *   code; chorus_last_error() gives the detail text of the calling thread's
+ *   last failure.  No C++ exception crosses this boundary.
+ *
+ *   Ownership: the caller owns every device buffer (state, residual,
+ *   workspace, geometry image, network weights); the library never
+ *   allocates or frees device memory.  A mesh handle owns host arrays only
+ *   and remembers the device geometry image registered by
+ *   chorus_mesh_upload, which must stay alive while the handle is used.
+ *   Handles are not thread-safe: use one handle from one thread at a time.
+ *
+ *   State layout: Q is the physical conserved vector (rho, rho u, rho v,
+ *   rho w, E) at the N^3 solution points of each element, structure of
+ *   arrays [5][E][N^3] in float64, solution point index i + N (j + N k)
+ *   with i along the element's local xi axis (Section 3: DOFs = E N^3).
+ *
+ *   Hex20 node order (local reference cube [0,1]^3): corners (i,j,k) in
+ *   {0,1}^3 at index i + 2j + 4k; xi-edge midpoints (1/2,j,k) at 8 + j + 2k;
+ *   eta-edge midpoints (i,1/2,k) at 12 + i + 2k; zeta-edge midpoints
+ *   (i,j,1/2) at 16 + i + 2j.  Local faces 0..5 = xi=0, xi=1, eta=0, eta=1,
+ *   zeta=0, zeta=1.  Face tags: -1 interior, 1 inner wall, 2 outer wall,
+ *   3 far-field state.
+ *
+ *   stream: a hipStream_t passed as void* (NULL = default stream).
+ */
+#ifndef CHORUS_H
+#define CHORUS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CHORUS_OK = 0,
+    CHORUS_EINVAL = -1,      /* bad argument: null pointer, size, order   */
+    CHORUS_EMESH = -2,       /* non-conforming mesh, unmatched face, |J|<=0 */
+    CHORUS_ENOTSUP = -3,     /* valid but unsupported combination         */
+    CHORUS_EHIP = -4,        /* HIP runtime error                         */
+    CHORUS_ENONFINITE = -5,  /* NaN/Inf or non-positive rho/p found        */
+    CHORUS_ESTATE = -6       /* call order: e.g. no geometry uploaded      */
+};
+
+enum { CHORUS_FP64 = 0, CHORUS_MIXED = 1 };            /* chorus_physics.precision */
+enum { CHORUS_CHECK_FINITE = 1 };                      /* chorus_physics.flags     */
+enum { CHORUS_BC_INTERIOR = -1, CHORUS_BC_INNER = 1, CHORUS_BC_OUTER = 2,
+       CHORUS_BC_STATE = 3 };
+
+typedef struct chorus_mesh_s *chorus_mesh_t;
+
+/* Cubed-sphere shell: 6 equiangular panels of panel_n x panel_n columns and
+ * radial_n uniform layers between r_inner and r_outer (the paper's shells
+ * are all-hex with uniform radial spacing, Section 3 mesh figure). */
+typedef struct {
+    int32_t panel_n, radial_n, order;
+    double r_inner, r_outer;
+} chorus_shell_desc;
+
+/* Explicit hex20 mesh (arrays are copied; caller keeps ownership). */
+typedef struct {
+    int64_t n_nodes;
+    const double *xyz;        /* [n_nodes][3]                                 */
+    int64_t n_elems;
+    const int64_t *elem20;    /* [n_elems][20] node indices, order above      */
+    const int32_t *face_bc;   /* [n_elems][6] face tags                       */
+    const int64_t *match_id;  /* [n_nodes] topological ids (periodic images
+                                 share one) or NULL for the node index         */
+    int32_t order;            /* N, 2..6                                      */
+} chorus_hex20_desc;
+
+/* Physics (Section 2).  g_vec = -GM x / r^3; rotation Omega about z; mu =
+ * rho nu; diffusive energy flux f = -kappa rho T grad S - kappa_r rho c_p
+ * grad T; walls impermeable and stress-free (Section 5) with f.r_hat =
+ * F_bottom at the inner wall and T = T_top at the outer wall (T_top <= 0:
+ * interior temperature kept). */
+typedef struct {
+    double gamma, R_gas, GM, omega, nu, kappa, kappa_r, T_top, F_bottom;
+    double bc_state[5];       /* state for CHORUS_BC_STATE faces              */
+    int32_t precision;        /* CHORUS_FP64 or CHORUS_MIXED                  */
+    int32_t closure;          /* 0 = plain SD                                 */
+    int32_t flags;            /* CHORUS_CHECK_FINITE                          */
+    int32_t reserved;
+} chorus_physics;
+
+/* Build a cubed-sphere shell mesh (host only). */
+int chorus_mesh_create(const chorus_shell_desc *desc, chorus_mesh_t *out);
+/* Build a mesh from explicit hex20 arrays (host only). */
+int chorus_mesh_create_hex20(const chorus_hex20_desc *desc, chorus_mesh_t *out);
+int chorus_mesh_destroy(chorus_mesh_t mesh);
+
+/* Sizes: elements, order, solution points (E N^3), faces (interior + wall),
+ * wall faces and the byte size of the device geometry image. */
+int chorus_mesh_query(chorus_mesh_t mesh, int64_t *n_elems, int32_t *order,
+                      int64_t *n_solpts, int64_t *n_faces, int64_t *n_wall_faces,
+                      size_t *device_bytes);
+/* Hex20 arrays of the mesh (host buffers of n_nodes*3, n_elems*20,
+ * n_elems*6); n_nodes is returned first when xyz == NULL. */
+int chorus_mesh_nodes(chorus_mesh_t mesh, int64_t *n_nodes, double *xyz, int64_t *elem20,
+                      int32_t *face_bc);
+/* Solution-point coordinates [3][E N^3] and quadrature weights
+ * w_i w_j w_k |J| [E N^3] (host buffers). */
+int chorus_mesh_solpts(chorus_mesh_t mesh, double *xyz_host, double *wJ_host);
+/* Geometry as used by the kernels (host buffers, any may be NULL):
+ * |J| [E N^3]; |J| grad xi_d at solution points [E N^3][3 d][3 c];
+ * |J| grad xi_d at the d-flux points [E][3 d][(N+1) N^2][3 c] (flux point
+ * index a + (N+1)(t1 + N t2), a along d, t1 < t2 the other axes). */
+int chorus_mesh_geometry(chorus_mesh_t mesh, double *jac, double *met_sol, double *met_flux);
+/* Face table: neighbour element, neighbour face and orientation code
+ * (swap*4 + flip1*2 + flip2) per element face, -1 on boundaries. */
+int chorus_mesh_face_table(chorus_mesh_t mesh, int32_t *nbr_elem, int32_t *nbr_face,
+                           int32_t *orient);
+/* Copy the geometry image into the caller-owned device buffer dev_buf of
+ * at least device_bytes bytes and register it with the handle.
+ * Synchronises the stream. */
+int chorus_mesh_upload(chorus_mesh_t mesh, void *dev_buf, size_t bytes, void *stream);
+
+/* Workspace bytes needed by residual/step calls with these physics. */
+int chorus_workspace_bytes(chorus_mesh_t mesh, const chorus_physics *phys, size_t *bytes);
+
+/* Polytropic adiabatic initial state (Section 4.2) at the solution points:
+ * depth 1, rho = p = 1 at mid-layer, given aspect ratio beta, density scale
+ * heights n_rho and index poly_n; optional entropy perturbation
+ * S' = amp c_p noise[i] at fixed pressure (noise: host [E N^3] or NULL).
+ * Q_host [5][E N^3]; pars (may be NULL) receives chi_o, c, alpha, GM. */
+int chorus_init_polytrope(chorus_mesh_t mesh, double beta, double n_rho, double poly_n,
+                          double gamma, double R_gas, const double *noise, double amp,
+                          double *Q_host, double pars[4]);
+
+/* Mixed mode: register the background state Q0 (device, [5][E N^3] FP64)
+ * and compute its FP64 inviscid residual into the workspace.  Synchronises. */
+int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q0_dev,
+                          void *ws, void *stream);
+
+/* SD residual dQ/dt = -(div F~)/|J| - M at the solution points (Section 3:
+ * transformed equations, Rusanov + BR1 interface treatment).
+ * Q_dev, dQdt_dev: device [5][E N^3] float64. */
+int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q_dev,
+                       double *dQdt_dev, void *ws, void *stream);
+
+/* n_steps SSP-RK3 steps of size dt, in place on Q_dev. */
+int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev, double dt,
+                   int32_t n_steps, void *ws, void *stream);
+
+/* sum over solution points of w w w |J| Q_v, fixed reduction order; the
+ * 5 sums are returned on the host (synchronises). */
+int chorus_conserved_sums(chorus_mesh_t mesh, const double *Q_dev, double out_host[5], void *ws,
+                          void *stream);
+
+/* Largest stable-looking step: cfl * min_e(h_e / N) / max(|u| + c), from
+ * the host state Q_host [5][E N^3] (host only). */
+int chorus_stable_dt(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q_host,
+                     double cfl, double *dt);
+
+/* Opt-in kernel timing for benchmarks: while enabled, every kernel launch of
+ * chorus_sd_residual / chorus_rk_step is bracketed by a pair of HIP events
+ * recorded on the launch stream (no extra work is launched).
+ * chorus_kernel_times waits for the recorded events and returns, per kernel
+ * kind (0 face-trace, 1 gradient/viscous-trace, 2 residual + RK stage), the
+ * summed milliseconds and launch counts, then clears the record.  Not
+ * thread-safe; process-wide. */
+int chorus_kernel_timing(int enable);
+int chorus_kernel_times(double ms[3], int64_t counts[3]);
+
+const char *chorus_strerror(int status);
+int chorus_last_error(char *buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHORUS_H */

@@ -1,0 +1,276 @@
+"""Thin Python binding of libchorus.so (MI355X spectral-difference solver).
+
+Argument marshalling only: every step of the residual and the time step runs
+in the library's HIP kernels.  PyTorch provides device memory and streams.
+The functions carry the names of the C entry points in include/chorus.h.
+If the shared library is missing this module raises at import time; there is
+no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchorus.so")
+
+CHORUS_OK = 0
+CHORUS_FP64, CHORUS_MIXED = 0, 1
+CHORUS_CHECK_FINITE = 1
+ERRORS = {-1: "EINVAL", -2: "EMESH", -3: "ENOTSUP", -4: "EHIP", -5: "ENONFINITE", -6: "ESTATE"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libchorus.so is not built; run __graft_entry__.build() or "
+                      "python paper_1503_00834_amd/build.py")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class ChorusError(RuntimeError):
+    def __init__(self, status, where):
+        buf = ctypes.create_string_buffer(512)
+        _lib.chorus_last_error(buf, 512)
+        self.status = status
+        super().__init__("%s failed: %s (%s)" % (where, ERRORS.get(status, status),
+                                                 buf.value.decode(errors="replace")))
+
+
+class ShellDesc(ctypes.Structure):
+    _fields_ = [("panel_n", ctypes.c_int32), ("radial_n", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("r_inner", ctypes.c_double), ("r_outer", ctypes.c_double)]
+
+
+class Hex20Desc(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("xyz", ctypes.c_void_p), ("n_elems", ctypes.c_int64),
+                ("elem20", ctypes.c_void_p), ("face_bc", ctypes.c_void_p), ("match_id", ctypes.c_void_p),
+                ("order", ctypes.c_int32)]
+
+
+class Physics(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("R_gas", ctypes.c_double), ("GM", ctypes.c_double),
+                ("omega", ctypes.c_double), ("nu", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("kappa_r", ctypes.c_double), ("T_top", ctypes.c_double), ("F_bottom", ctypes.c_double),
+                ("bc_state", ctypes.c_double * 5), ("precision", ctypes.c_int32),
+                ("closure", ctypes.c_int32), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def physics(gamma=5.0 / 3.0, R_gas=1.0, GM=0.0, omega=0.0, nu=0.0, kappa=0.0, kappa_r=0.0, T_top=0.0,
+            F_bottom=0.0, bc_state=(1.0, 0.0, 0.0, 0.0, 1.5), precision=CHORUS_FP64, closure=0, flags=0):
+    p = Physics()
+    p.gamma, p.R_gas, p.GM, p.omega, p.nu = gamma, R_gas, GM, omega, nu
+    p.kappa, p.kappa_r, p.T_top, p.F_bottom = kappa, kappa_r, T_top, F_bottom
+    for i in range(5):
+        p.bc_state[i] = bc_state[i]
+    p.precision, p.closure, p.flags = precision, closure, flags
+    return p
+
+
+_P = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_SIGS = {
+    "chorus_mesh_create": [ctypes.POINTER(ShellDesc), ctypes.POINTER(_P)],
+    "chorus_mesh_create_hex20": [ctypes.POINTER(Hex20Desc), ctypes.POINTER(_P)],
+    "chorus_mesh_destroy": [_P],
+    "chorus_mesh_query": [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)],
+    "chorus_mesh_nodes": [_P, ctypes.POINTER(ctypes.c_int64), _P, _P, _P],
+    "chorus_mesh_solpts": [_P, _P, _P],
+    "chorus_mesh_geometry": [_P, _P, _P, _P],
+    "chorus_mesh_face_table": [_P, _P, _P, _P],
+    "chorus_mesh_upload": [_P, _P, ctypes.c_size_t, _P],
+    "chorus_workspace_bytes": [_P, ctypes.POINTER(Physics), ctypes.POINTER(ctypes.c_size_t)],
+    "chorus_init_polytrope": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_double, _P, ctypes.c_double, _P, _P],
+    "chorus_set_background": [_P, ctypes.POINTER(Physics), _P, _P, _P],
+    "chorus_sd_residual": [_P, ctypes.POINTER(Physics), _P, _P, _P, _P],
+    "chorus_rk_step": [_P, ctypes.POINTER(Physics), _P, ctypes.c_double, ctypes.c_int32, _P, _P],
+    "chorus_conserved_sums": [_P, _P, _P, _P, _P],
+    "chorus_stable_dt": [_P, ctypes.POINTER(Physics), _P, ctypes.c_double, _dp],
+    "chorus_last_error": [ctypes.c_char_p, ctypes.c_size_t],
+    "chorus_kernel_timing": [ctypes.c_int],
+    "chorus_kernel_times": [_P, _P],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.chorus_strerror.argtypes = [ctypes.c_int]
+_lib.chorus_strerror.restype = ctypes.c_char_p
+
+
+def _check(rc, where):
+    if rc != CHORUS_OK:
+        raise ChorusError(rc, where)
+
+
+def _ptr(a):
+    """Address of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+# ---------------------------------------------------------------------------
+# mesh handle
+# ---------------------------------------------------------------------------
+class Mesh:
+    """Owner of a chorus mesh handle plus its device geometry image."""
+
+    def __init__(self, handle):
+        self.handle = _P(handle)
+        e, n, s, f, w, b = (ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(),
+                            ctypes.c_int64(), ctypes.c_size_t())
+        _check(_lib.chorus_mesh_query(self.handle, e, n, s, f, w, b), "chorus_mesh_query")
+        self.n_elems, self.order, self.n_solpts = e.value, n.value, s.value
+        self.n_faces, self.n_wall_faces, self.device_bytes = f.value, w.value, b.value
+        self.image = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _lib.chorus_mesh_destroy(h)
+            self.handle = None
+
+    # host queries ---------------------------------------------------------
+    def solpts(self):
+        xyz = np.zeros((3, self.n_solpts))
+        wJ = np.zeros(self.n_solpts)
+        _check(_lib.chorus_mesh_solpts(self.handle, _ptr(xyz), _ptr(wJ)), "chorus_mesh_solpts")
+        return xyz, wJ
+
+    def geometry(self):
+        N, E = self.order, self.n_elems
+        jac = np.zeros(self.n_solpts)
+        met = np.zeros((self.n_solpts, 3, 3))
+        metf = np.zeros((E, 3, (N + 1) * N * N, 3))
+        _check(_lib.chorus_mesh_geometry(self.handle, _ptr(jac), _ptr(met), _ptr(metf)),
+               "chorus_mesh_geometry")
+        return jac, met, metf
+
+    def face_table(self):
+        ne = np.zeros(self.n_elems * 6, dtype=np.int32)
+        nf = np.zeros_like(ne)
+        o = np.zeros_like(ne)
+        _check(_lib.chorus_mesh_face_table(self.handle, _ptr(ne), _ptr(nf), _ptr(o)),
+               "chorus_mesh_face_table")
+        return ne.reshape(-1, 6), nf.reshape(-1, 6), o.reshape(-1, 6)
+
+    def nodes(self):
+        n = ctypes.c_int64()
+        _check(_lib.chorus_mesh_nodes(self.handle, n, None, None, None), "chorus_mesh_nodes")
+        xyz = np.zeros((n.value, 3))
+        e20 = np.zeros((self.n_elems, 20), dtype=np.int64)
+        fbc = np.zeros((self.n_elems, 6), dtype=np.int32)
+        _check(_lib.chorus_mesh_nodes(self.handle, n, _ptr(xyz), _ptr(e20), _ptr(fbc)), "chorus_mesh_nodes")
+        return xyz, e20, fbc
+
+    def init_polytrope(self, beta, n_rho, poly_n=1.5, gamma=5.0 / 3.0, R_gas=1.0, noise=None, amp=1e-4):
+        Q = np.zeros((5, self.n_solpts))
+        pars = np.zeros(4)
+        nz = None if noise is None else np.ascontiguousarray(noise, dtype=np.float64).reshape(-1)
+        _check(_lib.chorus_init_polytrope(self.handle, beta, n_rho, poly_n, gamma, R_gas, _ptr(nz), amp,
+                                          _ptr(Q), _ptr(pars)), "chorus_init_polytrope")
+        return Q, dict(chi_o=pars[0], c=pars[1], alpha=pars[2], GM=pars[3])
+
+    def stable_dt(self, phys, Q_host, cfl):
+        Qh = np.ascontiguousarray(Q_host, dtype=np.float64)
+        dt = ctypes.c_double()
+        _check(_lib.chorus_stable_dt(self.handle, ctypes.byref(phys), _ptr(Qh), cfl, ctypes.byref(dt)),
+               "chorus_stable_dt")
+        return dt.value
+
+    # device ---------------------------------------------------------------
+    def upload(self, device="cuda", stream=None):
+        import torch
+        self.image = torch.empty(self.device_bytes + 256, dtype=torch.uint8, device=device)
+        base = self.image.data_ptr()
+        off = (-base) % 256
+        self._image_ptr = base + off
+        _check(_lib.chorus_mesh_upload(self.handle, _P(self._image_ptr), self.device_bytes, _P(_stream(stream))),
+               "chorus_mesh_upload")
+        return self
+
+    def workspace(self, phys, device="cuda"):
+        import torch
+        b = ctypes.c_size_t()
+        _check(_lib.chorus_workspace_bytes(self.handle, ctypes.byref(phys), ctypes.byref(b)),
+               "chorus_workspace_bytes")
+        return torch.empty(b.value, dtype=torch.uint8, device=device)
+
+
+def chorus_mesh_create(panel_n, radial_n, order, r_inner, r_outer):
+    d = ShellDesc(panel_n, radial_n, order, r_inner, r_outer)
+    h = _P()
+    _check(_lib.chorus_mesh_create(ctypes.byref(d), ctypes.byref(h)), "chorus_mesh_create")
+    return Mesh(h.value)
+
+
+def chorus_mesh_create_hex20(xyz, elem20, face_bc, order, match_id=None):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    elem20 = np.ascontiguousarray(elem20, dtype=np.int64)
+    face_bc = np.ascontiguousarray(face_bc, dtype=np.int32)
+    mid = None if match_id is None else np.ascontiguousarray(match_id, dtype=np.int64)
+    d = Hex20Desc(xyz.shape[0], _ptr(xyz), elem20.shape[0], _ptr(elem20), _ptr(face_bc), _ptr(mid), order)
+    h = _P()
+    _check(_lib.chorus_mesh_create_hex20(ctypes.byref(d), ctypes.byref(h)), "chorus_mesh_create_hex20")
+    return Mesh(h.value)
+
+
+def _ws_ptr(ws):
+    return _P(ws.data_ptr())
+
+
+def chorus_sd_residual(mesh, phys, Q, dQdt, ws, stream=None):
+    """dQ/dt of the device state Q ([5, E N^3] float64) into dQdt."""
+    assert Q.is_contiguous() and dQdt.is_contiguous() and Q.numel() == 5 * mesh.n_solpts
+    _check(_lib.chorus_sd_residual(mesh.handle, ctypes.byref(phys), _P(Q.data_ptr()), _P(dQdt.data_ptr()),
+                                   _ws_ptr(ws), _P(_stream(stream))), "chorus_sd_residual")
+
+
+def chorus_rk_step(mesh, phys, Q, dt, n_steps, ws, stream=None):
+    """n_steps SSP-RK3 steps in place on the device state Q."""
+    assert Q.is_contiguous() and Q.numel() == 5 * mesh.n_solpts
+    _check(_lib.chorus_rk_step(mesh.handle, ctypes.byref(phys), _P(Q.data_ptr()), float(dt), int(n_steps),
+                               _ws_ptr(ws), _P(_stream(stream))), "chorus_rk_step")
+
+
+def chorus_conserved_sums(mesh, Q, ws, stream=None):
+    out = np.zeros(5)
+    _check(_lib.chorus_conserved_sums(mesh.handle, _P(Q.data_ptr()), _ptr(out), _ws_ptr(ws),
+                                      _P(_stream(stream))), "chorus_conserved_sums")
+    return out
+
+
+def chorus_set_background(mesh, phys, Q0, ws, stream=None):
+    _check(_lib.chorus_set_background(mesh.handle, ctypes.byref(phys), _P(Q0.data_ptr()), _ws_ptr(ws),
+                                      _P(_stream(stream))), "chorus_set_background")
+
+
+def chorus_kernel_timing(enable):
+    _check(_lib.chorus_kernel_timing(1 if enable else 0), "chorus_kernel_timing")
+
+
+KERNEL_KINDS = ("k_trace", "k_grad", "k_resid")
+
+
+def chorus_kernel_times():
+    """{kind: (total_ms, launches)} since the last read (synchronises)."""
+    ms = np.zeros(3)
+    cnt = np.zeros(3, dtype=np.int64)
+    _check(_lib.chorus_kernel_times(_ptr(ms), _ptr(cnt)), "chorus_kernel_times")
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
+def mesh_from_arrays(m, order):
+    """Mesh handle from a chorus_inputs.Hex20Mesh."""
+    return chorus_mesh_create_hex20(m.xyz, m.elem20, m.face_bc, order, m.match_id)

@@ -1,0 +1,40 @@
+// Kernel launchers shared by the ABI layer and the kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "chorus_internal.hpp"
+#include "physics.hpp"
+
+namespace chorus {
+
+// device geometry image views
+struct Geo {
+    const double *solgeo;   // [E][13][NP]
+    const double *fluxgeo;  // [E][3][3][NFL]
+    const int32_t *link;    // [E][6]
+    const int32_t *info;    // [E][6]
+    int64_t E;
+};
+
+// stage combination Q_out = ca Qn + cb (Q + dt R); mode 0 writes R only
+struct StageArgs {
+    const double *Qn;  // step-start state (may alias Qout)
+    double *Qout;      // stage output (may alias Q or Qn)
+    double *TQout;     // face traces of Q_out (RK mode) or null
+    double ca, cb, dt;
+    int mode;          // 0 residual, 1 RK stage
+};
+
+hipError_t launch_trace(const Mesh &m, const Geo &G, const double *Q, double *TQ, hipStream_t s);
+hipError_t launch_grad(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
+                       double *TV, hipStream_t s);
+hipError_t launch_resid(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
+                        const double *TV, const StageArgs &sa, hipStream_t s);
+hipError_t launch_sums(const double *Q, const double *solw, int64_t n, double *part, int nblocks, double *out,
+                       hipStream_t s);
+hipError_t launch_check(const double *Q, int64_t n, double gm1, int *flag, hipStream_t s);
+
+}  // namespace chorus

@@ -1,0 +1,532 @@
+// HIP kernels (gfx950) of the spectral-difference residual and the SSP-RK3
+// update (Section 3 of the paper; SSP-RK3 as the explicit integrator).
+//
+// One residual evaluation is split in two element passes because BR1 needs
+// two neighbour exchanges (Section 3, viscous treatment):
+//
+//   k_grad   Q (own element) + neighbours' Q face traces
+//            -> common interface solution, gradients at solution points,
+//               viscous flux of the own side at interior interface points
+//               (written as the viscous face trace TV)
+//   k_resid  Q + neighbours' Q and viscous traces
+//            -> gradients again, fluxes at all flux points, Rusanov + averaged
+//               viscous common fluxes at interfaces, divergence of the flux
+//               polynomials, source, and either dQ/dt or the fused SSP-RK3
+//               stage combination; in RK mode it also writes the face traces
+//               of the new stage value for the next pass.
+//
+// Work mapping: a workgroup of NT threads owns EPB elements; every phase is a
+// strided loop over (element, point) items with all element data staged in
+// LDS.  No atomics: every output is written by exactly one thread in a fixed
+// summation order, so results are bitwise run-to-run deterministic.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "launch.hpp"
+
+namespace chorus {
+
+template <int N>
+struct Ops {
+    double I[N + 1][N];  // I[m][s] = h_s(xf[m])
+    double D[N][N + 1];  // D[s][m] = l_m'(xs[s])
+    double B[N][N];      // sum_{m=1}^{N-1} D[s][m] I[m][s']: interior flux points folded
+};
+
+
+
+// line through solution point (a along d; t1 < t2 the tangential indices)
+template <int N>
+__device__ __forceinline__ int sol_of(int d, int a, int t1, int t2) {
+    return d == 0 ? a + N * (t1 + N * t2) : (d == 1 ? t1 + N * (a + N * t2) : t1 + N * (t2 + N * a));
+}
+template <int N>
+__device__ __forceinline__ int stride_of(int d) {
+    return d == 0 ? 1 : (d == 1 ? N : N * N);
+}
+template <int N>
+__device__ __forceinline__ void split_sol(int d, int p, int &a, int &t1, int &t2) {
+    const int i = p % N, j = (p / N) % N, k = p / (N * N);
+    if (d == 0) { a = i; t1 = j; t2 = k; }
+    else if (d == 1) { a = j; t1 = i; t2 = k; }
+    else { a = k; t1 = i; t2 = j; }
+}
+template <int N>
+__device__ __forceinline__ int map_face_point(int o, int t1, int t2) {
+    int u1 = (o & 4) ? t2 : t1, u2 = (o & 4) ? t1 : t2;
+    if (o & 2) u1 = N - 1 - u1;
+    if (o & 1) u2 = N - 1 - u2;
+    return u1 + N * u2;
+}
+
+// ---------------------------------------------------------------------------
+// shared phases
+// ---------------------------------------------------------------------------
+template <int N, int EPB, int NT>
+__device__ __forceinline__ void load_q(const double *__restrict__ Q, int64_t E, int64_t e0,
+                                       double (*sq)[5][N * N * N]) {
+    constexpr int NP = N * N * N;
+    for (int it = threadIdx.x; it < EPB * 5 * NP; it += NT) {
+        const int el = it / (5 * NP), r = it % (5 * NP), v = r / NP, p = r % NP;
+        const int64_t e = e0 + el;
+        sq[el][v][p] = (e < E) ? Q[((int64_t)v * E + e) * NP + p] : (v == 0 || v == 4 ? 1.0 : 0.0);
+    }
+}
+
+// common interface solution Q* at the 6 N^2 face points (BR1 average with
+// the neighbour trace, wall state, or average with the far-field state)
+template <int N, int EPB, int NT>
+__device__ __forceinline__ void common_solution(const Ops<N> &op, const Geo &G, const PhysParams &P,
+                                                const double *__restrict__ TQ, int64_t e0,
+                                                double (*sq)[5][N * N * N],
+                                                double (*sqs)[6][5][N * N]) {
+    constexpr int NF2 = N * N, NFL = (N + 1) * N * N;
+    for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        const int64_t e = e0 + el;
+        if (e >= G.E) continue;
+        const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
+        const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
+        double qo[5], qs[5];
+        for (int v = 0; v < 5; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) s += op.I[m][b] * sq[el][v][base + b * st];
+            qo[v] = s;
+        }
+        const int32_t nb = G.link[e * 6 + f];
+        const int32_t inf = G.info[e * 6 + f];
+        const int bc = (inf >> 6) - 1;
+        if (nb >= 0) {
+            const int f2 = inf & 7, o = (inf >> 3) & 7;
+            const int pn = map_face_point<N>(o, t1, t2);
+            const double *tq = TQ + ((int64_t)nb * 6 + f2) * 5 * NF2;
+            for (int v = 0; v < 5; ++v) qs[v] = 0.5 * (qo[v] + tq[v * NF2 + pn]);
+        } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
+            const int fl = m + (N + 1) * (t1 + N * t2);
+            const double sg = (f & 1) ? 1.0 : -1.0;
+            double S[3];
+            for (int c = 0; c < 3; ++c) S[c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+            wall_state(qo, S, bc == CHORUS_BC_OUTER, P, qs);
+        } else {
+            for (int v = 0; v < 5; ++v) qs[v] = 0.5 * (qo[v] + P.bc_state[v]);
+        }
+        for (int v = 0; v < 5; ++v) sqs[el][f][v][pp] = qs[v];
+    }
+}
+
+// gradients of the conserved variables at the solution points:
+// dQ/dxi_d = B q_line + D[.,0] Q*_0 + D[.,N] Q*_N, then grad_x = sum_d G_d dQ/dxi_d
+template <int N, int EPB, int NT>
+__device__ __forceinline__ void gradients(const Ops<N> &op, const Geo &G, int64_t e0,
+                                          double (*sq)[5][N * N * N], double (*sqs)[6][5][N * N],
+                                          double (*sgr)[15][N * N * N]) {
+    constexpr int NP = N * N * N;
+    for (int it = threadIdx.x; it < EPB * NP; it += NT) {
+        const int el = it / NP, p = it % NP;
+        const int64_t e = e0 + el;
+        if (e >= G.E) continue;
+        double dq[3][5];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int a, t1, t2;
+            split_sol<N>(d, p, a, t1, t2);
+            const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d), pp = t1 + N * t2;
+            for (int v = 0; v < 5; ++v) {
+                double s = op.D[a][0] * sqs[el][2 * d][v][pp] + op.D[a][N] * sqs[el][2 * d + 1][v][pp];
+#pragma unroll
+                for (int b = 0; b < N; ++b) s += op.B[a][b] * sq[el][v][base + b * st];
+                dq[d][v] = s;
+            }
+        }
+        const double *gs = G.solgeo + e * 13 * NP + p;
+        double Gm[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) Gm[t] = gs[t * NP];
+        for (int v = 0; v < 5; ++v)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                sgr[el][v * 3 + c][p] = Gm[c] * dq[0][v] + Gm[3 + c] * dq[1][v] + Gm[6 + c] * dq[2][v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+// face traces of Q: TQ[e][f][v][pp]
+template <int N, int EPB, int NT>
+__global__ __launch_bounds__(NT) void k_trace(Ops<N> op, Geo G, const double *__restrict__ Q,
+                                              double *__restrict__ TQ) {
+    constexpr int NP = N * N * N, NF2 = N * N;
+    __shared__ double sq[EPB][5][NP];
+    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    load_q<N, EPB, NT>(Q, G.E, e0, sq);
+    __syncthreads();
+    for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        const int64_t e = e0 + el;
+        if (e >= G.E) continue;
+        const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
+        const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
+        for (int v = 0; v < 5; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) s += op.I[m][b] * sq[el][v][base + b * st];
+            TQ[((e * 6 + f) * 5 + v) * NF2 + pp] = s;
+        }
+    }
+}
+
+// viscous flux of the own side at interior interface points, along the
+// outward area vector: TV[e][f][v][pp]
+template <int N, int EPB, int NT>
+__global__ __launch_bounds__(NT) void k_grad(Ops<N> op, Geo G, PhysParams P, const double *__restrict__ Q,
+                                             const double *__restrict__ TQ, double *__restrict__ TV) {
+    constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
+    __shared__ double sq[EPB][5][NP];
+    __shared__ double sqs[EPB][6][5][NF2];
+    __shared__ double sgr[EPB][15][NP];
+    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    load_q<N, EPB, NT>(Q, G.E, e0, sq);
+    __syncthreads();
+    common_solution<N, EPB, NT>(op, G, P, TQ, e0, sq, sqs);
+    __syncthreads();
+    gradients<N, EPB, NT>(op, G, e0, sq, sqs, sgr);
+    __syncthreads();
+    for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        const int64_t e = e0 + el;
+        if (e >= G.E) continue;
+        if (G.link[e * 6 + f] < 0) continue;
+        const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
+        const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
+        double q[5], g[5][3];
+        for (int v = 0; v < 5; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) s += op.I[m][b] * sq[el][v][base + b * st];
+            q[v] = s;
+            for (int c = 0; c < 3; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int b = 0; b < N; ++b) t += op.I[m][b] * sgr[el][v * 3 + c][base + b * st];
+                g[v][c] = t;
+            }
+        }
+        const int fl = m + (N + 1) * (t1 + N * t2);
+        const double sg = (f & 1) ? 1.0 : -1.0;
+        double S[3], fv[5];
+        for (int c = 0; c < 3; ++c) S[c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+        flux_viscous(q, g, S, P, fv);
+        for (int v = 0; v < 5; ++v) TV[((e * 6 + f) * 5 + v) * NF2 + pp] = fv[v];
+    }
+}
+
+
+
+template <int N, int EPB, int NT>
+__global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, const double *Q,
+                                              const double *__restrict__ TQ,
+                                              const double *__restrict__ TV, StageArgs S_) {
+    constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
+    __shared__ double sq[EPB][5][NP];
+    __shared__ double sqs[EPB][6][5][NF2];
+    __shared__ double sgr[EPB][15][NP];
+    __shared__ double sft[EPB][5][NFL];
+    __shared__ double sdiv[EPB][5][NP];
+    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    const double gm1 = P.gamma - 1.0;
+    load_q<N, EPB, NT>(Q, G.E, e0, sq);
+    __syncthreads();
+    common_solution<N, EPB, NT>(op, G, P, TQ, e0, sq, sqs);
+    __syncthreads();
+    gradients<N, EPB, NT>(op, G, e0, sq, sqs, sgr);
+    __syncthreads();
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+        // transformed flux at the d-flux points
+        for (int it = threadIdx.x; it < EPB * NFL; it += NT) {
+            const int el = it / NFL, fl = it % NFL;
+            const int64_t e = e0 + el;
+            if (e >= G.E) continue;
+            const int m = fl % (N + 1), t1 = (fl / (N + 1)) % N, t2 = fl / ((N + 1) * N);
+            const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
+            double q[5], g[5][3], S[3], F[5];
+            for (int v = 0; v < 5; ++v) {
+                double s = 0.0;
+#pragma unroll
+                for (int b = 0; b < N; ++b) s += op.I[m][b] * sq[el][v][base + b * st];
+                q[v] = s;
+                for (int c = 0; c < 3; ++c) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int b = 0; b < N; ++b) t += op.I[m][b] * sgr[el][v * 3 + c][base + b * st];
+                    g[v][c] = t;
+                }
+            }
+            for (int c = 0; c < 3; ++c) S[c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+            if (m > 0 && m < N) {
+                double fi[5], fv[5];
+                flux_inviscid(q, S, gm1, fi);
+                flux_viscous(q, g, S, P, fv);
+                for (int v = 0; v < 5; ++v) F[v] = fi[v] - fv[v];
+            } else {
+                const int f = 2 * d + (m == N ? 1 : 0);
+                const double sg = (m == N) ? 1.0 : -1.0;
+                double So[3] = {sg * S[0], sg * S[1], sg * S[2]}, phi[5];
+                const int32_t nb = G.link[e * 6 + f];
+                const int32_t inf = G.info[e * 6 + f];
+                const int bc = (inf >> 6) - 1;
+                if (nb >= 0) {
+                    const int f2 = inf & 7, o = (inf >> 3) & 7;
+                    const int pn = map_face_point<N>(o, t1, t2);
+                    const double *tq = TQ + ((int64_t)nb * 6 + f2) * 5 * NF2;
+                    const double *tv = TV + ((int64_t)nb * 6 + f2) * 5 * NF2;
+                    double qn[5], fvo[5];
+                    for (int v = 0; v < 5; ++v) qn[v] = tq[v * NF2 + pn];
+                    flux_rusanov(q, qn, So, P, phi);
+                    flux_viscous(q, g, So, P, fvo);
+                    // the neighbour stored its viscous flux along its own outward
+                    // area vector, which is -So
+                    for (int v = 0; v < 5; ++v) phi[v] -= 0.5 * (fvo[v] + (-tv[v * NF2 + pn]));
+                } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
+                    flux_wall(q, g, So, bc == CHORUS_BC_OUTER, P, phi);
+                } else {
+                    double fvo[5];
+                    flux_rusanov(q, P.bc_state, So, P, phi);
+                    flux_viscous(q, g, So, P, fvo);
+                    for (int v = 0; v < 5; ++v) phi[v] -= 0.5 * fvo[v];
+                }
+                for (int v = 0; v < 5; ++v) F[v] = sg * phi[v];
+            }
+            for (int v = 0; v < 5; ++v) sft[el][v][fl] = F[v];
+        }
+        __syncthreads();
+        // derivative of the flux polynomial along d at the solution points
+        for (int it = threadIdx.x; it < EPB * NP; it += NT) {
+            const int el = it / NP, p = it % NP;
+            int a, t1, t2;
+            split_sol<N>(d, p, a, t1, t2);
+            const int fb = (N + 1) * (t1 + N * t2);
+            for (int v = 0; v < 5; ++v) {
+                double s = 0.0;
+#pragma unroll
+                for (int mm = 0; mm <= N; ++mm) s += op.D[a][mm] * sft[el][v][fb + mm];
+                sdiv[el][v][p] = (d == 0) ? s : sdiv[el][v][p] + s;
+            }
+        }
+        __syncthreads();
+    }
+    // source and output
+    for (int it = threadIdx.x; it < EPB * NP; it += NT) {
+        const int el = it / NP, p = it % NP;
+        const int64_t e = e0 + el;
+        if (e >= G.E) continue;
+        const double *gs = G.solgeo + e * 13 * NP + p;
+        const double iJ = gs[9 * NP];
+        const double g0 = P.GM * gs[10 * NP], g1 = P.GM * gs[11 * NP], g2 = P.GM * gs[12 * NP];
+        const double rho = sq[el][0][p], mx = sq[el][1][p], my = sq[el][2][p], mz = sq[el][3][p];
+        double M[5];
+        M[0] = 0.0;
+        M[1] = rho * g0 - 2.0 * P.omega * my;
+        M[2] = rho * g1 + 2.0 * P.omega * mx;
+        M[3] = rho * g2;
+        M[4] = mx * g0 + my * g1 + mz * g2;
+        for (int v = 0; v < 5; ++v) {
+            const double R = -sdiv[el][v][p] * iJ - M[v];
+            const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
+            if (S_.mode == 0) {
+                S_.Qout[gi] = R;
+            } else {
+                const double qn = (S_.ca != 0.0) ? S_.Qn[gi] : 0.0;
+                const double qv = S_.ca * qn + S_.cb * (sq[el][v][p] + S_.dt * R);
+                S_.Qout[gi] = qv;
+                sq[el][v][p] = qv;
+            }
+        }
+    }
+    if (S_.mode == 0 || S_.TQout == nullptr) return;
+    __syncthreads();
+    for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        const int64_t e = e0 + el;
+        if (e >= G.E) continue;
+        const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
+        const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
+        for (int v = 0; v < 5; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) s += op.I[m][b] * sq[el][v][base + b * st];
+            S_.TQout[((e * 6 + f) * 5 + v) * NF2 + pp] = s;
+        }
+    }
+}
+
+// fixed-order partial sums of w w w |J| Q_v over element blocks
+template <int NT>
+__global__ __launch_bounds__(NT) void k_sums_partial(const double *__restrict__ Q,
+                                                     const double *__restrict__ solw, int64_t n,
+                                                     int64_t chunk, double *__restrict__ part) {
+    __shared__ double red[NT];
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
+    for (int v = 0; v < 5; ++v) {
+        double s = 0.0;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += NT) s += solw[i] * Q[(int64_t)v * n + i];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = NT / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(int64_t)v * gridDim.x + blockIdx.x] = red[0];
+        __syncthreads();
+    }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_sums_final(const double *__restrict__ part, int nb,
+                                                   double *__restrict__ out) {
+    __shared__ double red[NT];
+    for (int v = 0; v < 5; ++v) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nb; i += NT) s += part[(int64_t)v * nb + i];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = NT / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[v] = red[0];
+        __syncthreads();
+    }
+}
+
+// non-finite / non-positive density or pressure check: flag[0] set to 1
+__global__ void k_check(const double *__restrict__ Q, int64_t n, double gm1, int *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double r = Q[i], mx = Q[n + i], my = Q[2 * n + i], mz = Q[3 * n + i], E = Q[4 * n + i];
+    const double p = gm1 * (E - 0.5 * (mx * mx + my * my + mz * mz) / r);
+    const bool ok = (r > 0.0) && (p > 0.0) && (r < 1e300) && (p < 1e300) && (mx == mx) && (my == my) &&
+                    (mz == mz);
+    if (!ok) flag[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+struct LaunchCfg {
+    int epb, nt;
+};
+
+template <int N>
+static Ops<N> make_ops(const Basis1D &b) {
+    Ops<N> o;
+    for (int m = 0; m <= N; ++m)
+        for (int s = 0; s < N; ++s) o.I[m][s] = b.I[m][s];
+    for (int s = 0; s < N; ++s)
+        for (int m = 0; m <= N; ++m) o.D[s][m] = b.D[s][m];
+    for (int a = 0; a < N; ++a)
+        for (int s = 0; s < N; ++s) {
+            double v = 0.0;
+            for (int m = 1; m < N; ++m) v += b.D[a][m] * b.I[m][s];
+            o.B[a][s] = v;
+        }
+    return o;
+}
+
+// elements per block / threads per block for each order
+template <int N>
+struct Cfg;
+template <> struct Cfg<2> { static constexpr int EPB = 8, NT = 64; };
+template <> struct Cfg<3> { static constexpr int EPB = 2, NT = 64; };
+template <> struct Cfg<4> { static constexpr int EPB = 1, NT = 64; };
+template <> struct Cfg<5> { static constexpr int EPB = 1, NT = 128; };
+template <> struct Cfg<6> { static constexpr int EPB = 1, NT = 256; };
+
+struct Bufs {
+    const double *Q;
+    const double *TQ;
+    double *TQw;
+    double *TV;
+};
+
+template <int N>
+static hipError_t launch_trace_t(const Mesh &m, const Geo &G, const double *Q, double *TQ, hipStream_t s) {
+    constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
+    const Ops<N> op = make_ops<N>(m.basis);
+    const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
+    hipLaunchKernelGGL((k_trace<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, op, G, Q, TQ);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_grad_t(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q,
+                                const double *TQ, double *TV, hipStream_t s) {
+    constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
+    const Ops<N> op = make_ops<N>(m.basis);
+    const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
+    hipLaunchKernelGGL((k_grad<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, op, G, P, Q, TQ, TV);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_resid_t(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q,
+                                 const double *TQ, const double *TV, const StageArgs &sa, hipStream_t s) {
+    constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
+    const Ops<N> op = make_ops<N>(m.basis);
+    const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
+    hipLaunchKernelGGL((k_resid<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, op, G, P, Q, TQ, TV, sa);
+    return hipGetLastError();
+}
+
+#define CHORUS_DISPATCH(N_, CALL)            \
+    switch (N_) {                            \
+        case 2: return CALL(2);              \
+        case 3: return CALL(3);              \
+        case 4: return CALL(4);              \
+        case 5: return CALL(5);              \
+        case 6: return CALL(6);              \
+        default: return hipErrorInvalidValue; \
+    }
+
+hipError_t launch_trace(const Mesh &m, const Geo &G, const double *Q, double *TQ, hipStream_t s) {
+#define C_(n) launch_trace_t<n>(m, G, Q, TQ, s)
+    CHORUS_DISPATCH(m.N, C_)
+#undef C_
+}
+hipError_t launch_grad(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
+                       double *TV, hipStream_t s) {
+#define C_(n) launch_grad_t<n>(m, G, P, Q, TQ, TV, s)
+    CHORUS_DISPATCH(m.N, C_)
+#undef C_
+}
+hipError_t launch_resid(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
+                        const double *TV, const StageArgs &sa, hipStream_t s) {
+#define C_(n) launch_resid_t<n>(m, G, P, Q, TQ, TV, sa, s)
+    CHORUS_DISPATCH(m.N, C_)
+#undef C_
+}
+
+hipError_t launch_sums(const double *Q, const double *solw, int64_t n, double *part, int nblocks, double *out,
+                       hipStream_t s) {
+    const int64_t chunk = (n + nblocks - 1) / nblocks;
+    hipLaunchKernelGGL((k_sums_partial<256>), dim3(nblocks), dim3(256), 0, s, Q, solw, n, chunk, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sums_final<256>), dim3(1), dim3(256), 0, s, part, nblocks, out);
+    return hipGetLastError();
+}
+
+__global__ void k_clear_flag(int *flag) { flag[0] = 0; }
+
+hipError_t launch_check(const double *Q, int64_t n, double gm1, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, s, flag);
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_check, dim3(nb), dim3(256), 0, s, Q, n, gm1, flag);
+    return hipGetLastError();
+}
+
+}  // namespace chorus

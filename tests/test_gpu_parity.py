@@ -1,0 +1,179 @@
+"""GPU parity of the FP64 SD residual and SSP-RK3 update against the CPU
+oracle, through the C-ABI.
+
+Tolerance (FP64 mode): per conserved variable v,
+    ||R_gpu,v - R_oracle,v||_2 <= max(1e-12 ||R_oracle,v||_2, 8 * floor_v)
+where floor_v is the oracle's own rounding sensitivity: the change of its
+output when every input value is perturbed by one unit in the last place.
+The GPU evaluates the same formulas with a different summation order and
+fused multiply-adds, which is a rounding-level perturbation of the same size;
+floor_v matters only for near-cancelling outputs (hydrostatic momentum).
+"""
+import numpy as np
+import pytest
+
+from chorus_inputs import box_mesh, cubed_sphere_shell, two_element_mesh, uniform_noise
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ch(torch_dev):
+    import paper_1503_00834_amd as ch
+    return ch
+
+
+def ulp_perturb(Q, seed=7):
+    rng = np.random.default_rng(seed)
+    return Q * (1.0 + np.finfo(np.float64).eps * rng.choice([-1.0, 1.0], size=Q.shape))
+
+
+def assert_parity(R_gpu, R_ref, R_pert, what, rel=1e-12):
+    R_gpu = R_gpu.reshape(5, -1)
+    R_ref = R_ref.reshape(5, -1)
+    floor = np.linalg.norm((R_pert.reshape(5, -1) - R_ref), axis=1)
+    for v in range(5):
+        err = np.linalg.norm(R_gpu[v] - R_ref[v])
+        ref = np.linalg.norm(R_ref[v])
+        tol = max(rel * ref, 8.0 * floor[v], 1e-300)
+        assert err <= tol, "%s var %d: err %.3e tol %.3e (ref %.3e floor %.3e)" % (
+            what, v, err, tol, ref, floor[v])
+
+
+def ora_phys(oracle_mod, p):
+    return oracle_mod.phys(gamma=p.gamma, R_gas=p.R_gas, GM=p.GM, omega=p.omega, nu=p.nu, kappa=p.kappa,
+                           kappa_r=p.kappa_r, T_top=p.T_top, F_bottom=p.F_bottom,
+                           bc_state=tuple(p.bc_state))
+
+
+def gpu_residual(ch, torch, cm, phys, Q):
+    Qd = torch.from_numpy(np.ascontiguousarray(Q.reshape(5, -1))).cuda()
+    R = torch.empty_like(Qd)
+    ws = cm.workspace(phys)
+    ch.chorus_sd_residual(cm, phys, Qd, R, ws)
+    torch.cuda.synchronize()
+    return R.cpu().numpy()
+
+
+def shell_case(oracle_mod, ch, panel_n, radial_n, N, beta=0.7, n_rho=1.0, amp=1e-2, seed=0):
+    ri, ro = beta / (1 - beta), 1 / (1 - beta)
+    m = cubed_sphere_shell(panel_n, radial_n, ri, ro)
+    om = oracle_mod.OracleMesh(m, N)
+    Q, pars = om.polytrope(beta, n_rho, noise=uniform_noise(om.n_solpts, seed), amp=amp)
+    # add a seeded velocity field so that every flux term is exercised
+    rng = np.random.default_rng(seed + 1)
+    Q[1:4] = 0.05 * Q[0] * rng.uniform(-1, 1, size=Q[1:4].shape)
+    Q[4] += 0.5 * (Q[1:4] ** 2).sum(0) / Q[0]
+    phys = ch.physics(GM=pars["GM"], omega=1.0, nu=1e-3, kappa=1e-3, kappa_r=2e-4, T_top=pars["chi_o"],
+                      F_bottom=0.01)
+    return m, om, Q, phys
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_residual_parity_shell(ch, oracle_mod, torch_dev, N):
+    m, om, Q, phys = shell_case(oracle_mod, ch, 3, 2, N)
+    cm = ch.mesh_from_arrays(m, N).upload()
+    R = gpu_residual(ch, torch_dev, cm, phys, Q)
+    op = ora_phys(oracle_mod, phys)
+    assert_parity(R, om.residual(op, Q), om.residual(op, ulp_perturb(Q)), "shell N=%d" % N)
+
+
+def test_residual_parity_c1_config(ch, oracle_mod, torch_dev):
+    """The 288-hex, N=3 shell of the plain FP64 configuration."""
+    m, om, Q, phys = shell_case(oracle_mod, ch, 4, 3, 3, amp=1e-4)
+    cm = ch.mesh_from_arrays(m, 3).upload()
+    R = gpu_residual(ch, torch_dev, cm, phys, Q)
+    op = ora_phys(oracle_mod, phys)
+    assert_parity(R, om.residual(op, Q), om.residual(op, ulp_perturb(Q)), "C1")
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
+def test_residual_parity_periodic_box_all_orders(ch, oracle_mod, torch_dev, N):
+    m = box_mesh(3, 3, 3, periodic=(True,) * 3, curve=0.03)
+    om = oracle_mod.OracleMesh(m, N)
+    xyz, _ = om.solpts()
+    x, y, z = xyz
+    Q = np.stack([1 + 0.2 * np.sin(2 * np.pi * (x + y)), 0.3 + 0.1 * np.cos(2 * np.pi * z),
+                  -0.2 + 0.05 * np.sin(2 * np.pi * x), 0.1 * np.cos(2 * np.pi * y), 2.5 + 0.1 * np.sin(2 * np.pi * z)])
+    phys = ch.physics(GM=1.0, omega=0.5, nu=1e-2, kappa=1e-2, kappa_r=1e-3)
+    cm = ch.mesh_from_arrays(m, N).upload()
+    R = gpu_residual(ch, torch_dev, cm, phys, Q)
+    op = ora_phys(oracle_mod, phys)
+    Qo = Q.reshape(5, om.E, om.np)
+    assert_parity(R, om.residual(op, Qo), om.residual(op, ulp_perturb(Qo)), "box N=%d" % N)
+
+
+@pytest.mark.parametrize("rot", [0, 3, 7, 13, 22])
+def test_residual_parity_orientations(ch, oracle_mod, torch_dev, rot):
+    m = two_element_mesh(rot)
+    om = oracle_mod.OracleMesh(m, 3)
+    xyz, _ = om.solpts()
+    x, y, z = xyz
+    Q = np.stack([1 + 0.1 * np.sin(x + 2 * y), 0.1 * np.cos(z), 0.05 * x, -0.02 * y * z, 2.5 + 0.1 * np.cos(x * y)])
+    phys = ch.physics(nu=1e-2, kappa=1e-2, GM=0.5, omega=0.3, bc_state=(1, 0, 0, 0, 2.5))
+    cm = ch.mesh_from_arrays(m, 3).upload()
+    R = gpu_residual(ch, torch_dev, cm, phys, Q)
+    op = ora_phys(oracle_mod, phys)
+    Qo = Q.reshape(5, om.E, om.np)
+    assert_parity(R, om.residual(op, Qo), om.residual(op, ulp_perturb(Qo)), "rot %d" % rot)
+
+
+def test_rk3_ten_steps_parity_c1(ch, oracle_mod, torch_dev):
+    """10 SSP-RK3 steps on the 288-hex N=3 shell (the plain FP64 config)."""
+    torch = torch_dev
+    m, om, Q, phys = shell_case(oracle_mod, ch, 4, 3, 3, amp=1e-4)
+    cm = ch.mesh_from_arrays(m, 3).upload()
+    dt = 0.02
+    Qd = torch.from_numpy(np.ascontiguousarray(Q.reshape(5, -1))).cuda()
+    ws = cm.workspace(phys)
+    ch.chorus_rk_step(cm, phys, Qd, dt, 10, ws)
+    torch.cuda.synchronize()
+    Qg = Qd.cpu().numpy()
+    op = ora_phys(oracle_mod, phys)
+    Qr = om.rk3(op, Q, dt, 10).reshape(5, -1)
+    Qp = om.rk3(op, ulp_perturb(Q), dt, 10).reshape(5, -1)
+    # compare the change over the run (the state itself is background-sized)
+    Q0 = Q.reshape(5, -1)
+    assert_parity(Qg - Q0, Qr - Q0, Qp - Q0, "rk3 C1")
+
+
+def test_deterministic_and_conservative(ch, oracle_mod, torch_dev):
+    torch = torch_dev
+    m, om, Q, phys = shell_case(oracle_mod, ch, 4, 3, 3, amp=1e-3)
+    cm = ch.mesh_from_arrays(m, 3).upload()
+    ws = cm.workspace(phys)
+    outs = []
+    for _ in range(2):
+        Qd = torch.from_numpy(np.ascontiguousarray(Q.reshape(5, -1))).cuda()
+        ch.chorus_rk_step(cm, phys, Qd, 0.02, 5, ws)
+        torch.cuda.synchronize()
+        outs.append(Qd.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    Q0 = torch.from_numpy(np.ascontiguousarray(Q.reshape(5, -1))).cuda()
+    s0 = ch.chorus_conserved_sums(cm, Q0, ws)
+    s1 = ch.chorus_conserved_sums(cm, torch.from_numpy(outs[0]).cuda(), ws)
+    assert abs(s1[0] - s0[0]) < 1e-14 * abs(s0[0])
+    # the sums agree with the oracle's serial sums
+    np.testing.assert_allclose(s0, om.sums(Q), rtol=1e-13, atol=1e-13)
+
+
+def test_check_finite_flag(ch, oracle_mod, torch_dev):
+    torch = torch_dev
+    m, om, Q, phys = shell_case(oracle_mod, ch, 2, 1, 3)
+    cm = ch.mesh_from_arrays(m, 3).upload()
+    phys.flags = ch.CHORUS_CHECK_FINITE
+    Qb = Q.reshape(5, -1).copy()
+    Qb[0, 5] = -1.0  # negative density, set from the host
+    Qd = torch.from_numpy(Qb).cuda()
+    R = torch.empty_like(Qd)
+    with pytest.raises(ch.ChorusError) as ei:
+        ch.chorus_sd_residual(cm, phys, Qd, R, cm.workspace(phys))
+    assert ei.value.status == -5
