@@ -161,8 +161,10 @@ int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev
 int chorus_conserved_sums(chorus_mesh_t mesh, const double *Q_dev, double out_host[5], void *ws,
                           void *stream);
 
-/* Largest stable-looking step: cfl * min_e(h_e / N) / max(|u| + c), from
- * the host state Q_host [5][E N^3] (host only). */
+/* Explicit time step from the host state Q_host [5][E N^3] (host only):
+ * dt = cfl / (N max_points sum_d (|u . grad xi_d| + c |grad xi_d|)), the
+ * acoustic CFL condition dt < delta / c_s of Section 7 measured in
+ * reference-element units and summed over the three directions. */
 int chorus_stable_dt(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q_host,
                      double cfl, double *dt);
 

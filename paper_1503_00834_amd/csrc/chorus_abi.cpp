@@ -510,33 +510,32 @@ int chorus_stable_dt(chorus_mesh_t mesh, const chorus_physics *phys, const doubl
         set_error("null argument or non-positive cfl");
         return CHORUS_EINVAL;
     }
+    // multi-dimensional signal speed in reference units at every solution
+    // point: sum_d (|u . grad xi_d| + c |grad xi_d|)
     const int N = m->N, NP = N * N * N;
     const int64_t n = m->E * NP;
-    double hmin = 1e300, smax = 0.0;
-    for (int64_t e = 0; e < m->E; ++e) {
-        // shortest of the 12 corner-to-corner edges
-        for (int a = 0; a < 8; ++a)
-            for (int ax = 0; ax < 3; ++ax) {
-                if (a & (1 << ax)) continue;
-                const int bcorner = a | (1 << ax);
-                const double *xa = &m->xyz[m->elem20[e * 20 + a] * 3];
-                const double *xb = &m->xyz[m->elem20[e * 20 + bcorner] * 3];
-                const double dx = xb[0] - xa[0], dy = xb[1] - xa[1], dz = xb[2] - xa[2];
-                hmin = std::fmin(hmin, std::sqrt(dx * dx + dy * dy + dz * dz));
-            }
-    }
+    double smax = 0.0;
     for (int64_t g = 0; g < n; ++g) {
         const double r = Q_host[g], mx = Q_host[n + g], my = Q_host[2 * n + g], mz = Q_host[3 * n + g];
         const double E = Q_host[4 * n + g];
-        const double u2 = (mx * mx + my * my + mz * mz) / (r * r);
-        const double p = (phys->gamma - 1.0) * (E - 0.5 * r * u2);
-        smax = std::fmax(smax, std::sqrt(u2) + std::sqrt(phys->gamma * p / r));
+        const double u[3] = {mx / r, my / r, mz / r};
+        const double p = (phys->gamma - 1.0) * (E - 0.5 * (mx * u[0] + my * u[1] + mz * u[2]));
+        const double c = std::sqrt(phys->gamma * p / r);
+        const double J = m->jac[g];
+        double sum = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double *a = &m->met[(g * 3 + d) * 3];
+            const double un = (u[0] * a[0] + u[1] * a[1] + u[2] * a[2]) / J;
+            sum += std::fabs(un) + c * std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) / J;
+        }
+        if (!(sum == sum)) smax = NAN;
+        else smax = std::fmax(smax, sum);
     }
     if (!(smax > 0.0) || !std::isfinite(smax)) {
         set_error("stable_dt: state has no finite positive signal speed");
         return CHORUS_ENONFINITE;
     }
-    *dt = cfl * (hmin / N) / smax;
+    *dt = cfl / (N * smax);
     return CHORUS_OK;
 }
 
