@@ -45,6 +45,36 @@ def alg_bytes_per_stage_point(N, precision):
     return per
 
 
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sd_kernels.hip", "physics.hpp", "launch.hpp"):
+        with open(os.path.join(ROOT, "paper_1503_00834_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per k_resid launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    name = os.path.join(ROOT, "profiles", "sd_%s_%s.md" % (precision, workload))
+    if not os.path.exists(name):
+        return None
+    vals = {}
+    with open(name) as f:
+        for line in f:
+            line = line.strip()
+            for key in ("source_sha256:", "traffic_bytes_per_launch:"):
+                if line.startswith(key):
+                    vals[key[:-1]] = line.split(":", 1)[1].strip()
+    if vals.get("source_sha256") != kernel_source_sha():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(cfg, budget_s=15.0):
     """The CPU oracle on the same workload for a bounded number of steps."""
     import oracle
@@ -167,7 +197,8 @@ def main():
         "config": {"workload": args.workload, "hexes": mesh.n_elems, "order": N, "dofs": mesh.n_solpts,
                    "precision": args.precision, "integrator": "SSP-RK3", "dt": dt},
         "roofline": {"bound": "hbm", "kernel": "k_resid", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, args.precision),
                      "alg_bytes_per_launch": alg, "avg_launch_ms": avg_s * 1e3},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in ktimes.items()},
     }
