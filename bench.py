@@ -48,7 +48,7 @@ def alg_bytes_per_stage_point(N, precision):
 def kernel_source_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("sd_kernels.hip", "physics.hpp", "launch.hpp"):
+    for f in ("sd_kernels.hip", "sd_mixed.hip", "sd_common.hpp", "physics.hpp", "launch.hpp"):
         with open(os.path.join(ROOT, "paper_1503_00834_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -151,8 +151,9 @@ def main():
     Q = torch.from_numpy(Qh).cuda()
     ws = mesh.workspace(phys)
     if prec == ch.CHORUS_MIXED:
-        Q0 = Q.clone()
-        ch.chorus_set_background(mesh, phys, Q0, ws)
+        # background: the polytrope without the perturbation (at rest)
+        Q0h, _ = mesh.init_polytrope(cfg["beta"], cfg["n_rho"], poly_n=cfg["poly_n"])
+        ch.chorus_set_background(mesh, phys, torch.from_numpy(Q0h).cuda(), ws)
     log("E=%d N=%d DOFs=%d dt=%.3e; warmup %d" % (mesh.n_elems, N, mesh.n_solpts, dt, args.warmup))
     stream = torch.cuda.current_stream()
     ch.chorus_rk_step(mesh, phys, Q, dt, args.warmup, ws, stream)

@@ -25,14 +25,19 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // workspace layout
 struct WsLayout {
-    size_t Qs, TQ0, TQ1, TV, part, sums, flag, total;
+    size_t Qs, TQ0, TQ1, TV, part, sums, flag;
+    // mixed-precision path
+    size_t P0, P1, TQm0, TQm1, TVm, bg, bgT, R0, Q0;
+    bool mixed;
+    size_t total;
 };
 static constexpr int kSumBlocks = 512;
 
-static WsLayout ws_layout(const Mesh &m) {
+static WsLayout ws_layout(const Mesh &m, bool mixed) {
     const int N = m.N, NP = N * N * N, NF2 = N * N;
     const int64_t E = m.E;
     WsLayout w;
+    w.mixed = mixed;
     size_t off = 0;
     w.Qs = off;   off = align256(off + sizeof(double) * 5 * E * NP);
     w.TQ0 = off;  off = align256(off + sizeof(double) * E * 6 * 5 * NF2);
@@ -41,8 +46,35 @@ static WsLayout ws_layout(const Mesh &m) {
     w.part = off; off = align256(off + sizeof(double) * 5 * kSumBlocks);
     w.sums = off; off = align256(off + sizeof(double) * 8);
     w.flag = off; off = align256(off + sizeof(int) * 4);
+    w.P0 = w.P1 = w.TQm0 = w.TQm1 = w.TVm = w.bg = w.bgT = w.R0 = w.Q0 = 0;
+    if (mixed) {
+        w.P0 = off;   off = align256(off + sizeof(double) * 5 * E * NP);
+        w.P1 = off;   off = align256(off + sizeof(double) * 5 * E * NP);
+        w.TQm0 = off; off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
+        w.TQm1 = off; off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
+        w.TVm = off;  off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
+        w.bg = off;   off = align256(off + sizeof(float) * E * 2 * NP);
+        w.bgT = off;  off = align256(off + sizeof(float) * E * 6 * 2 * NF2);
+        w.R0 = off;   off = align256(off + sizeof(float) * 5 * E * NP);
+        w.Q0 = off;   off = align256(off + sizeof(double) * 5 * E * NP);
+    }
     w.total = off;
     return w;
+}
+
+static GeoM geom_of(const Mesh &m, const WsLayout &w, unsigned char *W) {
+    const unsigned char *b = (const unsigned char *)m.dev_image;
+    GeoM g;
+    g.solgeo32 = (const float *)(b + m.layout.solgeo32);
+    g.fluxgeo32 = (const float *)(b + m.layout.fluxgeo32);
+    g.link = (const int32_t *)(b + m.layout.link);
+    g.info = (const int32_t *)(b + m.layout.info);
+    g.E = m.E;
+    g.bg = (const float *)(W + w.bg);
+    g.bgT = (const float *)(W + w.bgT);
+    g.R0 = (const float *)(W + w.R0);
+    g.Q0 = (const double *)(W + w.Q0);
+    return g;
 }
 
 static Geo geo_of(const Mesh &m) {
@@ -69,13 +101,24 @@ static int check_phys(const chorus_physics *p) {
         set_error("physics: unknown precision");
         return CHORUS_EINVAL;
     }
-    if (p->precision == CHORUS_MIXED) {
-        set_error("mixed precision path is not available in this build");
-        return CHORUS_ENOTSUP;
-    }
     if (p->closure != 0) {
         set_error("learned closure is not available in this build");
         return CHORUS_ENOTSUP;
+    }
+    return CHORUS_OK;
+}
+
+// the mixed path needs a registered background computed with the same
+// inviscid physics, in the same workspace, on a mesh without state faces
+static int check_mixed(const Mesh &m, const chorus_physics *p, const void *ws) {
+    if (!m.bg_ready || m.bg_ws != ws) {
+        set_error("mixed precision needs chorus_set_background with this workspace first");
+        return CHORUS_ESTATE;
+    }
+    const chorus_physics &b = m.bg_phys;
+    if (b.gamma != p->gamma || b.R_gas != p->R_gas || b.GM != p->GM || b.omega != p->omega) {
+        set_error("mixed precision: gamma, R_gas, GM and omega must match the background's");
+        return CHORUS_ESTATE;
     }
     return CHORUS_OK;
 }
@@ -365,7 +408,7 @@ int chorus_workspace_bytes(chorus_mesh_t mesh, const chorus_physics *phys, size_
         return CHORUS_EINVAL;
     }
     (void)phys;
-    *bytes = ws_layout(*m).total;
+    *bytes = ws_layout(*m, phys && phys->precision == CHORUS_MIXED).total;
     return CHORUS_OK;
 }
 
@@ -412,9 +455,54 @@ int chorus_init_polytrope(chorus_mesh_t mesh, double beta, double n_rho, double 
 
 int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q0_dev, void *ws,
                           void *stream) {
-    (void)mesh; (void)phys; (void)Q0_dev; (void)ws; (void)stream;
-    set_error("mixed precision path is not available in this build");
-    return CHORUS_ENOTSUP;
+    Mesh *m = reinterpret_cast<Mesh *>(mesh);
+    int rc = check_ready(m);
+    if (rc) return rc;
+    rc = check_phys(phys);
+    if (rc) return rc;
+    if (!Q0_dev || !ws) {
+        set_error("null device pointer");
+        return CHORUS_EINVAL;
+    }
+    for (int32_t b : m->face_bc)
+        if (b == CHORUS_BC_STATE) {
+            set_error("mixed precision supports interior and wall faces only");
+            return CHORUS_ENOTSUP;
+        }
+    const WsLayout w = ws_layout(*m, true);
+    unsigned char *W = (unsigned char *)ws;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = m->E * m->N * m->N * m->N;
+    double *Q0 = (double *)(W + w.Q0);
+    int *flag = (int *)(W + w.flag);
+    hipError_t e = hipMemcpyAsync(Q0, Q0_dev, sizeof(double) * 5 * n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_clear_flag(flag, s);
+    if (e == hipSuccess) e = launch_bg_setup(*m, Q0, (float *)(W + w.bg), (float *)(W + w.bgT), flag, s);
+    // R0: FP64 residual of Q0 with the inviscid physics only
+    chorus_physics pin = *phys;
+    pin.nu = pin.kappa = pin.kappa_r = 0.0;
+    pin.F_bottom = 0.0;
+    pin.precision = CHORUS_FP64;
+    const PhysParams P = params_of(&pin);
+    const Geo G = geo_of(*m);
+    double *R0d = (double *)(W + w.Qs), *TQ = (double *)(W + w.TQ0), *TV = (double *)(W + w.TV);
+    if (e == hipSuccess) e = launch_trace(*m, G, Q0, TQ, s);
+    if (e == hipSuccess) e = launch_grad(*m, G, P, Q0, TQ, TV, s);
+    StageArgs sa{nullptr, R0d, nullptr, 0.0, 1.0, 0.0, 0};
+    if (e == hipSuccess) e = launch_resid(*m, G, P, Q0, TQ, TV, sa, s);
+    if (e == hipSuccess) e = launch_to_float(R0d, (float *)(W + w.R0), 5 * n, s);
+    int h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "set_background");
+    if (h) {
+        set_error("background state must be at rest (zero momentum)");
+        return CHORUS_EINVAL;
+    }
+    m->bg_ready = true;
+    m->bg_ws = ws;
+    m->bg_phys = *phys;
+    return CHORUS_OK;
 }
 
 int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q_dev, double *dQdt_dev,
@@ -428,12 +516,27 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
         set_error("null device pointer");
         return CHORUS_EINVAL;
     }
-    const WsLayout w = ws_layout(*m);
+    const bool mixed = phys->precision == CHORUS_MIXED;
+    const WsLayout w = ws_layout(*m, mixed);
     unsigned char *W = (unsigned char *)ws;
-    double *TQ = (double *)(W + w.TQ0), *TV = (double *)(W + w.TV);
-    const Geo G = geo_of(*m);
     const PhysParams P = params_of(phys);
     hipStream_t s = (hipStream_t)stream;
+    if (mixed) {
+        rc = check_mixed(*m, phys, ws);
+        if (rc) return rc;
+        const GeoM g = geom_of(*m, w, W);
+        double *P0 = (double *)(W + w.P0);
+        float *TQm = (float *)(W + w.TQm0), *TVm = (float *)(W + w.TVm);
+        hipError_t e = timed(0, s, [&] { return launch_pert_begin(*m, g, Q_dev, P0, TQm, s); });
+        if (e == hipSuccess) e = timed(1, s, [&] { return launch_grad_mixed(*m, g, P, P0, TQm, TVm, s); });
+        MixedStageArgs a{nullptr, dQdt_dev, nullptr, 0.0, 1.0, 0.0, 0};
+        if (e == hipSuccess) e = timed(2, s, [&] { return launch_resid_mixed(*m, g, P, P0, TQm, TVm, a, s); });
+        if (e != hipSuccess) return hip_fail(e, "sd_residual (mixed)");
+        if (phys->flags & CHORUS_CHECK_FINITE) return finite_check(*m, P, Q_dev, w, W, s);
+        return CHORUS_OK;
+    }
+    double *TQ = (double *)(W + w.TQ0), *TV = (double *)(W + w.TV);
+    const Geo G = geo_of(*m);
     hipError_t e = timed(0, s, [&] { return launch_trace(*m, G, Q_dev, TQ, s); });
     if (e == hipSuccess) e = timed(1, s, [&] { return launch_grad(*m, G, P, Q_dev, TQ, TV, s); });
     StageArgs sa{nullptr, dQdt_dev, nullptr, 0.0, 1.0, 0.0, 0};
@@ -455,8 +558,37 @@ int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev
         return CHORUS_EINVAL;
     }
     if (n_steps == 0) return CHORUS_OK;
-    const WsLayout w = ws_layout(*m);
+    const bool mixed = phys->precision == CHORUS_MIXED;
+    const WsLayout w = ws_layout(*m, mixed);
     unsigned char *W = (unsigned char *)ws;
+    if (mixed) {
+        rc = check_mixed(*m, phys, ws);
+        if (rc) return rc;
+        const GeoM g = geom_of(*m, w, W);
+        const PhysParams P = params_of(phys);
+        hipStream_t s = (hipStream_t)stream;
+        double *Pb[2] = {(double *)(W + w.P0), (double *)(W + w.P1)};
+        float *TQb[2] = {(float *)(W + w.TQm0), (float *)(W + w.TQm1)};
+        float *TVm = (float *)(W + w.TVm);
+        int cur = 0;
+        hipError_t e = timed(0, s, [&] { return launch_pert_begin(*m, g, Q_dev, Pb[0], TQb[cur], s); });
+        const double ca[3] = {0.0, 0.75, 1.0 / 3.0}, cb[3] = {1.0, 0.25, 2.0 / 3.0};
+        for (int st = 0; st < n_steps && e == hipSuccess; ++st) {
+            for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+                const double *pin = (k == 0) ? Pb[0] : Pb[1];
+                double *pout = (k == 2) ? Pb[0] : Pb[1];
+                e = timed(1, s, [&] { return launch_grad_mixed(*m, g, P, pin, TQb[cur], TVm, s); });
+                if (e != hipSuccess) break;
+                MixedStageArgs a{Pb[0], pout, TQb[cur ^ 1], ca[k], cb[k], dt, 1};
+                e = timed(2, s, [&] { return launch_resid_mixed(*m, g, P, pin, TQb[cur], TVm, a, s); });
+                cur ^= 1;
+            }
+        }
+        if (e == hipSuccess) e = launch_pert_end(g.Q0, Pb[0], Q_dev, 5 * m->E * m->N * m->N * m->N, s);
+        if (e != hipSuccess) return hip_fail(e, "rk_step (mixed)");
+        if (phys->flags & CHORUS_CHECK_FINITE) return finite_check(*m, P, Q_dev, w, W, s);
+        return CHORUS_OK;
+    }
     double *Qs = (double *)(W + w.Qs), *TV = (double *)(W + w.TV);
     double *TQb[2] = {(double *)(W + w.TQ0), (double *)(W + w.TQ1)};
     const Geo G = geo_of(*m);
@@ -491,7 +623,7 @@ int chorus_conserved_sums(chorus_mesh_t mesh, const double *Q_dev, double out_ho
         set_error("null argument");
         return CHORUS_EINVAL;
     }
-    const WsLayout w = ws_layout(*m);
+    const WsLayout w = ws_layout(*m, false);
     unsigned char *W = (unsigned char *)ws;
     const double *solw = (const double *)((const unsigned char *)m->dev_image + m->layout.solw);
     hipStream_t s = (hipStream_t)stream;

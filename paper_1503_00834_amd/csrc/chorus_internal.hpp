@@ -65,7 +65,9 @@ struct Mesh {
     void *dev_image = nullptr;          // registered caller-owned device buffer
     int device = -1;
     // mixed-mode background registered by chorus_set_background
-    const double *bg_Q0 = nullptr;
+    bool bg_ready = false;
+    const void *bg_ws = nullptr;
+    chorus_physics bg_phys{};
     int64_t n_nodes() const { return (int64_t)xyz.size() / 3; }
 };
 

@@ -36,5 +36,36 @@ hipError_t launch_resid(const Mesh &m, const Geo &G, const PhysParams &P, const 
 hipError_t launch_sums(const double *Q, const double *solw, int64_t n, double *part, int nblocks, double *out,
                        hipStream_t s);
 hipError_t launch_check(const double *Q, int64_t n, double gm1, int *flag, hipStream_t s);
+hipError_t launch_clear_flag(int *flag, hipStream_t s);
+
+// mixed-precision path: FP32 geometry, background arrays and FP64 Q0 copy
+struct GeoM {
+    const float *solgeo32;   // [E][13][NP]
+    const float *fluxgeo32;  // [E][3][3][NFL]
+    const int32_t *link;     // [E][6]
+    const int32_t *info;     // [E][6]
+    int64_t E;
+    const float *bg;         // [E][2][NP]  rho0, E0
+    const float *bgT;        // [E][6][2][NF2] rho0, E0 face traces
+    const float *R0;         // [5][E][NP]  background residual
+    const double *Q0;        // [5][E][NP]  background state
+};
+
+struct MixedStageArgs {
+    const double *Pn;  // step-start perturbation (may alias Pout)
+    double *Pout;      // stage output, or dQ/dt in mode 0
+    float *TQout;      // FP32 face traces of Pout (RK mode) or null
+    double ca, cb, dt;
+    int mode;          // 0 residual, 1 RK stage
+};
+
+hipError_t launch_pert_begin(const Mesh &m, const GeoM &g, const double *Q, double *Pq, float *TQ, hipStream_t s);
+hipError_t launch_grad_mixed(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
+                             float *TV, hipStream_t s);
+hipError_t launch_resid_mixed(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
+                              const float *TV, const MixedStageArgs &a, hipStream_t s);
+hipError_t launch_bg_setup(const Mesh &m, const double *Q0, float *bg, float *bgT, int *flag, hipStream_t s);
+hipError_t launch_pert_end(const double *Q0, const double *Pq, double *Q, int64_t n, hipStream_t s);
+hipError_t launch_to_float(const double *a, float *b, int64_t n, hipStream_t s);
 
 }  // namespace chorus

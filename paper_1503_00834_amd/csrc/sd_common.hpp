@@ -1,0 +1,63 @@
+// Index helpers and 1D operator tables shared by the FP64 and mixed
+// precision SD kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "chorus_internal.hpp"
+
+namespace chorus {
+
+// 1D SD operators of order N in arithmetic type T
+template <typename T, int N>
+struct OpsT {
+    T I[N + 1][N];  // I[m][s] = h_s(xf[m])
+    T D[N][N + 1];  // D[s][m] = l_m'(xs[s])
+    T B[N][N];      // sum_{m=1}^{N-1} D[s][m] I[m][s']: interior flux points folded
+};
+template <int N>
+using Ops = OpsT<double, N>;
+
+template <typename T, int N>
+inline OpsT<T, N> make_ops_t(const Basis1D &b) {
+    OpsT<T, N> o;
+    for (int m = 0; m <= N; ++m)
+        for (int s = 0; s < N; ++s) o.I[m][s] = (T)b.I[m][s];
+    for (int s = 0; s < N; ++s)
+        for (int m = 0; m <= N; ++m) o.D[s][m] = (T)b.D[s][m];
+    for (int a = 0; a < N; ++a)
+        for (int s = 0; s < N; ++s) {
+            double v = 0.0;
+            for (int m = 1; m < N; ++m) v += b.D[a][m] * b.I[m][s];
+            o.B[a][s] = (T)v;
+        }
+    return o;
+}
+
+
+
+// line through solution point (a along d; t1 < t2 the tangential indices)
+template <int N>
+__device__ __forceinline__ int sol_of(int d, int a, int t1, int t2) {
+    return d == 0 ? a + N * (t1 + N * t2) : (d == 1 ? t1 + N * (a + N * t2) : t1 + N * (t2 + N * a));
+}
+template <int N>
+__device__ __forceinline__ int stride_of(int d) {
+    return d == 0 ? 1 : (d == 1 ? N : N * N);
+}
+template <int N>
+__device__ __forceinline__ void split_sol(int d, int p, int &a, int &t1, int &t2) {
+    const int i = p % N, j = (p / N) % N, k = p / (N * N);
+    if (d == 0) { a = i; t1 = j; t2 = k; }
+    else if (d == 1) { a = j; t1 = i; t2 = k; }
+    else { a = k; t1 = i; t2 = j; }
+}
+template <int N>
+__device__ __forceinline__ int map_face_point(int o, int t1, int t2) {
+    int u1 = (o & 4) ? t2 : t1, u2 = (o & 4) ? t1 : t2;
+    if (o & 2) u1 = N - 1 - u1;
+    if (o & 1) u2 = N - 1 - u2;
+    return u1 + N * u2;
+}
+
+}  // namespace chorus

@@ -24,41 +24,9 @@
 #include <cstdint>
 
 #include "launch.hpp"
+#include "sd_common.hpp"
 
 namespace chorus {
-
-template <int N>
-struct Ops {
-    double I[N + 1][N];  // I[m][s] = h_s(xf[m])
-    double D[N][N + 1];  // D[s][m] = l_m'(xs[s])
-    double B[N][N];      // sum_{m=1}^{N-1} D[s][m] I[m][s']: interior flux points folded
-};
-
-
-
-// line through solution point (a along d; t1 < t2 the tangential indices)
-template <int N>
-__device__ __forceinline__ int sol_of(int d, int a, int t1, int t2) {
-    return d == 0 ? a + N * (t1 + N * t2) : (d == 1 ? t1 + N * (a + N * t2) : t1 + N * (t2 + N * a));
-}
-template <int N>
-__device__ __forceinline__ int stride_of(int d) {
-    return d == 0 ? 1 : (d == 1 ? N : N * N);
-}
-template <int N>
-__device__ __forceinline__ void split_sol(int d, int p, int &a, int &t1, int &t2) {
-    const int i = p % N, j = (p / N) % N, k = p / (N * N);
-    if (d == 0) { a = i; t1 = j; t2 = k; }
-    else if (d == 1) { a = j; t1 = i; t2 = k; }
-    else { a = k; t1 = i; t2 = j; }
-}
-template <int N>
-__device__ __forceinline__ int map_face_point(int o, int t1, int t2) {
-    int u1 = (o & 4) ? t2 : t1, u2 = (o & 4) ? t1 : t2;
-    if (o & 2) u1 = N - 1 - u1;
-    if (o & 1) u2 = N - 1 - u2;
-    return u1 + N * u2;
-}
 
 // ---------------------------------------------------------------------------
 // shared phases
@@ -423,18 +391,7 @@ struct LaunchCfg {
 
 template <int N>
 static Ops<N> make_ops(const Basis1D &b) {
-    Ops<N> o;
-    for (int m = 0; m <= N; ++m)
-        for (int s = 0; s < N; ++s) o.I[m][s] = b.I[m][s];
-    for (int s = 0; s < N; ++s)
-        for (int m = 0; m <= N; ++m) o.D[s][m] = b.D[s][m];
-    for (int a = 0; a < N; ++a)
-        for (int s = 0; s < N; ++s) {
-            double v = 0.0;
-            for (int m = 1; m < N; ++m) v += b.D[a][m] * b.I[m][s];
-            o.B[a][s] = v;
-        }
-    return o;
+    return make_ops_t<double, N>(b);
 }
 
 // elements per block / threads per block for each order
@@ -521,6 +478,11 @@ hipError_t launch_sums(const double *Q, const double *solw, int64_t n, double *p
 }
 
 __global__ void k_clear_flag(int *flag) { flag[0] = 0; }
+
+hipError_t launch_clear_flag(int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, s, flag);
+    return hipGetLastError();
+}
 
 hipError_t launch_check(const double *Q, int64_t n, double gm1, int *flag, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, s, flag);

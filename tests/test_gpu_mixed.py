@@ -1,0 +1,163 @@
+"""GPU tests of the mixed FP32/FP64 perturbation path.
+
+Gate (the benchmark metric's condition): after 100 SSP-RK3 steps of the
+41,472-hex N=4 workload, the mixed state agrees with the FP64 plain state to
+<= 1e-6 relative L2 error per conserved variable.  The FP64 plain path is
+itself held to the oracle by test_gpu_parity.py.
+
+Residual-level check against the oracle: the FP32 part of the mixed residual
+carries only the perturbation, so its error is measured relative to the
+perturbation part of the oracle residual, R(Q) - R(Q0):
+    ||R_mixed,v - R_oracle,v|| <= 2e-5 ||R_oracle,v(Q) - R_oracle,v(Q0)|| + 1e-6 ||R_oracle,v(Q0)||.
+2e-5 covers FP32 rounding (6e-8) amplified by the derivative operators'
+cancellation (3(N+1) terms with |D| up to ~10, factor <= ~200 at N <= 4);
+the second term is the FP32 rounding of the stored background residual.
+"""
+import numpy as np
+import pytest
+
+from chorus_inputs import cubed_sphere_shell, uniform_noise, CONFIGS, shell_params_from_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ch(torch_dev):
+    import paper_1503_00834_amd as ch
+    return ch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a.reshape(5, -1))).cuda()
+
+
+def _case(oracle_mod, N, amp=1e-3, vel=1e-3, seed=3):
+    beta, n_rho = 0.7, 1.0
+    ri, ro = beta / (1 - beta), 1 / (1 - beta)
+    m = cubed_sphere_shell(3, 2, ri, ro)
+    om = oracle_mod.OracleMesh(m, N)
+    Q0, pars = om.polytrope(beta, n_rho)
+    Q, _ = om.polytrope(beta, n_rho, noise=uniform_noise(om.n_solpts, seed), amp=amp)
+    rng = np.random.default_rng(seed + 1)
+    Q[1:4] = vel * Q[0] * rng.uniform(-1, 1, size=Q[1:4].shape)
+    Q[4] += 0.5 * (Q[1:4] ** 2).sum(0) / Q[0]
+    return m, om, Q0, Q, pars
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_mixed_residual_vs_oracle(ch, oracle_mod, torch_dev, N):
+    torch = torch_dev
+    m, om, Q0, Q, pars = _case(oracle_mod, N)
+    kw = dict(GM=pars["GM"], omega=1.0, nu=1e-3, kappa=1e-3, kappa_r=1e-4, T_top=pars["chi_o"], F_bottom=0.01)
+    phys = ch.physics(precision=ch.CHORUS_MIXED, **kw)
+    cm = ch.mesh_from_arrays(m, N).upload()
+    ws = cm.workspace(phys)
+    ch.chorus_set_background(cm, phys, _dev(torch, Q0), ws)
+    R = torch.empty_like(_dev(torch, Q))
+    ch.chorus_sd_residual(cm, phys, _dev(torch, Q), R, ws)
+    torch.cuda.synchronize()
+    Rg = R.cpu().numpy()
+    op = oracle_mod.phys(**kw)
+    Rr = om.residual(op, Q).reshape(5, -1)
+    Rb = om.residual(op, Q0).reshape(5, -1)
+    for v in range(5):
+        err = np.linalg.norm(Rg[v] - Rr[v])
+        tol = 2e-5 * np.linalg.norm(Rr[v] - Rb[v]) + 1e-6 * np.linalg.norm(Rb[v])
+        assert err <= tol, (v, err, tol)
+
+
+def test_mixed_background_is_steady_part(ch, oracle_mod, torch_dev):
+    """At Q = Q0 the mixed residual is the background residual plus the
+    (FP32) viscous residual of Q0, i.e. the FP64 residual of Q0 to FP32
+    rounding of its size."""
+    torch = torch_dev
+    m, om, Q0, _, pars = _case(oracle_mod, 3)
+    kw = dict(GM=pars["GM"], omega=1.0, nu=1e-3, kappa=1e-3, T_top=pars["chi_o"])
+    phys = ch.physics(precision=ch.CHORUS_MIXED, **kw)
+    cm = ch.mesh_from_arrays(m, 3).upload()
+    ws = cm.workspace(phys)
+    ch.chorus_set_background(cm, phys, _dev(torch, Q0), ws)
+    R = torch.empty_like(_dev(torch, Q0))
+    ch.chorus_sd_residual(cm, phys, _dev(torch, Q0), R, ws)
+    torch.cuda.synchronize()
+    Rr = om.residual(oracle_mod.phys(**kw), Q0).reshape(5, -1)
+    Rg = R.cpu().numpy()
+    for v in range(5):
+        assert np.linalg.norm(Rg[v] - Rr[v]) <= 1e-6 * max(np.linalg.norm(Rr[v]), 1e-300) + 1e-12
+
+
+def test_mixed_100_steps_vs_fp64_full_workload(ch, torch_dev):
+    """The benchmark metric's gate on the benchmark workload."""
+    torch = torch_dev
+    cfg = CONFIGS["jupiter_41k_N4"]
+    ri, ro = shell_params_from_config(cfg)
+    cm = ch.chorus_mesh_create(cfg["panel_n"], cfg["radial_n"], 4, ri, ro).upload()
+    Qh, pars = cm.init_polytrope(cfg["beta"], cfg["n_rho"], noise=uniform_noise(cm.n_solpts, cfg["seed"]),
+                                 amp=1e-4)
+    Q0h, _ = cm.init_polytrope(cfg["beta"], cfg["n_rho"])
+    kw = dict(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"], T_top=pars["chi_o"])
+    p64 = ch.physics(**kw)
+    pmx = ch.physics(precision=ch.CHORUS_MIXED, **kw)
+    dt = cm.stable_dt(p64, Qh, cfg["cfl"])
+    Qa = torch.from_numpy(Qh).cuda()
+    ch.chorus_rk_step(cm, p64, Qa, dt, 100, cm.workspace(p64))
+    wsm = cm.workspace(pmx)
+    ch.chorus_set_background(cm, pmx, torch.from_numpy(Q0h).cuda(), wsm)
+    Qb = torch.from_numpy(Qh).cuda()
+    ch.chorus_rk_step(cm, pmx, Qb, dt, 100, wsm)
+    torch.cuda.synchronize()
+    A, B = Qa.cpu().numpy(), Qb.cpu().numpy()
+    assert np.isfinite(A).all() and np.isfinite(B).all()
+    rel = [np.linalg.norm(B[v] - A[v]) / np.linalg.norm(A[v]) for v in range(5)]
+    # stricter diagnostic for rho and E: relative to the change from Q0
+    rel_pert = [np.linalg.norm(B[v] - A[v]) / np.linalg.norm(A[v] - Q0h[v]) for v in (0, 4)]
+    print("mixed vs fp64 after 100 steps: rel", rel, "rel to perturbation (rho, E)", rel_pert)
+    assert max(rel) <= 1e-6, rel
+
+
+def test_mixed_deterministic_and_mass(ch, oracle_mod, torch_dev):
+    torch = torch_dev
+    m, om, Q0, Q, pars = _case(oracle_mod, 3)
+    phys = ch.physics(precision=ch.CHORUS_MIXED, GM=pars["GM"], omega=1.0, nu=1e-3, kappa=1e-3,
+                      T_top=pars["chi_o"])
+    cm = ch.mesh_from_arrays(m, 3).upload()
+    ws = cm.workspace(phys)
+    ch.chorus_set_background(cm, phys, _dev(torch, Q0), ws)
+    outs = []
+    for _ in range(2):
+        Qd = _dev(torch, Q)
+        ch.chorus_rk_step(cm, phys, Qd, 0.01, 5, ws)
+        torch.cuda.synchronize()
+        outs.append(Qd.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    s0 = ch.chorus_conserved_sums(cm, _dev(torch, Q), ws)
+    s1 = ch.chorus_conserved_sums(cm, torch.from_numpy(outs[0]).cuda(), ws)
+    assert abs(s1[0] - s0[0]) < 1e-10 * abs(s0[0])
+
+
+def test_mixed_call_order_errors(ch, oracle_mod, torch_dev):
+    torch = torch_dev
+    m, om, Q0, Q, pars = _case(oracle_mod, 3)
+    phys = ch.physics(precision=ch.CHORUS_MIXED, GM=pars["GM"], omega=1.0)
+    cm = ch.mesh_from_arrays(m, 3).upload()
+    ws = cm.workspace(phys)
+    R = torch.empty_like(_dev(torch, Q))
+    with pytest.raises(ch.ChorusError) as ei:
+        ch.chorus_sd_residual(cm, phys, _dev(torch, Q), R, ws)
+    assert ei.value.status == -6
+    with pytest.raises(ch.ChorusError) as ei:
+        ch.chorus_set_background(cm, phys, _dev(torch, Q), ws)  # has momentum
+    assert ei.value.status == -1
+    ch.chorus_set_background(cm, phys, _dev(torch, Q0), ws)
+    other = ch.physics(precision=ch.CHORUS_MIXED, GM=pars["GM"] * 1.01, omega=1.0)
+    with pytest.raises(ch.ChorusError) as ei:
+        ch.chorus_sd_residual(cm, other, _dev(torch, Q), R, ws)
+    assert ei.value.status == -6
