@@ -27,7 +27,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct WsLayout {
     size_t Qs, TQ0, TQ1, TV, part, sums, flag;
     // mixed-precision path
-    size_t P0, P1, TQm0, TQm1, TVm, bg, bgT, R0, Q0;
+    size_t P0, P1, TQm0, TQm1, TVm, bg, dbg, gS0, R0, Q0;
     bool mixed;
     size_t total;
 };
@@ -46,7 +46,7 @@ static WsLayout ws_layout(const Mesh &m, bool mixed) {
     w.part = off; off = align256(off + sizeof(double) * 5 * kSumBlocks);
     w.sums = off; off = align256(off + sizeof(double) * 8);
     w.flag = off; off = align256(off + sizeof(int) * 4);
-    w.P0 = w.P1 = w.TQm0 = w.TQm1 = w.TVm = w.bg = w.bgT = w.R0 = w.Q0 = 0;
+    w.P0 = w.P1 = w.TQm0 = w.TQm1 = w.TVm = w.bg = w.dbg = w.gS0 = w.R0 = w.Q0 = 0;
     if (mixed) {
         w.P0 = off;   off = align256(off + sizeof(double) * 5 * E * NP);
         w.P1 = off;   off = align256(off + sizeof(double) * 5 * E * NP);
@@ -54,7 +54,8 @@ static WsLayout ws_layout(const Mesh &m, bool mixed) {
         w.TQm1 = off; off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
         w.TVm = off;  off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
         w.bg = off;   off = align256(off + sizeof(float) * E * 2 * NP);
-        w.bgT = off;  off = align256(off + sizeof(float) * E * 6 * 2 * NF2);
+        w.dbg = off;  off = align256(off + sizeof(float) * E * 6 * 2 * NF2);
+        w.gS0 = off;  off = align256(off + sizeof(float) * E * 3 * (N + 1) * NF2);
         w.R0 = off;   off = align256(off + sizeof(float) * 5 * E * NP);
         w.Q0 = off;   off = align256(off + sizeof(double) * 5 * E * NP);
     }
@@ -71,7 +72,8 @@ static GeoM geom_of(const Mesh &m, const WsLayout &w, unsigned char *W) {
     g.info = (const int32_t *)(b + m.layout.info);
     g.E = m.E;
     g.bg = (const float *)(W + w.bg);
-    g.bgT = (const float *)(W + w.bgT);
+    g.dbg = (const float *)(W + w.dbg);
+    g.gS0 = (const float *)(W + w.gS0);
     g.R0 = (const float *)(W + w.R0);
     g.Q0 = (const double *)(W + w.Q0);
     return g;
@@ -116,8 +118,9 @@ static int check_mixed(const Mesh &m, const chorus_physics *p, const void *ws) {
         return CHORUS_ESTATE;
     }
     const chorus_physics &b = m.bg_phys;
-    if (b.gamma != p->gamma || b.R_gas != p->R_gas || b.GM != p->GM || b.omega != p->omega) {
-        set_error("mixed precision: gamma, R_gas, GM and omega must match the background's");
+    if (b.gamma != p->gamma || b.R_gas != p->R_gas || b.GM != p->GM || b.omega != p->omega || b.nu != p->nu ||
+        b.kappa != p->kappa || b.kappa_r != p->kappa_r || b.T_top != p->T_top || b.F_bottom != p->F_bottom) {
+        set_error("mixed precision: the physics must match the one passed to chorus_set_background");
         return CHORUS_ESTATE;
     }
     return CHORUS_OK;
@@ -476,17 +479,16 @@ int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const 
     double *Q0 = (double *)(W + w.Q0);
     int *flag = (int *)(W + w.flag);
     hipError_t e = hipMemcpyAsync(Q0, Q0_dev, sizeof(double) * 5 * n, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = launch_clear_flag(flag, s);
-    if (e == hipSuccess) e = launch_bg_setup(*m, Q0, (float *)(W + w.bg), (float *)(W + w.bgT), flag, s);
-    // R0: FP64 residual of Q0 with the inviscid physics only
-    chorus_physics pin = *phys;
-    pin.nu = pin.kappa = pin.kappa_r = 0.0;
-    pin.F_bottom = 0.0;
-    pin.precision = CHORUS_FP64;
-    const PhysParams P = params_of(&pin);
+    chorus_physics p64 = *phys;
+    p64.precision = CHORUS_FP64;
+    const PhysParams P = params_of(&p64);
     const Geo G = geo_of(*m);
     double *R0d = (double *)(W + w.Qs), *TQ = (double *)(W + w.TQ0), *TV = (double *)(W + w.TV);
+    if (e == hipSuccess) e = launch_clear_flag(flag, s);
     if (e == hipSuccess) e = launch_trace(*m, G, Q0, TQ, s);
+    if (e == hipSuccess) e = launch_bg_setup(*m, G, Q0, TQ, (float *)(W + w.bg), (float *)(W + w.dbg), flag, s);
+    if (e == hipSuccess) e = launch_bg_entropy(*m, G, P, Q0, TQ, (float *)(W + w.gS0), s);
+    // R0 = R(Q0), the complete FP64 residual of the background
     if (e == hipSuccess) e = launch_grad(*m, G, P, Q0, TQ, TV, s);
     StageArgs sa{nullptr, R0d, nullptr, 0.0, 1.0, 0.0, 0};
     if (e == hipSuccess) e = launch_resid(*m, G, P, Q0, TQ, TV, sa, s);

@@ -46,7 +46,8 @@ struct GeoM {
     const int32_t *info;     // [E][6]
     int64_t E;
     const float *bg;         // [E][2][NP]  rho0, E0
-    const float *bgT;        // [E][6][2][NF2] rho0, E0 face traces
+    const float *dbg;        // [E][6][2][NF2] neighbour minus own background face trace
+    const float *gS0;        // [E][3][NFL] background entropy gradient along the flux metric
     const float *R0;         // [5][E][NP]  background residual
     const double *Q0;        // [5][E][NP]  background state
 };
@@ -64,7 +65,10 @@ hipError_t launch_grad_mixed(const Mesh &m, const GeoM &g, const PhysParams &P, 
                              float *TV, hipStream_t s);
 hipError_t launch_resid_mixed(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
                               const float *TV, const MixedStageArgs &a, hipStream_t s);
-hipError_t launch_bg_setup(const Mesh &m, const double *Q0, float *bg, float *bgT, int *flag, hipStream_t s);
+hipError_t launch_bg_setup(const Mesh &m, const Geo &G, const double *Q0, const double *TQ0, float *bg, float *dbg,
+                           int *flag, hipStream_t s);
+hipError_t launch_bg_entropy(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q0, const double *TQ,
+                             float *out, hipStream_t s);
 hipError_t launch_pert_end(const double *Q0, const double *Pq, double *Q, int64_t n, hipStream_t s);
 hipError_t launch_to_float(const double *a, float *b, int64_t n, hipStream_t s);
 

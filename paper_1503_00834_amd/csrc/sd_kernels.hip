@@ -331,6 +331,53 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, co
     }
 }
 
+// entropy gradient of a state at rest along the flux-point metric:
+// out[e][d][fl] = grad S . (|J| grad xi_d) at the d-flux points, with the BR1
+// gradients of the FP64 path (S = c_p ln(p^(1/gamma)/rho), p = (gamma-1) E
+// for zero momentum); used by the mixed-precision path
+template <int N, int EPB, int NT>
+__global__ __launch_bounds__(NT) void k_bg_entropy(Ops<N> op, Geo G, PhysParams P, const double *__restrict__ Q0,
+                                                   const double *__restrict__ TQ, float *__restrict__ out) {
+    constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
+    __shared__ double sq[EPB][5][NP];
+    __shared__ double sqs[EPB][6][5][NF2];
+    __shared__ double sgr[EPB][15][NP];
+    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    load_q<N, EPB, NT>(Q0, G.E, e0, sq);
+    __syncthreads();
+    common_solution<N, EPB, NT>(op, G, P, TQ, e0, sq, sqs);
+    __syncthreads();
+    gradients<N, EPB, NT>(op, G, e0, sq, sqs, sgr);
+    __syncthreads();
+    const double gm1 = P.gamma - 1.0;
+    for (int it = threadIdx.x; it < EPB * 3 * NFL; it += NT) {
+        const int el = it / (3 * NFL), r = it % (3 * NFL), d = r / NFL, fl = r % NFL;
+        const int64_t e = e0 + el;
+        if (e >= G.E) continue;
+        const int m = fl % (N + 1), t1 = (fl / (N + 1)) % N, t2 = fl / ((N + 1) * N);
+        const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
+        double rho = 0.0, E = 0.0, gr = 0.0, gE = 0.0;
+        for (int b = 0; b < N; ++b) {
+            const double w = op.I[m][b];
+            rho += w * sq[el][0][base + b * st];
+            E += w * sq[el][4][base + b * st];
+        }
+        for (int c = 0; c < 3; ++c) {
+            const double S = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+            double a = 0.0, b2 = 0.0;
+            for (int b = 0; b < N; ++b) {
+                const double w = op.I[m][b];
+                a += w * sgr[el][0 * 3 + c][base + b * st];
+                b2 += w * sgr[el][4 * 3 + c][base + b * st];
+            }
+            gr += a * S;
+            gE += b2 * S;
+        }
+        const double p = gm1 * E;
+        out[(e * 3 + d) * NFL + fl] = (float)(P.cp * (gm1 * gE / (P.gamma * p) - gr / rho));
+    }
+}
+
 // fixed-order partial sums of w w w |J| Q_v over element blocks
 template <int NT>
 __global__ __launch_bounds__(NT) void k_sums_partial(const double *__restrict__ Q,
@@ -463,6 +510,23 @@ hipError_t launch_grad(const Mesh &m, const Geo &G, const PhysParams &P, const d
 hipError_t launch_resid(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
                         const double *TV, const StageArgs &sa, hipStream_t s) {
 #define C_(n) launch_resid_t<n>(m, G, P, Q, TQ, TV, sa, s)
+    CHORUS_DISPATCH(m.N, C_)
+#undef C_
+}
+
+template <int N>
+static hipError_t launch_bg_entropy_t(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q0,
+                                      const double *TQ, float *out, hipStream_t s) {
+    constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
+    const Ops<N> op = make_ops<N>(m.basis);
+    const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
+    hipLaunchKernelGGL((k_bg_entropy<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, op, G, P, Q0, TQ, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bg_entropy(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q0, const double *TQ,
+                             float *out, hipStream_t s) {
+#define C_(n) launch_bg_entropy_t<n>(m, G, P, Q0, TQ, out, s)
     CHORUS_DISPATCH(m.N, C_)
 #undef C_
 }

@@ -2,19 +2,25 @@
 // FP32 interpolation, fluxes and derivatives on perturbations about a
 // hydrostatic background at rest (Q0 with zero momentum).
 //
-// Split of the residual (exact algebra, rounding aside):
-//   R(Q) = R0 + dR,   R0 = inviscid + source residual of Q0 (computed once in
-//   FP64 by the FP64 kernels, stored as FP32), and
-//   dR   = [inviscid + source](Q) - [inviscid + source](Q0) + viscous(Q).
-// The inviscid difference is evaluated without cancellation from the
-// perturbation P = Q - Q0:
-//   mass      m'.S
-//   momentum  m' (m'.S)/rho + p' S,        p' = (g-1)(E' - |m'|^2 / (2 rho))
-//   energy    (gamma E0 + E' + p') (m'.S)/rho
-//   Rusanov   1/2 (dF_L + dF_R) - 1/2 |S| [lam (P_R - P_L) + (lam - lam0)(Q0_R - Q0_L)]
-//   source    M(P) (M is linear in Q)
-// so FP32 rounding is relative to perturbation sizes; the viscous residual
-// (scaled by nu, kappa) is evaluated from the full state in FP32.
+// Split of the residual (exact algebra; only rounding differs):
+//   R(Q) = R0 + dR,  R0 = R(Q0) computed once in FP64 (stored FP32), and
+//   dR = R(Q) - R(Q0) evaluated from P = Q - Q0 without cancellation:
+//   * gradients are linear: grad Q = grad Q0 + grad P, each from its own
+//     BR1 common values (the wall state enters in perturbation form);
+//   * inviscid:  mass m'.S, momentum m'(m'.S)/rho + p'S,
+//                energy (gamma E0 + E' + p')(m'.S)/rho,
+//                p' = (gamma-1)(E' - |m'|^2/(2 rho));
+//   * Rusanov:   1/2 (dF_L + dF_R) - 1/2 |S| [lam (P_R - P_L) + (lam - lam0) dQ0],
+//                lam - lam0 formed from the small quantities |u.n| + (c - c0)
+//                and the background sound-speed jump;
+//   * viscous:   tau(Q) (tau0 = 0), and the diffusive energy flux as
+//                kappa/R [p' (gS0.S) + p ((gS - gS0).S)] + kappa_r terms, with
+//                (gS - gS0).S written through grad P and the background
+//                gradients, and gS0.S (the background entropy gradient along
+//                S) computed in FP64 once;
+//   * source:    M(P) (linear).
+// FP32 rounding therefore scales with the perturbation, and the hydrostatic
+// and isentropic cancellations of the background stay in FP64.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -28,52 +34,6 @@ template <int N>
 using OpsF = OpsT<float, N>;
 
 // ---------------------------------------------------------------------------
-// pointwise perturbation fluxes
-// ---------------------------------------------------------------------------
-// (F(Q) - F(Q0)) . S with m0 = 0, from the full density and energy and the
-// perturbation momentum and energy
-__device__ __forceinline__ void dflux_inviscid(float rho, const float m[3], float E, float Ep,
-                                               const float S[3], float gm1, float gam, float out[5]) {
-    const float inv = 1.0f / rho;
-    const float mS = m[0] * S[0] + m[1] * S[1] + m[2] * S[2];
-    const float mm = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
-    const float pp = gm1 * (Ep - 0.5f * mm * inv);
-    const float uS = mS * inv;
-    out[0] = mS;
-    out[1] = m[0] * uS + pp * S[0];
-    out[2] = m[1] * uS + pp * S[1];
-    out[3] = m[2] * uS + pp * S[2];
-    out[4] = (gam * E - gm1 * Ep + pp) * uS;
-}
-
-// viscous part of the wall flux (normal traction only, energy flux
-// F_bottom |S| at the inner wall, interior diffusive flux at the outer wall),
-// returned with the sign of a flux: (0, -tau_nn S, -e)
-__device__ __forceinline__ void flux_wall_viscous(const float q[5], const float g[5][3], const float S[3],
-                                                  bool outer, const PhysParams &P, float out[5]) {
-    PrimGrad<float> pg;
-    prim_grad(q, g, P, pg);
-    const float mu = pg.rho * (float)P.nu;
-    const float div = pg.du[0][0] + pg.du[1][1] + pg.du[2][2];
-    const float A2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
-    float ngn = 0.0f;
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) ngn += S[a] * pg.du[a][b] * S[b];
-    const float tnn = mu * (2.0f * ngn / A2 - (2.0f / 3.0f) * div);
-    float ev;
-    if (outer) {
-        const float dSS = pg.dS[0] * S[0] + pg.dS[1] * S[1] + pg.dS[2] * S[2];
-        const float dTS = pg.dT[0] * S[0] + pg.dT[1] * S[1] + pg.dT[2] * S[2];
-        ev = (float)P.kappa * pg.rho * pg.Tmp * dSS + (float)P.kappa_r * pg.rho * (float)P.cp * dTS;
-    } else {
-        ev = (float)P.F_bottom * sqrtf(A2);
-    }
-    out[0] = 0.0f;
-    for (int a = 0; a < 3; ++a) out[1 + a] = -tnn * S[a];
-    out[4] = -ev;
-}
-
-// ---------------------------------------------------------------------------
 // views
 // ---------------------------------------------------------------------------
 struct GeoF {
@@ -85,65 +45,148 @@ struct GeoF {
 };
 
 struct MixedBufs {
-    const float *bg;    // [E][2][NP]  rho0, E0 at solution points
-    const float *bgT;   // [E][6][2][NF2] rho0, E0 face traces (FP64 interpolation, rounded)
-    const float *R0;    // [5][E][NP]  background residual
+    const float *bg;    // [E][2][NP]    rho0, E0
+    const float *dbg;   // [E][6][2][NF2] neighbour minus own background face trace (rho, E)
+    const float *gS0;   // [E][3][NFL]   grad S0 . (|J| grad xi_d) at d-flux points
+    const float *R0;    // [5][E][NP]    R(Q0)
 };
 
-// sol-point field slots in LDS: full rho, m' (3), full E, rho', E'
-enum { F_RHO = 0, F_MX = 1, F_MY = 2, F_MZ = 3, F_E = 4, F_RP = 5, F_EP = 6, NFIELD = 7 };
+struct PhysF {
+    float gm1, gam, R, cp, GM, om, nu, kappa, kappa_r, RT_top;  // RT_top <= 0: off
+};
 
-template <int N, int EPB, int NT>
-__device__ __forceinline__ void load_fields(const double *__restrict__ Pq, const MixedBufs &B, int64_t E,
-                                            int64_t e0, float (*sf)[NFIELD][N * N * N]) {
-    constexpr int NP = N * N * N;
-    for (int it = threadIdx.x; it < EPB * NP; it += NT) {
-        const int el = it / NP, p = it % NP;
-        const int64_t e = e0 + el;
-        if (e >= E) {
-            sf[el][F_RHO][p] = 1.0f;
-            sf[el][F_MX][p] = sf[el][F_MY][p] = sf[el][F_MZ][p] = 0.0f;
-            sf[el][F_E][p] = 1.0f;
-            sf[el][F_RP][p] = sf[el][F_EP][p] = 0.0f;
-            continue;
-        }
-        const double pr = Pq[(0 * E + e) * NP + p], pe = Pq[(4 * E + e) * NP + p];
-        const float r0 = B.bg[(e * 2 + 0) * NP + p], E0 = B.bg[(e * 2 + 1) * NP + p];
-        sf[el][F_RHO][p] = (float)((double)r0 + pr);
-        sf[el][F_MX][p] = (float)Pq[(1 * E + e) * NP + p];
-        sf[el][F_MY][p] = (float)Pq[(2 * E + e) * NP + p];
-        sf[el][F_MZ][p] = (float)Pq[(3 * E + e) * NP + p];
-        sf[el][F_E][p] = (float)((double)E0 + pe);
-        sf[el][F_RP][p] = (float)pr;
-        sf[el][F_EP][p] = (float)pe;
-    }
+__device__ __forceinline__ PhysF physf_of(const PhysParams &P) {
+    PhysF f;
+    f.gm1 = (float)(P.gamma - 1.0);
+    f.gam = (float)P.gamma;
+    f.R = (float)P.R_gas;
+    f.cp = (float)P.cp;
+    f.GM = (float)P.GM;
+    f.om = (float)P.omega;
+    f.nu = (float)P.nu;
+    f.kappa = (float)P.kappa;
+    f.kappa_r = (float)P.kappa_r;
+    f.RT_top = (P.T_top > 0.0) ? (float)(P.R_gas * P.T_top) : -1.0f;
+    return f;
 }
 
-// neighbour face data: perturbation trace (5) and background trace (2)
-template <int N, int EPB, int NT>
-__device__ __forceinline__ void load_neighbours(const GeoF &G, const MixedBufs &B, const float *__restrict__ TQ,
-                                                int64_t e0, float (*snb)[6][7][N * N]) {
-    constexpr int NF2 = N * N;
-    for (int it = threadIdx.x; it < EPB * 6 * 7 * NF2; it += NT) {
-        const int el = it / (6 * 7 * NF2), r = it % (6 * 7 * NF2);
-        const int f = r / (7 * NF2), v = (r / NF2) % 7, pn = r % NF2;
-        const int64_t e = e0 + el;
-        float val = 0.0f;
-        if (e < G.E) {
-            const int32_t nb = G.link[e * 6 + f];
-            if (nb >= 0) {
-                const int f2 = G.info[e * 6 + f] & 7;
-                val = (v < 5) ? TQ[(((int64_t)nb * 6 + f2) * 5 + v) * NF2 + pn]
-                              : B.bgT[(((int64_t)nb * 6 + f2) * 2 + (v - 5)) * NF2 + pn];
-            }
-        }
-        snb[el][f][v][pn] = val;  // stored in the neighbour's point order
-    }
+// LDS field slots at solution points: perturbation (5), background (2)
+enum { F_RP = 0, F_MX = 1, F_MY = 2, F_MZ = 3, F_EP = 4, F_R0 = 5, F_E0 = 6, NFIELD = 7 };
+// gradient slots: field f, component c at slot 3 f + c
+constexpr int NGRAD = 3 * NFIELD;
+
+// point state at a flux point: background and perturbation values and
+// gradients (full gradient = background + perturbation)
+struct PtState {
+    float r0, E0, rp, m[3], Ep;          // values
+    float gr0[3], gE0[3];                // background gradients
+    float grp[3], gm[3][3], gEp[3];      // perturbation gradients
+};
+
+// ---------------------------------------------------------------------------
+// pointwise perturbation physics
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void dflux_inviscid(const PtState &s, const float S[3], const PhysF &F, float out[5]) {
+    const float rho = s.r0 + s.rp, E = s.E0 + s.Ep;
+    const float inv = 1.0f / rho;
+    const float mS = s.m[0] * S[0] + s.m[1] * S[1] + s.m[2] * S[2];
+    const float mm = s.m[0] * s.m[0] + s.m[1] * s.m[1] + s.m[2] * s.m[2];
+    const float pp = F.gm1 * (s.Ep - 0.5f * mm * inv);
+    const float uS = mS * inv;
+    out[0] = mS;
+    out[1] = s.m[0] * uS + pp * S[0];
+    out[2] = s.m[1] * uS + pp * S[1];
+    out[3] = s.m[2] * uS + pp * S[2];
+    out[4] = (F.gam * E - F.gm1 * s.Ep + pp) * uS;
 }
 
-// own face values of the listed sol fields at face point (f, t1, t2)
+// (F_v(Q) - F_v(Q0)) . S given gS0S = grad S0 . S.  outer_wall / inner_wall
+// select the wall forms (normal traction only; energy as interior at the
+// outer wall, none at the inner wall where the prescribed flux is in R0).
+__device__ __forceinline__ void dflux_viscous(const PtState &s, const float S[3], float gS0S, const PhysF &F,
+                                              int wall, float out[5]) {
+    const float rho = s.r0 + s.rp, inv = 1.0f / rho;
+    const float u[3] = {s.m[0] * inv, s.m[1] * inv, s.m[2] * inv};
+    float grho[3], du[3][3];
+    for (int c = 0; c < 3; ++c) grho[c] = s.gr0[c] + s.grp[c];
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) du[a][c] = (s.gm[a][c] - u[a] * grho[c]) * inv;
+    const float mu = rho * F.nu;
+    const float dv = du[0][0] + du[1][1] + du[2][2];
+    float tS[3];
+    if (wall == 0) {
+        for (int a = 0; a < 3; ++a) {
+            float t = 0.0f;
+            for (int b = 0; b < 3; ++b) t += (du[a][b] + du[b][a]) * S[b];
+            tS[a] = mu * (t - (2.0f / 3.0f) * dv * S[a]);
+        }
+    } else {
+        const float A2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
+        float ngn = 0.0f;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) ngn += S[a] * du[a][b] * S[b];
+        const float tnn = mu * (2.0f * ngn / A2 - (2.0f / 3.0f) * dv);
+        for (int a = 0; a < 3; ++a) tS[a] = tnn * S[a];
+    }
+    out[0] = 0.0f;
+    out[1] = tS[0];
+    out[2] = tS[1];
+    out[3] = tS[2];
+    if (wall == 1) {  // inner wall: stress free, no viscous work, energy flux in R0
+        out[1] = tS[0];
+        out[4] = 0.0f;
+        return;
+    }
+    // p' and grad p' (m0 = 0, u0 = 0)
+    const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const float pp = F.gm1 * (s.Ep - 0.5f * uu * rho);
+    const float p0 = F.gm1 * s.E0, p = p0 + pp;
+    float gpS = 0.0f, grpS = 0.0f, gr0S = 0.0f, gp0S = 0.0f;
+    for (int c = 0; c < 3; ++c) {
+        const float gp = F.gm1 * (s.gEp[c] - (u[0] * s.gm[0][c] + u[1] * s.gm[1][c] + u[2] * s.gm[2][c]) +
+                                  0.5f * uu * grho[c]);
+        gpS += gp * S[c];
+        grpS += s.grp[c] * S[c];
+        gr0S += s.gr0[c] * S[c];
+        gp0S += F.gm1 * s.gE0[c] * S[c];
+    }
+    // (grad S - grad S0).S / c_p
+    const float dgS = gpS / (F.gam * p) - gp0S * pp / (F.gam * p * p0) - grpS / rho + gr0S * s.rp / (rho * s.r0);
+    // rho T grad S . S - rho0 T0 grad S0 . S = (p' gS0S + p c_p dgS) / R
+    const float eS = F.kappa * (pp * gS0S + p * F.cp * dgS) / F.R;
+    // rho c_p grad T . S difference: c_p/R (grad p' . S - [p grad rho' . S / rho + grad rho0 . S (p/rho - p0/rho0)])
+    const float dpr = (pp * s.r0 - p0 * s.rp) / (rho * s.r0);
+    const float eT = F.kappa_r * F.cp / F.R * (gpS - (p * grpS * inv + gr0S * dpr));
+    const float work = (wall == 0) ? (u[0] * tS[0] + u[1] * tS[1] + u[2] * tS[2]) : 0.0f;
+    out[4] = work + eS + eT;
+}
+
+// ---------------------------------------------------------------------------
+// element phases (generic N; items per thread fixed at compile time)
+// ---------------------------------------------------------------------------
+template <int N, int EPB, int NT>
+struct Shape {
+    static constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
+    static constexpr int IT_SOL = (EPB * NP + NT - 1) / NT;
+    static constexpr int IT_FACE = (EPB * 6 * NF2 + NT - 1) / NT;
+    static constexpr int IT_FLUX = (EPB * 3 * NFL + NT - 1) / NT;
+};
+
 template <int N>
-__device__ __forceinline__ float face_interp(const OpsF<N> &op, const float *fld, int f, int t1, int t2) {
+struct MixedLds {
+    static constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
+    float f[NFIELD][NP];          // perturbation + background fields
+    float g[NGRAD][NP];           // gradients
+    float cs[NFIELD][6][NF2];     // common values (perturbation 0..4, background 5..6)
+    float nb[5][6][NF2];          // neighbour perturbation traces (neighbour point order)
+    float nv[5][6][NF2];          // neighbour viscous traces (k_resid only)
+    float db[2][6][NF2];          // own background jump (neighbour - own), rho and E
+    float ft[3][5][NFL];          // transformed flux (k_resid only)
+};
+
+// own face-point interpolation of a field stored in LDS
+template <int N>
+__device__ __forceinline__ float face_val(const OpsF<N> &op, const float *fld, int f, int t1, int t2) {
     const int d = f >> 1, m = (f & 1) ? N : 0;
     const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
     float s = 0.0f;
@@ -152,124 +195,159 @@ __device__ __forceinline__ float face_interp(const OpsF<N> &op, const float *fld
     return s;
 }
 
-// full state on both sides of face point (f, pp): own from interpolation,
-// neighbour from its traces; also the own perturbation and background.
-struct FaceStates {
-    float qL[5], qR[5];     // full
-    float pL[5], pR[5];     // perturbation
-    float r0L, E0L, r0R, E0R;
-};
-
-template <int N>
-__device__ __forceinline__ void face_states(const OpsF<N> &op, const float (*sf)[N * N * N],
-                                            const float (*nbf)[N * N], int o, int f, int t1, int t2,
-                                            FaceStates &s) {
-    const float rho = face_interp<N>(op, sf[F_RHO], f, t1, t2);
-    const float E = face_interp<N>(op, sf[F_E], f, t1, t2);
-    s.pL[0] = face_interp<N>(op, sf[F_RP], f, t1, t2);
-    s.pL[4] = face_interp<N>(op, sf[F_EP], f, t1, t2);
-    for (int a = 0; a < 3; ++a) s.pL[1 + a] = face_interp<N>(op, sf[F_MX + a], f, t1, t2);
-    s.qL[0] = rho;
-    s.qL[1] = s.pL[1];
-    s.qL[2] = s.pL[2];
-    s.qL[3] = s.pL[3];
-    s.qL[4] = E;
-    s.r0L = rho - s.pL[0];
-    s.E0L = E - s.pL[4];
-    const int pn = map_face_point<N>(o, t1, t2);
-    for (int v = 0; v < 5; ++v) s.pR[v] = nbf[v][pn];
-    s.r0R = nbf[5][pn];
-    s.E0R = nbf[6][pn];
-    s.qR[0] = s.r0R + s.pR[0];
-    s.qR[1] = s.pR[1];
-    s.qR[2] = s.pR[2];
-    s.qR[3] = s.pR[3];
-    s.qR[4] = s.E0R + s.pR[4];
+template <int N, int EPB, int NT>
+__device__ __forceinline__ void load_element(const double *__restrict__ Pq, const MixedBufs &B, const GeoF &G,
+                                             const float *__restrict__ TQ, const float *__restrict__ TV,
+                                             int64_t e0, MixedLds<N> *L) {
+    using Sh = Shape<N, EPB, NT>;
+    constexpr int NP = Sh::NP, NF2 = Sh::NF2;
+    const int64_t E = G.E;
+    for (int it = threadIdx.x; it < EPB * NP; it += NT) {
+        const int el = it / NP, p = it % NP;
+        const int64_t e = e0 + el;
+        MixedLds<N> &l = L[el];
+        if (e < E) {
+            for (int v = 0; v < 5; ++v) l.f[v][p] = (float)Pq[((int64_t)v * E + e) * NP + p];
+            l.f[F_R0][p] = B.bg[(e * 2 + 0) * NP + p];
+            l.f[F_E0][p] = B.bg[(e * 2 + 1) * NP + p];
+        } else {
+            for (int v = 0; v < 5; ++v) l.f[v][p] = 0.0f;
+            l.f[F_R0][p] = 1.0f;
+            l.f[F_E0][p] = 1.0f;
+        }
+    }
+    for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pn = r % NF2;
+        const int64_t e = e0 + el;
+        MixedLds<N> &l = L[el];
+        int32_t nb = -1, f2 = 0;
+        if (e < E) {
+            nb = G.link[e * 6 + f];
+            f2 = G.info[e * 6 + f] & 7;
+            l.db[0][f][pn] = B.dbg[((e * 6 + f) * 2 + 0) * NF2 + pn];
+            l.db[1][f][pn] = B.dbg[((e * 6 + f) * 2 + 1) * NF2 + pn];
+        }
+        for (int v = 0; v < 5; ++v) {
+            const int64_t gi = (((int64_t)nb * 6 + f2) * 5 + v) * NF2 + pn;
+            l.nb[v][f][pn] = (nb >= 0) ? TQ[gi] : 0.0f;
+            if (TV) l.nv[v][f][pn] = (nb >= 0) ? TV[gi] : 0.0f;
+        }
+    }
 }
 
-// BR1 common solution (full variables) at every face point
+// BR1 common values at the 6 N^2 face points: perturbation (5) and
+// background (rho0, E0)
 template <int N, int EPB, int NT>
-__device__ __forceinline__ void common_solution_mixed(const OpsF<N> &op, const GeoF &G, const PhysParams &P,
-                                                      int64_t e0, float (*sf)[NFIELD][N * N * N],
-                                                      float (*snb)[6][7][N * N], float (*sqs)[6][5][N * N]) {
+__device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, const PhysF &F, int64_t e0,
+                                              MixedLds<N> *L) {
     constexpr int NF2 = N * N, NFL = (N + 1) * N * N;
     for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
+        MixedLds<N> &l = L[el];
         const int t1 = pp % N, t2 = pp / N;
+        float pv[5];
+        for (int v = 0; v < 5; ++v) pv[v] = face_val<N>(op, l.f[v], f, t1, t2);
+        const float r0 = face_val<N>(op, l.f[F_R0], f, t1, t2), E0 = face_val<N>(op, l.f[F_E0], f, t1, t2);
         const int32_t nb = G.link[e * 6 + f], inf = G.info[e * 6 + f];
-        const int bc = (inf >> 6) - 1;
-        float qs[5];
         if (nb >= 0) {
-            FaceStates s;
-            face_states<N>(op, sf[el], snb[el][f], (inf >> 3) & 7, f, t1, t2, s);
-            for (int v = 0; v < 5; ++v) qs[v] = 0.5f * (s.qL[v] + s.qR[v]);
+            const int pn = map_face_point<N>((inf >> 3) & 7, t1, t2);
+            for (int v = 0; v < 5; ++v) l.cs[v][f][pp] = 0.5f * (pv[v] + l.nb[v][f][pn]);
+            l.cs[F_R0][f][pp] = r0 + 0.5f * l.db[0][f][pp];
+            l.cs[F_E0][f][pp] = E0 + 0.5f * l.db[1][f][pp];
         } else {
-            float q[5];
-            q[0] = face_interp<N>(op, sf[el][F_RHO], f, t1, t2);
-            for (int a = 0; a < 3; ++a) q[1 + a] = face_interp<N>(op, sf[el][F_MX + a], f, t1, t2);
-            q[4] = face_interp<N>(op, sf[el][F_E], f, t1, t2);
+            // wall state in perturbation form: rho' kept, normal momentum
+            // removed, pressure kept (outer wall with T_top: p = rho R T_top)
+            const bool outer = ((inf >> 6) - 1) == CHORUS_BC_OUTER;
             const int d = f >> 1, m = (f & 1) ? N : 0;
             const int fl = m + (N + 1) * (t1 + N * t2);
-            const float sg = (f & 1) ? 1.0f : -1.0f;
             float S[3];
-            for (int c = 0; c < 3; ++c) S[c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
-            wall_state(q, S, bc == CHORUS_BC_OUTER, P, qs);
+            for (int c = 0; c < 3; ++c) S[c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+            const float A2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
+            const float mn = (pv[1] * S[0] + pv[2] * S[1] + pv[3] * S[2]) / A2;
+            float mb[3];
+            for (int a = 0; a < 3; ++a) mb[a] = pv[1 + a] - mn * S[a];
+            const float rho = r0 + pv[0];
+            const float mm = pv[1] * pv[1] + pv[2] * pv[2] + pv[3] * pv[3];
+            const float mbb = mb[0] * mb[0] + mb[1] * mb[1] + mb[2] * mb[2];
+            float Eb;  // E_b - E0_b
+            if (outer && F.RT_top > 0.0f) Eb = F.RT_top * pv[0] / F.gm1 + 0.5f * mbb / rho;
+            else Eb = pv[4] - 0.5f * mm / rho + 0.5f * mbb / rho;
+            l.cs[0][f][pp] = pv[0];
+            for (int a = 0; a < 3; ++a) l.cs[1 + a][f][pp] = mb[a];
+            l.cs[4][f][pp] = Eb;
+            l.cs[F_R0][f][pp] = r0;
+            l.cs[F_E0][f][pp] = (outer && F.RT_top > 0.0f) ? r0 * F.RT_top / F.gm1 : E0;
         }
-        for (int v = 0; v < 5; ++v) sqs[el][f][v][pp] = qs[v];
     }
 }
 
-// gradients of the full conserved variables at the solution points
+// gradients of the 7 fields at the solution points
 template <int N, int EPB, int NT>
-__device__ __forceinline__ void gradients_mixed(const OpsF<N> &op, const GeoF &G, int64_t e0,
-                                                float (*sf)[NFIELD][N * N * N], float (*sqs)[6][5][N * N],
-                                                float (*sgr)[15][N * N * N]) {
+__device__ __forceinline__ void gradients(const OpsF<N> &op, const GeoF &G, int64_t e0, MixedLds<N> *L) {
     constexpr int NP = N * N * N;
     for (int it = threadIdx.x; it < EPB * NP; it += NT) {
         const int el = it / NP, p = it % NP;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
-        float dq[3][5];
+        MixedLds<N> &l = L[el];
+        const float *gs = G.solgeo + e * 13 * NP + p;
+        float Gm[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) Gm[t] = gs[t * NP];
+        float dq[3][NFIELD];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             int a, t1, t2;
             split_sol<N>(d, p, a, t1, t2);
             const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d), pp = t1 + N * t2;
 #pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                float s = op.D[a][0] * sqs[el][2 * d][v][pp] + op.D[a][N] * sqs[el][2 * d + 1][v][pp];
+            for (int v = 0; v < NFIELD; ++v) {
+                float s = op.D[a][0] * l.cs[v][2 * d][pp] + op.D[a][N] * l.cs[v][2 * d + 1][pp];
 #pragma unroll
-                for (int b = 0; b < N; ++b) s += op.B[a][b] * sf[el][v][base + b * st];
+                for (int b = 0; b < N; ++b) s += op.B[a][b] * l.f[v][base + b * st];
                 dq[d][v] = s;
             }
         }
-        const float *gs = G.solgeo + e * 13 * NP + p;
-        float Gm[9];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) Gm[t] = gs[t * NP];
-#pragma unroll
-        for (int v = 0; v < 5; ++v)
+        for (int v = 0; v < NFIELD; ++v)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                sgr[el][v * 3 + c][p] = Gm[c] * dq[0][v] + Gm[3 + c] * dq[1][v] + Gm[6 + c] * dq[2][v];
+                l.g[3 * v + c][p] = Gm[c] * dq[0][v] + Gm[3 + c] * dq[1][v] + Gm[6 + c] * dq[2][v];
     }
 }
 
-// gradient at a flux point (m along d) by interpolation along the line
+// point state at the flux point m of the line (base, st)
 template <int N>
-__device__ __forceinline__ void grad_at(const OpsF<N> &op, const float (*gr)[N * N * N], int m, int base, int st,
-                                        float g[5][3]) {
+__device__ __forceinline__ void state_at(const OpsF<N> &op, const MixedLds<N> &l, int m, int base, int st,
+                                         PtState &s) {
+    float w[N];
 #pragma unroll
-    for (int v = 0; v < 5; ++v)
+    for (int b = 0; b < N; ++b) w[b] = op.I[m][b];
+    auto I = [&](const float *fld) {
+        float t = 0.0f;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float t = 0.0f;
+        for (int b = 0; b < N; ++b) t += w[b] * fld[base + b * st];
+        return t;
+    };
+    s.rp = I(l.f[F_RP]);
+    s.m[0] = I(l.f[F_MX]);
+    s.m[1] = I(l.f[F_MY]);
+    s.m[2] = I(l.f[F_MZ]);
+    s.Ep = I(l.f[F_EP]);
+    s.r0 = I(l.f[F_R0]);
+    s.E0 = I(l.f[F_E0]);
 #pragma unroll
-            for (int b = 0; b < N; ++b) t += op.I[m][b] * gr[v * 3 + c][base + b * st];
-            g[v][c] = t;
-        }
+    for (int c = 0; c < 3; ++c) {
+        s.grp[c] = I(l.g[3 * F_RP + c]);
+        s.gm[0][c] = I(l.g[3 * F_MX + c]);
+        s.gm[1][c] = I(l.g[3 * F_MY + c]);
+        s.gm[2][c] = I(l.g[3 * F_MZ + c]);
+        s.gEp[c] = I(l.g[3 * F_EP + c]);
+        s.gr0[c] = I(l.g[3 * F_R0 + c]);
+        s.gE0[c] = I(l.g[3 * F_E0 + c]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -301,159 +379,158 @@ __global__ __launch_bounds__(NT) void k_pert_begin(OpsF<N> op, GeoF G, const dou
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
         for (int v = 0; v < 5; ++v)
-            TQ[((e * 6 + f) * 5 + v) * NF2 + pp] = face_interp<N>(op, sp[el][v], f, pp % N, pp / N);
+            TQ[((e * 6 + f) * 5 + v) * NF2 + pp] = face_val<N>(op, sp[el][v], f, pp % N, pp / N);
     }
 }
 
-// viscous flux of the own side (full state, FP32) at interior interface
-// points along the outward area vector: TV[e][f][v][pp]
+// viscous-flux difference of the own side at interior interface points
+// along the outward area vector: TV[e][f][v][pp]
 template <int N, int EPB, int NT>
 __global__ __launch_bounds__(NT) void k_grad_mixed(OpsF<N> op, GeoF G, MixedBufs B, PhysParams P,
                                                    const double *__restrict__ Pq, const float *__restrict__ TQ,
                                                    float *__restrict__ TV) {
-    constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
-    __shared__ float sf[EPB][NFIELD][NP];
-    __shared__ float snb[EPB][6][7][NF2];
-    __shared__ float sqs[EPB][6][5][NF2];
-    __shared__ float sgr[EPB][15][NP];
+    constexpr int NF2 = N * N, NFL = (N + 1) * N * N;
+    __shared__ MixedLds<N> L[EPB];
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
-    load_neighbours<N, EPB, NT>(G, B, TQ, e0, snb);
-    load_fields<N, EPB, NT>(Pq, B, G.E, e0, sf);
+    const PhysF F = physf_of(P);
+    load_element<N, EPB, NT>(Pq, B, G, TQ, nullptr, e0, L);
     __syncthreads();
-    common_solution_mixed<N, EPB, NT>(op, G, P, e0, sf, snb, sqs);
+    common_values<N, EPB, NT>(op, G, F, e0, L);
     __syncthreads();
-    gradients_mixed<N, EPB, NT>(op, G, e0, sf, sqs, sgr);
+    gradients<N, EPB, NT>(op, G, e0, L);
     __syncthreads();
     for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
         const int64_t e = e0 + el;
         if (e >= G.E || G.link[e * 6 + f] < 0) continue;
         const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
-        const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
-        float q[5], g[5][3];
-        q[0] = face_interp<N>(op, sf[el][F_RHO], f, t1, t2);
-        for (int a = 0; a < 3; ++a) q[1 + a] = face_interp<N>(op, sf[el][F_MX + a], f, t1, t2);
-        q[4] = face_interp<N>(op, sf[el][F_E], f, t1, t2);
-        grad_at<N>(op, sgr[el], m, base, st, g);
         const int fl = m + (N + 1) * (t1 + N * t2);
         const float sg = (f & 1) ? 1.0f : -1.0f;
         float S[3], fv[5];
         for (int c = 0; c < 3; ++c) S[c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
-        flux_viscous(q, g, S, P, fv);
+        const float gS0S = sg * B.gS0[(e * 3 + d) * NFL + fl];
+        PtState s;
+        state_at<N>(op, L[el], m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), s);
+        dflux_viscous(s, S, gS0S, F, 0, fv);
         for (int v = 0; v < 5; ++v) TV[((e * 6 + f) * 5 + v) * NF2 + pp] = fv[v];
     }
 }
 
 struct MixedStage {
     const double *Pn;  // step-start perturbation (may alias Pout)
-    double *Pout;      // stage output (or dQ/dt in mode 0)
+    double *Pout;      // stage output, or dQ/dt in mode 0
     float *TQout;      // FP32 face traces of Pout (RK mode)
     double ca, cb, dt;
     int mode;          // 0 residual (R0 + dR), 1 RK stage
 };
 
 template <int N, int EPB, int NT>
-__global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBufs B, PhysParams P,
-                                                    const double *Pq, const float *__restrict__ TQ,
-                                                    const float *__restrict__ TV, MixedStage S_) {
-    constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
-    __shared__ float sf[EPB][NFIELD][NP];
-    __shared__ float snb[EPB][6][7][NF2];
-    __shared__ float snv[EPB][6][5][NF2];
-    __shared__ float sqs[EPB][6][5][NF2];
-    __shared__ float sgr[EPB][15][NP];
-    __shared__ float sft[EPB][3][5][NFL];
+__global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBufs B, PhysParams P, const double *Pq,
+                                                    const float *__restrict__ TQ, const float *__restrict__ TV,
+                                                    MixedStage S_) {
+    using Sh = Shape<N, EPB, NT>;
+    constexpr int NP = Sh::NP, NF2 = Sh::NF2, NFL = Sh::NFL;
+    __shared__ MixedLds<N> L[EPB];
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
-    const float gm1 = (float)(P.gamma - 1.0), gam = (float)P.gamma;
-    load_neighbours<N, EPB, NT>(G, B, TQ, e0, snb);
-    for (int it = threadIdx.x; it < EPB * 6 * 5 * NF2; it += NT) {
-        const int el = it / (6 * 5 * NF2), r = it % (6 * 5 * NF2);
-        const int f = r / (5 * NF2), v = (r / NF2) % 5, pn = r % NF2;
+    const PhysF F = physf_of(P);
+    // flux-point geometry of this thread's items, loaded up front
+    float Sv[Sh::IT_FLUX][3], gSv[Sh::IT_FLUX];
+#pragma unroll
+    for (int k = 0; k < Sh::IT_FLUX; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const int el = it / (3 * NFL), r = it % (3 * NFL), d = r / NFL, fl = r % NFL;
         const int64_t e = e0 + el;
-        float val = 0.0f;
-        if (e < G.E) {
-            const int32_t nb = G.link[e * 6 + f];
-            if (nb >= 0) val = TV[(((int64_t)nb * 6 + (G.info[e * 6 + f] & 7)) * 5 + v) * NF2 + pn];
-        }
-        snv[el][f][v][pn] = val;
+        const bool ok = it < EPB * 3 * NFL && e < G.E;
+        for (int c = 0; c < 3; ++c) Sv[k][c] = ok ? G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
+        gSv[k] = ok ? B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
     }
-    load_fields<N, EPB, NT>(Pq, B, G.E, e0, sf);
+    load_element<N, EPB, NT>(Pq, B, G, TQ, TV, e0, L);
     __syncthreads();
-    common_solution_mixed<N, EPB, NT>(op, G, P, e0, sf, snb, sqs);
+    common_values<N, EPB, NT>(op, G, F, e0, L);
     __syncthreads();
-    gradients_mixed<N, EPB, NT>(op, G, e0, sf, sqs, sgr);
+    gradients<N, EPB, NT>(op, G, e0, L);
     __syncthreads();
-    // transformed perturbation flux at every flux point of all directions
-    for (int it = threadIdx.x; it < EPB * 3 * NFL; it += NT) {
+#pragma unroll
+    for (int k = 0; k < Sh::IT_FLUX; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * 3 * NFL) break;
         const int el = it / (3 * NFL), r = it % (3 * NFL), d = r / NFL, fl = r % NFL;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
+        MixedLds<N> &l = L[el];
         const int m = fl % (N + 1), t1 = (fl / (N + 1)) % N, t2 = fl / ((N + 1) * N);
         const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
-        float Sv[3], F[5];
-        for (int c = 0; c < 3; ++c) Sv[c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
-        float g[5][3];
-        grad_at<N>(op, sgr[el], m, base, st, g);
+        PtState s;
+        state_at<N>(op, l, m, base, st, s);
+        float Fo[5];
         if (m > 0 && m < N) {
-            float q[5], Ep = 0.0f;
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                float s = 0.0f;
-#pragma unroll
-                for (int b = 0; b < N; ++b) s += op.I[m][b] * sf[el][v][base + b * st];
-                q[v] = s;
-            }
-#pragma unroll
-            for (int b = 0; b < N; ++b) Ep += op.I[m][b] * sf[el][F_EP][base + b * st];
             float fi[5], fv[5];
-            dflux_inviscid(q[0], &q[1], q[4], Ep, Sv, gm1, gam, fi);
-            flux_viscous(q, g, Sv, P, fv);
-            for (int v = 0; v < 5; ++v) F[v] = fi[v] - fv[v];
+            dflux_inviscid(s, Sv[k], F, fi);
+            dflux_viscous(s, Sv[k], gSv[k], F, 0, fv);
+            for (int v = 0; v < 5; ++v) Fo[v] = fi[v] - fv[v];
         } else {
             const int f = 2 * d + (m == N ? 1 : 0);
             const float sg = (m == N) ? 1.0f : -1.0f;
-            float So[3] = {sg * Sv[0], sg * Sv[1], sg * Sv[2]}, phi[5];
+            const float So[3] = {sg * Sv[k][0], sg * Sv[k][1], sg * Sv[k][2]};
+            const float gS0S = sg * gSv[k];
             const int32_t nb = G.link[e * 6 + f], inf = G.info[e * 6 + f];
-            const int bc = (inf >> 6) - 1;
+            float phi[5];
             if (nb >= 0) {
-                FaceStates s;
-                const int o = (inf >> 3) & 7;
-                face_states<N>(op, sf[el], snb[el][f], o, f, t1, t2, s);
+                const int pp = t1 + N * t2, pn = map_face_point<N>((inf >> 3) & 7, t1, t2);
+                // neighbour state from its perturbation trace and the background jump
+                PtState r = s;
+                r.rp = l.nb[0][f][pn];
+                r.m[0] = l.nb[1][f][pn];
+                r.m[1] = l.nb[2][f][pn];
+                r.m[2] = l.nb[3][f][pn];
+                r.Ep = l.nb[4][f][pn];
+                const float dr0 = l.db[0][f][pp], dE0 = l.db[1][f][pp];
+                r.r0 = s.r0 + dr0;
+                r.E0 = s.E0 + dE0;
                 float fL[5], fR[5], fvL[5];
-                dflux_inviscid(s.qL[0], &s.qL[1], s.qL[4], s.pL[4], So, gm1, gam, fL);
-                dflux_inviscid(s.qR[0], &s.qR[1], s.qR[4], s.pR[4], So, gm1, gam, fR);
-                const float A = sqrtf(So[0] * So[0] + So[1] * So[1] + So[2] * So[2]);
-                const float iA = 1.0f / A;
-                const float unL = fabsf((s.qL[1] * So[0] + s.qL[2] * So[1] + s.qL[3] * So[2]) * iA / s.qL[0]);
-                const float unR = fabsf((s.qR[1] * So[0] + s.qR[2] * So[1] + s.qR[3] * So[2]) * iA / s.qR[0]);
-                const float cL = sqrtf(gam * pressure_of(s.qL, gm1) / s.qL[0]);
-                const float cR = sqrtf(gam * pressure_of(s.qR, gm1) / s.qR[0]);
-                const float c0L = sqrtf(gam * gm1 * s.E0L / s.r0L), c0R = sqrtf(gam * gm1 * s.E0R / s.r0R);
-                const float lam = fmaxf(unL + cL, unR + cR), lam0 = fmaxf(c0L, c0R);
-                const float hl = 0.5f * lam * A, hd = 0.5f * (lam - lam0) * A;
-                const float dq0[5] = {s.r0R - s.r0L, 0.0f, 0.0f, 0.0f, s.E0R - s.E0L};
-                for (int v = 0; v < 5; ++v)
-                    phi[v] = 0.5f * (fL[v] + fR[v]) - hl * (s.pR[v] - s.pL[v]) - hd * dq0[v];
-                flux_viscous(s.qL, g, So, P, fvL);
-                const int pn = map_face_point<N>(o, t1, t2);
-                for (int v = 0; v < 5; ++v) phi[v] -= 0.5f * (fvL[v] + (-snv[el][f][v][pn]));
+                dflux_inviscid(s, So, F, fL);
+                dflux_inviscid(r, So, F, fR);
+                const float A = sqrtf(So[0] * So[0] + So[1] * So[1] + So[2] * So[2]), iA = 1.0f / A;
+                // |u.n| + (c - c0) on each side; c^2 - c0^2 = gamma (p' rho0 - p0 rho') / (rho rho0)
+                auto excess = [&](const PtState &q) {
+                    const float rho = q.r0 + q.rp, inv = 1.0f / rho;
+                    const float un = fabsf((q.m[0] * So[0] + q.m[1] * So[1] + q.m[2] * So[2]) * iA * inv);
+                    const float mm = q.m[0] * q.m[0] + q.m[1] * q.m[1] + q.m[2] * q.m[2];
+                    const float pp_ = F.gm1 * (q.Ep - 0.5f * mm * inv), p0 = F.gm1 * q.E0;
+                    const float c0 = sqrtf(F.gam * p0 / q.r0);
+                    const float dc2 = F.gam * (pp_ * q.r0 - p0 * q.rp) / (rho * q.r0);
+                    const float c = sqrtf(c0 * c0 + dc2);
+                    return un + dc2 / (c + c0);
+                };
+                const float eL = excess(s), eR = excess(r);
+                const float c0L = sqrtf(F.gam * F.gm1 * s.E0 / s.r0), c0R = sqrtf(F.gam * F.gm1 * r.E0 / r.r0);
+                // background sound-speed jump c0R - c0L from the FP64 background jump
+                const float dc0 = F.gam * F.gm1 * (dE0 * s.r0 - s.E0 * dr0) / (s.r0 * r.r0 * (c0L + c0R));
+                const float dlam = fmaxf(eL, eR + dc0) - fmaxf(0.0f, dc0);
+                const float lam0 = c0L + fmaxf(0.0f, dc0);
+                const float hl = 0.5f * (lam0 + dlam) * A, hd = 0.5f * dlam * A;
+                const float pR[5] = {r.rp, r.m[0], r.m[1], r.m[2], r.Ep};
+                const float pL[5] = {s.rp, s.m[0], s.m[1], s.m[2], s.Ep};
+                const float dq0[5] = {dr0, 0.0f, 0.0f, 0.0f, dE0};
+                for (int v = 0; v < 5; ++v) phi[v] = 0.5f * (fL[v] + fR[v]) - hl * (pR[v] - pL[v]) - hd * dq0[v];
+                dflux_viscous(s, So, gS0S, F, 0, fvL);
+                // the neighbour stored its flux along its own outward vector (-So)
+                for (int v = 0; v < 5; ++v) phi[v] -= 0.5f * (fvL[v] + (-l.nv[v][f][pn]));
             } else {
-                // wall: inviscid perturbation (0, p' S, 0) + viscous wall flux
-                float q[5], Ep = 0.0f;
-                for (int v = 0; v < 5; ++v) {
-                    float s = 0.0f;
-                    for (int b = 0; b < N; ++b) s += op.I[m][b] * sf[el][v][base + b * st];
-                    q[v] = s;
-                }
-                for (int b = 0; b < N; ++b) Ep += op.I[m][b] * sf[el][F_EP][base + b * st];
-                const float mm = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
-                const float pp = gm1 * (Ep - 0.5f * mm / q[0]);
-                flux_wall_viscous(q, g, So, bc == CHORUS_BC_OUTER, P, phi);
-                for (int a = 0; a < 3; ++a) phi[1 + a] += pp * So[a];
+                // wall: inviscid (0, p' S, 0); viscous wall form
+                const bool outer = ((inf >> 6) - 1) == CHORUS_BC_OUTER;
+                const float rho = s.r0 + s.rp;
+                const float mm = s.m[0] * s.m[0] + s.m[1] * s.m[1] + s.m[2] * s.m[2];
+                const float pp = F.gm1 * (s.Ep - 0.5f * mm / rho);
+                float fv[5];
+                dflux_viscous(s, So, gS0S, F, outer ? 2 : 1, fv);
+                phi[0] = 0.0f;
+                for (int a = 0; a < 3; ++a) phi[1 + a] = pp * So[a] - fv[1 + a];
+                phi[4] = -fv[4];
             }
-            for (int v = 0; v < 5; ++v) F[v] = sg * phi[v];
+            for (int v = 0; v < 5; ++v) Fo[v] = sg * phi[v];
         }
-        for (int v = 0; v < 5; ++v) sft[el][d][v][fl] = F[v];
+        for (int v = 0; v < 5; ++v) l.ft[d][v][fl] = Fo[v];
     }
     __syncthreads();
     // divergence, source, background residual and stage update
@@ -461,6 +538,7 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
         const int el = it / NP, p = it % NP;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
+        MixedLds<N> &l = L[el];
         float div[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -471,19 +549,18 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
             for (int v = 0; v < 5; ++v) {
                 float s = 0.0f;
 #pragma unroll
-                for (int mm = 0; mm <= N; ++mm) s += op.D[a][mm] * sft[el][d][v][fb + mm];
+                for (int mm = 0; mm <= N; ++mm) s += op.D[a][mm] * l.ft[d][v][fb + mm];
                 div[v] += s;
             }
         }
         const float *gs = G.solgeo + e * 13 * NP + p;
         const float iJ = gs[9 * NP];
-        const float GMf = (float)P.GM, Om = (float)P.omega;
-        const float g0 = GMf * gs[10 * NP], g1 = GMf * gs[11 * NP], g2 = GMf * gs[12 * NP];
-        const float rp = sf[el][F_RP][p], mx = sf[el][F_MX][p], my = sf[el][F_MY][p], mz = sf[el][F_MZ][p];
+        const float g0 = F.GM * gs[10 * NP], g1 = F.GM * gs[11 * NP], g2 = F.GM * gs[12 * NP];
+        const float rp = l.f[F_RP][p], mx = l.f[F_MX][p], my = l.f[F_MY][p], mz = l.f[F_MZ][p];
         float M[5];
         M[0] = 0.0f;
-        M[1] = rp * g0 - 2.0f * Om * my;
-        M[2] = rp * g1 + 2.0f * Om * mx;
+        M[1] = rp * g0 - 2.0f * F.om * my;
+        M[2] = rp * g1 + 2.0f * F.om * mx;
         M[3] = rp * g2;
         M[4] = mx * g0 + my * g1 + mz * g2;
         float newp[5];
@@ -499,13 +576,8 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
                 newp[v] = (float)pv;
             }
         }
-        if (S_.mode != 0) {
-            sf[el][F_RP][p] = newp[0];
-            sf[el][F_MX][p] = newp[1];
-            sf[el][F_MY][p] = newp[2];
-            sf[el][F_MZ][p] = newp[3];
-            sf[el][F_EP][p] = newp[4];
-        }
+        if (S_.mode != 0)
+            for (int v = 0; v < 5; ++v) l.f[v][p] = newp[v];
     }
     if (S_.mode == 0 || S_.TQout == nullptr) return;
     __syncthreads();
@@ -513,13 +585,8 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
-        const int t1 = pp % N, t2 = pp / N;
-        float* out = S_.TQout + (e * 6 + f) * 5 * NF2 + pp;
-        out[0 * NF2] = face_interp<N>(op, sf[el][F_RP], f, t1, t2);
-        out[1 * NF2] = face_interp<N>(op, sf[el][F_MX], f, t1, t2);
-        out[2 * NF2] = face_interp<N>(op, sf[el][F_MY], f, t1, t2);
-        out[3 * NF2] = face_interp<N>(op, sf[el][F_MZ], f, t1, t2);
-        out[4 * NF2] = face_interp<N>(op, sf[el][F_EP], f, t1, t2);
+        float *out = S_.TQout + (e * 6 + f) * 5 * NF2 + pp;
+        for (int v = 0; v < 5; ++v) out[v * NF2] = face_val<N>(op, L[el].f[v], f, pp % N, pp / N);
     }
 }
 
@@ -530,15 +597,16 @@ __global__ void k_pert_end(const double *__restrict__ Q0, const double *__restri
     if (i < n) Q[i] = Q0[i] + Pq[i];
 }
 
-// background setup: rho0, E0 (FP32) at solution points, their face traces
-// (FP64 interpolation, rounded), and a flag if Q0 has non-zero momentum
+// background setup (FP64): rho0, E0 (FP32) at solution points; the jump of
+// the background face traces across each interface (neighbour minus own,
+// from the FP64 traces TQ0 of Q0, rounded to FP32); a flag if Q0 moves
 template <int N, int EPB, int NT>
-__global__ __launch_bounds__(NT) void k_bg_setup(Ops<N> op, int64_t E, const double *__restrict__ Q0,
-                                                 float *__restrict__ bg, float *__restrict__ bgT,
-                                                 int *__restrict__ flag) {
+__global__ __launch_bounds__(NT) void k_bg_setup(Ops<N> op, Geo G, const double *__restrict__ Q0,
+                                                 const double *__restrict__ TQ0, float *__restrict__ bg,
+                                                 float *__restrict__ dbg, int *__restrict__ flag) {
     constexpr int NP = N * N * N, NF2 = N * N;
     __shared__ double s0[EPB][2][NP];
-    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    const int64_t e0 = (int64_t)blockIdx.x * EPB, E = G.E;
     for (int it = threadIdx.x; it < EPB * NP; it += NT) {
         const int el = it / NP, p = it % NP;
         const int64_t e = e0 + el;
@@ -558,10 +626,17 @@ __global__ __launch_bounds__(NT) void k_bg_setup(Ops<N> op, int64_t E, const dou
         if (e >= E) continue;
         const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
         const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
+        const int32_t nb = G.link[e * 6 + f];
         for (int v = 0; v < 2; ++v) {
-            double s = 0.0;
-            for (int b = 0; b < N; ++b) s += op.I[m][b] * s0[el][v][base + b * st];
-            bgT[((e * 6 + f) * 2 + v) * NF2 + pp] = (float)s;
+            double own = 0.0;
+            for (int b = 0; b < N; ++b) own += op.I[m][b] * s0[el][v][base + b * st];
+            double jump = 0.0;
+            if (nb >= 0) {
+                const int inf = G.info[e * 6 + f];
+                const int pn = map_face_point<N>((inf >> 3) & 7, t1, t2);
+                jump = TQ0[(((int64_t)nb * 6 + (inf & 7)) * 5 + (v == 0 ? 0 : 4)) * NF2 + pn] - own;
+            }
+            dbg[((e * 6 + f) * 2 + v) * NF2 + pp] = (float)jump;
         }
     }
 }
@@ -594,7 +669,8 @@ static GeoF geof_of(const GeoM &g) {
 static MixedBufs bufs_of(const GeoM &g) {
     MixedBufs b;
     b.bg = g.bg;
-    b.bgT = g.bgT;
+    b.dbg = g.dbg;
+    b.gS0 = g.gS0;
     b.R0 = g.R0;
     return b;
 }
@@ -627,11 +703,12 @@ static hipError_t resid_mixed_t(const Mesh &m, const GeoM &g, const PhysParams &
     return hipGetLastError();
 }
 template <int N>
-static hipError_t bg_setup_t(const Mesh &m, const double *Q0, float *bg, float *bgT, int *flag, hipStream_t s) {
+static hipError_t bg_setup_t(const Mesh &m, const Geo &G, const double *Q0, const double *TQ0, float *bg, float *dbg,
+                             int *flag, hipStream_t s) {
     constexpr int EPB = CfgM<N>::EPB, NT = CfgM<N>::NT;
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
-    hipLaunchKernelGGL((k_bg_setup<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, make_ops_t<double, N>(m.basis), m.E, Q0,
-                       bg, bgT, flag);
+    hipLaunchKernelGGL((k_bg_setup<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, make_ops_t<double, N>(m.basis), G, Q0,
+                       TQ0, bg, dbg, flag);
     return hipGetLastError();
 }
 
@@ -662,8 +739,9 @@ hipError_t launch_resid_mixed(const Mesh &m, const GeoM &g, const PhysParams &P,
     CHORUS_DISPATCH_M(m.N, C_)
 #undef C_
 }
-hipError_t launch_bg_setup(const Mesh &m, const double *Q0, float *bg, float *bgT, int *flag, hipStream_t s) {
-#define C_(n) bg_setup_t<n>(m, Q0, bg, bgT, flag, s)
+hipError_t launch_bg_setup(const Mesh &m, const Geo &G, const double *Q0, const double *TQ0, float *bg, float *dbg,
+                           int *flag, hipStream_t s) {
+#define C_(n) bg_setup_t<n>(m, G, Q0, TQ0, bg, dbg, flag, s)
     CHORUS_DISPATCH_M(m.N, C_)
 #undef C_
 }
