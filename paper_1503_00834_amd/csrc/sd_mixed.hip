@@ -33,6 +33,11 @@ namespace chorus {
 template <int N>
 using OpsF = OpsT<float, N>;
 
+// hardware reciprocal (1 ulp): every FP32 quantity here is
+// perturbation-scaled, so this rounding is of the same order as the FP32
+// arithmetic itself
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // ---------------------------------------------------------------------------
 // views
 // ---------------------------------------------------------------------------
@@ -88,7 +93,7 @@ struct PtState {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void dflux_inviscid(const PtState &s, const float S[3], const PhysF &F, float out[5]) {
     const float rho = s.r0 + s.rp, E = s.E0 + s.Ep;
-    const float inv = 1.0f / rho;
+    const float inv = rcp(rho);
     const float mS = s.m[0] * S[0] + s.m[1] * S[1] + s.m[2] * S[2];
     const float mm = s.m[0] * s.m[0] + s.m[1] * s.m[1] + s.m[2] * s.m[2];
     const float pp = F.gm1 * (s.Ep - 0.5f * mm * inv);
@@ -105,7 +110,7 @@ __device__ __forceinline__ void dflux_inviscid(const PtState &s, const float S[3
 // outer wall, none at the inner wall where the prescribed flux is in R0).
 __device__ __forceinline__ void dflux_viscous(const PtState &s, const float S[3], float gS0S, const PhysF &F,
                                               int wall, float out[5]) {
-    const float rho = s.r0 + s.rp, inv = 1.0f / rho;
+    const float rho = s.r0 + s.rp, inv = rcp(rho);
     const float u[3] = {s.m[0] * inv, s.m[1] * inv, s.m[2] * inv};
     float grho[3], du[3][3];
     for (int c = 0; c < 3; ++c) grho[c] = s.gr0[c] + s.grp[c];
@@ -125,7 +130,7 @@ __device__ __forceinline__ void dflux_viscous(const PtState &s, const float S[3]
         float ngn = 0.0f;
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) ngn += S[a] * du[a][b] * S[b];
-        const float tnn = mu * (2.0f * ngn / A2 - (2.0f / 3.0f) * dv);
+        const float tnn = mu * (2.0f * ngn * rcp(A2) - (2.0f / 3.0f) * dv);
         for (int a = 0; a < 3; ++a) tS[a] = tnn * S[a];
     }
     out[0] = 0.0f;
@@ -151,12 +156,14 @@ __device__ __forceinline__ void dflux_viscous(const PtState &s, const float S[3]
         gp0S += F.gm1 * s.gE0[c] * S[c];
     }
     // (grad S - grad S0).S / c_p
-    const float dgS = gpS / (F.gam * p) - gp0S * pp / (F.gam * p * p0) - grpS / rho + gr0S * s.rp / (rho * s.r0);
+    const float igp = rcp(F.gam * p), ir0 = rcp(s.r0);
+    const float dgS = igp * (gpS - gp0S * pp * rcp(p0)) - inv * (grpS - gr0S * s.rp * ir0);
     // rho T grad S . S - rho0 T0 grad S0 . S = (p' gS0S + p c_p dgS) / R
-    const float eS = F.kappa * (pp * gS0S + p * F.cp * dgS) / F.R;
+    const float iR = rcp(F.R);
+    const float eS = F.kappa * (pp * gS0S + p * F.cp * dgS) * iR;
     // rho c_p grad T . S difference: c_p/R (grad p' . S - [p grad rho' . S / rho + grad rho0 . S (p/rho - p0/rho0)])
-    const float dpr = (pp * s.r0 - p0 * s.rp) / (rho * s.r0);
-    const float eT = F.kappa_r * F.cp / F.R * (gpS - (p * grpS * inv + gr0S * dpr));
+    const float dpr = (pp * s.r0 - p0 * s.rp) * inv * ir0;
+    const float eT = F.kappa_r * F.cp * iR * (gpS - (p * grpS * inv + gr0S * dpr));
     const float work = (wall == 0) ? (u[0] * tS[0] + u[1] * tS[1] + u[2] * tS[2]) : 0.0f;
     out[4] = work + eS + eT;
 }
@@ -164,25 +171,128 @@ __device__ __forceinline__ void dflux_viscous(const PtState &s, const float S[3]
 // ---------------------------------------------------------------------------
 // element phases (generic N; items per thread fixed at compile time)
 // ---------------------------------------------------------------------------
-template <int N, int EPB, int NT>
-struct Shape {
-    static constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
-    static constexpr int IT_SOL = (EPB * NP + NT - 1) / NT;
-    static constexpr int IT_FACE = (EPB * 6 * NF2 + NT - 1) / NT;
-    static constexpr int IT_FLUX = (EPB * 3 * NFL + NT - 1) / NT;
-};
-
 template <int N>
 struct MixedLds {
     static constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
     float f[NFIELD][NP];          // perturbation + background fields
     float g[NGRAD][NP];           // gradients
     float cs[NFIELD][6][NF2];     // common values (perturbation 0..4, background 5..6)
-    float nb[5][6][NF2];          // neighbour perturbation traces (neighbour point order)
-    float nv[5][6][NF2];          // neighbour viscous traces (k_resid only)
-    float db[2][6][NF2];          // own background jump (neighbour - own), rho and E
+    float nb[6][5][NF2];          // neighbour perturbation traces at own face points
+    float nv[6][5][NF2];          // neighbour viscous traces at own face points (k_resid)
+    float db[6][2][NF2];          // background jump (neighbour - own), rho and E
     float ft[3][5][NFL];          // transformed flux (k_resid only)
+    int32_t lk[6], inf[6];        // neighbour element and info word per face
 };
+
+template <int N, int EPB, int NT>
+struct Shape {
+    static constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
+    static constexpr int IT_SOL = (EPB * NP + NT - 1) / NT;
+    static constexpr int IT_FACE = (EPB * 6 * NF2 + NT - 1) / NT;
+    static constexpr int IT_FLUX = (EPB * 3 * NFL + NT - 1) / NT;
+    static constexpr int NINT = 3 * (N - 1) * N * N;  // interior flux points per element
+    static constexpr int IT_INT = (EPB * NINT + NT - 1) / NT;
+    static constexpr int MB = 6 * 5 * NF2;             // mailbox floats per element
+    static constexpr int IT_MB = (EPB * MB + NT - 1) / NT;
+    static constexpr int DB = 6 * 2 * NF2;
+    static constexpr int IT_DB = (EPB * DB + NT - 1) / NT;
+};
+
+// registers holding one thread's share of an element block's global inputs;
+// everything is issued before the first use so that a block waits for
+// memory once
+template <int N, int EPB, int NT>
+struct Prologue {
+    using Sh = Shape<N, EPB, NT>;
+    double P[Sh::IT_SOL][5];
+    float bg[Sh::IT_SOL][2];
+    float gs[Sh::IT_SOL][13];
+    float mq[Sh::IT_MB], mv[Sh::IT_MB], db[Sh::IT_DB];
+    int32_t lk, inf;
+};
+
+// issue the loads (mailboxes are read as one contiguous block per element;
+// mv only when TV != null)
+template <int N, int EPB, int NT>
+__device__ __forceinline__ void prologue_load(const double *Pq, const MixedBufs &B, const GeoF &G,
+                                              const float *__restrict__ TQ, const float *__restrict__ TV,
+                                              int64_t e0, Prologue<N, EPB, NT> &R) {
+    using Sh = Shape<N, EPB, NT>;
+    constexpr int NP = Sh::NP;
+    const int64_t E = G.E;
+    const int64_t nel = (E - e0 < EPB) ? (E - e0) : EPB;
+#pragma unroll
+    for (int k = 0; k < Sh::IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const int el = it / NP, p = it % NP;
+        const int64_t e = e0 + el;
+        const bool ok = it < EPB * NP && e < E;
+        for (int v = 0; v < 5; ++v) R.P[k][v] = ok ? Pq[((int64_t)v * E + e) * NP + p] : 0.0;
+        R.bg[k][0] = ok ? B.bg[(e * 2 + 0) * NP + p] : 1.0f;
+        R.bg[k][1] = ok ? B.bg[(e * 2 + 1) * NP + p] : 1.0f;
+        for (int t = 0; t < 13; ++t) R.gs[k][t] = ok ? G.solgeo[(e * 13 + t) * NP + p] : 1.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < Sh::IT_MB; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const bool ok = it < nel * Sh::MB;
+        R.mq[k] = ok ? TQ[e0 * Sh::MB + it] : 0.0f;
+        R.mv[k] = (ok && TV) ? TV[e0 * Sh::MB + it] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < Sh::IT_DB; ++k) {
+        const int it = threadIdx.x + k * NT;
+        R.db[k] = (it < nel * Sh::DB) ? B.dbg[e0 * Sh::DB + it] : 0.0f;
+    }
+    const int it = threadIdx.x;
+    const bool okl = it < EPB * 6 && e0 + it / 6 < E;
+    R.lk = okl ? G.link[e0 * 6 + it] : -1;
+    R.inf = okl ? G.info[e0 * 6 + it] : 0;
+}
+
+// move the prologue registers into the element LDS
+template <int N, int EPB, int NT>
+__device__ __forceinline__ void prologue_store(const Prologue<N, EPB, NT> &R, MixedLds<N> *L) {
+    using Sh = Shape<N, EPB, NT>;
+    constexpr int NP = Sh::NP;
+#pragma unroll
+    for (int k = 0; k < Sh::IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * NP) break;
+        const int el = it / NP, p = it % NP;
+        for (int v = 0; v < 5; ++v) L[el].f[v][p] = (float)R.P[k][v];
+        L[el].f[F_R0][p] = R.bg[k][0];
+        L[el].f[F_E0][p] = R.bg[k][1];
+    }
+#pragma unroll
+    for (int k = 0; k < Sh::IT_MB; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * Sh::MB) break;
+        (&L[it / Sh::MB].nb[0][0][0])[it % Sh::MB] = R.mq[k];
+        (&L[it / Sh::MB].nv[0][0][0])[it % Sh::MB] = R.mv[k];
+    }
+#pragma unroll
+    for (int k = 0; k < Sh::IT_DB; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * Sh::DB) break;
+        (&L[it / Sh::DB].db[0][0][0])[it % Sh::DB] = R.db[k];
+    }
+    if ((int)threadIdx.x < EPB * 6) {
+        L[threadIdx.x / 6].lk[threadIdx.x % 6] = R.lk;
+        L[threadIdx.x / 6].inf[threadIdx.x % 6] = R.inf;
+    }
+}
+
+// push a value of own face point (f, pp) into the neighbour's mailbox at the
+// neighbour's point index (no-op on boundary faces)
+template <int N>
+__device__ __forceinline__ int64_t mailbox_slot(int32_t nb, int32_t inf, int pp) {
+    constexpr int NF2 = N * N;
+    const int f2 = inf & 7, o = (inf >> 3) & 7;
+    const int pn = map_face_point<N>(o, pp % N, pp / N);
+    return ((int64_t)nb * 6 + f2) * 5 * NF2 + pn;
+}
+
 
 // own face-point interpolation of a field stored in LDS
 template <int N>
@@ -193,46 +303,6 @@ __device__ __forceinline__ float face_val(const OpsF<N> &op, const float *fld, i
 #pragma unroll
     for (int b = 0; b < N; ++b) s += op.I[m][b] * fld[base + b * st];
     return s;
-}
-
-template <int N, int EPB, int NT>
-__device__ __forceinline__ void load_element(const double *__restrict__ Pq, const MixedBufs &B, const GeoF &G,
-                                             const float *__restrict__ TQ, const float *__restrict__ TV,
-                                             int64_t e0, MixedLds<N> *L) {
-    using Sh = Shape<N, EPB, NT>;
-    constexpr int NP = Sh::NP, NF2 = Sh::NF2;
-    const int64_t E = G.E;
-    for (int it = threadIdx.x; it < EPB * NP; it += NT) {
-        const int el = it / NP, p = it % NP;
-        const int64_t e = e0 + el;
-        MixedLds<N> &l = L[el];
-        if (e < E) {
-            for (int v = 0; v < 5; ++v) l.f[v][p] = (float)Pq[((int64_t)v * E + e) * NP + p];
-            l.f[F_R0][p] = B.bg[(e * 2 + 0) * NP + p];
-            l.f[F_E0][p] = B.bg[(e * 2 + 1) * NP + p];
-        } else {
-            for (int v = 0; v < 5; ++v) l.f[v][p] = 0.0f;
-            l.f[F_R0][p] = 1.0f;
-            l.f[F_E0][p] = 1.0f;
-        }
-    }
-    for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
-        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pn = r % NF2;
-        const int64_t e = e0 + el;
-        MixedLds<N> &l = L[el];
-        int32_t nb = -1, f2 = 0;
-        if (e < E) {
-            nb = G.link[e * 6 + f];
-            f2 = G.info[e * 6 + f] & 7;
-            l.db[0][f][pn] = B.dbg[((e * 6 + f) * 2 + 0) * NF2 + pn];
-            l.db[1][f][pn] = B.dbg[((e * 6 + f) * 2 + 1) * NF2 + pn];
-        }
-        for (int v = 0; v < 5; ++v) {
-            const int64_t gi = (((int64_t)nb * 6 + f2) * 5 + v) * NF2 + pn;
-            l.nb[v][f][pn] = (nb >= 0) ? TQ[gi] : 0.0f;
-            if (TV) l.nv[v][f][pn] = (nb >= 0) ? TV[gi] : 0.0f;
-        }
-    }
 }
 
 // BR1 common values at the 6 N^2 face points: perturbation (5) and
@@ -250,12 +320,11 @@ __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, 
         float pv[5];
         for (int v = 0; v < 5; ++v) pv[v] = face_val<N>(op, l.f[v], f, t1, t2);
         const float r0 = face_val<N>(op, l.f[F_R0], f, t1, t2), E0 = face_val<N>(op, l.f[F_E0], f, t1, t2);
-        const int32_t nb = G.link[e * 6 + f], inf = G.info[e * 6 + f];
+        const int32_t nb = l.lk[f], inf = l.inf[f];
         if (nb >= 0) {
-            const int pn = map_face_point<N>((inf >> 3) & 7, t1, t2);
-            for (int v = 0; v < 5; ++v) l.cs[v][f][pp] = 0.5f * (pv[v] + l.nb[v][f][pn]);
-            l.cs[F_R0][f][pp] = r0 + 0.5f * l.db[0][f][pp];
-            l.cs[F_E0][f][pp] = E0 + 0.5f * l.db[1][f][pp];
+            for (int v = 0; v < 5; ++v) l.cs[v][f][pp] = 0.5f * (pv[v] + l.nb[f][v][pp]);
+            l.cs[F_R0][f][pp] = r0 + 0.5f * l.db[f][0][pp];
+            l.cs[F_E0][f][pp] = E0 + 0.5f * l.db[f][1][pp];
         } else {
             // wall state in perturbation form: rho' kept, normal momentum
             // removed, pressure kept (outer wall with T_top: p = rho R T_top)
@@ -265,37 +334,39 @@ __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, 
             float S[3];
             for (int c = 0; c < 3; ++c) S[c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
             const float A2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
-            const float mn = (pv[1] * S[0] + pv[2] * S[1] + pv[3] * S[2]) / A2;
+            const float mn = (pv[1] * S[0] + pv[2] * S[1] + pv[3] * S[2]) * rcp(A2);
             float mb[3];
             for (int a = 0; a < 3; ++a) mb[a] = pv[1 + a] - mn * S[a];
-            const float rho = r0 + pv[0];
+            const float irho = rcp(r0 + pv[0]), igm1 = rcp(F.gm1);
             const float mm = pv[1] * pv[1] + pv[2] * pv[2] + pv[3] * pv[3];
             const float mbb = mb[0] * mb[0] + mb[1] * mb[1] + mb[2] * mb[2];
             float Eb;  // E_b - E0_b
-            if (outer && F.RT_top > 0.0f) Eb = F.RT_top * pv[0] / F.gm1 + 0.5f * mbb / rho;
-            else Eb = pv[4] - 0.5f * mm / rho + 0.5f * mbb / rho;
+            if (outer && F.RT_top > 0.0f) Eb = F.RT_top * pv[0] * igm1 + 0.5f * mbb * irho;
+            else Eb = pv[4] + 0.5f * (mbb - mm) * irho;
             l.cs[0][f][pp] = pv[0];
             for (int a = 0; a < 3; ++a) l.cs[1 + a][f][pp] = mb[a];
             l.cs[4][f][pp] = Eb;
             l.cs[F_R0][f][pp] = r0;
-            l.cs[F_E0][f][pp] = (outer && F.RT_top > 0.0f) ? r0 * F.RT_top / F.gm1 : E0;
+            l.cs[F_E0][f][pp] = (outer && F.RT_top > 0.0f) ? r0 * F.RT_top * igm1 : E0;
         }
     }
 }
 
 // gradients of the 7 fields at the solution points
 template <int N, int EPB, int NT>
-__device__ __forceinline__ void gradients(const OpsF<N> &op, const GeoF &G, int64_t e0, MixedLds<N> *L) {
+__device__ __forceinline__ void gradients(const OpsF<N> &op, const GeoF &G, int64_t e0, MixedLds<N> *L,
+                                          const float (*gsol)[13]) {
+    using Sh = Shape<N, EPB, NT>;
     constexpr int NP = N * N * N;
-    for (int it = threadIdx.x; it < EPB * NP; it += NT) {
+#pragma unroll
+    for (int k = 0; k < Sh::IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * NP) break;
         const int el = it / NP, p = it % NP;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
         MixedLds<N> &l = L[el];
-        const float *gs = G.solgeo + e * 13 * NP + p;
-        float Gm[9];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) Gm[t] = gs[t * NP];
+        const float *Gm = gsol[k];
         float dq[3][NFIELD];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -378,8 +449,10 @@ __global__ __launch_bounds__(NT) void k_pert_begin(OpsF<N> op, GeoF G, const dou
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
-        for (int v = 0; v < 5; ++v)
-            TQ[((e * 6 + f) * 5 + v) * NF2 + pp] = face_val<N>(op, sp[el][v], f, pp % N, pp / N);
+        const int32_t nb = G.link[e * 6 + f];
+        if (nb < 0) continue;
+        const int64_t slot = mailbox_slot<N>(nb, G.info[e * 6 + f], pp);
+        for (int v = 0; v < 5; ++v) TQ[slot + v * NF2] = face_val<N>(op, sp[el][v], f, pp % N, pp / N);
     }
 }
 
@@ -390,29 +463,46 @@ __global__ __launch_bounds__(NT) void k_grad_mixed(OpsF<N> op, GeoF G, MixedBufs
                                                    const double *__restrict__ Pq, const float *__restrict__ TQ,
                                                    float *__restrict__ TV) {
     constexpr int NF2 = N * N, NFL = (N + 1) * N * N;
+    using Sh = Shape<N, EPB, NT>;
     __shared__ MixedLds<N> L[EPB];
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     const PhysF F = physf_of(P);
-    load_element<N, EPB, NT>(Pq, B, G, TQ, nullptr, e0, L);
+    // face-point geometry of this thread's face items, loaded up front
+    float Sf[Sh::IT_FACE][3], gSf[Sh::IT_FACE];
+#pragma unroll
+    for (int k = 0; k < Sh::IT_FACE; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        const int64_t e = e0 + el;
+        const bool ok = it < EPB * 6 * NF2 && e < G.E;
+        const int d = f >> 1, fl = ((f & 1) ? N : 0) + (N + 1) * pp;
+        const float sg = (f & 1) ? 1.0f : -1.0f;
+        for (int c = 0; c < 3; ++c) Sf[k][c] = ok ? sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
+        gSf[k] = ok ? sg * B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
+    }
+    Prologue<N, EPB, NT> R;
+    prologue_load<N, EPB, NT>(Pq, B, G, TQ, nullptr, e0, R);
+    prologue_store<N, EPB, NT>(R, L);
     __syncthreads();
     common_values<N, EPB, NT>(op, G, F, e0, L);
     __syncthreads();
-    gradients<N, EPB, NT>(op, G, e0, L);
+    gradients<N, EPB, NT>(op, G, e0, L, R.gs);
     __syncthreads();
-    for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
+#pragma unroll
+    for (int k = 0; k < Sh::IT_FACE; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * 6 * NF2) break;
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
         const int64_t e = e0 + el;
-        if (e >= G.E || G.link[e * 6 + f] < 0) continue;
+        const int32_t nb = L[el].lk[f];
+        if (e >= G.E || nb < 0) continue;
         const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
-        const int fl = m + (N + 1) * (t1 + N * t2);
-        const float sg = (f & 1) ? 1.0f : -1.0f;
-        float S[3], fv[5];
-        for (int c = 0; c < 3; ++c) S[c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
-        const float gS0S = sg * B.gS0[(e * 3 + d) * NFL + fl];
-        PtState s;
-        state_at<N>(op, L[el], m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), s);
-        dflux_viscous(s, S, gS0S, F, 0, fv);
-        for (int v = 0; v < 5; ++v) TV[((e * 6 + f) * 5 + v) * NF2 + pp] = fv[v];
+        float fv[5];
+        PtState st;
+        state_at<N>(op, L[el], m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), st);
+        dflux_viscous(st, Sf[k], gSf[k], F, 0, fv);
+        const int64_t slot = mailbox_slot<N>(nb, L[el].inf[f], pp);
+        for (int v = 0; v < 5; ++v) TV[slot + v * NF2] = fv[v];
     }
 }
 
@@ -433,108 +523,148 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
     __shared__ MixedLds<N> L[EPB];
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     const PhysF F = physf_of(P);
-    // flux-point geometry of this thread's items, loaded up front
-    float Sv[Sh::IT_FLUX][3], gSv[Sh::IT_FLUX];
+    // geometry of this thread's interior flux points and interface points,
+    // loaded up front.  Interior item it: el, d, interior index a = 1..N-1,
+    // tangential t1, t2; interface item: el, face f, point pp.
+    constexpr int NINT = Sh::NINT;
+    float Si[Sh::IT_INT][3], gSi[Sh::IT_INT];
 #pragma unroll
-    for (int k = 0; k < Sh::IT_FLUX; ++k) {
+    for (int k = 0; k < Sh::IT_INT; ++k) {
         const int it = threadIdx.x + k * NT;
-        const int el = it / (3 * NFL), r = it % (3 * NFL), d = r / NFL, fl = r % NFL;
+        const int el = it / NINT, r = it % NINT, d = r / ((N - 1) * NF2), q = r % ((N - 1) * NF2);
+        const int fl = 1 + q % (N - 1) + (N + 1) * (q / (N - 1));
         const int64_t e = e0 + el;
-        const bool ok = it < EPB * 3 * NFL && e < G.E;
-        for (int c = 0; c < 3; ++c) Sv[k][c] = ok ? G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
-        gSv[k] = ok ? B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
+        const bool ok = it < EPB * NINT && e < G.E;
+        for (int c = 0; c < 3; ++c) Si[k][c] = ok ? G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
+        gSi[k] = ok ? B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
     }
-    load_element<N, EPB, NT>(Pq, B, G, TQ, TV, e0, L);
+    float Sf[Sh::IT_FACE][3], gSf[Sh::IT_FACE];
+#pragma unroll
+    for (int k = 0; k < Sh::IT_FACE; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        const int64_t e = e0 + el;
+        const bool ok = it < EPB * 6 * NF2 && e < G.E;
+        const int d = f >> 1, fl = ((f & 1) ? N : 0) + (N + 1) * pp;
+        const float sg = (f & 1) ? 1.0f : -1.0f;
+        for (int c = 0; c < 3; ++c) Sf[k][c] = ok ? sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
+        gSf[k] = ok ? sg * B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
+    }
+    Prologue<N, EPB, NT> R;
+    prologue_load<N, EPB, NT>(Pq, B, G, TQ, TV, e0, R);
+    double pn[Sh::IT_SOL][5];
+    float r0v[Sh::IT_SOL][5];
+#pragma unroll
+    for (int k = 0; k < Sh::IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const int el = it / NP, p = it % NP;
+        const int64_t e = e0 + el;
+        const bool ok = it < EPB * NP && e < G.E;
+        for (int v = 0; v < 5; ++v) {
+            const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
+            r0v[k][v] = ok ? B.R0[gi] : 0.0f;
+            pn[k][v] = (ok && S_.mode != 0 && S_.ca != 0.0) ? S_.Pn[gi] : 0.0;
+        }
+    }
+    prologue_store<N, EPB, NT>(R, L);
     __syncthreads();
     common_values<N, EPB, NT>(op, G, F, e0, L);
     __syncthreads();
-    gradients<N, EPB, NT>(op, G, e0, L);
+    gradients<N, EPB, NT>(op, G, e0, L, R.gs);
     __syncthreads();
+    // transformed perturbation flux at the interior flux points
 #pragma unroll
-    for (int k = 0; k < Sh::IT_FLUX; ++k) {
+    for (int k = 0; k < Sh::IT_INT; ++k) {
         const int it = threadIdx.x + k * NT;
-        if (it >= EPB * 3 * NFL) break;
-        const int el = it / (3 * NFL), r = it % (3 * NFL), d = r / NFL, fl = r % NFL;
-        const int64_t e = e0 + el;
-        if (e >= G.E) continue;
+        if (it >= EPB * NINT) break;
+        const int el = it / NINT, r = it % NINT, d = r / ((N - 1) * NF2), q = r % ((N - 1) * NF2);
+        const int m = 1 + q % (N - 1), tt = q / (N - 1), t1 = tt % N, t2 = tt / N;
+        if (e0 + el >= G.E) continue;
         MixedLds<N> &l = L[el];
-        const int m = fl % (N + 1), t1 = (fl / (N + 1)) % N, t2 = fl / ((N + 1) * N);
-        const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
         PtState s;
-        state_at<N>(op, l, m, base, st, s);
-        float Fo[5];
-        if (m > 0 && m < N) {
-            float fi[5], fv[5];
-            dflux_inviscid(s, Sv[k], F, fi);
-            dflux_viscous(s, Sv[k], gSv[k], F, 0, fv);
-            for (int v = 0; v < 5; ++v) Fo[v] = fi[v] - fv[v];
+        state_at<N>(op, l, m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), s);
+        float fi[5], fv[5];
+        dflux_inviscid(s, Si[k], F, fi);
+        dflux_viscous(s, Si[k], gSi[k], F, 0, fv);
+        const int fl = m + (N + 1) * tt;
+        for (int v = 0; v < 5; ++v) l.ft[d][v][fl] = fi[v] - fv[v];
+    }
+    // common fluxes at the interface points (outward area vector So)
+#pragma unroll
+    for (int k = 0; k < Sh::IT_FACE; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * 6 * NF2) break;
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        if (e0 + el >= G.E) continue;
+        MixedLds<N> &l = L[el];
+        const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
+        const float sg = (f & 1) ? 1.0f : -1.0f;
+        const float *So = Sf[k];
+        const float gS0S = gSf[k];
+        PtState s;
+        state_at<N>(op, l, m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), s);
+        const int32_t nb = l.lk[f], inf = l.inf[f];
+        float phi[5];
+        if (nb >= 0) {
+            // neighbour state from its perturbation trace and the background jump
+            PtState r = s;
+            r.rp = l.nb[f][0][pp];
+            r.m[0] = l.nb[f][1][pp];
+            r.m[1] = l.nb[f][2][pp];
+            r.m[2] = l.nb[f][3][pp];
+            r.Ep = l.nb[f][4][pp];
+            const float dr0 = l.db[f][0][pp], dE0 = l.db[f][1][pp];
+            r.r0 = s.r0 + dr0;
+            r.E0 = s.E0 + dE0;
+            float fL[5], fR[5], fvL[5];
+            dflux_inviscid(s, So, F, fL);
+            dflux_inviscid(r, So, F, fR);
+            const float A = sqrtf(So[0] * So[0] + So[1] * So[1] + So[2] * So[2]), iA = rcp(A);
+            // |u.n| + (c - c0) on each side; c^2 - c0^2 = gamma (p' rho0 - p0 rho') / (rho rho0)
+            auto excess = [&](const PtState &q, float &c0) {
+                const float inv = rcp(q.r0 + q.rp), ir0 = rcp(q.r0);
+                const float un = fabsf((q.m[0] * So[0] + q.m[1] * So[1] + q.m[2] * So[2]) * iA * inv);
+                const float mm = q.m[0] * q.m[0] + q.m[1] * q.m[1] + q.m[2] * q.m[2];
+                const float pp_ = F.gm1 * (q.Ep - 0.5f * mm * inv), p0 = F.gm1 * q.E0;
+                c0 = sqrtf(F.gam * p0 * ir0);
+                const float dc2 = F.gam * (pp_ * q.r0 - p0 * q.rp) * inv * ir0;
+                const float c = sqrtf(c0 * c0 + dc2);
+                return un + dc2 * rcp(c + c0);
+            };
+            float c0L, c0R;
+            const float eL = excess(s, c0L), eR = excess(r, c0R);
+            // background sound-speed jump c0R - c0L from the FP64 background jump
+            const float dc0 = F.gam * F.gm1 * (dE0 * s.r0 - s.E0 * dr0) * rcp(s.r0 * r.r0 * (c0L + c0R));
+            const float dlam = fmaxf(eL, eR + dc0) - fmaxf(0.0f, dc0);
+            const float lam0 = c0L + fmaxf(0.0f, dc0);
+            const float hl = 0.5f * (lam0 + dlam) * A, hd = 0.5f * dlam * A;
+            const float pR[5] = {r.rp, r.m[0], r.m[1], r.m[2], r.Ep};
+            const float pL[5] = {s.rp, s.m[0], s.m[1], s.m[2], s.Ep};
+            const float dq0[5] = {dr0, 0.0f, 0.0f, 0.0f, dE0};
+            for (int v = 0; v < 5; ++v) phi[v] = 0.5f * (fL[v] + fR[v]) - hl * (pR[v] - pL[v]) - hd * dq0[v];
+            dflux_viscous(s, So, gS0S, F, 0, fvL);
+            // the neighbour stored its flux along its own outward vector (-So)
+            for (int v = 0; v < 5; ++v) phi[v] -= 0.5f * (fvL[v] + (-l.nv[f][v][pp]));
         } else {
-            const int f = 2 * d + (m == N ? 1 : 0);
-            const float sg = (m == N) ? 1.0f : -1.0f;
-            const float So[3] = {sg * Sv[k][0], sg * Sv[k][1], sg * Sv[k][2]};
-            const float gS0S = sg * gSv[k];
-            const int32_t nb = G.link[e * 6 + f], inf = G.info[e * 6 + f];
-            float phi[5];
-            if (nb >= 0) {
-                const int pp = t1 + N * t2, pn = map_face_point<N>((inf >> 3) & 7, t1, t2);
-                // neighbour state from its perturbation trace and the background jump
-                PtState r = s;
-                r.rp = l.nb[0][f][pn];
-                r.m[0] = l.nb[1][f][pn];
-                r.m[1] = l.nb[2][f][pn];
-                r.m[2] = l.nb[3][f][pn];
-                r.Ep = l.nb[4][f][pn];
-                const float dr0 = l.db[0][f][pp], dE0 = l.db[1][f][pp];
-                r.r0 = s.r0 + dr0;
-                r.E0 = s.E0 + dE0;
-                float fL[5], fR[5], fvL[5];
-                dflux_inviscid(s, So, F, fL);
-                dflux_inviscid(r, So, F, fR);
-                const float A = sqrtf(So[0] * So[0] + So[1] * So[1] + So[2] * So[2]), iA = 1.0f / A;
-                // |u.n| + (c - c0) on each side; c^2 - c0^2 = gamma (p' rho0 - p0 rho') / (rho rho0)
-                auto excess = [&](const PtState &q) {
-                    const float rho = q.r0 + q.rp, inv = 1.0f / rho;
-                    const float un = fabsf((q.m[0] * So[0] + q.m[1] * So[1] + q.m[2] * So[2]) * iA * inv);
-                    const float mm = q.m[0] * q.m[0] + q.m[1] * q.m[1] + q.m[2] * q.m[2];
-                    const float pp_ = F.gm1 * (q.Ep - 0.5f * mm * inv), p0 = F.gm1 * q.E0;
-                    const float c0 = sqrtf(F.gam * p0 / q.r0);
-                    const float dc2 = F.gam * (pp_ * q.r0 - p0 * q.rp) / (rho * q.r0);
-                    const float c = sqrtf(c0 * c0 + dc2);
-                    return un + dc2 / (c + c0);
-                };
-                const float eL = excess(s), eR = excess(r);
-                const float c0L = sqrtf(F.gam * F.gm1 * s.E0 / s.r0), c0R = sqrtf(F.gam * F.gm1 * r.E0 / r.r0);
-                // background sound-speed jump c0R - c0L from the FP64 background jump
-                const float dc0 = F.gam * F.gm1 * (dE0 * s.r0 - s.E0 * dr0) / (s.r0 * r.r0 * (c0L + c0R));
-                const float dlam = fmaxf(eL, eR + dc0) - fmaxf(0.0f, dc0);
-                const float lam0 = c0L + fmaxf(0.0f, dc0);
-                const float hl = 0.5f * (lam0 + dlam) * A, hd = 0.5f * dlam * A;
-                const float pR[5] = {r.rp, r.m[0], r.m[1], r.m[2], r.Ep};
-                const float pL[5] = {s.rp, s.m[0], s.m[1], s.m[2], s.Ep};
-                const float dq0[5] = {dr0, 0.0f, 0.0f, 0.0f, dE0};
-                for (int v = 0; v < 5; ++v) phi[v] = 0.5f * (fL[v] + fR[v]) - hl * (pR[v] - pL[v]) - hd * dq0[v];
-                dflux_viscous(s, So, gS0S, F, 0, fvL);
-                // the neighbour stored its flux along its own outward vector (-So)
-                for (int v = 0; v < 5; ++v) phi[v] -= 0.5f * (fvL[v] + (-l.nv[v][f][pn]));
-            } else {
-                // wall: inviscid (0, p' S, 0); viscous wall form
-                const bool outer = ((inf >> 6) - 1) == CHORUS_BC_OUTER;
-                const float rho = s.r0 + s.rp;
-                const float mm = s.m[0] * s.m[0] + s.m[1] * s.m[1] + s.m[2] * s.m[2];
-                const float pp = F.gm1 * (s.Ep - 0.5f * mm / rho);
-                float fv[5];
-                dflux_viscous(s, So, gS0S, F, outer ? 2 : 1, fv);
-                phi[0] = 0.0f;
-                for (int a = 0; a < 3; ++a) phi[1 + a] = pp * So[a] - fv[1 + a];
-                phi[4] = -fv[4];
-            }
-            for (int v = 0; v < 5; ++v) Fo[v] = sg * phi[v];
+            // wall: inviscid (0, p' S, 0); viscous wall form
+            const bool outer = ((inf >> 6) - 1) == CHORUS_BC_OUTER;
+            const float mm = s.m[0] * s.m[0] + s.m[1] * s.m[1] + s.m[2] * s.m[2];
+            const float pp = F.gm1 * (s.Ep - 0.5f * mm * rcp(s.r0 + s.rp));
+            float fv[5];
+            dflux_viscous(s, So, gS0S, F, outer ? 2 : 1, fv);
+            phi[0] = 0.0f;
+            for (int a = 0; a < 3; ++a) phi[1 + a] = pp * So[a] - fv[1 + a];
+            phi[4] = -fv[4];
         }
-        for (int v = 0; v < 5; ++v) l.ft[d][v][fl] = Fo[v];
+        const int fl = m + (N + 1) * pp;
+        for (int v = 0; v < 5; ++v) l.ft[d][v][fl] = sg * phi[v];
     }
     __syncthreads();
     // divergence, source, background residual and stage update
-    for (int it = threadIdx.x; it < EPB * NP; it += NT) {
+#pragma unroll
+    for (int k = 0; k < Sh::IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * NP) break;
         const int el = it / NP, p = it % NP;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
@@ -553,9 +683,8 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
                 div[v] += s;
             }
         }
-        const float *gs = G.solgeo + e * 13 * NP + p;
-        const float iJ = gs[9 * NP];
-        const float g0 = F.GM * gs[10 * NP], g1 = F.GM * gs[11 * NP], g2 = F.GM * gs[12 * NP];
+        const float iJ = R.gs[k][9];
+        const float g0 = F.GM * R.gs[k][10], g1 = F.GM * R.gs[k][11], g2 = F.GM * R.gs[k][12];
         const float rp = l.f[F_RP][p], mx = l.f[F_MX][p], my = l.f[F_MY][p], mz = l.f[F_MZ][p];
         float M[5];
         M[0] = 0.0f;
@@ -566,12 +695,11 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
         float newp[5];
         for (int v = 0; v < 5; ++v) {
             const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
-            const double R = (double)B.R0[gi] + (double)(-div[v] * iJ - M[v]);
+            const double Rv = (double)r0v[k][v] + (double)(-div[v] * iJ - M[v]);
             if (S_.mode == 0) {
-                S_.Pout[gi] = R;
+                S_.Pout[gi] = Rv;
             } else {
-                const double pn = (S_.ca != 0.0) ? S_.Pn[gi] : 0.0;
-                const double pv = S_.ca * pn + S_.cb * (Pq[gi] + S_.dt * R);
+                const double pv = S_.ca * pn[k][v] + S_.cb * (R.P[k][v] + S_.dt * Rv);
                 S_.Pout[gi] = pv;
                 newp[v] = (float)pv;
             }
@@ -584,8 +712,9 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
     for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
         const int64_t e = e0 + el;
-        if (e >= G.E) continue;
-        float *out = S_.TQout + (e * 6 + f) * 5 * NF2 + pp;
+        const int32_t nb = L[el].lk[f];
+        if (e >= G.E || nb < 0) continue;
+        float *out = S_.TQout + mailbox_slot<N>(nb, L[el].inf[f], pp);
         for (int v = 0; v < 5; ++v) out[v * NF2] = face_val<N>(op, L[el].f[v], f, pp % N, pp / N);
     }
 }
