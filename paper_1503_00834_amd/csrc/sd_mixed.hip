@@ -176,11 +176,10 @@ struct MixedLds {
     static constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
     float f[NFIELD][NP];          // perturbation + background fields
     float g[NGRAD][NP];           // gradients
-    float cs[NFIELD][6][NF2];     // common values (perturbation 0..4, background 5..6)
-    float nb[6][5][NF2];          // neighbour perturbation traces at own face points
-    float nv[6][5][NF2];          // neighbour viscous traces at own face points (k_resid)
-    float db[6][2][NF2];          // background jump (neighbour - own), rho and E
-    float ft[3][5][NFL];          // transformed flux (k_resid only)
+    union {
+        float cs[NFIELD][6][NF2];  // common values (perturbation 0..4, background 5..6)
+        float ft[3][5][NFL];       // transformed flux, written after cs is consumed
+    } u;
     int32_t lk[6], inf[6];        // neighbour element and info word per face
 };
 
@@ -193,9 +192,7 @@ struct Shape {
     static constexpr int NINT = 3 * (N - 1) * N * N;  // interior flux points per element
     static constexpr int IT_INT = (EPB * NINT + NT - 1) / NT;
     static constexpr int MB = 6 * 5 * NF2;             // mailbox floats per element
-    static constexpr int IT_MB = (EPB * MB + NT - 1) / NT;
     static constexpr int DB = 6 * 2 * NF2;
-    static constexpr int IT_DB = (EPB * DB + NT - 1) / NT;
 };
 
 // registers holding one thread's share of an element block's global inputs;
@@ -206,8 +203,10 @@ struct Prologue {
     using Sh = Shape<N, EPB, NT>;
     double P[Sh::IT_SOL][5];
     float bg[Sh::IT_SOL][2];
-    float gs[Sh::IT_SOL][13];
-    float mq[Sh::IT_MB], mv[Sh::IT_MB], db[Sh::IT_DB];
+    float gs[Sh::IT_SOL][9];
+    // neighbour data at this thread's face items (face item it: el, f, pp):
+    // perturbation trace, viscous trace, background jump
+    float nq[Sh::IT_FACE][5], nv[Sh::IT_FACE][5], db[Sh::IT_FACE][2];
     int32_t lk, inf;
 };
 
@@ -218,7 +217,7 @@ __device__ __forceinline__ void prologue_load(const double *Pq, const MixedBufs 
                                               const float *__restrict__ TQ, const float *__restrict__ TV,
                                               int64_t e0, Prologue<N, EPB, NT> &R) {
     using Sh = Shape<N, EPB, NT>;
-    constexpr int NP = Sh::NP;
+    constexpr int NP = Sh::NP, NF2 = Sh::NF2;
     const int64_t E = G.E;
     const int64_t nel = (E - e0 < EPB) ? (E - e0) : EPB;
 #pragma unroll
@@ -230,19 +229,20 @@ __device__ __forceinline__ void prologue_load(const double *Pq, const MixedBufs 
         for (int v = 0; v < 5; ++v) R.P[k][v] = ok ? Pq[((int64_t)v * E + e) * NP + p] : 0.0;
         R.bg[k][0] = ok ? B.bg[(e * 2 + 0) * NP + p] : 1.0f;
         R.bg[k][1] = ok ? B.bg[(e * 2 + 1) * NP + p] : 1.0f;
-        for (int t = 0; t < 13; ++t) R.gs[k][t] = ok ? G.solgeo[(e * 13 + t) * NP + p] : 1.0f;
+        for (int t = 0; t < 9; ++t) R.gs[k][t] = ok ? G.solgeo[(e * 13 + t) * NP + p] : 1.0f;
     }
 #pragma unroll
-    for (int k = 0; k < Sh::IT_MB; ++k) {
+    for (int k = 0; k < Sh::IT_FACE; ++k) {
         const int it = threadIdx.x + k * NT;
-        const bool ok = it < nel * Sh::MB;
-        R.mq[k] = ok ? TQ[e0 * Sh::MB + it] : 0.0f;
-        R.mv[k] = (ok && TV) ? TV[e0 * Sh::MB + it] : 0.0f;
-    }
-#pragma unroll
-    for (int k = 0; k < Sh::IT_DB; ++k) {
-        const int it = threadIdx.x + k * NT;
-        R.db[k] = (it < nel * Sh::DB) ? B.dbg[e0 * Sh::DB + it] : 0.0f;
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        const bool ok = it < EPB * 6 * NF2 && el < nel;
+        const int64_t base = (e0 + el) * 6 + f;
+        for (int v = 0; v < 5; ++v) {
+            R.nq[k][v] = ok ? TQ[(base * 5 + v) * NF2 + pp] : 0.0f;
+            R.nv[k][v] = (ok && TV) ? TV[(base * 5 + v) * NF2 + pp] : 0.0f;
+        }
+        R.db[k][0] = ok ? B.dbg[(base * 2 + 0) * NF2 + pp] : 0.0f;
+        R.db[k][1] = ok ? B.dbg[(base * 2 + 1) * NF2 + pp] : 0.0f;
     }
     const int it = threadIdx.x;
     const bool okl = it < EPB * 6 && e0 + it / 6 < E;
@@ -263,19 +263,6 @@ __device__ __forceinline__ void prologue_store(const Prologue<N, EPB, NT> &R, Mi
         for (int v = 0; v < 5; ++v) L[el].f[v][p] = (float)R.P[k][v];
         L[el].f[F_R0][p] = R.bg[k][0];
         L[el].f[F_E0][p] = R.bg[k][1];
-    }
-#pragma unroll
-    for (int k = 0; k < Sh::IT_MB; ++k) {
-        const int it = threadIdx.x + k * NT;
-        if (it >= EPB * Sh::MB) break;
-        (&L[it / Sh::MB].nb[0][0][0])[it % Sh::MB] = R.mq[k];
-        (&L[it / Sh::MB].nv[0][0][0])[it % Sh::MB] = R.mv[k];
-    }
-#pragma unroll
-    for (int k = 0; k < Sh::IT_DB; ++k) {
-        const int it = threadIdx.x + k * NT;
-        if (it >= EPB * Sh::DB) break;
-        (&L[it / Sh::DB].db[0][0][0])[it % Sh::DB] = R.db[k];
     }
     if ((int)threadIdx.x < EPB * 6) {
         L[threadIdx.x / 6].lk[threadIdx.x % 6] = R.lk;
@@ -309,9 +296,13 @@ __device__ __forceinline__ float face_val(const OpsF<N> &op, const float *fld, i
 // background (rho0, E0)
 template <int N, int EPB, int NT>
 __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, const PhysF &F, int64_t e0,
-                                              MixedLds<N> *L) {
+                                              MixedLds<N> *L, const Prologue<N, EPB, NT> &R) {
+    using Sh = Shape<N, EPB, NT>;
     constexpr int NF2 = N * N, NFL = (N + 1) * N * N;
-    for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
+#pragma unroll
+    for (int k = 0; k < Sh::IT_FACE; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * 6 * NF2) break;
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
@@ -322,9 +313,9 @@ __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, 
         const float r0 = face_val<N>(op, l.f[F_R0], f, t1, t2), E0 = face_val<N>(op, l.f[F_E0], f, t1, t2);
         const int32_t nb = l.lk[f], inf = l.inf[f];
         if (nb >= 0) {
-            for (int v = 0; v < 5; ++v) l.cs[v][f][pp] = 0.5f * (pv[v] + l.nb[f][v][pp]);
-            l.cs[F_R0][f][pp] = r0 + 0.5f * l.db[f][0][pp];
-            l.cs[F_E0][f][pp] = E0 + 0.5f * l.db[f][1][pp];
+            for (int v = 0; v < 5; ++v) l.u.cs[v][f][pp] = 0.5f * (pv[v] + R.nq[k][v]);
+            l.u.cs[F_R0][f][pp] = r0 + 0.5f * R.db[k][0];
+            l.u.cs[F_E0][f][pp] = E0 + 0.5f * R.db[k][1];
         } else {
             // wall state in perturbation form: rho' kept, normal momentum
             // removed, pressure kept (outer wall with T_top: p = rho R T_top)
@@ -343,11 +334,11 @@ __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, 
             float Eb;  // E_b - E0_b
             if (outer && F.RT_top > 0.0f) Eb = F.RT_top * pv[0] * igm1 + 0.5f * mbb * irho;
             else Eb = pv[4] + 0.5f * (mbb - mm) * irho;
-            l.cs[0][f][pp] = pv[0];
-            for (int a = 0; a < 3; ++a) l.cs[1 + a][f][pp] = mb[a];
-            l.cs[4][f][pp] = Eb;
-            l.cs[F_R0][f][pp] = r0;
-            l.cs[F_E0][f][pp] = (outer && F.RT_top > 0.0f) ? r0 * F.RT_top * igm1 : E0;
+            l.u.cs[0][f][pp] = pv[0];
+            for (int a = 0; a < 3; ++a) l.u.cs[1 + a][f][pp] = mb[a];
+            l.u.cs[4][f][pp] = Eb;
+            l.u.cs[F_R0][f][pp] = r0;
+            l.u.cs[F_E0][f][pp] = (outer && F.RT_top > 0.0f) ? r0 * F.RT_top * igm1 : E0;
         }
     }
 }
@@ -355,7 +346,7 @@ __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, 
 // gradients of the 7 fields at the solution points
 template <int N, int EPB, int NT>
 __device__ __forceinline__ void gradients(const OpsF<N> &op, const GeoF &G, int64_t e0, MixedLds<N> *L,
-                                          const float (*gsol)[13]) {
+                                          const float (*gsol)[9]) {
     using Sh = Shape<N, EPB, NT>;
     constexpr int NP = N * N * N;
 #pragma unroll
@@ -375,7 +366,7 @@ __device__ __forceinline__ void gradients(const OpsF<N> &op, const GeoF &G, int6
             const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d), pp = t1 + N * t2;
 #pragma unroll
             for (int v = 0; v < NFIELD; ++v) {
-                float s = op.D[a][0] * l.cs[v][2 * d][pp] + op.D[a][N] * l.cs[v][2 * d + 1][pp];
+                float s = op.D[a][0] * l.u.cs[v][2 * d][pp] + op.D[a][N] * l.u.cs[v][2 * d + 1][pp];
 #pragma unroll
                 for (int b = 0; b < N; ++b) s += op.B[a][b] * l.f[v][base + b * st];
                 dq[d][v] = s;
@@ -484,7 +475,7 @@ __global__ __launch_bounds__(NT) void k_grad_mixed(OpsF<N> op, GeoF G, MixedBufs
     prologue_load<N, EPB, NT>(Pq, B, G, TQ, nullptr, e0, R);
     prologue_store<N, EPB, NT>(R, L);
     __syncthreads();
-    common_values<N, EPB, NT>(op, G, F, e0, L);
+    common_values<N, EPB, NT>(op, G, F, e0, L, R);
     __syncthreads();
     gradients<N, EPB, NT>(op, G, e0, L, R.gs);
     __syncthreads();
@@ -514,31 +505,24 @@ struct MixedStage {
     int mode;          // 0 residual (R0 + dR), 1 RK stage
 };
 
+// per-thread inputs of one element block for the residual pass
 template <int N, int EPB, int NT>
-__global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBufs B, PhysParams P, const double *Pq,
-                                                    const float *__restrict__ TQ, const float *__restrict__ TV,
-                                                    MixedStage S_) {
+struct ResidIn {
     using Sh = Shape<N, EPB, NT>;
-    constexpr int NP = Sh::NP, NF2 = Sh::NF2, NFL = Sh::NFL;
-    __shared__ MixedLds<N> L[EPB];
-    const int64_t e0 = (int64_t)blockIdx.x * EPB;
-    const PhysF F = physf_of(P);
-    // geometry of this thread's interior flux points and interface points,
-    // loaded up front.  Interior item it: el, d, interior index a = 1..N-1,
-    // tangential t1, t2; interface item: el, face f, point pp.
-    constexpr int NINT = Sh::NINT;
+    Prologue<N, EPB, NT> R;
     float Si[Sh::IT_INT][3], gSi[Sh::IT_INT];
-#pragma unroll
-    for (int k = 0; k < Sh::IT_INT; ++k) {
-        const int it = threadIdx.x + k * NT;
-        const int el = it / NINT, r = it % NINT, d = r / ((N - 1) * NF2), q = r % ((N - 1) * NF2);
-        const int fl = 1 + q % (N - 1) + (N + 1) * (q / (N - 1));
-        const int64_t e = e0 + el;
-        const bool ok = it < EPB * NINT && e < G.E;
-        for (int c = 0; c < 3; ++c) Si[k][c] = ok ? G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
-        gSi[k] = ok ? B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
-    }
     float Sf[Sh::IT_FACE][3], gSf[Sh::IT_FACE];
+};
+
+// issue every global load of the element block starting at e0.  Interior
+// flux item it: el, d, interior index a = 1..N-1, tangential t1, t2;
+// interface item: el, face f, point pp.
+template <int N, int EPB, int NT>
+__device__ __forceinline__ void resid_load(const GeoF &G, const MixedBufs &B, const double *Pq,
+                                           const float *__restrict__ TQ, const float *__restrict__ TV,
+                                           const MixedStage &S_, int64_t e0, ResidIn<N, EPB, NT> &In) {
+    using Sh = Shape<N, EPB, NT>;
+    constexpr int NP = Sh::NP, NF2 = Sh::NF2, NFL = Sh::NFL, NINT = Sh::NINT;
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
         const int it = threadIdx.x + k * NT;
@@ -547,28 +531,32 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
         const bool ok = it < EPB * 6 * NF2 && e < G.E;
         const int d = f >> 1, fl = ((f & 1) ? N : 0) + (N + 1) * pp;
         const float sg = (f & 1) ? 1.0f : -1.0f;
-        for (int c = 0; c < 3; ++c) Sf[k][c] = ok ? sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
-        gSf[k] = ok ? sg * B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
+        for (int c = 0; c < 3; ++c) In.Sf[k][c] = ok ? sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
+        In.gSf[k] = ok ? sg * B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
     }
-    Prologue<N, EPB, NT> R;
-    prologue_load<N, EPB, NT>(Pq, B, G, TQ, TV, e0, R);
-    double pn[Sh::IT_SOL][5];
-    float r0v[Sh::IT_SOL][5];
 #pragma unroll
-    for (int k = 0; k < Sh::IT_SOL; ++k) {
+    for (int k = 0; k < Sh::IT_INT; ++k) {
         const int it = threadIdx.x + k * NT;
-        const int el = it / NP, p = it % NP;
+        const int el = it / NINT, r = it % NINT, d = r / ((N - 1) * NF2), q = r % ((N - 1) * NF2);
+        const int fl = 1 + q % (N - 1) + (N + 1) * (q / (N - 1));
         const int64_t e = e0 + el;
-        const bool ok = it < EPB * NP && e < G.E;
-        for (int v = 0; v < 5; ++v) {
-            const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
-            r0v[k][v] = ok ? B.R0[gi] : 0.0f;
-            pn[k][v] = (ok && S_.mode != 0 && S_.ca != 0.0) ? S_.Pn[gi] : 0.0;
-        }
+        const bool ok = it < EPB * NINT && e < G.E;
+        for (int c = 0; c < 3; ++c) In.Si[k][c] = ok ? G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
+        In.gSi[k] = ok ? B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
     }
-    prologue_store<N, EPB, NT>(R, L);
-    __syncthreads();
-    common_values<N, EPB, NT>(op, G, F, e0, L);
+    prologue_load<N, EPB, NT>(Pq, B, G, TQ, TV, e0, In.R);
+}
+
+// the residual pass of one element block from its loaded inputs (the block
+// LDS holds this element block's fields on entry)
+template <int N, int EPB, int NT>
+__device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, const MixedBufs &B, const double *Pq,
+                                              const PhysF &F, const MixedStage &S_, int64_t e0,
+                                              const ResidIn<N, EPB, NT> &In, MixedLds<N> *L) {
+    using Sh = Shape<N, EPB, NT>;
+    constexpr int NP = Sh::NP, NF2 = Sh::NF2, NINT = Sh::NINT;
+    const Prologue<N, EPB, NT> &R = In.R;
+    common_values<N, EPB, NT>(op, G, F, e0, L, R);
     __syncthreads();
     gradients<N, EPB, NT>(op, G, e0, L, R.gs);
     __syncthreads();
@@ -584,10 +572,10 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
         PtState s;
         state_at<N>(op, l, m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), s);
         float fi[5], fv[5];
-        dflux_inviscid(s, Si[k], F, fi);
-        dflux_viscous(s, Si[k], gSi[k], F, 0, fv);
+        dflux_inviscid(s, In.Si[k], F, fi);
+        dflux_viscous(s, In.Si[k], In.gSi[k], F, 0, fv);
         const int fl = m + (N + 1) * tt;
-        for (int v = 0; v < 5; ++v) l.ft[d][v][fl] = fi[v] - fv[v];
+        for (int v = 0; v < 5; ++v) l.u.ft[d][v][fl] = fi[v] - fv[v];
     }
     // common fluxes at the interface points (outward area vector So)
 #pragma unroll
@@ -599,8 +587,8 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
         MixedLds<N> &l = L[el];
         const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
         const float sg = (f & 1) ? 1.0f : -1.0f;
-        const float *So = Sf[k];
-        const float gS0S = gSf[k];
+        const float *So = In.Sf[k];
+        const float gS0S = In.gSf[k];
         PtState s;
         state_at<N>(op, l, m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), s);
         const int32_t nb = l.lk[f], inf = l.inf[f];
@@ -608,12 +596,12 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
         if (nb >= 0) {
             // neighbour state from its perturbation trace and the background jump
             PtState r = s;
-            r.rp = l.nb[f][0][pp];
-            r.m[0] = l.nb[f][1][pp];
-            r.m[1] = l.nb[f][2][pp];
-            r.m[2] = l.nb[f][3][pp];
-            r.Ep = l.nb[f][4][pp];
-            const float dr0 = l.db[f][0][pp], dE0 = l.db[f][1][pp];
+            r.rp = R.nq[k][0];
+            r.m[0] = R.nq[k][1];
+            r.m[1] = R.nq[k][2];
+            r.m[2] = R.nq[k][3];
+            r.Ep = R.nq[k][4];
+            const float dr0 = R.db[k][0], dE0 = R.db[k][1];
             r.r0 = s.r0 + dr0;
             r.E0 = s.E0 + dE0;
             float fL[5], fR[5], fvL[5];
@@ -644,7 +632,7 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
             for (int v = 0; v < 5; ++v) phi[v] = 0.5f * (fL[v] + fR[v]) - hl * (pR[v] - pL[v]) - hd * dq0[v];
             dflux_viscous(s, So, gS0S, F, 0, fvL);
             // the neighbour stored its flux along its own outward vector (-So)
-            for (int v = 0; v < 5; ++v) phi[v] -= 0.5f * (fvL[v] + (-l.nv[f][v][pp]));
+            for (int v = 0; v < 5; ++v) phi[v] -= 0.5f * (fvL[v] + (-R.nv[k][v]));
         } else {
             // wall: inviscid (0, p' S, 0); viscous wall form
             const bool outer = ((inf >> 6) - 1) == CHORUS_BC_OUTER;
@@ -657,7 +645,7 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
             phi[4] = -fv[4];
         }
         const int fl = m + (N + 1) * pp;
-        for (int v = 0; v < 5; ++v) l.ft[d][v][fl] = sg * phi[v];
+        for (int v = 0; v < 5; ++v) l.u.ft[d][v][fl] = sg * phi[v];
     }
     __syncthreads();
     // divergence, source, background residual and stage update
@@ -679,12 +667,22 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
             for (int v = 0; v < 5; ++v) {
                 float s = 0.0f;
 #pragma unroll
-                for (int mm = 0; mm <= N; ++mm) s += op.D[a][mm] * l.ft[d][v][fb + mm];
+                for (int mm = 0; mm <= N; ++mm) s += op.D[a][mm] * l.u.ft[d][v][fb + mm];
                 div[v] += s;
             }
         }
-        const float iJ = R.gs[k][9];
-        const float g0 = F.GM * R.gs[k][10], g1 = F.GM * R.gs[k][11], g2 = F.GM * R.gs[k][12];
+        // stage-update operands, loaded here rather than held through the flux phase
+        const float *gsp = G.solgeo + e * 13 * NP + p;
+        const float iJ = gsp[9 * NP];
+        const float g0 = F.GM * gsp[10 * NP], g1 = F.GM * gsp[11 * NP], g2 = F.GM * gsp[12 * NP];
+        double pin[5], pst[5];
+        float r0s[5];
+        for (int v = 0; v < 5; ++v) {
+            const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
+            r0s[v] = B.R0[gi];
+            pin[v] = Pq[gi];
+            pst[v] = (S_.mode != 0 && S_.ca != 0.0) ? S_.Pn[gi] : 0.0;
+        }
         const float rp = l.f[F_RP][p], mx = l.f[F_MX][p], my = l.f[F_MY][p], mz = l.f[F_MZ][p];
         float M[5];
         M[0] = 0.0f;
@@ -695,11 +693,11 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
         float newp[5];
         for (int v = 0; v < 5; ++v) {
             const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
-            const double Rv = (double)r0v[k][v] + (double)(-div[v] * iJ - M[v]);
+            const double Rv = (double)r0s[v] + (double)(-div[v] * iJ - M[v]);
             if (S_.mode == 0) {
                 S_.Pout[gi] = Rv;
             } else {
-                const double pv = S_.ca * pn[k][v] + S_.cb * (R.P[k][v] + S_.dt * Rv);
+                const double pv = S_.ca * pst[v] + S_.cb * (pin[v] + S_.dt * Rv);
                 S_.Pout[gi] = pv;
                 newp[v] = (float)pv;
             }
@@ -716,6 +714,32 @@ __global__ __launch_bounds__(NT) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBuf
         if (e >= G.E || nb < 0) continue;
         float *out = S_.TQout + mailbox_slot<N>(nb, L[el].inf[f], pp);
         for (int v = 0; v < 5; ++v) out[v * NF2] = face_val<N>(op, L[el].f[v], f, pp % N, pp / N);
+    }
+}
+
+
+// one block processes K consecutive element blocks, loading the next block's
+// inputs while it computes the current one
+template <int N, int EPB, int NT, int K, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBufs B, PhysParams P, const double *Pq,
+                                                    const float *__restrict__ TQ, const float *__restrict__ TV,
+                                                    MixedStage S_) {
+    __shared__ MixedLds<N> L[EPB];
+    const PhysF F = physf_of(P);
+    const int64_t eb = (int64_t)blockIdx.x * EPB * K;
+    ResidIn<N, EPB, NT> cur;
+    resid_load<N, EPB, NT>(G, B, Pq, TQ, TV, S_, eb, cur);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int64_t e0 = eb + (int64_t)j * EPB;
+        if (e0 >= G.E) break;
+        prologue_store<N, EPB, NT>(cur.R, L);
+        __syncthreads();
+        ResidIn<N, EPB, NT> nxt;
+        if (j + 1 < K) resid_load<N, EPB, NT>(G, B, Pq, TQ, TV, S_, e0 + EPB, nxt);
+        resid_compute<N, EPB, NT>(op, G, B, Pq, F, S_, e0, cur, L);
+        __syncthreads();
+        if (j + 1 < K) cur = nxt;
     }
 }
 
@@ -780,11 +804,11 @@ __global__ void k_to_float(const double *__restrict__ a, float *__restrict__ b, 
 // ---------------------------------------------------------------------------
 template <int N>
 struct CfgM;
-template <> struct CfgM<2> { static constexpr int EPB = 8, NT = 64; };
-template <> struct CfgM<3> { static constexpr int EPB = 2, NT = 64; };
-template <> struct CfgM<4> { static constexpr int EPB = 1, NT = 64; };
-template <> struct CfgM<5> { static constexpr int EPB = 1, NT = 128; };
-template <> struct CfgM<6> { static constexpr int EPB = 1, NT = 256; };
+template <> struct CfgM<2> { static constexpr int EPB = 8, NT = 64, K = 1, MINW = 2; };
+template <> struct CfgM<3> { static constexpr int EPB = 2, NT = 64, K = 1, MINW = 3; };
+template <> struct CfgM<4> { static constexpr int EPB = 1, NT = 64, K = 1, MINW = 3; };
+template <> struct CfgM<5> { static constexpr int EPB = 1, NT = 128, K = 1, MINW = 2; };
+template <> struct CfgM<6> { static constexpr int EPB = 1, NT = 256, K = 1, MINW = 1; };
 
 static GeoF geof_of(const GeoM &g) {
     GeoF o;
@@ -824,11 +848,14 @@ static hipError_t grad_mixed_t(const Mesh &m, const GeoM &g, const PhysParams &P
 template <int N>
 static hipError_t resid_mixed_t(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq,
                                 const float *TQ, const float *TV, const MixedStageArgs &a, hipStream_t s) {
-    constexpr int EPB = CfgM<N>::EPB, NT = CfgM<N>::NT;
-    const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
+    constexpr int EPB = CfgM<N>::EPB, NT = CfgM<N>::NT, K = CfgM<N>::K;
+    const unsigned nb = (unsigned)((m.E + EPB * K - 1) / (EPB * K));
+    static_assert(K >= 1, "at least one element block per workgroup");
     MixedStage st{a.Pn, a.Pout, a.TQout, a.ca, a.cb, a.dt, a.mode};
-    hipLaunchKernelGGL((k_resid_mixed<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, make_ops_t<float, N>(m.basis),
-                       geof_of(g), bufs_of(g), P, Pq, TQ, TV, st);
+    // at N = 3, 4 the block is held to three waves per SIMD (a few spilled
+    // registers cost less than a third of the latency-hiding waves)
+    hipLaunchKernelGGL((k_resid_mixed<N, EPB, NT, K, CfgM<N>::MINW>), dim3(nb), dim3(NT), 0, s,
+                       make_ops_t<float, N>(m.basis), geof_of(g), bufs_of(g), P, Pq, TQ, TV, st);
     return hipGetLastError();
 }
 template <int N>
