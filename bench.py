@@ -80,11 +80,14 @@ def measured_traffic(workload, precision):
 
 
 def alg_flops_per_stage_point(N):
-    """Algorithmic flops per solution point and residual stage: the survey's
-    operation-count model (line operators 90 (N+1) multiply-adds per point
-    and stage, about 150 flops per flux point for the pointwise fluxes,
-    sources and the stage update), which gives about 5.0 kflop per point and
-    SSP-RK3 step at N = 4 (4.7k at N = 3)."""
+    """Algorithmic flops per solution point and residual stage (operation
+    count of the method, +-30 %): the line operators (interpolation of 5
+    values, differentiation of 5, interpolation of 15 gradients, divergence
+    of 5 fluxes) take 90 (N+1) multiply-adds per point; the pointwise
+    inviscid + viscous fluxes about 150 flops per flux point, of which there
+    are 3 (N+1)/N per solution point; the face fluxes, the source and the
+    stage update a few tens more.  Per SSP-RK3 step this is about 4.7k
+    flops per point at N = 3 and 5.0k at N = 4."""
     per_step = {2: 4.4e3, 3: 4.7e3, 4: 5.0e3, 5: 5.4e3, 6: 5.9e3}[N]
     return per_step / 3.0
 
