@@ -19,7 +19,9 @@ _SRC = os.path.join(_HERE, "chorus_oracle.c")
 def build(force=True):
     """Compile the oracle with gcc (FP64, no contraction, no fast-math)."""
     os.makedirs(_BUILD, exist_ok=True)
-    if not force and os.path.exists(_LIB_PATH):
+    if (not force and os.path.exists(_LIB_PATH)
+            and os.path.getmtime(_LIB_PATH) >= max(os.path.getmtime(_SRC),
+                                                   os.path.getmtime(_SRC[:-1] + "h"))):
         return _LIB_PATH
     tmp = _LIB_PATH + ".tmp"
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
@@ -53,6 +55,8 @@ def lib():
         L.ora_faces.argtypes = [P, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_int)]
         L.ora_residual.argtypes = [P, P, dp, dp]
+        L.ora_residual_sgs.argtypes = [P, P, dp, dp, dp]
+        L.ora_gradients.argtypes = [P, P, dp, dp]
         L.ora_rk3.argtypes = [P, P, dp, ctypes.c_double, ctypes.c_int]
         L.ora_sums.argtypes = [P, dp, dp]
         L.ora_polytrope.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -148,11 +152,24 @@ class OracleMesh:
                         npnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
         return ne.reshape(self.E, 6), nf.reshape(self.E, 6), npnt.reshape(self.E, 6, self.N ** 2)
 
-    def residual(self, ph, Q):
+    def residual(self, ph, Q, sgs=None):
+        """dQ/dt [5][E][N^3]; sgs: optional additional Cartesian flux
+        [15][E][N^3] (v*3+c) at the solution points."""
         Q = np.ascontiguousarray(Q, dtype=np.float64).reshape(5, self.E, self.np)
         R = np.zeros_like(Q)
-        lib().ora_residual(self._h, ctypes.byref(ph), _dp(Q), _dp(R))
+        if sgs is None:
+            lib().ora_residual(self._h, ctypes.byref(ph), _dp(Q), _dp(R))
+        else:
+            sg = np.ascontiguousarray(sgs, dtype=np.float64).reshape(15, self.E, self.np)
+            lib().ora_residual_sgs(self._h, ctypes.byref(ph), _dp(Q), _dp(sg), _dp(R))
         return R
+
+    def gradients(self, ph, Q):
+        """BR1 gradients of the conserved variables [15][E][N^3] (v*3+c)."""
+        Q = np.ascontiguousarray(Q, dtype=np.float64).reshape(5, self.E, self.np)
+        G = np.zeros((15, self.E, self.np))
+        lib().ora_gradients(self._h, ctypes.byref(ph), _dp(Q), _dp(G))
+        return G
 
     def rk3(self, ph, Q, dt, nsteps):
         Q = np.array(Q, dtype=np.float64, copy=True).reshape(5, self.E, self.np)

@@ -648,17 +648,21 @@ static void wall_state(const ora_phys *ph, const double q[5], const double n[3],
 /* ------------------------------------------------------------------------ */
 /* residual                                                                  */
 /* ------------------------------------------------------------------------ */
-void ora_residual(const ora_mesh *m, const ora_phys *ph, const double *Q, double *dQdt)
-{
-    const int N = m->N, np = m->np, nf2 = m->nf2, nfl = m->nfl;
-    const long E = m->E;
-    double *Qf = m->Qf, *Qs = m->Qs, *grad = m->grad, *gradf = m->gradf, *Ft = m->Ft;
 #define QF(d, e, v, f) Qf[(((long)(d) * E + (e)) * 5 + (v)) * nfl + (f)]
 #define QS(e, fc, v, p) Qs[(((e) * 6 + (fc)) * 5 + (v)) * nf2 + (p)]
 #define GR(e, v, c, p) grad[(((e) * 5 + (v)) * 3 + (c)) * np + (p)]
 #define GF(d, e, v, c, f) gradf[((((long)(d) * E + (e)) * 5 + (v)) * 3 + (c)) * nfl + (f)]
 #define FT(d, e, v, f) Ft[(((long)(d) * E + (e)) * 5 + (v)) * nfl + (f)]
 #define QIN(v, e, p) Q[((long)(v) * E + (e)) * np + (p)]
+
+/* steps 1-3 of the residual: flux-point values, common interface solution
+ * and the BR1 gradients of the conserved variables at the solution points
+ * (left in m->Qf, m->Qs, m->grad) */
+static void interface_and_gradients(const ora_mesh *m, const ora_phys *ph, const double *Q)
+{
+    const int N = m->N, np = m->np, nf2 = m->nf2, nfl = m->nfl;
+    const long E = m->E;
+    double *Qf = m->Qf, *Qs = m->Qs, *grad = m->grad;
 
     /* step 1: Q at the flux points of each direction (interpolation along
      * the line through the flux point) */
@@ -747,6 +751,68 @@ void ora_residual(const ora_mesh *m, const ora_phys *ph, const double *Q, double
                         }
                 }
 
+}
+
+/* Gradients of the conserved variables at the solution points, the BR1
+ * values the viscous flux uses (Section 3): out[v*3+c][E][N^3] = dQ_v/dx_c. */
+void ora_gradients(const ora_mesh *m, const ora_phys *ph, const double *Q, double *out)
+{
+    const int np = m->np;
+    const long E = m->E;
+    const double *grad = m->grad;
+    interface_and_gradients(m, ph, Q);
+    for (long e = 0; e < E; ++e)
+        for (int v = 0; v < 5; ++v)
+            for (int c = 0; c < 3; ++c)
+                for (int p = 0; p < np; ++p)
+                    out[((long)(v * 3 + c) * E + e) * np + p] = GR(e, v, c, p);
+}
+
+void ora_residual(const ora_mesh *m, const ora_phys *ph, const double *Q, double *dQdt)
+{
+    ora_residual_sgs(m, ph, Q, NULL, dQdt);
+}
+
+/* Residual with an additional flux: sgs[v*3+c][E][N^3] (Cartesian
+ * component c of a flux of variable v at the solution points, e.g. a
+ * learned subgrid-scale flux) enters the total flux F_inv - F_v + sgs.  It is
+ * interpolated to the flux points along each line like the gradients,
+ * averaged between the two sides at interior interfaces and left out at
+ * wall and far-field faces (no subgrid transport through a boundary). */
+void ora_residual_sgs(const ora_mesh *m, const ora_phys *ph, const double *Q, const double *sgs,
+                      double *dQdt)
+{
+    const int N = m->N, np = m->np, nf2 = m->nf2, nfl = m->nfl;
+    const long E = m->E;
+    double *Qf = m->Qf, *grad = m->grad, *gradf = m->gradf, *Ft = m->Ft;
+    double *sgsf = NULL;
+#define SF(d, e, v, c, f) sgsf[((((long)(d) * E + (e)) * 5 + (v)) * 3 + (c)) * nfl + (f)]
+
+    interface_and_gradients(m, ph, Q);
+
+    /* step 4b: the additional flux at the flux points */
+    if (sgs) {
+        sgsf = malloc(sizeof(double) * 3 * E * 15 * nfl);
+        if (!sgsf)
+            abort();
+#pragma omp parallel for schedule(static)
+        for (long e = 0; e < E; ++e)
+            for (int d = 0; d < 3; ++d)
+                for (int t2 = 0; t2 < N; ++t2)
+                    for (int t1 = 0; t1 < N; ++t1)
+                        for (int a = 0; a <= N; ++a)
+                            for (int v = 0; v < 5; ++v)
+                                for (int c = 0; c < 3; ++c) {
+                                    double s = 0.0;
+                                    for (int b = 0; b < N; ++b) {
+                                        int ijk[3];
+                                        dir_ijk(d, b, t1, t2, ijk);
+                                        s += m->I[a * N + b] * sgs[((long)(v * 3 + c) * E + e) * np + sol_index(m, ijk)];
+                                    }
+                                    SF(d, e, v, c, fl_index(m, a, t1, t2)) = s;
+                                }
+    }
+
     /* step 4: gradients interpolated to the flux points */
 #pragma omp parallel for schedule(static)
     for (long e = 0; e < E; ++e)
@@ -783,8 +849,12 @@ void ora_residual(const ora_mesh *m, const ora_phys *ph, const double *Q, double
                         const double *S = &m->metf[((e * 3 + d) * nfl + fi) * 3];
                         inviscid_flux(ph, q, S, fi_);
                         viscous_flux(ph, q, g, S, fv);
-                        for (int v = 0; v < 5; ++v)
+                        for (int v = 0; v < 5; ++v) {
                             FT(d, e, v, fi) = fi_[v] - fv[v];
+                            if (sgsf)
+                                for (int c = 0; c < 3; ++c)
+                                    FT(d, e, v, fi) += SF(d, e, v, c, fi) * S[c];
+                        }
                     }
 
     /* step 6: common fluxes at the interface points.  Each interior face is
@@ -827,6 +897,10 @@ void ora_residual(const ora_mesh *m, const ora_phys *ph, const double *Q, double
                         viscous_flux(ph, qR, gR, S, fvR);
                         for (int v = 0; v < 5; ++v)
                             phi[v] -= 0.5 * (fvL[v] + fvR[v]);
+                        if (sgsf)
+                            for (int v = 0; v < 5; ++v)
+                                for (int c = 0; c < 3; ++c)
+                                    phi[v] += 0.5 * (SF(d, e, v, c, fi) + SF(d2, e2, v, c, fi2)) * S[c];
                         double sg2 = (f2 % 2) ? 1.0 : -1.0;
                         for (int v = 0; v < 5; ++v)
                             FT(d2, e2, v, fi2) = sg2 * (-phi[v]);
@@ -897,13 +971,15 @@ void ora_residual(const ora_mesh *m, const ora_phys *ph, const double *Q, double
                     for (int v = 0; v < 5; ++v)
                         dQdt[((long)v * E + e) * np + p] = -div[v] / J - M[v];
                 }
+    free(sgsf);
+#undef SF
+}
 #undef QF
 #undef QS
 #undef GR
 #undef GF
 #undef FT
 #undef QIN
-}
 
 /* SSP-RK3 (Shu-Osher form) */
 void ora_rk3(const ora_mesh *m, const ora_phys *ph, double *Q, double dt, int nsteps)

@@ -56,6 +56,13 @@ void ora_geometry(const ora_mesh *m, double *jac, double *met_sol, double *met_f
 void ora_faces(const ora_mesh *m, long *nbr_e, int *nbr_f, int *nbr_p);
 
 void ora_residual(const ora_mesh *m, const ora_phys *ph, const double *Q, double *dQdt);
+/* residual with an additional Cartesian flux sgs[v*3+c][E][N^3] at the
+ * solution points (NULL: none), see the definition */
+void ora_residual_sgs(const ora_mesh *m, const ora_phys *ph, const double *Q, const double *sgs,
+                      double *dQdt);
+/* BR1 gradients of the conserved variables at the solution points,
+ * out[v*3+c][E][N^3] */
+void ora_gradients(const ora_mesh *m, const ora_phys *ph, const double *Q, double *out);
 void ora_rk3(const ora_mesh *m, const ora_phys *ph, double *Q, double dt, int nsteps);
 /* sum over all solution points of w w w |J| Q_v, fixed serial order */
 void ora_sums(const ora_mesh *m, const double *Q, double out[5]);
