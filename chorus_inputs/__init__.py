@@ -2,7 +2,8 @@
 
 This package only *generates inputs*: 20-node hexahedral meshes (a
 cubed-sphere shell and Cartesian boxes, optionally periodic and curved) and
-seeded random numbers.  It holds none of the spectral-difference arithmetic:
+seeded random numbers (noise, initial network parameters, smooth random
+velocity fields).  It holds none of the spectral-difference arithmetic:
 no solution/flux points, no interpolation, no metrics, no fluxes and no
 physical initial state.  Both sides consume exactly these arrays.
 
@@ -17,8 +18,8 @@ Boundary tags: -1 interior, 1 inner sphere wall, 2 outer sphere wall,
 """
 from .meshes import (HEX20_LOCAL, Hex20Mesh, cubed_sphere_shell, box_mesh,
                      two_element_mesh, shell_params_from_config,
-                     uniform_noise, CONFIGS)
+                     uniform_noise, mlp_init, random_velocity, CONFIGS)
 
 __all__ = ["HEX20_LOCAL", "Hex20Mesh", "cubed_sphere_shell", "box_mesh",
            "two_element_mesh", "shell_params_from_config", "uniform_noise",
-           "CONFIGS"]
+           "mlp_init", "random_velocity", "CONFIGS"]

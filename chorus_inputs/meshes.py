@@ -297,3 +297,34 @@ def uniform_noise(shape, seed):
     """I.i.d. U(-1, 1) samples from numpy's PCG64 with the given seed."""
     rng = np.random.Generator(np.random.PCG64(int(seed)))
     return rng.uniform(-1.0, 1.0, size=shape)
+
+
+def mlp_init(seed, n_in=20, n_hid=64, n_out=15):
+    """Seeded initial parameters of the closure network in its documented
+    layout W1[h][in], b1[h], W2[h][h], b2[h], W3[out][h], b3[out]: Glorot
+    uniform weights U(-a, a), a = sqrt(6 / (fan_in + fan_out)), zero biases."""
+    rng = np.random.Generator(np.random.PCG64(int(seed)))
+    parts = []
+    for fi, fo in ((n_in, n_hid), (n_hid, n_hid), (n_hid, n_out)):
+        a = np.sqrt(6.0 / (fi + fo))
+        parts.append(rng.uniform(-a, a, size=fo * fi))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts)
+
+
+def random_velocity(xyz, seed, n_modes=24, k_min=2.0, k_max=6.0, amp=1.0):
+    """Seeded smooth random vector field at points xyz [3][n]: a sum of
+    n_modes plane waves a_m sin(k_m . x + phi_m) with |k_m| uniform in
+    [k_min, k_max], random directions, a_m perpendicular to k_m
+    (divergence-free), normalised to RMS amp over the points."""
+    rng = np.random.Generator(np.random.PCG64(int(seed)))
+    xyz = np.asarray(xyz, dtype=np.float64)
+    u = np.zeros_like(xyz)
+    for _ in range(n_modes):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        k = d * rng.uniform(k_min, k_max)
+        a = np.cross(d, rng.normal(size=3))
+        u += a[:, None] * np.sin(k @ xyz + rng.uniform(0, 2 * np.pi))[None, :]
+    rms = np.sqrt((u ** 2).sum(0).mean())
+    return u * (amp / rms)

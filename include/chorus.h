@@ -57,6 +57,7 @@ enum {
 };
 
 enum { CHORUS_FP64 = 0, CHORUS_MIXED = 1 };            /* chorus_physics.precision */
+enum { CHORUS_CLOSURE_NONE = 0, CHORUS_CLOSURE_MLP = 1 }; /* chorus_physics.closure */
 enum { CHORUS_CHECK_FINITE = 1 };                      /* chorus_physics.flags     */
 enum { CHORUS_BC_INTERIOR = -1, CHORUS_BC_INNER = 1, CHORUS_BC_OUTER = 2,
        CHORUS_BC_STATE = 3 };
@@ -92,9 +93,13 @@ typedef struct {
     double gamma, R_gas, GM, omega, nu, kappa, kappa_r, T_top, F_bottom;
     double bc_state[5];       /* state for CHORUS_BC_STATE faces              */
     int32_t precision;        /* CHORUS_FP64 or CHORUS_MIXED                  */
-    int32_t closure;          /* 0 = plain SD                                 */
+    int32_t closure;          /* CHORUS_CLOSURE_NONE, or CHORUS_CLOSURE_MLP:
+                                 add the learned subgrid flux (order 3, FP64
+                                 precision only; see the closure section)     */
     int32_t flags;            /* CHORUS_CHECK_FINITE                          */
     int32_t reserved;
+    const void *closure_model;/* device image from chorus_closure_pack when
+                                 closure == CHORUS_CLOSURE_MLP, else ignored   */
 } chorus_physics;
 
 /* Build a cubed-sphere shell mesh (host only). */
@@ -177,6 +182,72 @@ int chorus_stable_dt(chorus_mesh_t mesh, const chorus_physics *phys, const doubl
  * thread-safe; process-wide. */
 int chorus_kernel_timing(int enable);
 int chorus_kernel_times(double ms[3], int64_t counts[3]);
+
+/* ------------------------------------------------------------------------
+ * Learned subgrid closure.  The paper names large-eddy simulation with
+ * subgrid modelling as the code's next step (Summary) and treats entropy
+ * diffusion as a parameterisation of unresolved motion (Section 2).  Here a
+ * pointwise network 20 -> 64 -> 64 -> 15 with GELU (x Phi(x)) activations
+ * maps the features of a solution point -- the conserved state Q (5) and
+ * its BR1 gradients dQ_v/dx_c (15, index 5 + 3 v + c) -- to a Cartesian
+ * subgrid flux tau[3 v + c] that is added to the total flux: interpolated
+ * to the flux points like the gradients, averaged between the two sides of
+ * an interior interface, and left out at wall and far-field faces.
+ *
+ * Parameter vector (FP32, CHORUS_MLP_NPARAM values, z_j = sum_i W[j][i]
+ * x_i + b_j): W1[64][20], b1[64], W2[64][64], b2[64], W3[15][64], b3[15].
+ * Normalisation (FP32, CHORUS_MLP_NNORM values): x_mean[20], x_inv_std[20],
+ * y_mean[15], y_std[15]; network input x = (feature - x_mean) x_inv_std,
+ * output tau = y_mean + y_std y.
+ * Inference runs on bfloat16 matrix cores with FP32 accumulation (inputs,
+ * weights and hidden activations rounded to bfloat16, nearest-even);
+ * training runs in FP32.
+ * ---------------------------------------------------------------------- */
+enum { CHORUS_MLP_IN = 20, CHORUS_MLP_HIDDEN = 64, CHORUS_MLP_OUT = 15, CHORUS_MLP_NPARAM = 6479,
+       CHORUS_MLP_NNORM = 70 };
+
+/* Byte size of the packed inference image. */
+int chorus_closure_model_bytes(size_t *bytes);
+/* Pack FP32 parameters and normalisation (device) into the inference image
+ * model_dev (device, chorus_closure_model_bytes, 256-byte aligned).
+ * Synchronises; returns CHORUS_ENONFINITE (image marked unusable) if any
+ * value is NaN or infinite, so a caller can fall back to the plain solve. */
+int chorus_closure_pack(const float *params_dev, const float *norm_dev, void *model_dev, void *stream);
+/* Raw features at every solution point: X_dev [E N^3][20] FP32 (Q, then
+ * the BR1 gradients), from Q_dev [5][E N^3] (FP64 precision, any order). */
+int chorus_closure_features(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q_dev, float *X_dev,
+                            void *ws, void *stream);
+/* Subgrid flux of the network phys->closure_model at every solution point:
+ * sgs_dev [15][E N^3] FP32 (order 3, FP64 precision). */
+int chorus_closure_infer(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q_dev, float *sgs_dev,
+                         void *ws, void *stream);
+/* Training workspace bytes for mini-batches of up to `batch` samples. */
+int chorus_closure_train_workspace_bytes(int64_t batch, size_t *bytes);
+/* Mean-squared-error loss over n samples (X_dev [n][20] normalised inputs,
+ * Y_dev [n][15] normalised targets) and its gradient with respect to the
+ * parameter vector: grad_dev [CHORUS_MLP_NPARAM], loss_dev [1] (device,
+ * FP32, fixed summation order).  n <= the workspace's batch. */
+int chorus_closure_grad(const float *X_dev, const float *Y_dev, int64_t n, const float *params_dev,
+                        float *grad_dev, float *loss_dev, void *ws, size_t ws_bytes, void *stream);
+/* `iters` Adam steps (Kingma & Ba 2015) on mini-batches: iteration i uses
+ * the samples idx_dev[i batch .. (i+1) batch - 1] (int32, device; the
+ * caller draws them).  params/adam_m/adam_v [CHORUS_MLP_NPARAM] FP32 are
+ * updated in place; the bias correction uses step step0 + i + 1;
+ * hyper = (lr, beta1, beta2, eps); loss_dev [iters] receives the loss of
+ * each mini-batch before its update. */
+int chorus_closure_train(const float *X_dev, const float *Y_dev, int64_t n, const int32_t *idx_dev,
+                         int32_t batch, int32_t iters, float *params_dev, float *adam_m_dev, float *adam_v_dev,
+                         int64_t step0, const double hyper[4], float *loss_dev, void *ws, size_t ws_bytes,
+                         void *stream);
+/* Training targets from a higher-order solution on the same hex mesh:
+ * per element the L2 projection of |J| U onto tensor polynomials of
+ * degree N_c - 1, divided by |J| at the coarse solution points (G U;
+ * preserves element integrals).  Qbar_dev [5][E N_c^3] = G Q and
+ * tau_dev [15][E N_c^3] = G F(Q) - F(G Q), F the Cartesian inviscid flux
+ * (Section 2), both FP64.  fine and coarse: the same hex mesh at orders
+ * N_f > N_c, both uploaded; gamma: ratio of specific heats. */
+int chorus_closure_filter(chorus_mesh_t fine, chorus_mesh_t coarse, double gamma, const double *Qfine_dev,
+                          double *Qbar_dev, double *tau_dev, void *stream);
 
 const char *chorus_strerror(int status);
 int chorus_last_error(char *buf, size_t len);

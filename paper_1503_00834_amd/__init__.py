@@ -16,7 +16,10 @@ LIB_PATH = os.path.join(_HERE, "libchorus.so")
 
 CHORUS_OK = 0
 CHORUS_FP64, CHORUS_MIXED = 0, 1
+CHORUS_CLOSURE_NONE, CHORUS_CLOSURE_MLP = 0, 1
 CHORUS_CHECK_FINITE = 1
+CHORUS_MLP_IN, CHORUS_MLP_HIDDEN, CHORUS_MLP_OUT = 20, 64, 15
+CHORUS_MLP_NPARAM, CHORUS_MLP_NNORM = 6479, 70
 ERRORS = {-1: "EINVAL", -2: "EMESH", -3: "ENOTSUP", -4: "EHIP", -5: "ENONFINITE", -6: "ESTATE"}
 
 if not os.path.exists(LIB_PATH):
@@ -51,17 +54,23 @@ class Physics(ctypes.Structure):
                 ("omega", ctypes.c_double), ("nu", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("kappa_r", ctypes.c_double), ("T_top", ctypes.c_double), ("F_bottom", ctypes.c_double),
                 ("bc_state", ctypes.c_double * 5), ("precision", ctypes.c_int32),
-                ("closure", ctypes.c_int32), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("closure", ctypes.c_int32), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("closure_model", ctypes.c_void_p)]
 
 
 def physics(gamma=5.0 / 3.0, R_gas=1.0, GM=0.0, omega=0.0, nu=0.0, kappa=0.0, kappa_r=0.0, T_top=0.0,
-            F_bottom=0.0, bc_state=(1.0, 0.0, 0.0, 0.0, 1.5), precision=CHORUS_FP64, closure=0, flags=0):
+            F_bottom=0.0, bc_state=(1.0, 0.0, 0.0, 0.0, 1.5), precision=CHORUS_FP64, closure=0, flags=0,
+            closure_model=None):
+    """chorus_physics; closure_model: a ClosureModel (or a device address)
+    used when closure == CHORUS_CLOSURE_MLP."""
     p = Physics()
     p.gamma, p.R_gas, p.GM, p.omega, p.nu = gamma, R_gas, GM, omega, nu
     p.kappa, p.kappa_r, p.T_top, p.F_bottom = kappa, kappa_r, T_top, F_bottom
     for i in range(5):
         p.bc_state[i] = bc_state[i]
     p.precision, p.closure, p.flags = precision, closure, flags
+    if closure_model is not None:
+        p.closure_model = closure_model if isinstance(closure_model, int) else closure_model.ptr
     return p
 
 
@@ -90,6 +99,15 @@ _SIGS = {
     "chorus_last_error": [ctypes.c_char_p, ctypes.c_size_t],
     "chorus_kernel_timing": [ctypes.c_int],
     "chorus_kernel_times": [_P, _P],
+    "chorus_closure_model_bytes": [ctypes.POINTER(ctypes.c_size_t)],
+    "chorus_closure_pack": [_P, _P, _P, _P],
+    "chorus_closure_features": [_P, ctypes.POINTER(Physics), _P, _P, _P, _P],
+    "chorus_closure_infer": [_P, ctypes.POINTER(Physics), _P, _P, _P, _P],
+    "chorus_closure_train_workspace_bytes": [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
+    "chorus_closure_grad": [_P, _P, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_size_t, _P],
+    "chorus_closure_train": [_P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P,
+                             ctypes.c_int64, _P, _P, _P, ctypes.c_size_t, _P],
+    "chorus_closure_filter": [_P, _P, ctypes.c_double, _P, _P, _P, _P],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -274,3 +292,88 @@ def chorus_kernel_times():
 def mesh_from_arrays(m, order):
     """Mesh handle from a chorus_inputs.Hex20Mesh."""
     return chorus_mesh_create_hex20(m.xyz, m.elem20, m.face_bc, order, m.match_id)
+
+
+# ---------------------------------------------------------------------------
+# learned subgrid closure
+# ---------------------------------------------------------------------------
+def _aligned(nbytes, device="cuda"):
+    """(tensor, 256-byte aligned address) of a device byte buffer."""
+    import torch
+    t = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    return t, t.data_ptr() + (-t.data_ptr()) % 256
+
+
+class ClosureModel:
+    """Packed bfloat16 inference image of the closure network (device)."""
+
+    def __init__(self, device="cuda"):
+        b = ctypes.c_size_t()
+        _check(_lib.chorus_closure_model_bytes(ctypes.byref(b)), "chorus_closure_model_bytes")
+        self.nbytes = b.value
+        self._buf, self.ptr = _aligned(self.nbytes, device)
+
+
+def chorus_closure_pack(params, norm, model=None, stream=None):
+    """Pack FP32 device tensors params [6479] and norm [70] into a
+    ClosureModel; raises ChorusError (status ENONFINITE) on NaN/Inf."""
+    assert params.is_contiguous() and params.numel() == CHORUS_MLP_NPARAM
+    assert norm.is_contiguous() and norm.numel() == CHORUS_MLP_NNORM
+    model = model or ClosureModel(params.device)
+    _check(_lib.chorus_closure_pack(_P(params.data_ptr()), _P(norm.data_ptr()), _P(model.ptr),
+                                    _P(_stream(stream))), "chorus_closure_pack")
+    return model
+
+
+def chorus_closure_features(mesh, phys, Q, X, ws, stream=None):
+    """Raw features X [E N^3, 20] (float32) of the device state Q."""
+    assert Q.is_contiguous() and X.is_contiguous() and X.numel() == 20 * mesh.n_solpts
+    _check(_lib.chorus_closure_features(mesh.handle, ctypes.byref(phys), _P(Q.data_ptr()), _P(X.data_ptr()),
+                                        _ws_ptr(ws), _P(_stream(stream))), "chorus_closure_features")
+
+
+def chorus_closure_infer(mesh, phys, Q, sgs, ws, stream=None):
+    """Subgrid flux sgs [15, E N^3] (float32) of the network in phys."""
+    assert Q.is_contiguous() and sgs.is_contiguous() and sgs.numel() == 15 * mesh.n_solpts
+    _check(_lib.chorus_closure_infer(mesh.handle, ctypes.byref(phys), _P(Q.data_ptr()), _P(sgs.data_ptr()),
+                                     _ws_ptr(ws), _P(_stream(stream))), "chorus_closure_infer")
+
+
+def closure_train_workspace(batch, device="cuda"):
+    import torch
+    b = ctypes.c_size_t()
+    _check(_lib.chorus_closure_train_workspace_bytes(int(batch), ctypes.byref(b)),
+           "chorus_closure_train_workspace_bytes")
+    return torch.empty(b.value, dtype=torch.uint8, device=device)
+
+
+def chorus_closure_grad(X, Y, params, grad, loss, ws, stream=None):
+    n = X.shape[0]
+    assert X.is_contiguous() and Y.is_contiguous() and X.numel() == 20 * n and Y.numel() == 15 * n
+    _check(_lib.chorus_closure_grad(_P(X.data_ptr()), _P(Y.data_ptr()), n, _P(params.data_ptr()),
+                                    _P(grad.data_ptr()), _P(loss.data_ptr()), _ws_ptr(ws), ws.numel(),
+                                    _P(_stream(stream))), "chorus_closure_grad")
+
+
+def chorus_closure_train(X, Y, idx, batch, iters, params, adam_m, adam_v, step0, hyper, losses, ws,
+                         stream=None):
+    """iters Adam steps on the mini-batches idx[i*batch:(i+1)*batch]."""
+    n = X.shape[0]
+    assert X.is_contiguous() and Y.is_contiguous() and idx.is_contiguous() and idx.numel() >= batch * iters
+    assert losses.numel() >= iters
+    h = np.ascontiguousarray(hyper, dtype=np.float64)
+    _check(_lib.chorus_closure_train(_P(X.data_ptr()), _P(Y.data_ptr()), n, _P(idx.data_ptr()), int(batch),
+                                     int(iters), _P(params.data_ptr()), _P(adam_m.data_ptr()),
+                                     _P(adam_v.data_ptr()), int(step0), _ptr(h), _P(losses.data_ptr()),
+                                     _ws_ptr(ws), ws.numel(), _P(_stream(stream))), "chorus_closure_train")
+
+
+def chorus_closure_filter(fine, coarse, gamma, Qf, Qbar, tau, stream=None):
+    """Filtered state Qbar [5, E Nc^3] and subgrid flux targets tau
+    [15, E Nc^3] (float64) of the fine device state Qf."""
+    assert Qf.is_contiguous() and Qbar.is_contiguous() and tau.is_contiguous()
+    assert Qf.numel() == 5 * fine.n_solpts and Qbar.numel() == 5 * coarse.n_solpts
+    assert tau.numel() == 15 * coarse.n_solpts
+    _check(_lib.chorus_closure_filter(fine.handle, coarse.handle, float(gamma), _P(Qf.data_ptr()),
+                                      _P(Qbar.data_ptr()), _P(tau.data_ptr()), _P(_stream(stream))),
+           "chorus_closure_filter")

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchorus.so")
-SOURCES = ["mesh_host.cpp", "chorus_abi.cpp", "sd_kernels.hip", "sd_mixed.hip"]
+SOURCES = ["mesh_host.cpp", "chorus_abi.cpp", "sd_kernels.hip", "sd_mixed.hip", "closure.hip"]
 ARCH = os.environ.get("CHORUS_OFFLOAD_ARCH", "gfx950")
 
 

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "launch.hpp"
+#include "mlp_bf16.hpp"
 
 namespace chorus {
 
@@ -26,6 +27,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // workspace layout
 struct WsLayout {
     size_t Qs, TQ0, TQ1, TV, part, sums, flag;
+    size_t tau;  // learned closure: subgrid flux [15][E][NP] FP32 (0 when off)
     // mixed-precision path
     size_t P0, P1, TQm0, TQm1, TVm, bg, dbg, gS0, R0, Q0;
     bool mixed;
@@ -33,7 +35,7 @@ struct WsLayout {
 };
 static constexpr int kSumBlocks = 512;
 
-static WsLayout ws_layout(const Mesh &m, bool mixed) {
+static WsLayout ws_layout(const Mesh &m, bool mixed, bool closure = false) {
     const int N = m.N, NP = N * N * N, NF2 = N * N;
     const int64_t E = m.E;
     WsLayout w;
@@ -46,6 +48,10 @@ static WsLayout ws_layout(const Mesh &m, bool mixed) {
     w.part = off; off = align256(off + sizeof(double) * 5 * kSumBlocks);
     w.sums = off; off = align256(off + sizeof(double) * 8);
     w.flag = off; off = align256(off + sizeof(int) * 4);
+    w.tau = 0;
+    if (closure) {
+        w.tau = off; off = align256(off + sizeof(float) * 15 * E * NP);
+    }
     w.P0 = w.P1 = w.TQm0 = w.TQm1 = w.TVm = w.bg = w.dbg = w.gS0 = w.R0 = w.Q0 = 0;
     if (mixed) {
         w.P0 = off;   off = align256(off + sizeof(double) * 5 * E * NP);
@@ -103,11 +109,38 @@ static int check_phys(const chorus_physics *p) {
         set_error("physics: unknown precision");
         return CHORUS_EINVAL;
     }
-    if (p->closure != 0) {
-        set_error("learned closure is not available in this build");
+    if (p->closure != CHORUS_CLOSURE_NONE && p->closure != CHORUS_CLOSURE_MLP) {
+        set_error("physics: unknown closure");
+        return CHORUS_EINVAL;
+    }
+    if (p->closure == CHORUS_CLOSURE_MLP) {
+        if (!p->closure_model) {
+            set_error("closure: no network image (closure_model is null)");
+            return CHORUS_EINVAL;
+        }
+        if (p->precision != CHORUS_FP64) {
+            set_error("closure: only the FP64 precision path carries the learned closure");
+            return CHORUS_ENOTSUP;
+        }
+    }
+    return CHORUS_OK;
+}
+
+static int check_closure_order(const Mesh &m, const chorus_physics *p) {
+    if (p->closure == CHORUS_CLOSURE_MLP && m.N != 3) {
+        set_error("closure: the learned closure runs at order 3 only");
         return CHORUS_ENOTSUP;
     }
     return CHORUS_OK;
+}
+
+static ClosureArgs closure_of(const chorus_physics *p, const WsLayout &w, unsigned char *W) {
+    ClosureArgs C{nullptr, nullptr};
+    if (p->closure == CHORUS_CLOSURE_MLP) {
+        C.model = (const unsigned char *)p->closure_model;
+        C.tau = (float *)(W + w.tau);
+    }
+    return C;
 }
 
 // the mixed path needs a registered background computed with the same
@@ -410,8 +443,8 @@ int chorus_workspace_bytes(chorus_mesh_t mesh, const chorus_physics *phys, size_
         set_error("null argument");
         return CHORUS_EINVAL;
     }
-    (void)phys;
-    *bytes = ws_layout(*m, phys && phys->precision == CHORUS_MIXED).total;
+    *bytes = ws_layout(*m, phys && phys->precision == CHORUS_MIXED,
+                       phys && phys->closure == CHORUS_CLOSURE_MLP).total;
     return CHORUS_OK;
 }
 
@@ -489,9 +522,10 @@ int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const 
     if (e == hipSuccess) e = launch_bg_setup(*m, G, Q0, TQ, (float *)(W + w.bg), (float *)(W + w.dbg), flag, s);
     if (e == hipSuccess) e = launch_bg_entropy(*m, G, P, Q0, TQ, (float *)(W + w.gS0), s);
     // R0 = R(Q0), the complete FP64 residual of the background
-    if (e == hipSuccess) e = launch_grad(*m, G, P, Q0, TQ, TV, s);
+    const ClosureArgs C0{nullptr, nullptr};
+    if (e == hipSuccess) e = launch_grad(*m, G, P, Q0, TQ, TV, C0, s);
     StageArgs sa{nullptr, R0d, nullptr, 0.0, 1.0, 0.0, 0};
-    if (e == hipSuccess) e = launch_resid(*m, G, P, Q0, TQ, TV, sa, s);
+    if (e == hipSuccess) e = launch_resid(*m, G, P, Q0, TQ, TV, sa, C0, s);
     if (e == hipSuccess) e = launch_to_float(R0d, (float *)(W + w.R0), 5 * n, s);
     int h = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -518,10 +552,13 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
         set_error("null device pointer");
         return CHORUS_EINVAL;
     }
+    rc = check_closure_order(*m, phys);
+    if (rc) return rc;
     const bool mixed = phys->precision == CHORUS_MIXED;
-    const WsLayout w = ws_layout(*m, mixed);
+    const WsLayout w = ws_layout(*m, mixed, phys->closure == CHORUS_CLOSURE_MLP);
     unsigned char *W = (unsigned char *)ws;
     const PhysParams P = params_of(phys);
+    const ClosureArgs C = closure_of(phys, w, W);
     hipStream_t s = (hipStream_t)stream;
     if (mixed) {
         rc = check_mixed(*m, phys, ws);
@@ -540,9 +577,9 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
     double *TQ = (double *)(W + w.TQ0), *TV = (double *)(W + w.TV);
     const Geo G = geo_of(*m);
     hipError_t e = timed(0, s, [&] { return launch_trace(*m, G, Q_dev, TQ, s); });
-    if (e == hipSuccess) e = timed(1, s, [&] { return launch_grad(*m, G, P, Q_dev, TQ, TV, s); });
+    if (e == hipSuccess) e = timed(1, s, [&] { return launch_grad(*m, G, P, Q_dev, TQ, TV, C, s); });
     StageArgs sa{nullptr, dQdt_dev, nullptr, 0.0, 1.0, 0.0, 0};
-    if (e == hipSuccess) e = timed(2, s, [&] { return launch_resid(*m, G, P, Q_dev, TQ, TV, sa, s); });
+    if (e == hipSuccess) e = timed(2, s, [&] { return launch_resid(*m, G, P, Q_dev, TQ, TV, sa, C, s); });
     if (e != hipSuccess) return hip_fail(e, "sd_residual");
     if (phys->flags & CHORUS_CHECK_FINITE) return finite_check(*m, P, Q_dev, w, W, s);
     return CHORUS_OK;
@@ -560,9 +597,12 @@ int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev
         return CHORUS_EINVAL;
     }
     if (n_steps == 0) return CHORUS_OK;
+    rc = check_closure_order(*m, phys);
+    if (rc) return rc;
     const bool mixed = phys->precision == CHORUS_MIXED;
-    const WsLayout w = ws_layout(*m, mixed);
+    const WsLayout w = ws_layout(*m, mixed, phys->closure == CHORUS_CLOSURE_MLP);
     unsigned char *W = (unsigned char *)ws;
+    const ClosureArgs C = closure_of(phys, w, W);
     if (mixed) {
         rc = check_mixed(*m, phys, ws);
         if (rc) return rc;
@@ -605,10 +645,10 @@ int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev
         for (int k = 0; k < 3 && e == hipSuccess; ++k) {
             const double *qin = (k == 0) ? Q_dev : Qs;
             double *qout = (k == 2) ? Q_dev : Qs;
-            e = timed(1, s, [&] { return launch_grad(*m, G, P, qin, TQb[cur], TV, s); });
+            e = timed(1, s, [&] { return launch_grad(*m, G, P, qin, TQb[cur], TV, C, s); });
             if (e != hipSuccess) break;
             StageArgs sa{Q_dev, qout, TQb[cur ^ 1], ca[k], cb[k], dt, 1};
-            e = timed(2, s, [&] { return launch_resid(*m, G, P, qin, TQb[cur], TV, sa, s); });
+            e = timed(2, s, [&] { return launch_resid(*m, G, P, qin, TQb[cur], TV, sa, C, s); });
             cur ^= 1;
         }
     }
@@ -702,6 +742,310 @@ int chorus_kernel_times(double ms[3], int64_t counts[3]) {
     }
     g_launches.clear();
     return rc;
+}
+
+
+// ---------------------------------------------------------------------------
+// learned subgrid closure
+// ---------------------------------------------------------------------------
+int chorus_closure_model_bytes(size_t *bytes) {
+    if (!bytes) {
+        set_error("null argument");
+        return CHORUS_EINVAL;
+    }
+    *bytes = kMlpModelBytes;
+    return CHORUS_OK;
+}
+
+int chorus_closure_pack(const float *params_dev, const float *norm_dev, void *model_dev, void *stream) {
+    if (!params_dev || !norm_dev || !model_dev) {
+        set_error("null device pointer");
+        return CHORUS_EINVAL;
+    }
+    if (((uintptr_t)model_dev) & 255) {
+        set_error("model image must be 256-byte aligned");
+        return CHORUS_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *M = (unsigned char *)model_dev;
+    hipError_t e = launch_pack(params_dev, norm_dev, M, s);
+    int ok = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&ok, M + kMlpFlagOff, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "closure_pack");
+    if (ok != 1) {
+        set_error("closure_pack: non-finite parameter or normalisation value");
+        return CHORUS_ENONFINITE;
+    }
+    return CHORUS_OK;
+}
+
+int chorus_closure_features(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q_dev, float *X_dev,
+                            void *ws, void *stream) {
+    Mesh *m = reinterpret_cast<Mesh *>(mesh);
+    int rc = check_ready(m);
+    if (rc) return rc;
+    rc = check_phys(phys);
+    if (rc) return rc;
+    if (!Q_dev || !X_dev || !ws) {
+        set_error("null device pointer");
+        return CHORUS_EINVAL;
+    }
+    if (phys->precision != CHORUS_FP64) {
+        set_error("closure_features: FP64 precision only");
+        return CHORUS_ENOTSUP;
+    }
+    const WsLayout w = ws_layout(*m, false);
+    unsigned char *W = (unsigned char *)ws;
+    const Geo G = geo_of(*m);
+    const PhysParams P = params_of(phys);
+    hipStream_t s = (hipStream_t)stream;
+    double *TQ = (double *)(W + w.TQ0);
+    hipError_t e = launch_trace(*m, G, Q_dev, TQ, s);
+    if (e == hipSuccess) e = launch_features(*m, G, P, Q_dev, TQ, X_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "closure_features");
+    return CHORUS_OK;
+}
+
+int chorus_closure_infer(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q_dev, float *sgs_dev,
+                         void *ws, void *stream) {
+    Mesh *m = reinterpret_cast<Mesh *>(mesh);
+    int rc = check_ready(m);
+    if (rc) return rc;
+    rc = check_phys(phys);
+    if (rc) return rc;
+    if (phys->closure != CHORUS_CLOSURE_MLP) {
+        set_error("closure_infer: physics has no closure (closure != CHORUS_CLOSURE_MLP)");
+        return CHORUS_EINVAL;
+    }
+    rc = check_closure_order(*m, phys);
+    if (rc) return rc;
+    if (!Q_dev || !sgs_dev || !ws) {
+        set_error("null device pointer");
+        return CHORUS_EINVAL;
+    }
+    const WsLayout w = ws_layout(*m, false, true);
+    unsigned char *W = (unsigned char *)ws;
+    const Geo G = geo_of(*m);
+    const PhysParams P = params_of(phys);
+    hipStream_t s = (hipStream_t)stream;
+    double *TQ = (double *)(W + w.TQ0), *TV = (double *)(W + w.TV);
+    const ClosureArgs C{(const unsigned char *)phys->closure_model, sgs_dev};
+    hipError_t e = launch_trace(*m, G, Q_dev, TQ, s);
+    if (e == hipSuccess) e = launch_grad(*m, G, P, Q_dev, TQ, TV, C, s);
+    if (e != hipSuccess) return hip_fail(e, "closure_infer");
+    return CHORUS_OK;
+}
+
+struct TrainLayout {
+    size_t H1, G1, H2, G2, dZ1, dZ2, dY, lossv, part, grad, total;
+};
+
+static TrainLayout train_layout(int64_t B) {
+    TrainLayout L;
+    size_t off = 0;
+    const size_t row = sizeof(float) * 64 * (size_t)B;
+    L.H1 = off;  off = align256(off + row);
+    L.G1 = off;  off = align256(off + row);
+    L.H2 = off;  off = align256(off + row);
+    L.G2 = off;  off = align256(off + row);
+    L.dZ1 = off; off = align256(off + row);
+    L.dZ2 = off; off = align256(off + row);
+    L.dY = off;  off = align256(off + sizeof(float) * 16 * (size_t)B);
+    L.lossv = off; off = align256(off + sizeof(float) * (size_t)B);
+    L.part = off;  off = align256(off + sizeof(float) * kMlpParams * (size_t)((B + 63) / 64));
+    L.grad = off;  off = align256(off + sizeof(float) * kMlpParams);
+    L.total = off;
+    return L;
+}
+
+static TrainBufs train_bufs(const TrainLayout &L, unsigned char *W, int64_t n_mean) {
+    TrainBufs T;
+    T.H1 = (float *)(W + L.H1);
+    T.G1 = (float *)(W + L.G1);
+    T.H2 = (float *)(W + L.H2);
+    T.G2 = (float *)(W + L.G2);
+    T.dZ1 = (float *)(W + L.dZ1);
+    T.dZ2 = (float *)(W + L.dZ2);
+    T.dY = (float *)(W + L.dY);
+    T.lossv = (float *)(W + L.lossv);
+    T.part = (float *)(W + L.part);
+    T.n_mean = n_mean;
+    return T;
+}
+
+static constexpr int64_t kMaxBatch = 1 << 20;
+
+int chorus_closure_train_workspace_bytes(int64_t batch, size_t *bytes) {
+    if (!bytes || batch < 1 || batch > kMaxBatch) {
+        set_error("closure workspace: need 1 <= batch <= 2^20");
+        return CHORUS_EINVAL;
+    }
+    *bytes = train_layout(batch).total;
+    return CHORUS_OK;
+}
+
+int chorus_closure_grad(const float *X_dev, const float *Y_dev, int64_t n, const float *params_dev,
+                        float *grad_dev, float *loss_dev, void *ws, size_t ws_bytes, void *stream) {
+    if (!X_dev || !Y_dev || !params_dev || !grad_dev || !loss_dev || !ws) {
+        set_error("null device pointer");
+        return CHORUS_EINVAL;
+    }
+    if (n < 1 || n > kMaxBatch || train_layout(n).total > ws_bytes) {
+        set_error("closure_grad: need 1 <= n <= 2^20 and a workspace for n samples");
+        return CHORUS_EINVAL;
+    }
+    const TrainLayout L = train_layout(n);
+    unsigned char *W = (unsigned char *)ws;
+    const TrainBufs T = train_bufs(L, W, n);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_train_grad(X_dev, Y_dev, nullptr, 0, (int)n, params_dev, T, grad_dev, loss_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "closure_grad");
+    return CHORUS_OK;
+}
+
+int chorus_closure_train(const float *X_dev, const float *Y_dev, int64_t n, const int32_t *idx_dev, int32_t batch,
+                         int32_t iters, float *params_dev, float *adam_m_dev, float *adam_v_dev, int64_t step0,
+                         const double hyper[4], float *loss_dev, void *ws, size_t ws_bytes, void *stream) {
+    if (!X_dev || !Y_dev || !idx_dev || !params_dev || !adam_m_dev || !adam_v_dev || !hyper || !loss_dev || !ws) {
+        set_error("null argument");
+        return CHORUS_EINVAL;
+    }
+    if (n < 1 || n > INT32_MAX || batch < 1 || batch > kMaxBatch || iters < 0 || step0 < 0 ||
+        train_layout(batch).total > ws_bytes) {
+        set_error("closure_train: need 1 <= n < 2^31, 1 <= batch <= 2^20, iters >= 0, step0 >= 0 and a "
+                  "workspace for the batch");
+        return CHORUS_EINVAL;
+    }
+    const double lr = hyper[0], b1 = hyper[1], b2 = hyper[2], eps = hyper[3];
+    if (!(lr > 0.0) || !(b1 >= 0.0 && b1 < 1.0) || !(b2 >= 0.0 && b2 < 1.0) || !(eps > 0.0)) {
+        set_error("closure_train: need lr > 0, 0 <= beta < 1, eps > 0");
+        return CHORUS_EINVAL;
+    }
+    if (iters == 0) return CHORUS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    // every sample index must address a row of X and Y
+    std::vector<int32_t> hidx((size_t)iters * batch);
+    hipError_t e = hipMemcpyAsync(hidx.data(), idx_dev, sizeof(int32_t) * hidx.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "closure_train");
+    for (int32_t v : hidx)
+        if (v < 0 || v >= n) {
+            set_error("closure_train: sample index out of range");
+            return CHORUS_EINVAL;
+        }
+    const TrainLayout L = train_layout(batch);
+    unsigned char *W = (unsigned char *)ws;
+    const TrainBufs T = train_bufs(L, W, batch);
+    float *grad = (float *)(W + L.grad);
+    for (int32_t it = 0; it < iters && e == hipSuccess; ++it) {
+        e = launch_train_grad(X_dev, Y_dev, idx_dev, (int64_t)it * batch, batch, params_dev, T, grad,
+                              loss_dev + it, s);
+        if (e != hipSuccess) break;
+        const double t = (double)(step0 + it + 1);
+        AdamArgs a;
+        a.lr = (float)lr;
+        a.b1 = (float)b1;
+        a.b2 = (float)b2;
+        a.eps = (float)eps;
+        a.inv_bc1 = (float)(1.0 / (1.0 - std::pow(b1, t)));
+        a.inv_bc2 = (float)(1.0 / (1.0 - std::pow(b2, t)));
+        e = launch_adam(params_dev, adam_m_dev, adam_v_dev, grad, a, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "closure_train");
+    return CHORUS_OK;
+}
+
+// Gauss-Legendre nodes and weights on [0, 1] (Newton on the three-term
+// recurrence)
+static void gauss01(int n, double *x, double *w) {
+    for (int i = 0; i < n; ++i) {
+        double t = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2 * k - 1) * t * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) p0 = 1.0;
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+            const double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-16) break;
+        }
+        x[i] = 0.5 * (1.0 - t);
+        w[i] = 1.0 / ((1.0 - t * t) * dp * dp);  // (2 / ((1-t^2) P'^2)) / 2
+    }
+}
+
+// shifted Legendre polynomial of degree k on [0, 1]
+static double legendre01(int k, double x) {
+    const double t = 2.0 * x - 1.0;
+    double p0 = 1.0, p1 = t;
+    if (k == 0) return 1.0;
+    for (int j = 2; j <= k; ++j) {
+        const double p2 = ((2 * j - 1) * t * p1 - (j - 1) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+    }
+    return p1;
+}
+
+int chorus_closure_filter(chorus_mesh_t fine, chorus_mesh_t coarse, double gamma, const double *Qfine_dev,
+                          double *Qbar_dev, double *tau_dev, void *stream) {
+    Mesh *mf = reinterpret_cast<Mesh *>(fine);
+    Mesh *mc = reinterpret_cast<Mesh *>(coarse);
+    int rc = check_ready(mf);
+    if (rc) return rc;
+    rc = check_ready(mc);
+    if (rc) return rc;
+    if (!Qfine_dev || !Qbar_dev || !tau_dev || !(gamma > 1.0)) {
+        set_error("null device pointer or gamma <= 1");
+        return CHORUS_EINVAL;
+    }
+    if (mf->E != mc->E || mf->elem20 != mc->elem20 || mf->xyz != mc->xyz) {
+        set_error("closure_filter: fine and coarse must be the same hex mesh");
+        return CHORUS_EINVAL;
+    }
+    if (mf->N > 6 || mc->N > 3 || mc->N < 1 || mf->N <= mc->N) {
+        set_error("closure_filter: need coarse order <= 3, fine order <= 6 and fine order > coarse order");
+        return CHORUS_ENOTSUP;
+    }
+    FilterArgs A;
+    A.Qf = Qfine_dev;
+    A.solgeo_f = (const double *)((const unsigned char *)mf->dev_image + mf->layout.solgeo);
+    A.solgeo_c = (const double *)((const unsigned char *)mc->dev_image + mc->layout.solgeo);
+    A.Qbar = Qbar_dev;
+    A.tau = tau_dev;
+    A.E = mf->E;
+    A.nf = mf->N;
+    A.nc = mc->N;
+    A.gamma = gamma;
+    // P[a][i] = sum_k (2k+1) L_k(xc_a) int_0^1 L_k h_i, h_i the Lagrange basis
+    // on the fine solution points (quadrature exact for degree nf + nc)
+    const int nq = mf->N + mc->N;
+    double xq[16], wq[16];
+    gauss01(nq, xq, wq);
+    const double *xf = mf->basis.xs, *xc = mc->basis.xs;
+    for (int a = 0; a < 3; ++a)
+        for (int i = 0; i < 6; ++i) A.P[a][i] = 0.0;
+    for (int i = 0; i < mf->N; ++i) {
+        for (int k = 0; k < mc->N; ++k) {
+            double integ = 0.0;
+            for (int q = 0; q < nq; ++q) {
+                double h = 1.0;
+                for (int j = 0; j < mf->N; ++j)
+                    if (j != i) h *= (xq[q] - xf[j]) / (xf[i] - xf[j]);
+                integ += wq[q] * legendre01(k, xq[q]) * h;
+            }
+            for (int a = 0; a < mc->N; ++a) A.P[a][i] += (2 * k + 1) * legendre01(k, xc[a]) * integ;
+        }
+    }
+    hipError_t e = launch_filter(A, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "closure_filter");
+    return CHORUS_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,318 @@
+// Kernels of the learned subgrid closure that are not part of the SD
+// residual: packing the network for the bfloat16 matrix cores, FP32
+// training (forward, backward, Adam) and the per-element filter that makes
+// training targets from a higher-order solution.  The fused inference
+// lives with the residual kernels.
+//
+// Training is a sequence of small fixed-order kernels (no atomics), so a
+// run is bitwise reproducible:
+//   k_fwd_bwd    one thread per sample: forward pass, loss terms, and the
+//                pre-activation gradients dZ1, dZ2, dY (activations and
+//                GELU derivatives kept per sample, [t][64] rows)
+//   k_wgrad      one thread per (parameter, chunk of 64 samples): partial
+//                sums of the outer products
+//   k_wgrad_sum  chunk partials summed in chunk order
+//   k_loss       sum of the per-sample losses, fixed tree
+//   k_adam       Adam update (Kingma & Ba 2015) with bias correction
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "launch.hpp"
+#include "mlp_bf16.hpp"
+
+namespace chorus {
+
+// parameter vector offsets
+constexpr int kW1 = 0, kB1 = 1280, kW2 = 1344, kB2 = 5440, kW3 = 5504, kB3 = 6464;
+static_assert(kB3 + kMlpOut == kMlpParams, "parameter layout");
+
+// ---------------------------------------------------------------------------
+// packing
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_pack(const float *__restrict__ W, const float *__restrict__ norm,
+                                             unsigned char *__restrict__ model) {
+    const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
+    bool ok = true;
+    for (int q = lane; q < kMlpParams; q += 64) ok = ok && isfinite(W[q]);
+    for (int q = lane; q < 70; q += 64) ok = ok && isfinite(norm[q]);
+    uint32_t *fr = reinterpret_cast<uint32_t *>(model);
+    for (int f = 0; f < kMlpFrags; ++f) {
+        float a[8];
+        for (int i = 0; i < 8; ++i) {
+            float v = 0.0f;
+            if (f < 4) {
+                const int row = 16 * f + r, k = 8 * g + i;
+                v = (k < kMlpIn) ? W[kW1 + row * kMlpIn + k] : 0.0f;
+            } else if (f < 12) {
+                const int mt = (f - 4) >> 1, ks = (f - 4) & 1;
+                v = W[kW2 + (16 * mt + r) * kMlpHid + mlp_kperm(ks, g, i)];
+            } else {
+                const int ks = f - 12;
+                v = (r < kMlpOut) ? W[kW3 + r * kMlpHid + mlp_kperm(ks, g, i)] : 0.0f;
+            }
+            a[i] = v;
+        }
+        uint32_t *dst = fr + (f * 64 + lane) * 4;
+        for (int w = 0; w < 4; ++w) dst[w] = bf16_pair(a[2 * w], a[2 * w + 1]);
+    }
+    float *fl = reinterpret_cast<float *>(model + kMlpFloatOff);
+    for (int q = lane; q < kMlpNFloat; q += 64) {
+        float v = 0.0f;
+        if (q < kMlpB2) v = W[kB1 + q];
+        else if (q < kMlpB3) v = W[kB2 + q - kMlpB2];
+        else if (q < kMlpXMean) v = (q - kMlpB3 < kMlpOut) ? W[kB3 + q - kMlpB3] : 0.0f;
+        else if (q < kMlpXInv) v = norm[q - kMlpXMean];
+        else if (q < kMlpYMean) v = norm[20 + q - kMlpXInv];
+        else if (q < kMlpYStd) v = (q - kMlpYMean < kMlpOut) ? norm[40 + q - kMlpYMean] : 0.0f;
+        else v = (q - kMlpYStd < kMlpOut) ? norm[55 + q - kMlpYStd] : 0.0f;
+        fl[q] = v;
+    }
+    const bool all_ok = __all(ok);
+    if (lane == 0) reinterpret_cast<int *>(model + kMlpFlagOff)[0] = all_ok ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// training
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float gelu_prime_f(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+__global__ __launch_bounds__(64) void k_fwd_bwd(const float *__restrict__ X, const float *__restrict__ Y,
+                                                const int32_t *__restrict__ idx, int64_t base, int nb,
+                                                const float *__restrict__ W, TrainBufs T) {
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    if (t >= nb) return;
+    const int64_t s = idx ? (int64_t)idx[base + t] : base + t;
+    float x[kMlpIn];
+#pragma unroll
+    for (int i = 0; i < kMlpIn; ++i) x[i] = X[s * kMlpIn + i];
+    float *H1 = T.H1 + (int64_t)t * 64, *G1 = T.G1 + (int64_t)t * 64;
+    float *H2 = T.H2 + (int64_t)t * 64, *G2 = T.G2 + (int64_t)t * 64;
+    float h1[kMlpHid];
+#pragma unroll
+    for (int j = 0; j < kMlpHid; ++j) {
+        float z = W[kB1 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpIn; ++i) z += W[kW1 + j * kMlpIn + i] * x[i];
+        h1[j] = gelu_f(z);
+        H1[j] = h1[j];
+        G1[j] = gelu_prime_f(z);
+    }
+    float y[kMlpOut];
+#pragma unroll
+    for (int k = 0; k < kMlpOut; ++k) y[k] = W[kB3 + k];
+#pragma unroll 4
+    for (int j = 0; j < kMlpHid; ++j) {
+        float z = W[kB2 + j];
+#pragma unroll
+        for (int k = 0; k < kMlpHid; ++k) z += W[kW2 + j * kMlpHid + k] * h1[k];
+        const float h = gelu_f(z);
+        H2[j] = h;
+        G2[j] = gelu_prime_f(z);
+#pragma unroll
+        for (int k = 0; k < kMlpOut; ++k) y[k] += W[kW3 + k * kMlpHid + j] * h;
+    }
+    float l = 0.0f, dy[kMlpOut];
+    const float sc = 2.0f / ((float)T.n_mean * (float)kMlpOut);
+#pragma unroll
+    for (int k = 0; k < kMlpOut; ++k) {
+        const float e = y[k] - Y[s * kMlpOut + k];
+        l += e * e;
+        dy[k] = sc * e;
+        T.dY[(int64_t)t * 16 + k] = dy[k];
+    }
+    T.lossv[t] = l;
+    // back through layers 3 and 2: dZ2_j = (sum_k W3[k][j] dY_k) gelu'(z2_j),
+    // dH1_k = sum_j W2[j][k] dZ2_j
+    float dh1[kMlpHid];
+#pragma unroll
+    for (int k = 0; k < kMlpHid; ++k) dh1[k] = 0.0f;
+    float *dZ2 = T.dZ2 + (int64_t)t * 64, *dZ1 = T.dZ1 + (int64_t)t * 64;
+#pragma unroll 4
+    for (int j = 0; j < kMlpHid; ++j) {
+        float a = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kMlpOut; ++k) a += W[kW3 + k * kMlpHid + j] * dy[k];
+        const float dz = a * G2[j];
+        dZ2[j] = dz;
+#pragma unroll
+        for (int k = 0; k < kMlpHid; ++k) dh1[k] += W[kW2 + j * kMlpHid + k] * dz;
+    }
+#pragma unroll
+    for (int k = 0; k < kMlpHid; ++k) dZ1[k] = dh1[k] * G1[k];
+}
+
+// partial sums over chunk c (samples 64c .. 64c+63) of each parameter's
+// gradient: part[c][q]
+__global__ __launch_bounds__(64) void k_wgrad(const float *__restrict__ X, const int32_t *__restrict__ idx,
+                                              int64_t base, int nb, TrainBufs T) {
+    const int q = blockIdx.x * 64 + threadIdx.x, c = blockIdx.y;
+    if (q >= kMlpParams) return;
+    const int t0 = 64 * c, t1 = min(nb, t0 + 64);
+    float s = 0.0f;
+    if (q < kB1) {
+        const int j = q / kMlpIn, i = q % kMlpIn;
+        for (int t = t0; t < t1; ++t) {
+            const int64_t smp = idx ? (int64_t)idx[base + t] : base + t;
+            s += T.dZ1[(int64_t)t * 64 + j] * X[smp * kMlpIn + i];
+        }
+    } else if (q < kW2) {
+        const int j = q - kB1;
+        for (int t = t0; t < t1; ++t) s += T.dZ1[(int64_t)t * 64 + j];
+    } else if (q < kB2) {
+        const int j = (q - kW2) / kMlpHid, k = (q - kW2) % kMlpHid;
+        for (int t = t0; t < t1; ++t) s += T.dZ2[(int64_t)t * 64 + j] * T.H1[(int64_t)t * 64 + k];
+    } else if (q < kW3) {
+        const int j = q - kB2;
+        for (int t = t0; t < t1; ++t) s += T.dZ2[(int64_t)t * 64 + j];
+    } else if (q < kB3) {
+        const int k = (q - kW3) / kMlpHid, j = (q - kW3) % kMlpHid;
+        for (int t = t0; t < t1; ++t) s += T.dY[(int64_t)t * 16 + k] * T.H2[(int64_t)t * 64 + j];
+    } else {
+        const int k = q - kB3;
+        for (int t = t0; t < t1; ++t) s += T.dY[(int64_t)t * 16 + k];
+    }
+    T.part[(int64_t)c * kMlpParams + q] = s;
+}
+
+__global__ __launch_bounds__(64) void k_wgrad_sum(int nchunk, const float *__restrict__ part,
+                                                  float *__restrict__ grad) {
+    const int q = blockIdx.x * 64 + threadIdx.x;
+    if (q >= kMlpParams) return;
+    float s = 0.0f;
+    for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * kMlpParams + q];
+    grad[q] = s;
+}
+
+// loss = sum_t lossv[t] / (n_mean * 15): each lane sums a fixed strided
+// subset, then a fixed LDS tree
+__global__ __launch_bounds__(64) void k_loss(const float *__restrict__ lossv, int nb, int64_t n_mean,
+                                             float *__restrict__ out) {
+    __shared__ float red[64];
+    float s = 0.0f;
+    for (int t = threadIdx.x; t < nb; t += 64) s += lossv[t];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0] / ((float)n_mean * (float)kMlpOut);
+}
+
+__global__ __launch_bounds__(64) void k_adam(float *__restrict__ W, float *__restrict__ m, float *__restrict__ v,
+                                             const float *__restrict__ grad, AdamArgs a) {
+    const int q = blockIdx.x * 64 + threadIdx.x;
+    if (q >= kMlpParams) return;
+    const float g = grad[q];
+    const float mq = a.b1 * m[q] + (1.0f - a.b1) * g;
+    const float vq = a.b2 * v[q] + (1.0f - a.b2) * g * g;
+    m[q] = mq;
+    v[q] = vq;
+    W[q] -= a.lr * (mq * a.inv_bc1) / (sqrtf(vq * a.inv_bc2) + a.eps);
+}
+
+// ---------------------------------------------------------------------------
+// filter: per element L2 projection of |J| U to degree Nc - 1
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cart_flux(const double q[5], double gm1, double F[15]) {
+    const double r = q[0], m[3] = {q[1], q[2], q[3]}, E = q[4];
+    const double ir = 1.0 / r;
+    const double p = gm1 * (E - 0.5 * (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) * ir);
+    for (int c = 0; c < 3; ++c) {
+        F[c] = m[c];
+        for (int i = 0; i < 3; ++i) F[3 * (1 + i) + c] = m[i] * m[c] * ir + (i == c ? p : 0.0);
+        F[12 + c] = (E + p) * m[c] * ir;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_filter(FilterArgs A) {
+    constexpr int MAXF = 6, MAXC = 3;
+    __shared__ double U[20][MAXF * MAXF * MAXF];   // |J| Q (5) and |J| F(Q) (15) at the fine points
+    __shared__ double T1[20][MAXC * MAXF * MAXF];  // after the xi pass
+    __shared__ double T2[20][MAXC * MAXC * MAXF];  // after the eta pass
+    const int64_t e = blockIdx.x;
+    const int nf = A.nf, nc = A.nc, NPF = nf * nf * nf, NPC = nc * nc * nc;
+    const double gm1 = A.gamma - 1.0;
+    for (int p = threadIdx.x; p < NPF; p += 64) {
+        double q[5], F[15];
+        for (int v = 0; v < 5; ++v) q[v] = A.Qf[((int64_t)v * A.E + e) * NPF + p];
+        const double J = 1.0 / A.solgeo_f[(e * 13 + 9) * NPF + p];
+        cart_flux(q, gm1, F);
+        for (int v = 0; v < 5; ++v) U[v][p] = J * q[v];
+        for (int k = 0; k < 15; ++k) U[5 + k][p] = J * F[k];
+    }
+    __syncthreads();
+    // xi: (a, j, k) <- sum_i P[a][i] U(i, j, k)
+    for (int it = threadIdx.x; it < 20 * nc * nf * nf; it += 64) {
+        const int f = it / (nc * nf * nf), r = it % (nc * nf * nf), a = r % nc, jk = r / nc;
+        double s = 0.0;
+        for (int i = 0; i < nf; ++i) s += A.P[a][i] * U[f][i + nf * jk];
+        T1[f][a + nc * jk] = s;
+    }
+    __syncthreads();
+    // eta: (a, b, k) <- sum_j P[b][j] T1(a, j, k)
+    for (int it = threadIdx.x; it < 20 * nc * nc * nf; it += 64) {
+        const int f = it / (nc * nc * nf), r = it % (nc * nc * nf), a = r % nc, b = (r / nc) % nc, k = r / (nc * nc);
+        double s = 0.0;
+        for (int j = 0; j < nf; ++j) s += A.P[b][j] * T1[f][a + nc * (j + nf * k)];
+        T2[f][a + nc * (b + nc * k)] = s;
+    }
+    __syncthreads();
+    // zeta, divide by the coarse |J|, subgrid flux
+    for (int p = threadIdx.x; p < NPC; p += 64) {
+        const int a = p % nc, b = (p / nc) % nc, c = p / (nc * nc);
+        double g[20];
+        for (int f = 0; f < 20; ++f) {
+            double s = 0.0;
+            for (int k = 0; k < nf; ++k) s += A.P[c][k] * T2[f][a + nc * (b + nc * k)];
+            g[f] = s;
+        }
+        const double iJ = A.solgeo_c[(e * 13 + 9) * NPC + p];
+        double qb[5], F[15];
+        for (int v = 0; v < 5; ++v) qb[v] = g[v] * iJ;
+        cart_flux(qb, gm1, F);
+        for (int v = 0; v < 5; ++v) A.Qbar[((int64_t)v * A.E + e) * NPC + p] = qb[v];
+        for (int k = 0; k < 15; ++k)
+            A.tau[((int64_t)k * A.E + e) * NPC + p] = (k < 3) ? 0.0 : g[5 + k] * iJ - F[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_pack(const float *W, const float *norm, unsigned char *model, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack, dim3(1), dim3(64), 0, s, W, norm, model);
+    return hipGetLastError();
+}
+
+hipError_t launch_train_grad(const float *X, const float *Y, const int32_t *idx, int64_t base, int nb,
+                             const float *W, const TrainBufs &T, float *grad, float *loss, hipStream_t s) {
+    const int nchunk = (nb + 63) / 64;
+    hipLaunchKernelGGL(k_fwd_bwd, dim3(nchunk), dim3(64), 0, s, X, Y, idx, base, nb, W, T);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wgrad, dim3((kMlpParams + 63) / 64, nchunk), dim3(64), 0, s, X, idx, base, nb, T);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wgrad_sum, dim3((kMlpParams + 63) / 64), dim3(64), 0, s, nchunk, (const float *)T.part,
+                       grad);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_loss, dim3(1), dim3(64), 0, s, (const float *)T.lossv, nb, T.n_mean, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *W, float *m, float *v, const float *grad, const AdamArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3((kMlpParams + 63) / 64), dim3(64), 0, s, W, m, v, grad, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter(const FilterArgs &A, hipStream_t s) {
+    hipLaunchKernelGGL(k_filter, dim3((unsigned)A.E), dim3(64), 0, s, A);
+    return hipGetLastError();
+}
+
+}  // namespace chorus

@@ -28,11 +28,52 @@ struct StageArgs {
     int mode;          // 0 residual, 1 RK stage
 };
 
+// learned subgrid closure (FP64 path, N = 3): model == null switches it off
+struct ClosureArgs {
+    const unsigned char *model;  // packed BF16 network image
+    float *tau;                  // [15][E][NP] subgrid flux at the solution points (written by
+                                 // the gradient pass, read by the residual pass)
+};
+
 hipError_t launch_trace(const Mesh &m, const Geo &G, const double *Q, double *TQ, hipStream_t s);
 hipError_t launch_grad(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
-                       double *TV, hipStream_t s);
+                       double *TV, const ClosureArgs &C, hipStream_t s);
 hipError_t launch_resid(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
-                        const double *TV, const StageArgs &sa, hipStream_t s);
+                        const double *TV, const StageArgs &sa, const ClosureArgs &C, hipStream_t s);
+hipError_t launch_features(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
+                           float *X, hipStream_t s);
+// closure training buffers for a mini-batch of nb samples (rows of 64 or 16)
+struct TrainBufs {
+    float *H1, *G1, *H2, *G2, *dZ1, *dZ2;  // [nb][64]: activations, GELU derivatives, gradients
+    float *dY;                             // [nb][16]
+    float *lossv;                          // [nb]
+    float *part;                           // [ceil(nb/64)][6479] chunk partial gradients
+    int64_t n_mean;                        // samples the loss is averaged over
+};
+
+struct AdamArgs {
+    float lr, b1, b2, eps, inv_bc1, inv_bc2;  // inv_bc = 1 / (1 - beta^t)
+};
+
+// filter from order nf to order nc (nc <= 3, nf <= 6) on one hex mesh
+struct FilterArgs {
+    const double *Qf;        // [5][E][nf^3]
+    const double *solgeo_f;  // fine geometry image: 1/|J| at index 9 of [E][13][nf^3]
+    const double *solgeo_c;  // coarse geometry image
+    double *Qbar;            // [5][E][nc^3]
+    double *tau;             // [15][E][nc^3]
+    int64_t E;
+    int nf, nc;
+    double gamma;
+    double P[3][6];          // 1D projection: coarse point a <- fine point i
+};
+
+hipError_t launch_pack(const float *W, const float *norm, unsigned char *model, hipStream_t s);
+hipError_t launch_train_grad(const float *X, const float *Y, const int32_t *idx, int64_t base, int nb,
+                             const float *W, const TrainBufs &T, float *grad, float *loss, hipStream_t s);
+hipError_t launch_adam(float *W, float *m, float *v, const float *grad, const AdamArgs &a, hipStream_t s);
+hipError_t launch_filter(const FilterArgs &A, hipStream_t s);
+
 hipError_t launch_sums(const double *Q, const double *solw, int64_t n, double *part, int nblocks, double *out,
                        hipStream_t s);
 hipError_t launch_check(const double *Q, int64_t n, double gm1, int *flag, hipStream_t s);

@@ -24,6 +24,7 @@
 #include <cstdint>
 
 #include "launch.hpp"
+#include "mlp_bf16.hpp"
 #include "sd_common.hpp"
 
 namespace chorus {
@@ -148,13 +149,59 @@ __global__ __launch_bounds__(NT) void k_trace(Ops<N> op, Geo G, const double *__
 
 // viscous flux of the own side at interior interface points, along the
 // outward area vector: TV[e][f][v][pp]
+// learned subgrid flux at the solution points of the block's elements (one
+// wave, all points in 16-point tiles): features (Q, grad Q) -> network ->
+// stau (LDS) and tau[k][E][NP] (global)
 template <int N, int EPB, int NT>
+__device__ __forceinline__ void closure_tau(const ClosureArgs &C, int64_t E, int64_t e0,
+                                            double (*sq)[5][N * N * N], double (*sgr)[15][N * N * N],
+                                            float (*stau)[15][N * N * N]) {
+    constexpr int NP = N * N * N, NPTS = EPB * NP, NPT = (NPTS + 15) / 16;
+    static_assert(NT == 64, "the closure runs one wave per block");
+    const int lane = threadIdx.x, g = lane >> 4;
+    u32x4_t xb[NPT];
+#pragma unroll
+    for (int pt = 0; pt < NPT; ++pt) {
+        const int pidx = 16 * pt + (lane & 15);
+        const int el = pidx / NP, sp = pidx % NP;
+        const bool ok = pidx < NPTS && e0 + el < E;
+        float x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int f = 8 * g + i;
+            double raw = 0.0;
+            if (ok && f < 5) raw = sq[el][f][sp];
+            else if (ok && f < 20) raw = sgr[el][f - 5][sp];
+            x[i] = (ok && f < 20) ? mlp_norm_feature(C.model, f, raw) : 0.0f;
+        }
+        xb[pt] = u32x4_t{bf16_pair(x[0], x[1]), bf16_pair(x[2], x[3]), bf16_pair(x[4], x[5]), bf16_pair(x[6], x[7])};
+    }
+    f32x4_t out[NPT];
+    mlp_eval<NPT>(C.model, xb, out);
+#pragma unroll
+    for (int pt = 0; pt < NPT; ++pt) {
+        const int pidx = 16 * pt + (lane & 15);
+        const int el = pidx / NP, sp = pidx % NP;
+        if (pidx >= NPTS || e0 + el >= E) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * g + i;
+            if (k >= kMlpOut) continue;
+            stau[el][k][sp] = out[pt][i];
+            C.tau[((int64_t)k * E + e0 + el) * NP + sp] = out[pt][i];
+        }
+    }
+}
+
+template <int N, int EPB, int NT, bool CL>
 __global__ __launch_bounds__(NT) void k_grad(Ops<N> op, Geo G, PhysParams P, const double *__restrict__ Q,
-                                             const double *__restrict__ TQ, double *__restrict__ TV) {
+                                             const double *__restrict__ TQ, double *__restrict__ TV,
+                                             ClosureArgs C) {
     constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
     __shared__ double sq[EPB][5][NP];
     __shared__ double sqs[EPB][6][5][NF2];
     __shared__ double sgr[EPB][15][NP];
+    __shared__ float stau[CL ? EPB : 1][15][CL ? NP : 1];
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     load_q<N, EPB, NT>(Q, G.E, e0, sq);
     __syncthreads();
@@ -162,6 +209,10 @@ __global__ __launch_bounds__(NT) void k_grad(Ops<N> op, Geo G, PhysParams P, con
     __syncthreads();
     gradients<N, EPB, NT>(op, G, e0, sq, sqs, sgr);
     __syncthreads();
+    if constexpr (CL) {
+        closure_tau<N, EPB, NT>(C, G.E, e0, sq, sgr, stau);
+        __syncthreads();
+    }
     for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
         const int64_t e = e0 + el;
@@ -187,24 +238,65 @@ __global__ __launch_bounds__(NT) void k_grad(Ops<N> op, Geo G, PhysParams P, con
         double S[3], fv[5];
         for (int c = 0; c < 3; ++c) S[c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
         flux_viscous(q, g, S, P, fv);
+        if constexpr (CL) {
+            // the own-side subgrid flux enters the trace with the sign of -F_v
+            for (int v = 0; v < 5; ++v)
+                for (int c = 0; c < 3; ++c) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int b = 0; b < N; ++b) t += op.I[m][b] * (double)stau[el][v * 3 + c][base + b * st];
+                    fv[v] -= t * S[c];
+                }
+        }
         for (int v = 0; v < 5; ++v) TV[((e * 6 + f) * 5 + v) * NF2 + pp] = fv[v];
+    }
+}
+
+// raw closure features at the solution points: X[e NP + p][20] = (Q, grad Q)
+template <int N, int EPB, int NT>
+__global__ __launch_bounds__(NT) void k_features(Ops<N> op, Geo G, PhysParams P, const double *__restrict__ Q,
+                                                 const double *__restrict__ TQ, float *__restrict__ X) {
+    constexpr int NP = N * N * N, NF2 = N * N;
+    __shared__ double sq[EPB][5][NP];
+    __shared__ double sqs[EPB][6][5][NF2];
+    __shared__ double sgr[EPB][15][NP];
+    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    load_q<N, EPB, NT>(Q, G.E, e0, sq);
+    __syncthreads();
+    common_solution<N, EPB, NT>(op, G, P, TQ, e0, sq, sqs);
+    __syncthreads();
+    gradients<N, EPB, NT>(op, G, e0, sq, sqs, sgr);
+    __syncthreads();
+    for (int it = threadIdx.x; it < EPB * NP * 20; it += NT) {
+        const int el = it / (NP * 20), r = it % (NP * 20), p = r / 20, f = r % 20;
+        const int64_t e = e0 + el;
+        if (e >= G.E) continue;
+        X[(e * NP + p) * 20 + f] = (float)(f < 5 ? sq[el][f][p] : sgr[el][f - 5][p]);
     }
 }
 
 
 
-template <int N, int EPB, int NT>
+template <int N, int EPB, int NT, bool CL>
 __global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, const double *Q,
                                               const double *__restrict__ TQ,
-                                              const double *__restrict__ TV, StageArgs S_) {
+                                              const double *__restrict__ TV, StageArgs S_, ClosureArgs C) {
     constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
     __shared__ double sq[EPB][5][NP];
     __shared__ double sqs[EPB][6][5][NF2];
     __shared__ double sgr[EPB][15][NP];
     __shared__ double sft[EPB][5][NFL];
     __shared__ double sdiv[EPB][5][NP];
+    __shared__ float stau[CL ? EPB : 1][15][CL ? NP : 1];
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     const double gm1 = P.gamma - 1.0;
+    if constexpr (CL) {
+        for (int it = threadIdx.x; it < EPB * 15 * NP; it += NT) {
+            const int el = it / (15 * NP), r = it % (15 * NP), k = r / NP, p = r % NP;
+            const int64_t e = e0 + el;
+            stau[el][k][p] = (e < G.E) ? C.tau[((int64_t)k * G.E + e) * NP + p] : 0.0f;
+        }
+    }
     load_q<N, EPB, NT>(Q, G.E, e0, sq);
     __syncthreads();
     common_solution<N, EPB, NT>(op, G, P, TQ, e0, sq, sqs);
@@ -234,11 +326,24 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, co
                 }
             }
             for (int c = 0; c < 3; ++c) S[c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+            // learned subgrid flux along S (interpolated like the gradients)
+            double ts[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            if constexpr (CL) {
+                for (int v = 0; v < 5; ++v)
+                    for (int c = 0; c < 3; ++c) {
+                        double t = 0.0;
+#pragma unroll
+                        for (int b = 0; b < N; ++b) t += op.I[m][b] * (double)stau[el][v * 3 + c][base + b * st];
+                        ts[v] += t * S[c];
+                    }
+            }
             if (m > 0 && m < N) {
                 double fi[5], fv[5];
                 flux_inviscid(q, S, gm1, fi);
                 flux_viscous(q, g, S, P, fv);
                 for (int v = 0; v < 5; ++v) F[v] = fi[v] - fv[v];
+                if constexpr (CL)
+                    for (int v = 0; v < 5; ++v) F[v] += ts[v];
             } else {
                 const int f = 2 * d + (m == N ? 1 : 0);
                 const double sg = (m == N) ? 1.0 : -1.0;
@@ -255,8 +360,11 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, co
                     for (int v = 0; v < 5; ++v) qn[v] = tq[v * NF2 + pn];
                     flux_rusanov(q, qn, So, P, phi);
                     flux_viscous(q, g, So, P, fvo);
-                    // the neighbour stored its viscous flux along its own outward
-                    // area vector, which is -So
+                    // own subgrid flux along So (ts is along S = sg So)
+                    if constexpr (CL)
+                        for (int v = 0; v < 5; ++v) fvo[v] -= sg * ts[v];
+                    // the neighbour stored its viscous (minus subgrid) flux along
+                    // its own outward area vector, which is -So
                     for (int v = 0; v < 5; ++v) phi[v] -= 0.5 * (fvo[v] + (-tv[v * NF2 + pn]));
                 } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
                     flux_wall(q, g, So, bc == CHORUS_BC_OUTER, P, phi);
@@ -468,21 +576,46 @@ static hipError_t launch_trace_t(const Mesh &m, const Geo &G, const double *Q, d
 
 template <int N>
 static hipError_t launch_grad_t(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q,
-                                const double *TQ, double *TV, hipStream_t s) {
+                                const double *TQ, double *TV, const ClosureArgs &C, hipStream_t s) {
     constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
     const Ops<N> op = make_ops<N>(m.basis);
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
-    hipLaunchKernelGGL((k_grad<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, op, G, P, Q, TQ, TV);
+    if (C.model) {
+        if constexpr (N == 3)
+            hipLaunchKernelGGL((k_grad<N, EPB, NT, true>), dim3(nb), dim3(NT), 0, s, op, G, P, Q, TQ, TV, C);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((k_grad<N, EPB, NT, false>), dim3(nb), dim3(NT), 0, s, op, G, P, Q, TQ, TV, C);
+    }
     return hipGetLastError();
 }
 
 template <int N>
 static hipError_t launch_resid_t(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q,
-                                 const double *TQ, const double *TV, const StageArgs &sa, hipStream_t s) {
+                                 const double *TQ, const double *TV, const StageArgs &sa, const ClosureArgs &C,
+                                 hipStream_t s) {
     constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
     const Ops<N> op = make_ops<N>(m.basis);
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
-    hipLaunchKernelGGL((k_resid<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, op, G, P, Q, TQ, TV, sa);
+    if (C.model) {
+        if constexpr (N == 3)
+            hipLaunchKernelGGL((k_resid<N, EPB, NT, true>), dim3(nb), dim3(NT), 0, s, op, G, P, Q, TQ, TV, sa, C);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((k_resid<N, EPB, NT, false>), dim3(nb), dim3(NT), 0, s, op, G, P, Q, TQ, TV, sa, C);
+    }
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_features_t(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q,
+                                    const double *TQ, float *X, hipStream_t s) {
+    constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
+    const Ops<N> op = make_ops<N>(m.basis);
+    const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
+    hipLaunchKernelGGL((k_features<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, op, G, P, Q, TQ, X);
     return hipGetLastError();
 }
 
@@ -502,14 +635,20 @@ hipError_t launch_trace(const Mesh &m, const Geo &G, const double *Q, double *TQ
 #undef C_
 }
 hipError_t launch_grad(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
-                       double *TV, hipStream_t s) {
-#define C_(n) launch_grad_t<n>(m, G, P, Q, TQ, TV, s)
+                       double *TV, const ClosureArgs &C, hipStream_t s) {
+#define C_(n) launch_grad_t<n>(m, G, P, Q, TQ, TV, C, s)
     CHORUS_DISPATCH(m.N, C_)
 #undef C_
 }
 hipError_t launch_resid(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
-                        const double *TV, const StageArgs &sa, hipStream_t s) {
-#define C_(n) launch_resid_t<n>(m, G, P, Q, TQ, TV, sa, s)
+                        const double *TV, const StageArgs &sa, const ClosureArgs &C, hipStream_t s) {
+#define C_(n) launch_resid_t<n>(m, G, P, Q, TQ, TV, sa, C, s)
+    CHORUS_DISPATCH(m.N, C_)
+#undef C_
+}
+hipError_t launch_features(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
+                           float *X, hipStream_t s) {
+#define C_(n) launch_features_t<n>(m, G, P, Q, TQ, X, s)
     CHORUS_DISPATCH(m.N, C_)
 #undef C_
 }

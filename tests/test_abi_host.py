@@ -114,3 +114,20 @@ def test_stable_dt_positive(ch, oracle_mod):
     Q, pars = cm.init_polytrope(0.7, 1.0)
     dt = cm.stable_dt(ch.physics(GM=pars["GM"]), Q, 0.5)
     assert 1e-3 < dt < 0.2
+
+
+def test_closure_host_errors():
+    """Closure entry points validate their arguments before any device work."""
+    import ctypes
+    import paper_1503_00834_amd as ch
+    L = ch._lib
+    b = ctypes.c_size_t()
+    assert L.chorus_closure_model_bytes(ctypes.byref(b)) == 0 and b.value == 15360
+    assert L.chorus_closure_train_workspace_bytes(0, ctypes.byref(b)) == -1
+    assert L.chorus_closure_train_workspace_bytes(4096, ctypes.byref(b)) == 0 and b.value > 4096 * 64 * 4 * 6
+    assert L.chorus_closure_pack(None, None, None, None) == -1
+    assert L.chorus_closure_grad(None, None, 10, None, None, None, None, 0, None) == -1
+    h = (ctypes.c_double * 4)(1e-3, 0.9, 0.999, 1e-8)
+    assert L.chorus_closure_train(None, None, 10, None, 1, 1, None, None, None, 0, h, None, None, 0,
+                                  None) == -1
+    assert ctypes.sizeof(ch.Physics) == 14 * 8 + 4 * 4 + 8
