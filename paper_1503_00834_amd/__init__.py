@@ -155,7 +155,7 @@ class Mesh:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:
             _lib.chorus_mesh_destroy(h)
             self.handle = None
 
