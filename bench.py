@@ -92,6 +92,29 @@ def alg_flops_per_stage_point(N):
     return per_step / 3.0
 
 
+def closure_leg(panel_n=32, radial_n=16):
+    """The learned closure on the closure-run shell (6 x 32 x 32 x 16 =
+    98,304 hexes): order-3 steps with and without the fused bfloat16
+    network, and the resolved order-6 run on the same mesh, per unit
+    simulated time.  The network's matrix-core rate is its algorithmic
+    flops (2 (20*64 + 64*64 + 64*15) = 12,672 per point) over the extra
+    time the fused gradient pass takes."""
+    from paper_1503_00834_amd import closure
+    c = closure.cost_per_time(panel_n, radial_n, kernel_times=True)
+    g_cl = c["closure"]["kernel_ms_per_launch"]["k_grad"]
+    g_pl = c["plain"]["kernel_ms_per_launch"]["k_grad"]
+    flops = 12672.0 * c["closure"]["points"]
+    dt_mlp = max(g_cl - g_pl, 1e-6) * 1e-3
+    return {"workload": "closure_98k_N3", "hexes": 6 * panel_n * panel_n * radial_n,
+            "dof_updates_per_s": {k: c[k]["dof_updates_per_s"] for k in ("closure", "plain", "resolved")},
+            "seconds_per_unit_time": {k: c[k]["seconds_per_time"] for k in ("closure", "plain", "resolved")},
+            "cost_ratio_resolved_over_closure": c["ratio_resolved_over_closure"],
+            "grad_kernel_ms": {"closure": g_cl, "plain": g_pl},
+            "mlp": {"bound": "mfma", "achieved": flops / dt_mlp / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                    "frac": flops / dt_mlp / 1e12 / 2500.0, "alg_flops_per_launch": flops,
+                    "note": "network time = fused gradient pass minus the plain one"}}
+
+
 def cpu_baseline(cfg, budget_s=15.0):
     """The CPU oracle on the same workload for a bounded number of steps."""
     import oracle
@@ -127,6 +150,7 @@ def main():
     ap.add_argument("--workload", default="jupiter_41k_N4")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB 5 times (HBM counter "
@@ -227,6 +251,10 @@ def main():
                      / (HBM_PEAK_GBS * 1e9)},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in ktimes.items()},
     }
+    if not args.no_closure:
+        log("closure leg")
+        out["closure"] = closure_leg()
+        torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)

@@ -154,7 +154,12 @@ class ShellDiagnostics:
     """Radial bins and spherical-harmonic basis on the solution points of a
     shell mesh (host arrays)."""
 
-    def __init__(self, mesh, r_inner, r_outer, n_bins=None, l_max=10, top_fraction=0.25):
+    def __init__(self, mesh, r_inner, r_outer, n_bins=None, l_max=10, top_depth=None):
+        """top_depth: thickness of the outer layer whose velocity is
+        projected on the spherical harmonics; it should cover whole element
+        layers (all solution points of a radial column), which makes the
+        solution-point quadrature of the projection accurate (default: the
+        whole shell)."""
         xyz, wJ = mesh.solpts()
         self.w = wJ
         r = np.sqrt((xyz ** 2).sum(0))
@@ -166,7 +171,8 @@ class ShellDiagnostics:
         self.r_mid = 0.5 * (edges[1:] + edges[:-1])
         self.bw = np.bincount(self.bin, weights=wJ, minlength=nb)
         # spectrum: volume-weighted projection of the top layer onto Y_lm
-        top = r >= r_outer - top_fraction * (r_outer - r_inner)
+        depth = (r_outer - r_inner) if top_depth is None else top_depth
+        top = r >= r_outer - depth * (1.0 + 1e-9)
         self.top = np.nonzero(top)[0]
         th = np.arccos(np.clip(xyz[2, self.top] / r[self.top], -1, 1))
         ph = np.arctan2(xyz[1, self.top], xyz[0, self.top])
@@ -365,7 +371,7 @@ def experiment(panel_n=6, radial_n=3, beta=0.7, n_rho=1.0, omega=0.5, nu=1e-3, v
     if pcl is not None:
         report["r2_heldout"], _ = apriori_r2(mc, pcl, Qb0, tau0)
     refs = [filter_to_coarse(mf, mc, gamma, s)[0] for s in snaps[n_train + 1:]]
-    diag = ShellDiagnostics(mc, ri, ro)
+    diag = ShellDiagnostics(mc, ri, ro, top_depth=(ro - ri) / radial_n)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     errs = judged_runs(mc, diag, pplain, pcl, Qb0, refs, dtc, steps_c, gamma)
@@ -377,7 +383,8 @@ def experiment(panel_n=6, radial_n=3, beta=0.7, n_rho=1.0, omega=0.5, nu=1e-3, v
     return report
 
 
-def cost_per_time(panel_n, radial_n, beta=0.7, order_fine=6, order_coarse=3, steps=4, cfl=0.3, seed=0):
+def cost_per_time(panel_n, radial_n, beta=0.7, order_fine=6, order_coarse=3, steps=4, cfl=0.3, seed=0,
+                  kernel_times=False):
     """GPU seconds per unit simulated time of the resolved run (order_fine)
     and of the coarse run (order_coarse) without and with the fused closure
     (a seeded untrained network: the arithmetic does not depend on the
@@ -418,6 +425,13 @@ def cost_per_time(panel_n, radial_n, beta=0.7, order_fine=6, order_coarse=3, ste
         sec = a.elapsed_time(b) * 1e-3
         out[name] = {"points": m.n_solpts, "dt": dt, "seconds_per_step": sec / steps,
                      "seconds_per_time": sec / (steps * dt), "dof_updates_per_s": m.n_solpts * steps / sec}
+        if kernel_times:
+            from . import chorus_kernel_timing, chorus_kernel_times
+            chorus_kernel_timing(True)
+            chorus_rk_step(m, ph, Q, dt, 1, ws)
+            torch.cuda.synchronize()
+            chorus_kernel_timing(False)
+            out[name]["kernel_ms_per_launch"] = {k: v[0] / max(v[1], 1) for k, v in chorus_kernel_times().items()}
         del Q, ws
     out["ratio_resolved_over_closure"] = out["resolved"]["seconds_per_time"] / out["closure"]["seconds_per_time"]
     return out
