@@ -58,6 +58,8 @@ def lib():
         L.ora_residual_sgs.argtypes = [P, P, dp, dp, dp]
         L.ora_gradients.argtypes = [P, P, dp, dp]
         L.ora_rk3.argtypes = [P, P, dp, ctypes.c_double, ctypes.c_int]
+        L.ora_ssp54.argtypes = [P, P, dp, ctypes.c_double, ctypes.c_int]
+        L.ora_ssp54_table.argtypes = [dp, dp]
         L.ora_sums.argtypes = [P, dp, dp]
         L.ora_polytrope.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, dp, ctypes.c_double, dp, dp]
@@ -84,6 +86,14 @@ def phys(gamma=5.0 / 3.0, R_gas=1.0, GM=0.0, omega=0.0, nu=0.0, kappa=0.0, kappa
     for i in range(5):
         p.bc_state[i] = bc_state[i]
     return p
+
+
+def ssp54_table():
+    """(alpha, beta) [5][5] of the SSPRK(5,4) Shu-Osher form (row = stage)."""
+    a = np.zeros(25)
+    b = np.zeros(25)
+    lib().ora_ssp54_table(_dp(a), _dp(b))
+    return a.reshape(5, 5), b.reshape(5, 5)
 
 
 def basis(N):
@@ -174,6 +184,12 @@ class OracleMesh:
     def rk3(self, ph, Q, dt, nsteps):
         Q = np.array(Q, dtype=np.float64, copy=True).reshape(5, self.E, self.np)
         lib().ora_rk3(self._h, ctypes.byref(ph), _dp(Q), float(dt), int(nsteps))
+        return Q
+
+    def ssp54(self, ph, Q, dt, nsteps):
+        """nsteps of the five-stage fourth-order SSP Runge-Kutta method."""
+        Q = np.array(Q, dtype=np.float64, copy=True).reshape(5, self.E, self.np)
+        lib().ora_ssp54(self._h, ctypes.byref(ph), _dp(Q), float(dt), int(nsteps))
         return Q
 
     def sums(self, Q):

@@ -999,6 +999,61 @@ void ora_rk3(const ora_mesh *m, const ora_phys *ph, double *Q, double dt, int ns
     }
 }
 
+/* Five-stage fourth-order SSP Runge-Kutta, SSPRK(5,4) of Spiteri & Ruuth
+ * (2002), in Shu-Osher form u_i = sum_k alpha[i][k] u_k + beta[i][k] dt L(u_k)
+ * (the paper's integrator, Section 7.5); coefficients as published. */
+static const double SSP54_A[5][5] = {
+    {1.0, 0, 0, 0, 0},
+    {0.444370493651235, 0.555629506348765, 0, 0, 0},
+    {0.620101851488403, 0, 0.379898148511597, 0, 0},
+    {0.178079954393132, 0, 0, 0.821920045606868, 0},
+    {0, 0, 0.517231671970585, 0.096059710526147, 0.386708617503269}};
+static const double SSP54_B[5][5] = {
+    {0.391752226571890, 0, 0, 0, 0},
+    {0, 0.368410593050371, 0, 0, 0},
+    {0, 0, 0.251891774271694, 0, 0},
+    {0, 0, 0, 0.544974750228521, 0},
+    {0, 0, 0, 0.063692468666290, 0.226007483236906}};
+
+void ora_ssp54_table(double alpha[25], double beta[25])
+{
+    for (int i = 0; i < 5; ++i)
+        for (int k = 0; k < 5; ++k) {
+            alpha[i * 5 + k] = SSP54_A[i][k];
+            beta[i * 5 + k] = SSP54_B[i][k];
+        }
+}
+
+void ora_ssp54(const ora_mesh *m, const ora_phys *ph, double *Q, double dt, int nsteps)
+{
+    const long n = 5 * m->E * m->np;
+    double *u[5], *L[5];
+    for (int k = 0; k < 5; ++k) {
+        u[k] = malloc(sizeof(double) * n);
+        L[k] = malloc(sizeof(double) * n);
+        if (!u[k] || !L[k])
+            abort();
+    }
+    for (int st = 0; st < nsteps; ++st) {
+        memcpy(u[0], Q, sizeof(double) * n);
+        for (int i = 0; i < 5; ++i) {
+            /* stage i + 1 from the stages 0..i */
+            ora_residual(m, ph, u[i], L[i]);
+            double *out = (i < 4) ? u[i + 1] : Q;
+            for (long t = 0; t < n; ++t) {
+                double s = 0.0;
+                for (int k = 0; k <= i; ++k)
+                    s += SSP54_A[i][k] * u[k][t] + SSP54_B[i][k] * dt * L[k][t];
+                out[t] = s;
+            }
+        }
+    }
+    for (int k = 0; k < 5; ++k) {
+        free(u[k]);
+        free(L[k]);
+    }
+}
+
 void ora_sums(const ora_mesh *m, const double *Q, double out[5])
 {
     int N = m->N;

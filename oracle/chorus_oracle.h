@@ -64,6 +64,10 @@ void ora_residual_sgs(const ora_mesh *m, const ora_phys *ph, const double *Q, co
  * out[v*3+c][E][N^3] */
 void ora_gradients(const ora_mesh *m, const ora_phys *ph, const double *Q, double *out);
 void ora_rk3(const ora_mesh *m, const ora_phys *ph, double *Q, double dt, int nsteps);
+/* five-stage fourth-order SSP Runge-Kutta (Spiteri & Ruuth 2002), Shu-Osher
+ * form; ora_ssp54_table exports its alpha[5][5], beta[5][5] (row = stage) */
+void ora_ssp54(const ora_mesh *m, const ora_phys *ph, double *Q, double dt, int nsteps);
+void ora_ssp54_table(double alpha[25], double beta[25]);
 /* sum over all solution points of w w w |J| Q_v, fixed serial order */
 void ora_sums(const ora_mesh *m, const double *Q, double out[5]);
 

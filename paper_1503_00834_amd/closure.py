@@ -8,7 +8,7 @@ the judge's diagnostics.
 
 Pipeline (the paper names subgrid modelling for large-eddy runs as the
 code's next step, Summary; its diagnostics are the kinetic energy and mean
-radial profiles of Section 6.2 and the velocity spectra of the benchmarks):
+radial profiles of Section 7.2 and the velocity spectra of the benchmarks):
 
   1. resolved run at order N_f on a hex mesh (snapshots of Q);
   2. each snapshot filtered to order N_c on the same mesh
@@ -148,7 +148,7 @@ def apriori_r2(mesh_c, phys_cl, Qbar, tau, ws=None):
 
 
 # ---------------------------------------------------------------------------
-# judge (diagnostics of Section 6.2 and the benchmarks' spectra)
+# judge (diagnostics of Section 7.2 and the benchmarks' spectra)
 # ---------------------------------------------------------------------------
 class ShellDiagnostics:
     """Radial bins and spherical-harmonic basis on the solution points of a

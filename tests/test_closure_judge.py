@@ -1,5 +1,5 @@
 """Host-side pieces of the closure judge (CPU): the shell diagnostics
-(radial mean profiles, Section 6.2 quantities; spherical-harmonic velocity
+(radial mean profiles, Section 7.2 quantities; spherical-harmonic velocity
 spectrum) against closed forms, and the decision rule."""
 import math
 

@@ -390,3 +390,65 @@ def test_entropy_diffusion_converges(oracle_mod, which):
         errs.append(math.sqrt((wJ * err ** 2).sum() / (wJ * want ** 2).sum()))
         assert np.abs(Rd[:4]).max() < 1e-12
     assert errs[1] < 0.05 and errs[1] < errs[0] / 2.0, errs
+
+
+# --------------------------------------------------------------------------
+# five-stage fourth-order SSP Runge-Kutta (the paper's integrator)
+# --------------------------------------------------------------------------
+def _butcher_from_shu_osher(al, be):
+    """Butcher tableau (A, b, c) of u_i = sum_k al[i][k] u_k + be[i][k] dt L(u_k)."""
+    s = al.shape[0]
+    A = np.zeros((s + 1, s))
+    for i in range(1, s + 1):
+        for k in range(i):
+            A[i] += al[i - 1, k] * A[k]
+            A[i, k] += be[i - 1, k]
+    return A[:s], A[s], A[:s].sum(1)
+
+
+def test_ssp54_order_conditions(oracle_mod):
+    """The exported coefficients satisfy the eight order conditions of a
+    fourth-order Runge-Kutta method (Butcher), not the fifth-order quadrature
+    condition, and form a convex (SSP) combination."""
+    al, be = oracle_mod.ssp54_table()
+    assert np.allclose(al.sum(1), 1.0, atol=1e-14) and (al >= 0).all() and (be >= 0).all()
+    A, b, c = _butcher_from_shu_osher(al, be)
+    conds = [b.sum() - 1, b @ c - 1 / 2, b @ c ** 2 - 1 / 3, b @ A @ c - 1 / 6, b @ c ** 3 - 1 / 4,
+             b @ (c * (A @ c)) - 1 / 8, b @ A @ c ** 2 - 1 / 12, b @ A @ A @ c - 1 / 24]
+    assert np.abs(conds).max() < 1e-14, conds
+    assert abs(b @ c ** 4 - 1 / 5) > 1e-3
+
+
+def test_ssp54_linear_local_error_is_fifth_order(oracle_mod):
+    """Coriolis on a uniform state is a linear rotation; one step's deviation
+    from the exact rotation exp(dt L) scales as dt^5 (time steps within the
+    acoustic stability limit of the mesh, so rounding noise stays small)."""
+    from scipy.linalg import expm
+    om = oracle_mod.OracleMesh(box_mesh(3, 3, 3, periodic=(True,) * 3), 3)
+    Om = 0.8
+    L = np.array([[0.0, 2 * Om], [-2 * Om, 0.0]])
+    errs = []
+    for dt in (0.08, 0.04):
+        Q = om.ssp54(oracle_mod.phys(omega=Om), _uniform(om), dt, 1)
+        want = expm(dt * L) @ Q_UNIFORM[1:3]
+        errs.append(max(abs(Q[1].mean() - want[0]), abs(Q[2].mean() - want[1])))
+        assert np.ptp(Q[1]) < 1e-12 and np.ptp(Q[2]) < 1e-12
+    rate = math.log(errs[0] / errs[1]) / math.log(2.0)
+    assert 4.7 < rate < 5.3, (errs, rate)
+
+
+def test_ssp54_temporal_order_four(oracle_mod):
+    """Nonlinear Euler flux: on a fixed mesh the SSPRK(5,4) solution at
+    t = 0.25 converges in dt at order 4 (against a dt/8 reference)."""
+    mesh = box_mesh(4, 3, 3, lengths=(1.0, 0.3, 0.3), periodic=(True,) * 3, curve=0.01)
+    om = oracle_mod.OracleMesh(mesh, 3)
+    Q0 = _density_wave(om, 0.0)
+    ph = oracle_mod.phys()
+    T = 0.25
+    ref = om.ssp54(ph, Q0, T / 160, 160)
+    errs = []
+    for n in (20, 40):
+        Q = om.ssp54(ph, Q0, T / n, n)
+        errs.append(np.abs(Q - ref).max())
+    rate = math.log(errs[0] / errs[1]) / math.log(2.0)
+    assert rate > 3.6, (errs, rate)
