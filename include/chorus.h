@@ -58,6 +58,7 @@ enum {
 
 enum { CHORUS_FP64 = 0, CHORUS_MIXED = 1 };            /* chorus_physics.precision */
 enum { CHORUS_CLOSURE_NONE = 0, CHORUS_CLOSURE_MLP = 1 }; /* chorus_physics.closure */
+enum { CHORUS_SSPRK3 = 0, CHORUS_SSPRK54 = 1 };         /* chorus_physics.integrator */
 enum { CHORUS_CHECK_FINITE = 1 };                      /* chorus_physics.flags     */
 enum { CHORUS_BC_INTERIOR = -1, CHORUS_BC_INNER = 1, CHORUS_BC_OUTER = 2,
        CHORUS_BC_STATE = 3 };
@@ -97,7 +98,8 @@ typedef struct {
                                  add the learned subgrid flux (order 3, FP64
                                  precision only; see the closure section)     */
     int32_t flags;            /* CHORUS_CHECK_FINITE                          */
-    int32_t reserved;
+    int32_t integrator;       /* chorus_rk_step: CHORUS_SSPRK3 or
+                                 CHORUS_SSPRK54                               */
     const void *closure_model;/* device image from chorus_closure_pack when
                                  closure == CHORUS_CLOSURE_MLP, else ignored   */
 } chorus_physics;
@@ -134,7 +136,9 @@ int chorus_mesh_face_table(chorus_mesh_t mesh, int32_t *nbr_elem, int32_t *nbr_f
  * Synchronises the stream. */
 int chorus_mesh_upload(chorus_mesh_t mesh, void *dev_buf, size_t bytes, void *stream);
 
-/* Workspace bytes needed by residual/step calls with these physics. */
+/* Workspace bytes for every residual, step, background and closure call on
+ * this mesh: one layout serves all precisions, closures and integrators
+ * (phys, if given, is only validated). */
 int chorus_workspace_bytes(chorus_mesh_t mesh, const chorus_physics *phys, size_t *bytes);
 
 /* Polytropic adiabatic initial state (Section 4.2) at the solution points:
@@ -157,7 +161,12 @@ int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const 
 int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q_dev,
                        double *dQdt_dev, void *ws, void *stream);
 
-/* n_steps SSP-RK3 steps of size dt, in place on Q_dev. */
+/* n_steps explicit Runge-Kutta steps of size dt, in place on Q_dev:
+ * phys->integrator = CHORUS_SSPRK3, the three-stage third-order SSP method
+ * (Shu-Osher), or CHORUS_SSPRK54, the five-stage fourth-order SSP method of
+ * Spiteri & Ruuth (2002) that the paper uses (Section 7.5), in Shu-Osher
+ * form with one extra accumulation register (the workspace grows by two
+ * state copies).  The state stays FP64 in both precisions. */
 int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev, double dt,
                    int32_t n_steps, void *ws, void *stream);
 

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libchorus.so")
 CHORUS_OK = 0
 CHORUS_FP64, CHORUS_MIXED = 0, 1
 CHORUS_CLOSURE_NONE, CHORUS_CLOSURE_MLP = 0, 1
+CHORUS_SSPRK3, CHORUS_SSPRK54 = 0, 1
 CHORUS_CHECK_FINITE = 1
 CHORUS_MLP_IN, CHORUS_MLP_HIDDEN, CHORUS_MLP_OUT = 20, 64, 15
 CHORUS_MLP_NPARAM, CHORUS_MLP_NNORM = 6479, 70
@@ -54,13 +55,13 @@ class Physics(ctypes.Structure):
                 ("omega", ctypes.c_double), ("nu", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("kappa_r", ctypes.c_double), ("T_top", ctypes.c_double), ("F_bottom", ctypes.c_double),
                 ("bc_state", ctypes.c_double * 5), ("precision", ctypes.c_int32),
-                ("closure", ctypes.c_int32), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("closure", ctypes.c_int32), ("flags", ctypes.c_int32), ("integrator", ctypes.c_int32),
                 ("closure_model", ctypes.c_void_p)]
 
 
 def physics(gamma=5.0 / 3.0, R_gas=1.0, GM=0.0, omega=0.0, nu=0.0, kappa=0.0, kappa_r=0.0, T_top=0.0,
             F_bottom=0.0, bc_state=(1.0, 0.0, 0.0, 0.0, 1.5), precision=CHORUS_FP64, closure=0, flags=0,
-            closure_model=None):
+            closure_model=None, integrator=CHORUS_SSPRK3):
     """chorus_physics; closure_model: a ClosureModel (or a device address)
     used when closure == CHORUS_CLOSURE_MLP."""
     p = Physics()
@@ -68,7 +69,7 @@ def physics(gamma=5.0 / 3.0, R_gas=1.0, GM=0.0, omega=0.0, nu=0.0, kappa=0.0, ka
     p.kappa, p.kappa_r, p.T_top, p.F_bottom = kappa, kappa_r, T_top, F_bottom
     for i in range(5):
         p.bc_state[i] = bc_state[i]
-    p.precision, p.closure, p.flags = precision, closure, flags
+    p.precision, p.closure, p.flags, p.integrator = precision, closure, flags, integrator
     if closure_model is not None:
         p.closure_model = closure_model if isinstance(closure_model, int) else closure_model.ptr
     return p
@@ -256,7 +257,7 @@ def chorus_sd_residual(mesh, phys, Q, dQdt, ws, stream=None):
 
 
 def chorus_rk_step(mesh, phys, Q, dt, n_steps, ws, stream=None):
-    """n_steps SSP-RK3 steps in place on the device state Q."""
+    """n_steps Runge-Kutta steps (phys.integrator) in place on the device state Q."""
     assert Q.is_contiguous() and Q.numel() == 5 * mesh.n_solpts
     _check(_lib.chorus_rk_step(mesh.handle, ctypes.byref(phys), _P(Q.data_ptr()), float(dt), int(n_steps),
                                _ws_ptr(ws), _P(_stream(stream))), "chorus_rk_step")

@@ -27,44 +27,47 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // workspace layout
 struct WsLayout {
     size_t Qs, TQ0, TQ1, TV, part, sums, flag;
+    size_t Q2, Q4;  // SSPRK(5,4): extra stage registers (FP64 path), 0 otherwise
     size_t tau;  // learned closure: subgrid flux [15][E][NP] FP32 (0 when off)
     // mixed-precision path
     size_t P0, P1, TQm0, TQm1, TVm, bg, dbg, gS0, R0, Q0;
+    size_t P2, P4;  // SSPRK(5,4) on the perturbation
     bool mixed;
     size_t total;
 };
 static constexpr int kSumBlocks = 512;
 
-static WsLayout ws_layout(const Mesh &m, bool mixed, bool closure = false) {
+// One layout for every mode (precision, closure, integrator), so that a
+// workspace sized by chorus_workspace_bytes serves any call on the mesh.
+static WsLayout ws_layout(const Mesh &m) {
     const int N = m.N, NP = N * N * N, NF2 = N * N;
     const int64_t E = m.E;
     WsLayout w;
-    w.mixed = mixed;
+    w.mixed = true;
     size_t off = 0;
-    w.Qs = off;   off = align256(off + sizeof(double) * 5 * E * NP);
+    const size_t state = sizeof(double) * 5 * E * NP;
+    w.Qs = off;   off = align256(off + state);
     w.TQ0 = off;  off = align256(off + sizeof(double) * E * 6 * 5 * NF2);
     w.TQ1 = off;  off = align256(off + sizeof(double) * E * 6 * 5 * NF2);
     w.TV = off;   off = align256(off + sizeof(double) * E * 6 * 5 * NF2);
     w.part = off; off = align256(off + sizeof(double) * 5 * kSumBlocks);
     w.sums = off; off = align256(off + sizeof(double) * 8);
     w.flag = off; off = align256(off + sizeof(int) * 4);
-    w.tau = 0;
-    if (closure) {
-        w.tau = off; off = align256(off + sizeof(float) * 15 * E * NP);
-    }
-    w.P0 = w.P1 = w.TQm0 = w.TQm1 = w.TVm = w.bg = w.dbg = w.gS0 = w.R0 = w.Q0 = 0;
-    if (mixed) {
-        w.P0 = off;   off = align256(off + sizeof(double) * 5 * E * NP);
-        w.P1 = off;   off = align256(off + sizeof(double) * 5 * E * NP);
-        w.TQm0 = off; off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
-        w.TQm1 = off; off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
-        w.TVm = off;  off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
-        w.bg = off;   off = align256(off + sizeof(float) * E * 2 * NP);
-        w.dbg = off;  off = align256(off + sizeof(float) * E * 6 * 2 * NF2);
-        w.gS0 = off;  off = align256(off + sizeof(float) * E * 3 * (N + 1) * NF2);
-        w.R0 = off;   off = align256(off + sizeof(float) * 5 * E * NP);
-        w.Q0 = off;   off = align256(off + sizeof(double) * 5 * E * NP);
-    }
+    w.tau = off;  off = align256(off + sizeof(float) * 15 * E * NP);
+    w.Q2 = off;   off = align256(off + state);
+    w.Q4 = off;   off = align256(off + state);
+    w.P0 = off;   off = align256(off + state);
+    w.P1 = off;   off = align256(off + state);
+    w.P2 = off;   off = align256(off + state);
+    w.P4 = off;   off = align256(off + state);
+    w.TQm0 = off; off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
+    w.TQm1 = off; off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
+    w.TVm = off;  off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
+    w.bg = off;   off = align256(off + sizeof(float) * E * 2 * NP);
+    w.dbg = off;  off = align256(off + sizeof(float) * E * 6 * 2 * NF2);
+    w.gS0 = off;  off = align256(off + sizeof(float) * E * 3 * (N + 1) * NF2);
+    w.R0 = off;   off = align256(off + sizeof(float) * 5 * E * NP);
+    w.Q0 = off;   off = align256(off + state);
     w.total = off;
     return w;
 }
@@ -107,6 +110,10 @@ static int check_phys(const chorus_physics *p) {
     }
     if (p->precision != CHORUS_FP64 && p->precision != CHORUS_MIXED) {
         set_error("physics: unknown precision");
+        return CHORUS_EINVAL;
+    }
+    if (p->integrator != CHORUS_SSPRK3 && p->integrator != CHORUS_SSPRK54) {
+        set_error("physics: unknown integrator");
         return CHORUS_EINVAL;
     }
     if (p->closure != CHORUS_CLOSURE_NONE && p->closure != CHORUS_CLOSURE_MLP) {
@@ -443,8 +450,7 @@ int chorus_workspace_bytes(chorus_mesh_t mesh, const chorus_physics *phys, size_
         set_error("null argument");
         return CHORUS_EINVAL;
     }
-    *bytes = ws_layout(*m, phys && phys->precision == CHORUS_MIXED,
-                       phys && phys->closure == CHORUS_CLOSURE_MLP).total;
+    *bytes = ws_layout(*m).total;
     return CHORUS_OK;
 }
 
@@ -505,7 +511,7 @@ int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const 
             set_error("mixed precision supports interior and wall faces only");
             return CHORUS_ENOTSUP;
         }
-    const WsLayout w = ws_layout(*m, true);
+    const WsLayout w = ws_layout(*m);
     unsigned char *W = (unsigned char *)ws;
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = m->E * m->N * m->N * m->N;
@@ -524,7 +530,7 @@ int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const 
     // R0 = R(Q0), the complete FP64 residual of the background
     const ClosureArgs C0{nullptr, nullptr};
     if (e == hipSuccess) e = launch_grad(*m, G, P, Q0, TQ, TV, C0, s);
-    StageArgs sa{nullptr, R0d, nullptr, 0.0, 1.0, 0.0, 0};
+    StageArgs sa{nullptr, R0d, nullptr, 0.0, 1.0, 0.0, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
     if (e == hipSuccess) e = launch_resid(*m, G, P, Q0, TQ, TV, sa, C0, s);
     if (e == hipSuccess) e = launch_to_float(R0d, (float *)(W + w.R0), 5 * n, s);
     int h = 0;
@@ -555,7 +561,7 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
     rc = check_closure_order(*m, phys);
     if (rc) return rc;
     const bool mixed = phys->precision == CHORUS_MIXED;
-    const WsLayout w = ws_layout(*m, mixed, phys->closure == CHORUS_CLOSURE_MLP);
+    const WsLayout w = ws_layout(*m);
     unsigned char *W = (unsigned char *)ws;
     const PhysParams P = params_of(phys);
     const ClosureArgs C = closure_of(phys, w, W);
@@ -568,7 +574,7 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
         float *TQm = (float *)(W + w.TQm0), *TVm = (float *)(W + w.TVm);
         hipError_t e = timed(0, s, [&] { return launch_pert_begin(*m, g, Q_dev, P0, TQm, s); });
         if (e == hipSuccess) e = timed(1, s, [&] { return launch_grad_mixed(*m, g, P, P0, TQm, TVm, s); });
-        MixedStageArgs a{nullptr, dQdt_dev, nullptr, 0.0, 1.0, 0.0, 0};
+        MixedStageArgs a{nullptr, dQdt_dev, nullptr, 0.0, 1.0, 0.0, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
         if (e == hipSuccess) e = timed(2, s, [&] { return launch_resid_mixed(*m, g, P, P0, TQm, TVm, a, s); });
         if (e != hipSuccess) return hip_fail(e, "sd_residual (mixed)");
         if (phys->flags & CHORUS_CHECK_FINITE) return finite_check(*m, P, Q_dev, w, W, s);
@@ -578,12 +584,47 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
     const Geo G = geo_of(*m);
     hipError_t e = timed(0, s, [&] { return launch_trace(*m, G, Q_dev, TQ, s); });
     if (e == hipSuccess) e = timed(1, s, [&] { return launch_grad(*m, G, P, Q_dev, TQ, TV, C, s); });
-    StageArgs sa{nullptr, dQdt_dev, nullptr, 0.0, 1.0, 0.0, 0};
+    StageArgs sa{nullptr, dQdt_dev, nullptr, 0.0, 1.0, 0.0, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
     if (e == hipSuccess) e = timed(2, s, [&] { return launch_resid(*m, G, P, Q_dev, TQ, TV, sa, C, s); });
     if (e != hipSuccess) return hip_fail(e, "sd_residual");
     if (phys->flags & CHORUS_CHECK_FINITE) return finite_check(*m, P, Q_dev, w, W, s);
     return CHORUS_OK;
 }
+
+// One Runge-Kutta stage in Shu-Osher form on the stage registers
+// (0: the step-start state, updated in place by the last stage; 1: the
+// running stage; 2, 3: extra registers of SSPRK(5,4)): reads register `in`,
+// writes `out` = c0 [a] + c1 (in + c2 dt R(in)) and, if tout >= 0,
+// [tout] = d0 [b] + d1 (in + d2 dt R(in)).
+struct StagePlan {
+    int in, out, a, b, tout;
+    double c0, c1, c2, d0, d1, d2;
+};
+
+// Shu-Osher SSP-RK3
+static const StagePlan kSSPRK3[3] = {
+    {0, 1, -1, -1, -1, 0.0, 1.0, 1.0, 0, 0, 0},
+    {1, 1, 0, -1, -1, 0.75, 0.25, 1.0, 0, 0, 0},
+    {1, 0, 0, -1, -1, 1.0 / 3.0, 2.0 / 3.0, 1.0, 0, 0, 0},
+};
+
+// SSPRK(5,4) of Spiteri & Ruuth (2002): u_i = sum_k alpha_ik u_k + beta_ik dt
+// L(u_k) with the published coefficients; the last stage needs u2, u3 and
+// L(u3), which stage 4 folds into register 2 (T = a52 u2 + a53 u3 + b53 dt
+// L(u3)), so u^{n+1} = T + a54 u4 + b54 dt L(u4)
+static const double kA10 = 1.0, kB10 = 0.391752226571890;
+static const double kA20 = 0.444370493651235, kA21 = 0.555629506348765, kB21 = 0.368410593050371;
+static const double kA30 = 0.620101851488403, kA32 = 0.379898148511597, kB32 = 0.251891774271694;
+static const double kA40 = 0.178079954393132, kA43 = 0.821920045606868, kB43 = 0.544974750228521;
+static const double kA52 = 0.517231671970585, kA53 = 0.096059710526147, kB53 = 0.063692468666290;
+static const double kA54 = 0.386708617503269, kB54 = 0.226007483236906;
+static const StagePlan kSSPRK54[5] = {
+    {0, 1, -1, -1, -1, 0.0, kA10, kB10 / kA10, 0, 0, 0},
+    {1, 2, 0, -1, -1, kA20, kA21, kB21 / kA21, 0, 0, 0},
+    {2, 1, 0, -1, -1, kA30, kA32, kB32 / kA32, 0, 0, 0},
+    {1, 3, 0, 2, 2, kA40, kA43, kB43 / kA43, kA52, kA53, kB53 / kA53},
+    {3, 0, 2, -1, -1, 1.0, kA54, kB54 / kA54, 0, 0, 0},
+};
 
 int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev, double dt, int32_t n_steps,
                    void *ws, void *stream) {
@@ -600,54 +641,58 @@ int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev
     rc = check_closure_order(*m, phys);
     if (rc) return rc;
     const bool mixed = phys->precision == CHORUS_MIXED;
-    const WsLayout w = ws_layout(*m, mixed, phys->closure == CHORUS_CLOSURE_MLP);
+    const bool rk54 = phys->integrator == CHORUS_SSPRK54;
+    const StagePlan *plan = rk54 ? kSSPRK54 : kSSPRK3;
+    const int nst = rk54 ? 5 : 3;
+    const WsLayout w = ws_layout(*m);
     unsigned char *W = (unsigned char *)ws;
     const ClosureArgs C = closure_of(phys, w, W);
+    const PhysParams P = params_of(phys);
+    hipStream_t s = (hipStream_t)stream;
     if (mixed) {
         rc = check_mixed(*m, phys, ws);
         if (rc) return rc;
         const GeoM g = geom_of(*m, w, W);
-        const PhysParams P = params_of(phys);
-        hipStream_t s = (hipStream_t)stream;
-        double *Pb[2] = {(double *)(W + w.P0), (double *)(W + w.P1)};
+        double *reg[4] = {(double *)(W + w.P0), (double *)(W + w.P1), rk54 ? (double *)(W + w.P2) : nullptr,
+                          rk54 ? (double *)(W + w.P4) : nullptr};
         float *TQb[2] = {(float *)(W + w.TQm0), (float *)(W + w.TQm1)};
         float *TVm = (float *)(W + w.TVm);
         int cur = 0;
-        hipError_t e = timed(0, s, [&] { return launch_pert_begin(*m, g, Q_dev, Pb[0], TQb[cur], s); });
-        const double ca[3] = {0.0, 0.75, 1.0 / 3.0}, cb[3] = {1.0, 0.25, 2.0 / 3.0};
+        hipError_t e = timed(0, s, [&] { return launch_pert_begin(*m, g, Q_dev, reg[0], TQb[cur], s); });
         for (int st = 0; st < n_steps && e == hipSuccess; ++st) {
-            for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-                const double *pin = (k == 0) ? Pb[0] : Pb[1];
-                double *pout = (k == 2) ? Pb[0] : Pb[1];
+            for (int k = 0; k < nst && e == hipSuccess; ++k) {
+                const StagePlan &sp = plan[k];
+                const double *pin = reg[sp.in];
                 e = timed(1, s, [&] { return launch_grad_mixed(*m, g, P, pin, TQb[cur], TVm, s); });
                 if (e != hipSuccess) break;
-                MixedStageArgs a{Pb[0], pout, TQb[cur ^ 1], ca[k], cb[k], dt, 1};
+                MixedStageArgs a{sp.a >= 0 ? reg[sp.a] : nullptr, reg[sp.out], TQb[cur ^ 1], sp.c0, sp.c1,
+                                 sp.c2 * dt, sp.b >= 0 ? reg[sp.b] : nullptr, sp.tout >= 0 ? reg[sp.tout] : nullptr,
+                                 sp.d0, sp.d1, sp.d2 * dt, 1};
                 e = timed(2, s, [&] { return launch_resid_mixed(*m, g, P, pin, TQb[cur], TVm, a, s); });
                 cur ^= 1;
             }
         }
-        if (e == hipSuccess) e = launch_pert_end(g.Q0, Pb[0], Q_dev, 5 * m->E * m->N * m->N * m->N, s);
+        if (e == hipSuccess) e = launch_pert_end(g.Q0, reg[0], Q_dev, 5 * m->E * m->N * m->N * m->N, s);
         if (e != hipSuccess) return hip_fail(e, "rk_step (mixed)");
         if (phys->flags & CHORUS_CHECK_FINITE) return finite_check(*m, P, Q_dev, w, W, s);
         return CHORUS_OK;
     }
-    double *Qs = (double *)(W + w.Qs), *TV = (double *)(W + w.TV);
+    double *TV = (double *)(W + w.TV);
+    double *reg[4] = {Q_dev, (double *)(W + w.Qs), rk54 ? (double *)(W + w.Q2) : nullptr,
+                      rk54 ? (double *)(W + w.Q4) : nullptr};
     double *TQb[2] = {(double *)(W + w.TQ0), (double *)(W + w.TQ1)};
     const Geo G = geo_of(*m);
-    const PhysParams P = params_of(phys);
-    hipStream_t s = (hipStream_t)stream;
     int cur = 0;
     hipError_t e = timed(0, s, [&] { return launch_trace(*m, G, Q_dev, TQb[cur], s); });
-    // SSP-RK3: Q1 = Q + dt R(Q); Q2 = 3/4 Q + 1/4 (Q1 + dt R(Q1));
-    //          Q  = 1/3 Q + 2/3 (Q2 + dt R(Q2))
-    const double ca[3] = {0.0, 0.75, 1.0 / 3.0}, cb[3] = {1.0, 0.25, 2.0 / 3.0};
     for (int st = 0; st < n_steps && e == hipSuccess; ++st) {
-        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-            const double *qin = (k == 0) ? Q_dev : Qs;
-            double *qout = (k == 2) ? Q_dev : Qs;
+        for (int k = 0; k < nst && e == hipSuccess; ++k) {
+            const StagePlan &sp = plan[k];
+            const double *qin = reg[sp.in];
             e = timed(1, s, [&] { return launch_grad(*m, G, P, qin, TQb[cur], TV, C, s); });
             if (e != hipSuccess) break;
-            StageArgs sa{Q_dev, qout, TQb[cur ^ 1], ca[k], cb[k], dt, 1};
+            StageArgs sa{sp.a >= 0 ? reg[sp.a] : nullptr, reg[sp.out], TQb[cur ^ 1], sp.c0, sp.c1, sp.c2 * dt,
+                         sp.b >= 0 ? reg[sp.b] : nullptr, sp.tout >= 0 ? reg[sp.tout] : nullptr, sp.d0, sp.d1,
+                         sp.d2 * dt, 1};
             e = timed(2, s, [&] { return launch_resid(*m, G, P, qin, TQb[cur], TV, sa, C, s); });
             cur ^= 1;
         }
@@ -665,7 +710,7 @@ int chorus_conserved_sums(chorus_mesh_t mesh, const double *Q_dev, double out_ho
         set_error("null argument");
         return CHORUS_EINVAL;
     }
-    const WsLayout w = ws_layout(*m, false);
+    const WsLayout w = ws_layout(*m);
     unsigned char *W = (unsigned char *)ws;
     const double *solw = (const double *)((const unsigned char *)m->dev_image + m->layout.solw);
     hipStream_t s = (hipStream_t)stream;
@@ -795,7 +840,7 @@ int chorus_closure_features(chorus_mesh_t mesh, const chorus_physics *phys, cons
         set_error("closure_features: FP64 precision only");
         return CHORUS_ENOTSUP;
     }
-    const WsLayout w = ws_layout(*m, false);
+    const WsLayout w = ws_layout(*m);
     unsigned char *W = (unsigned char *)ws;
     const Geo G = geo_of(*m);
     const PhysParams P = params_of(phys);
@@ -824,7 +869,7 @@ int chorus_closure_infer(chorus_mesh_t mesh, const chorus_physics *phys, const d
         set_error("null device pointer");
         return CHORUS_EINVAL;
     }
-    const WsLayout w = ws_layout(*m, false, true);
+    const WsLayout w = ws_layout(*m);
     unsigned char *W = (unsigned char *)ws;
     const Geo G = geo_of(*m);
     const PhysParams P = params_of(phys);

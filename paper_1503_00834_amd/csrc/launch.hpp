@@ -19,12 +19,19 @@ struct Geo {
     int64_t E;
 };
 
-// stage combination Q_out = ca Qn + cb (Q + dt R); mode 0 writes R only
+// stage combination of a Shu-Osher Runge-Kutta stage (mode 1):
+//   Qout = c0 A + c1 (Q + c2 R)              (A read only when c0 != 0)
+//   Tout = d0 B + d1 (Q + d2 R)  if Tout     (B read only when d0 != 0)
+// with Q the stage input and R = dQ/dt(Q); c2, d2 include dt.  Each output
+// may alias the array combined into it (A or B).  Mode 0 writes R to Qout.
 struct StageArgs {
-    const double *Qn;  // step-start state (may alias Qout)
-    double *Qout;      // stage output (may alias Q or Qn)
-    double *TQout;     // face traces of Q_out (RK mode) or null
-    double ca, cb, dt;
+    const double *A;
+    double *Qout;
+    double *TQout;     // face traces of Qout (RK mode) or null
+    double c0, c1, c2;
+    const double *B;
+    double *Tout;
+    double d0, d1, d2;
     int mode;          // 0 residual, 1 RK stage
 };
 
@@ -93,12 +100,16 @@ struct GeoM {
     const double *Q0;        // [5][E][NP]  background state
 };
 
+// as StageArgs, on the perturbation P (mode 0 writes dQ/dt to Pout)
 struct MixedStageArgs {
-    const double *Pn;  // step-start perturbation (may alias Pout)
-    double *Pout;      // stage output, or dQ/dt in mode 0
+    const double *A;
+    double *Pout;
     float *TQout;      // FP32 face traces of Pout (RK mode) or null
-    double ca, cb, dt;
-    int mode;          // 0 residual, 1 RK stage
+    double c0, c1, c2;
+    const double *B;
+    double *Tout;
+    double d0, d1, d2;
+    int mode;
 };
 
 hipError_t launch_pert_begin(const Mesh &m, const GeoM &g, const double *Q, double *Pq, float *TQ, hipStream_t s);

@@ -415,8 +415,13 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, co
             if (S_.mode == 0) {
                 S_.Qout[gi] = R;
             } else {
-                const double qn = (S_.ca != 0.0) ? S_.Qn[gi] : 0.0;
-                const double qv = S_.ca * qn + S_.cb * (sq[el][v][p] + S_.dt * R);
+                const double q = sq[el][v][p];
+                if (S_.Tout) {
+                    const double qb = (S_.d0 != 0.0) ? S_.B[gi] : 0.0;
+                    S_.Tout[gi] = S_.d0 * qb + S_.d1 * (q + S_.d2 * R);
+                }
+                const double qa = (S_.c0 != 0.0) ? S_.A[gi] : 0.0;
+                const double qv = S_.c0 * qa + S_.c1 * (q + S_.c2 * R);
                 S_.Qout[gi] = qv;
                 sq[el][v][p] = qv;
             }

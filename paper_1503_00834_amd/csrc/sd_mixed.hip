@@ -497,13 +497,8 @@ __global__ __launch_bounds__(NT) void k_grad_mixed(OpsF<N> op, GeoF G, MixedBufs
     }
 }
 
-struct MixedStage {
-    const double *Pn;  // step-start perturbation (may alias Pout)
-    double *Pout;      // stage output, or dQ/dt in mode 0
-    float *TQout;      // FP32 face traces of Pout (RK mode)
-    double ca, cb, dt;
-    int mode;          // 0 residual (R0 + dR), 1 RK stage
-};
+// stage combination on P (see MixedStageArgs); mode 0 writes R0 + dR
+using MixedStage = MixedStageArgs;
 
 // per-thread inputs of one element block for the residual pass
 template <int N, int EPB, int NT>
@@ -681,7 +676,7 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
             const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
             r0s[v] = B.R0[gi];
             pin[v] = Pq[gi];
-            pst[v] = (S_.mode != 0 && S_.ca != 0.0) ? S_.Pn[gi] : 0.0;
+            pst[v] = (S_.mode != 0 && S_.c0 != 0.0) ? S_.A[gi] : 0.0;
         }
         const float rp = l.f[F_RP][p], mx = l.f[F_MX][p], my = l.f[F_MY][p], mz = l.f[F_MZ][p];
         float M[5];
@@ -697,7 +692,11 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
             if (S_.mode == 0) {
                 S_.Pout[gi] = Rv;
             } else {
-                const double pv = S_.ca * pst[v] + S_.cb * (pin[v] + S_.dt * Rv);
+                if (S_.Tout) {
+                    const double pb = (S_.d0 != 0.0) ? S_.B[gi] : 0.0;
+                    S_.Tout[gi] = S_.d0 * pb + S_.d1 * (pin[v] + S_.d2 * Rv);
+                }
+                const double pv = S_.c0 * pst[v] + S_.c1 * (pin[v] + S_.c2 * Rv);
                 S_.Pout[gi] = pv;
                 newp[v] = (float)pv;
             }
@@ -851,7 +850,7 @@ static hipError_t resid_mixed_t(const Mesh &m, const GeoM &g, const PhysParams &
     constexpr int EPB = CfgM<N>::EPB, NT = CfgM<N>::NT, K = CfgM<N>::K;
     const unsigned nb = (unsigned)((m.E + EPB * K - 1) / (EPB * K));
     static_assert(K >= 1, "at least one element block per workgroup");
-    MixedStage st{a.Pn, a.Pout, a.TQout, a.ca, a.cb, a.dt, a.mode};
+    const MixedStage st = a;
     // at N = 3, 4 the block is held to three waves per SIMD (a few spilled
     // registers cost less than a third of the latency-hiding waves)
     hipLaunchKernelGGL((k_resid_mixed<N, EPB, NT, K, CfgM<N>::MINW>), dim3(nb), dim3(NT), 0, s,
