@@ -61,6 +61,8 @@ def lib():
         L.ora_ssp54.argtypes = [P, P, dp, ctypes.c_double, ctypes.c_int]
         L.ora_ssp54_table.argtypes = [dp, dp]
         L.ora_sums.argtypes = [P, dp, dp]
+        L.ora_angular_momentum.argtypes = [P, dp, dp]
+        L.ora_am_correct.argtypes = [P, dp, dp]
         L.ora_polytrope.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, dp, ctypes.c_double, dp, dp]
         _lib = L
@@ -197,6 +199,20 @@ class OracleMesh:
         out = np.zeros(5)
         lib().ora_sums(self._h, _dp(Q), _dp(out))
         return out
+
+    def angular_momentum(self, Q):
+        """(L [3], I [3]) of the state (Section 6)."""
+        Q = np.ascontiguousarray(Q, dtype=np.float64)
+        out = np.zeros(6)
+        lib().ora_angular_momentum(self._h, _dp(Q), _dp(out))
+        return out[:3], out[3:]
+
+    def am_correct(self, Q):
+        """(corrected copy of Q, applied dOmega [3])."""
+        Q = np.array(Q, dtype=np.float64, copy=True)
+        dO = np.zeros(3)
+        lib().ora_am_correct(self._h, _dp(Q), _dp(dO))
+        return Q, dO
 
     def polytrope(self, beta, n_rho, poly_n=1.5, gamma=5.0 / 3.0, R_gas=1.0, noise=None, amp=1e-4):
         Q = np.zeros((5, self.E, self.np))

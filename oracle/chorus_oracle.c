@@ -1054,6 +1054,68 @@ void ora_ssp54(const ora_mesh *m, const ora_phys *ph, double *Q, double dt, int 
     }
 }
 
+/* Angular-momentum bookkeeping of Section 6: out = (L_x, L_y, L_z, I_x, I_y,
+ * I_z), L = integral of rho r x u (the spherical-coordinate integrands of
+ * the paper written with x = r sin(theta) cos(phi), y = r sin(theta)
+ * sin(phi), z = r cos(theta)), I_x = integral of rho (y^2 + z^2) and so on;
+ * quadrature over the solution points with weights w w w |J|, serial order. */
+void ora_angular_momentum(const ora_mesh *m, const double *Q, double out[6])
+{
+    const long E = m->E;
+    const int np = m->np, N = m->N;
+    for (int k = 0; k < 6; ++k)
+        out[k] = 0.0;
+    for (long e = 0; e < E; ++e)
+        for (int p = 0; p < np; ++p) {
+            const int i = p % N, j = (p / N) % N, k = p / (N * N);
+            const double wJ = m->w[i] * m->w[j] * m->w[k] * m->jac[e * np + p];
+            const double *x = &m->xsol[(e * np + p) * 3];
+            const double rho = Q[(0 * E + e) * np + p];
+            const double mx = Q[(1 * E + e) * np + p], my = Q[(2 * E + e) * np + p], mz = Q[(3 * E + e) * np + p];
+            out[0] += wJ * (x[1] * mz - x[2] * my);
+            out[1] += wJ * (x[2] * mx - x[0] * mz);
+            out[2] += wJ * (x[0] * my - x[1] * mx);
+            out[3] += wJ * rho * (x[1] * x[1] + x[2] * x[2]);
+            out[4] += wJ * rho * (x[0] * x[0] + x[2] * x[2]);
+            out[5] += wJ * rho * (x[0] * x[0] + x[1] * x[1]);
+        }
+}
+
+/* Section 6, step 2: remove the rigid rotation dOmega_i = L_i / I_i,
+ * u_new = u - dOmega x r at every solution point (the paper's atan2 forms
+ * reduce to the components of dOmega x r); density and pressure are kept,
+ * so the total energy changes by the change of the kinetic energy.
+ * dOmega (may be NULL) receives the applied rates. */
+void ora_am_correct(const ora_mesh *m, double *Q, double dOmega[3])
+{
+    double LI[6], dO[3];
+    const long E = m->E;
+    const int np = m->np;
+    ora_angular_momentum(m, Q, LI);
+    for (int c = 0; c < 3; ++c)
+        dO[c] = LI[c] / LI[3 + c];
+    for (long e = 0; e < E; ++e)
+        for (int p = 0; p < np; ++p) {
+            const double *x = &m->xsol[(e * np + p) * 3];
+            double *q[5];
+            for (int v = 0; v < 5; ++v)
+                q[v] = &Q[((long)v * E + e) * np + p];
+            const double rho = *q[0];
+            const double u[3] = {*q[1] / rho, *q[2] / rho, *q[3] / rho};
+            const double un[3] = {u[0] - (dO[1] * x[2] - dO[2] * x[1]),
+                                  u[1] - (dO[2] * x[0] - dO[0] * x[2]),
+                                  u[2] - (dO[0] * x[1] - dO[1] * x[0])};
+            const double ke_old = 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            const double ke_new = 0.5 * rho * (un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+            for (int c = 0; c < 3; ++c)
+                *q[1 + c] = rho * un[c];
+            *q[4] += ke_new - ke_old;
+        }
+    if (dOmega)
+        for (int c = 0; c < 3; ++c)
+            dOmega[c] = dO[c];
+}
+
 void ora_sums(const ora_mesh *m, const double *Q, double out[5])
 {
     int N = m->N;

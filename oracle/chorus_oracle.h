@@ -68,6 +68,10 @@ void ora_rk3(const ora_mesh *m, const ora_phys *ph, double *Q, double dt, int ns
  * form; ora_ssp54_table exports its alpha[5][5], beta[5][5] (row = stage) */
 void ora_ssp54(const ora_mesh *m, const ora_phys *ph, double *Q, double dt, int nsteps);
 void ora_ssp54_table(double alpha[25], double beta[25]);
+/* angular momentum L (3) and diagonal moments of inertia I (3) over the
+ * shell (Section 6), and the rigid-rotation correction u -= (L_i/I_i) x r */
+void ora_angular_momentum(const ora_mesh *m, const double *Q, double out[6]);
+void ora_am_correct(const ora_mesh *m, double *Q, double dOmega[3]);
 /* sum over all solution points of w w w |J| Q_v, fixed serial order */
 void ora_sums(const ora_mesh *m, const double *Q, double out[5]);
 

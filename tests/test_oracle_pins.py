@@ -452,3 +452,75 @@ def test_ssp54_temporal_order_four(oracle_mod):
         errs.append(np.abs(Q - ref).max())
     rate = math.log(errs[0] / errs[1]) / math.log(2.0)
     assert rate > 3.6, (errs, rate)
+
+
+# --------------------------------------------------------------------------
+# angular-momentum correction (Section 6)
+# --------------------------------------------------------------------------
+def _shell_state_with_velocity(oracle_mod, u_fn, seed=0):
+    m = cubed_sphere_shell(4, 2, 2.0, 3.0)
+    om = oracle_mod.OracleMesh(m, 3)
+    Q, _ = om.polytrope(0.6, 1.0)
+    xyz, _ = om.solpts()
+    u = u_fn(xyz)
+    Q = Q.reshape(5, -1)
+    Q[1:4] = Q[0] * u
+    Q[4] += 0.5 * Q[0] * (u ** 2).sum(0)
+    return om, Q, xyz
+
+
+def test_angular_momentum_of_rigid_rotation(oracle_mod):
+    """rho(r) and u = Omega x r: L = I Omega with a diagonal inertia tensor,
+    so dOmega = Omega and the correction leaves the fluid at rest; rho and p
+    are unchanged."""
+    Om = np.array([0.03, -0.02, 0.05])
+    om, Q, xyz = _shell_state_with_velocity(oracle_mod, lambda x: np.cross(Om, x.T).T)
+    L, I = om.angular_momentum(Q)
+    _, wJ = om.solpts()
+    r2 = (xyz ** 2).sum(0)
+    for c in range(3):   # I_c = int rho (r^2 - x_c^2)
+        assert abs(I[c] - (wJ * Q[0] * (r2 - xyz[c] ** 2)).sum()) < 1e-12 * I[c]
+    np.testing.assert_allclose(L, I * Om, rtol=1e-12)
+    Qc, dO = om.am_correct(Q)
+    np.testing.assert_allclose(dO, Om, rtol=1e-12)
+    assert np.abs(Qc[1:4]).max() < 1e-13
+    np.testing.assert_allclose(Qc[0], Q[0], rtol=0)
+    p0 = (2.0 / 3.0) * (Q[4] - 0.5 * (Q[1:4] ** 2).sum(0) / Q[0])
+    p1 = (2.0 / 3.0) * (Qc[4] - 0.5 * (Qc[1:4] ** 2).sum(0) / Qc[0])
+    np.testing.assert_allclose(p1, p0, rtol=1e-13)
+
+
+def test_angular_momentum_removed_for_radial_density(oracle_mod):
+    """rho = rho(r) with an arbitrary velocity field: the shell's inertia
+    tensor is diagonal (octahedral symmetry of the mesh), so one correction
+    removes L to rounding."""
+    from chorus_inputs import random_velocity
+    om, Q, _ = _shell_state_with_velocity(oracle_mod, lambda x: random_velocity(x, 3, amp=0.1))
+    L, I = om.angular_momentum(Q)
+    assert np.abs(L).max() > 1e-3 * np.abs(I).max() * 1e-2
+    Qc, _ = om.am_correct(Q)
+    L2, _ = om.angular_momentum(Qc)
+    assert np.abs(L2).max() < 1e-12 * np.abs(L).max() + 1e-13 * I.max()
+
+
+def test_angular_momentum_correction_full_tensor(oracle_mod):
+    """Non-radial density: the correction removes the diagonal part, leaving
+    L' = -(I_offdiag) dOmega with I_ij = -int rho x_i x_j (closed form of
+    int rho r x (dOmega x r))."""
+    from chorus_inputs import random_velocity
+    om, Q, xyz = _shell_state_with_velocity(oracle_mod, lambda x: random_velocity(x, 4, amp=0.1))
+    _, wJ = om.solpts()
+    rho = Q[0] * (1.0 + 0.3 * np.sin(xyz[0]) * np.cos(0.7 * xyz[1] + 0.2))
+    Q = Q.copy()
+    u = Q[1:4] / Q[0]
+    Q[4] += 0.5 * (rho - Q[0]) * (u ** 2).sum(0)
+    Q[1:4] = rho * u
+    Q[0] = rho
+    Qc, dO = om.am_correct(Q)
+    L2, _ = om.angular_momentum(Qc)
+    Ioff = np.zeros((3, 3))
+    for i in range(3):
+        for j in range(3):
+            if i != j:
+                Ioff[i, j] = -(wJ * rho * xyz[i] * xyz[j]).sum()
+    np.testing.assert_allclose(L2, -Ioff @ dO, rtol=1e-9, atol=1e-14 * np.abs(Ioff).max())
