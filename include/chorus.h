@@ -175,6 +175,19 @@ int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev
 int chorus_conserved_sums(chorus_mesh_t mesh, const double *Q_dev, double out_host[5], void *ws,
                           void *stream);
 
+/* Angular momentum over the shell (Section 6): out_host = (L_x, L_y, L_z,
+ * I_x, I_y, I_z) with L = integral of rho r x u and I_x = integral of
+ * rho (y^2 + z^2) (likewise I_y, I_z), by the solution-point quadrature in a
+ * fixed reduction order.  Synchronises. */
+int chorus_angular_momentum(chorus_mesh_t mesh, const double *Q_dev, double out_host[6], void *ws, void *stream);
+/* Angular-momentum correction (Section 6): dOmega_c = L_c / I_c and, at
+ * every solution point, u <- u - dOmega x r (the paper's velocity update;
+ * its atan2 forms are the components of dOmega x r), keeping density and
+ * pressure (the total energy takes the kinetic-energy change).  The paper
+ * applies it every 5000 steps.  dOmega_host (may be NULL) receives the
+ * rates.  Synchronises for the reduction; the update is queued on stream. */
+int chorus_am_correct(chorus_mesh_t mesh, double *Q_dev, double dOmega_host[3], void *ws, void *stream);
+
 /* Explicit time step from the host state Q_host [5][E N^3] (host only):
  * dt = cfl / (N max_points sum_d (|u . grad xi_d| + c |grad xi_d|)), the
  * acoustic CFL condition dt < delta / c_s of Section 7 measured in

@@ -97,6 +97,8 @@ _SIGS = {
     "chorus_rk_step": [_P, ctypes.POINTER(Physics), _P, ctypes.c_double, ctypes.c_int32, _P, _P],
     "chorus_conserved_sums": [_P, _P, _P, _P, _P],
     "chorus_stable_dt": [_P, ctypes.POINTER(Physics), _P, ctypes.c_double, _dp],
+    "chorus_angular_momentum": [_P, _P, _P, _P, _P],
+    "chorus_am_correct": [_P, _P, _P, _P, _P],
     "chorus_last_error": [ctypes.c_char_p, ctypes.c_size_t],
     "chorus_kernel_timing": [ctypes.c_int],
     "chorus_kernel_times": [_P, _P],
@@ -268,6 +270,22 @@ def chorus_conserved_sums(mesh, Q, ws, stream=None):
     _check(_lib.chorus_conserved_sums(mesh.handle, _P(Q.data_ptr()), _ptr(out), _ws_ptr(ws),
                                       _P(_stream(stream))), "chorus_conserved_sums")
     return out
+
+
+def chorus_angular_momentum(mesh, Q, ws, stream=None):
+    """(L [3], I [3]) of the device state (synchronises)."""
+    out = np.zeros(6)
+    _check(_lib.chorus_angular_momentum(mesh.handle, _P(Q.data_ptr()), _ptr(out), _ws_ptr(ws),
+                                        _P(_stream(stream))), "chorus_angular_momentum")
+    return out[:3], out[3:]
+
+
+def chorus_am_correct(mesh, Q, ws, stream=None):
+    """Remove the rigid rotation L_c / I_c in place; returns dOmega [3]."""
+    dO = np.zeros(3)
+    _check(_lib.chorus_am_correct(mesh.handle, _P(Q.data_ptr()), _ptr(dO), _ws_ptr(ws), _P(_stream(stream))),
+           "chorus_am_correct")
+    return dO
 
 
 def chorus_set_background(mesh, phys, Q0, ws, stream=None):

@@ -50,7 +50,7 @@ static WsLayout ws_layout(const Mesh &m) {
     w.TQ0 = off;  off = align256(off + sizeof(double) * E * 6 * 5 * NF2);
     w.TQ1 = off;  off = align256(off + sizeof(double) * E * 6 * 5 * NF2);
     w.TV = off;   off = align256(off + sizeof(double) * E * 6 * 5 * NF2);
-    w.part = off; off = align256(off + sizeof(double) * 5 * kSumBlocks);
+    w.part = off; off = align256(off + sizeof(double) * 6 * kSumBlocks);
     w.sums = off; off = align256(off + sizeof(double) * 8);
     w.flag = off; off = align256(off + sizeof(int) * 4);
     w.tau = off;  off = align256(off + sizeof(float) * 15 * E * NP);
@@ -719,6 +719,53 @@ int chorus_conserved_sums(chorus_mesh_t mesh, const double *Q_dev, double out_ho
     if (e == hipSuccess) e = hipMemcpyAsync(out_host, out, 5 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "conserved_sums");
+    return CHORUS_OK;
+}
+
+int chorus_angular_momentum(chorus_mesh_t mesh, const double *Q_dev, double out_host[6], void *ws, void *stream) {
+    Mesh *m = reinterpret_cast<Mesh *>(mesh);
+    int rc = check_ready(m);
+    if (rc) return rc;
+    if (!Q_dev || !ws || !out_host) {
+        set_error("null argument");
+        return CHORUS_EINVAL;
+    }
+    const WsLayout w = ws_layout(*m);
+    unsigned char *W = (unsigned char *)ws;
+    const unsigned char *img = (const unsigned char *)m->dev_image;
+    hipStream_t s = (hipStream_t)stream;
+    double *out = (double *)(W + w.sums);
+    hipError_t e = launch_am_sums(Q_dev, (const double *)(img + m->layout.solw), (const double *)(img + m->layout.xsol),
+                                  m->E, m->N * m->N * m->N, (double *)(W + w.part), kSumBlocks, out, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out_host, out, 6 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "angular_momentum");
+    return CHORUS_OK;
+}
+
+int chorus_am_correct(chorus_mesh_t mesh, double *Q_dev, double dOmega_host[3], void *ws, void *stream) {
+    double LI[6];
+    int rc = chorus_angular_momentum(mesh, Q_dev, LI, ws, stream);
+    if (rc) return rc;
+    Mesh *m = reinterpret_cast<Mesh *>(mesh);
+    double dO[3];
+    for (int c = 0; c < 3; ++c) {
+        if (!(LI[3 + c] > 0.0)) {
+            set_error("am_correct: non-positive moment of inertia");
+            return CHORUS_ENONFINITE;
+        }
+        dO[c] = LI[c] / LI[3 + c];
+        if (!std::isfinite(dO[c])) {
+            set_error("am_correct: non-finite angular momentum");
+            return CHORUS_ENONFINITE;
+        }
+    }
+    const unsigned char *img = (const unsigned char *)m->dev_image;
+    hipError_t e = launch_am_apply(Q_dev, (const double *)(img + m->layout.xsol), m->E, m->N * m->N * m->N, dO,
+                                   (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "am_correct");
+    if (dOmega_host)
+        for (int c = 0; c < 3; ++c) dOmega_host[c] = dO[c];
     return CHORUS_OK;
 }
 

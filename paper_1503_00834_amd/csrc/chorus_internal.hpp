@@ -42,6 +42,7 @@ struct DeviceLayout {
     size_t solw = 0;       // f64 [E][NP]: w w w |J|
     size_t solgeo32 = 0;   // f32 copy of solgeo (mixed mode)
     size_t fluxgeo32 = 0;  // f32 copy of fluxgeo (mixed mode)
+    size_t xsol = 0;       // f64 [E][3][NP]: solution-point coordinates
     size_t total = 0;
 };
 

@@ -84,6 +84,11 @@ hipError_t launch_filter(const FilterArgs &A, hipStream_t s);
 hipError_t launch_sums(const double *Q, const double *solw, int64_t n, double *part, int nblocks, double *out,
                        hipStream_t s);
 hipError_t launch_check(const double *Q, int64_t n, double gm1, int *flag, hipStream_t s);
+// angular momentum and diagonal moments of inertia (6 rows of nblocks
+// partials in part, results in out[6]); rigid-rotation removal
+hipError_t launch_am_sums(const double *Q, const double *solw, const double *xsol, int64_t E, int NP, double *part,
+                          int nblocks, double *out, hipStream_t s);
+hipError_t launch_am_apply(double *Q, const double *xsol, int64_t E, int NP, const double dO[3], hipStream_t s);
 hipError_t launch_clear_flag(int *flag, hipStream_t s);
 
 // mixed-precision path: FP32 geometry, background arrays and FP64 Q0 copy

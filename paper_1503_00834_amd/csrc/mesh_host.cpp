@@ -562,6 +562,7 @@ static void build_image(Mesh &m) {
     L.solw = off;      off = align256(off + sizeof(double) * E * NP);
     L.solgeo32 = off;  off = align256(off + sizeof(float) * E * 13 * NP);
     L.fluxgeo32 = off; off = align256(off + sizeof(float) * E * 9 * NFL);
+    L.xsol = off;      off = align256(off + sizeof(double) * E * 3 * NP);
     L.total = off;
     m.image.assign(L.total, 0);
     double *sg = (double *)(m.image.data() + L.solgeo);
@@ -571,6 +572,7 @@ static void build_image(Mesh &m) {
     double *sw = (double *)(m.image.data() + L.solw);
     float *sg32 = (float *)(m.image.data() + L.solgeo32);
     float *fg32 = (float *)(m.image.data() + L.fluxgeo32);
+    double *xs = (double *)(m.image.data() + L.xsol);
     const Basis1D &b = m.basis;
     for (int64_t e = 0; e < E; ++e) {
         for (int p = 0; p < NP; ++p) {
@@ -582,6 +584,7 @@ static void build_image(Mesh &m) {
             const double *x = &m.xsol[(e * NP + p) * 3];
             double r = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
             for (int c = 0; c < 3; ++c) sg[(e * 13 + 10 + c) * NP + p] = x[c] / (r * r * r);
+            for (int c = 0; c < 3; ++c) xs[(e * 3 + c) * NP + p] = x[c];
             int i = p % N, j = (p / N) % N, k = p / (N * N);
             sw[e * NP + p] = b.w[i] * b.w[j] * b.w[k] * J;
         }

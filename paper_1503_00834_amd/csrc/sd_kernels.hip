@@ -514,10 +514,10 @@ __global__ __launch_bounds__(NT) void k_sums_partial(const double *__restrict__ 
 }
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_sums_final(const double *__restrict__ part, int nb,
+__global__ __launch_bounds__(NT) void k_sums_final(const double *__restrict__ part, int nb, int rows,
                                                    double *__restrict__ out) {
     __shared__ double red[NT];
-    for (int v = 0; v < 5; ++v) {
+    for (int v = 0; v < rows; ++v) {
         double s = 0.0;
         for (int i = threadIdx.x; i < nb; i += NT) s += part[(int64_t)v * nb + i];
         red[threadIdx.x] = s;
@@ -529,6 +529,59 @@ __global__ __launch_bounds__(NT) void k_sums_final(const double *__restrict__ pa
         if (threadIdx.x == 0) out[v] = red[0];
         __syncthreads();
     }
+}
+
+// angular momentum L = sum w|J| x cross m and the diagonal moments of
+// inertia I_c = sum w|J| rho (|x|^2 - x_c^2) (Section 6): block partials
+// part[q][block], q = Lx, Ly, Lz, Ix, Iy, Iz, over contiguous chunks of
+// solution points, fixed tree order
+template <int NT>
+__global__ __launch_bounds__(NT) void k_am_partial(const double *__restrict__ Q, const double *__restrict__ solw,
+                                                   const double *__restrict__ xsol, int64_t E, int NP,
+                                                   int64_t chunk, double *__restrict__ part) {
+    __shared__ double red[6][NT];
+    const int64_t n = E * NP;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
+    double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
+        const int64_t e = i / NP, p = i % NP;
+        const double x = xsol[(e * 3 + 0) * NP + p], y = xsol[(e * 3 + 1) * NP + p], z = xsol[(e * 3 + 2) * NP + p];
+        const double w = solw[i], rho = Q[i], mx = Q[n + i], my = Q[2 * n + i], mz = Q[3 * n + i];
+        s[0] += w * (y * mz - z * my);
+        s[1] += w * (z * mx - x * mz);
+        s[2] += w * (x * my - y * mx);
+        s[3] += w * rho * (y * y + z * z);
+        s[4] += w * rho * (x * x + z * z);
+        s[5] += w * rho * (x * x + y * y);
+    }
+    for (int q = 0; q < 6; ++q) red[q][threadIdx.x] = s[q];
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 6; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
+}
+
+// u <- u - dOmega x x at fixed rho and pressure (E changes by the kinetic
+// energy change)
+__global__ void k_am_apply(double *__restrict__ Q, const double *__restrict__ xsol, int64_t E, int NP, double dx,
+                           double dy, double dz) {
+    const int64_t n = E * NP;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t e = i / NP, p = i % NP;
+    const double x = xsol[(e * 3 + 0) * NP + p], y = xsol[(e * 3 + 1) * NP + p], z = xsol[(e * 3 + 2) * NP + p];
+    const double rho = Q[i];
+    const double u = Q[n + i] / rho, v = Q[2 * n + i] / rho, w = Q[3 * n + i] / rho;
+    const double un = u - (dy * z - dz * y), vn = v - (dz * x - dx * z), wn = w - (dx * y - dy * x);
+    const double dke = 0.5 * rho * ((un * un + vn * vn + wn * wn) - (u * u + v * v + w * w));
+    Q[n + i] = rho * un;
+    Q[2 * n + i] = rho * vn;
+    Q[3 * n + i] = rho * wn;
+    Q[4 * n + i] += dke;
 }
 
 // non-finite / non-positive density or pressure check: flag[0] set to 1
@@ -681,7 +734,25 @@ hipError_t launch_sums(const double *Q, const double *solw, int64_t n, double *p
     hipLaunchKernelGGL((k_sums_partial<256>), dim3(nblocks), dim3(256), 0, s, Q, solw, n, chunk, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_sums_final<256>), dim3(1), dim3(256), 0, s, part, nblocks, out);
+    hipLaunchKernelGGL((k_sums_final<256>), dim3(1), dim3(256), 0, s, part, nblocks, 5, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_am_sums(const double *Q, const double *solw, const double *xsol, int64_t E, int NP, double *part,
+                          int nblocks, double *out, hipStream_t s) {
+    const int64_t n = E * NP;
+    const int64_t chunk = (n + nblocks - 1) / nblocks;
+    hipLaunchKernelGGL((k_am_partial<256>), dim3(nblocks), dim3(256), 0, s, Q, solw, xsol, E, NP, chunk, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sums_final<256>), dim3(1), dim3(256), 0, s, part, nblocks, 6, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_am_apply(double *Q, const double *xsol, int64_t E, int NP, const double dO[3], hipStream_t s) {
+    const int64_t n = E * NP;
+    hipLaunchKernelGGL(k_am_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Q, xsol, E, NP, dO[0], dO[1],
+                       dO[2]);
     return hipGetLastError();
 }
 
