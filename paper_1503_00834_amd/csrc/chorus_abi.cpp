@@ -30,7 +30,7 @@ struct WsLayout {
     size_t Q2, Q4;  // SSPRK(5,4): extra stage registers (FP64 path), 0 otherwise
     size_t tau;  // learned closure: subgrid flux [15][E][NP] FP32 (0 when off)
     // mixed-precision path
-    size_t P0, P1, TQm0, TQm1, TVm, bg, dbg, gS0, R0, Q0;
+    size_t P0, P1, TQm0, TQm1, TVm, bg, dbg, gS0, R0, Q0, FFm;
     size_t P2, P4;  // SSPRK(5,4) on the perturbation
     bool mixed;
     size_t total;
@@ -68,6 +68,7 @@ static WsLayout ws_layout(const Mesh &m) {
     w.gS0 = off;  off = align256(off + sizeof(float) * E * 3 * (N + 1) * NF2);
     w.R0 = off;   off = align256(off + sizeof(float) * 5 * E * NP);
     w.Q0 = off;   off = align256(off + state);
+    w.FFm = off;  off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
     w.total = off;
     return w;
 }
@@ -85,6 +86,7 @@ static GeoM geom_of(const Mesh &m, const WsLayout &w, unsigned char *W) {
     g.gS0 = (const float *)(W + w.gS0);
     g.R0 = (const float *)(W + w.R0);
     g.Q0 = (const double *)(W + w.Q0);
+    g.FF = (float *)(W + w.FFm);
     return g;
 }
 

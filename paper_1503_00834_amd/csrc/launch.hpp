@@ -103,6 +103,7 @@ struct GeoM {
     const float *gS0;        // [E][3][NFL] background entropy gradient along the flux metric
     const float *R0;         // [5][E][NP]  background residual
     const double *Q0;        // [5][E][NP]  background state
+    float *FF;               // [E][6][5][NF2] own-side face flux (gradient -> residual pass)
 };
 
 // as StageArgs, on the perturbation P (mode 0 writes dQ/dt to Pout)

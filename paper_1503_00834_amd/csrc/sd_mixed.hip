@@ -54,6 +54,8 @@ struct MixedBufs {
     const float *dbg;   // [E][6][2][NF2] neighbour minus own background face trace (rho, E)
     const float *gS0;   // [E][3][NFL]   grad S0 . (|J| grad xi_d) at d-flux points
     const float *R0;    // [5][E][NP]    R(Q0)
+    float *FF;          // [E][6][5][NF2] own-side face flux along the outward area vector
+                        // (written by the gradient pass, read by the residual pass)
 };
 
 struct PhysF {
@@ -412,6 +414,63 @@ __device__ __forceinline__ void state_at(const OpsF<N> &op, const MixedLds<N> &l
     }
 }
 
+// Own-side part of the common transformed flux difference at a face point,
+// along the outward area vector So.  Interior face: the Rusanov flux of the
+// own state s and the neighbour state (perturbation trace nq, background
+// jump db) minus half of the own viscous flux fv (the neighbour's half is
+// added by the residual pass from the neighbour's viscous trace).  Wall
+// face: the complete wall flux (inviscid (0, p' So, 0); viscous wall form).
+__device__ __forceinline__ void face_flux_own(const PtState &s, const float nq[5], const float db[2], bool interior,
+                                              bool outer, const float So[3], float gS0S, const float fv_in[5],
+                                              const PhysF &F, float phi[5]) {
+    if (interior) {
+        PtState r = s;
+        r.rp = nq[0];
+        r.m[0] = nq[1];
+        r.m[1] = nq[2];
+        r.m[2] = nq[3];
+        r.Ep = nq[4];
+        const float dr0 = db[0], dE0 = db[1];
+        r.r0 = s.r0 + dr0;
+        r.E0 = s.E0 + dE0;
+        float fL[5], fR[5];
+        dflux_inviscid(s, So, F, fL);
+        dflux_inviscid(r, So, F, fR);
+        const float A = sqrtf(So[0] * So[0] + So[1] * So[1] + So[2] * So[2]), iA = rcp(A);
+        // |u.n| + (c - c0) on each side; c^2 - c0^2 = gamma (p' rho0 - p0 rho') / (rho rho0)
+        auto excess = [&](const PtState &q, float &c0) {
+            const float inv = rcp(q.r0 + q.rp), ir0 = rcp(q.r0);
+            const float un = fabsf((q.m[0] * So[0] + q.m[1] * So[1] + q.m[2] * So[2]) * iA * inv);
+            const float mm = q.m[0] * q.m[0] + q.m[1] * q.m[1] + q.m[2] * q.m[2];
+            const float pp_ = F.gm1 * (q.Ep - 0.5f * mm * inv), p0 = F.gm1 * q.E0;
+            c0 = sqrtf(F.gam * p0 * ir0);
+            const float dc2 = F.gam * (pp_ * q.r0 - p0 * q.rp) * inv * ir0;
+            const float c = sqrtf(c0 * c0 + dc2);
+            return un + dc2 * rcp(c + c0);
+        };
+        float c0L, c0R;
+        const float eL = excess(s, c0L), eR = excess(r, c0R);
+        // background sound-speed jump c0R - c0L from the FP64 background jump
+        const float dc0 = F.gam * F.gm1 * (dE0 * s.r0 - s.E0 * dr0) * rcp(s.r0 * r.r0 * (c0L + c0R));
+        const float dlam = fmaxf(eL, eR + dc0) - fmaxf(0.0f, dc0);
+        const float lam0 = c0L + fmaxf(0.0f, dc0);
+        const float hl = 0.5f * (lam0 + dlam) * A, hd = 0.5f * dlam * A;
+        const float pR[5] = {r.rp, r.m[0], r.m[1], r.m[2], r.Ep};
+        const float pL[5] = {s.rp, s.m[0], s.m[1], s.m[2], s.Ep};
+        const float dq0[5] = {dr0, 0.0f, 0.0f, 0.0f, dE0};
+        for (int v = 0; v < 5; ++v)
+            phi[v] = 0.5f * (fL[v] + fR[v]) - hl * (pR[v] - pL[v]) - hd * dq0[v] - 0.5f * fv_in[v];
+    } else {
+        const float mm = s.m[0] * s.m[0] + s.m[1] * s.m[1] + s.m[2] * s.m[2];
+        const float pp = F.gm1 * (s.Ep - 0.5f * mm * rcp(s.r0 + s.rp));
+        float fv[5];
+        dflux_viscous(s, So, gS0S, F, outer ? 2 : 1, fv);
+        phi[0] = 0.0f;
+        for (int a = 0; a < 3; ++a) phi[1 + a] = pp * So[a] - fv[1 + a];
+        phi[4] = -fv[4];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
@@ -448,7 +507,8 @@ __global__ __launch_bounds__(NT) void k_pert_begin(OpsF<N> op, GeoF G, const dou
 }
 
 // viscous-flux difference of the own side at interior interface points
-// along the outward area vector: TV[e][f][v][pp]
+// along the outward area vector, pushed to the neighbour: TV; and the
+// own-side face flux at every face point: FF (face_flux_own)
 template <int N, int EPB, int NT>
 __global__ __launch_bounds__(NT) void k_grad_mixed(OpsF<N> op, GeoF G, MixedBufs B, PhysParams P,
                                                    const double *__restrict__ Pq, const float *__restrict__ TQ,
@@ -485,15 +545,21 @@ __global__ __launch_bounds__(NT) void k_grad_mixed(OpsF<N> op, GeoF G, MixedBufs
         if (it >= EPB * 6 * NF2) break;
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
         const int64_t e = e0 + el;
-        const int32_t nb = L[el].lk[f];
-        if (e >= G.E || nb < 0) continue;
+        if (e >= G.E) continue;
+        const int32_t nb = L[el].lk[f], inf = L[el].inf[f];
         const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
-        float fv[5];
+        float fv[5], phi[5];
         PtState st;
         state_at<N>(op, L[el], m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), st);
-        dflux_viscous(st, Sf[k], gSf[k], F, 0, fv);
-        const int64_t slot = mailbox_slot<N>(nb, L[el].inf[f], pp);
-        for (int v = 0; v < 5; ++v) TV[slot + v * NF2] = fv[v];
+        if (nb >= 0) {
+            dflux_viscous(st, Sf[k], gSf[k], F, 0, fv);
+            const int64_t slot = mailbox_slot<N>(nb, inf, pp);
+            for (int v = 0; v < 5; ++v) TV[slot + v * NF2] = fv[v];
+        }
+        face_flux_own(st, R.nq[k], R.db[k], nb >= 0, ((inf >> 6) - 1) == CHORUS_BC_OUTER, Sf[k], gSf[k], fv, F,
+                      phi);
+        float *ff = B.FF + (e * 6 + f) * 5 * NF2 + pp;
+        for (int v = 0; v < 5; ++v) ff[v * NF2] = phi[v];
     }
 }
 
@@ -506,7 +572,7 @@ struct ResidIn {
     using Sh = Shape<N, EPB, NT>;
     Prologue<N, EPB, NT> R;
     float Si[Sh::IT_INT][3], gSi[Sh::IT_INT];
-    float Sf[Sh::IT_FACE][3], gSf[Sh::IT_FACE];
+    float ff[Sh::IT_FACE][5];  // own-side face flux from the gradient pass
 };
 
 // issue every global load of the element block starting at e0.  Interior
@@ -521,13 +587,10 @@ __device__ __forceinline__ void resid_load(const GeoF &G, const MixedBufs &B, co
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
         const int it = threadIdx.x + k * NT;
-        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        const int el = it / (6 * NF2), r = it % (6 * NF2);
         const int64_t e = e0 + el;
         const bool ok = it < EPB * 6 * NF2 && e < G.E;
-        const int d = f >> 1, fl = ((f & 1) ? N : 0) + (N + 1) * pp;
-        const float sg = (f & 1) ? 1.0f : -1.0f;
-        for (int c = 0; c < 3; ++c) In.Sf[k][c] = ok ? sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
-        In.gSf[k] = ok ? sg * B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
+        for (int v = 0; v < 5; ++v) In.ff[k][v] = ok ? B.FF[(e * 6 + r / NF2) * 5 * NF2 + v * NF2 + r % NF2] : 0.0f;
     }
 #pragma unroll
     for (int k = 0; k < Sh::IT_INT; ++k) {
@@ -572,7 +635,9 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
         const int fl = m + (N + 1) * tt;
         for (int v = 0; v < 5; ++v) l.u.ft[d][v][fl] = fi[v] - fv[v];
     }
-    // common fluxes at the interface points (outward area vector So)
+    // common fluxes at the interface points: own-side part from the gradient
+    // pass plus half the neighbour's viscous flux (stored along its own
+    // outward vector, -So)
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
         const int it = threadIdx.x + k * NT;
@@ -580,67 +645,11 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
         if (e0 + el >= G.E) continue;
         MixedLds<N> &l = L[el];
-        const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
+        const int d = f >> 1, m = (f & 1) ? N : 0;
         const float sg = (f & 1) ? 1.0f : -1.0f;
-        const float *So = In.Sf[k];
-        const float gS0S = In.gSf[k];
-        PtState s;
-        state_at<N>(op, l, m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), s);
-        const int32_t nb = l.lk[f], inf = l.inf[f];
-        float phi[5];
-        if (nb >= 0) {
-            // neighbour state from its perturbation trace and the background jump
-            PtState r = s;
-            r.rp = R.nq[k][0];
-            r.m[0] = R.nq[k][1];
-            r.m[1] = R.nq[k][2];
-            r.m[2] = R.nq[k][3];
-            r.Ep = R.nq[k][4];
-            const float dr0 = R.db[k][0], dE0 = R.db[k][1];
-            r.r0 = s.r0 + dr0;
-            r.E0 = s.E0 + dE0;
-            float fL[5], fR[5], fvL[5];
-            dflux_inviscid(s, So, F, fL);
-            dflux_inviscid(r, So, F, fR);
-            const float A = sqrtf(So[0] * So[0] + So[1] * So[1] + So[2] * So[2]), iA = rcp(A);
-            // |u.n| + (c - c0) on each side; c^2 - c0^2 = gamma (p' rho0 - p0 rho') / (rho rho0)
-            auto excess = [&](const PtState &q, float &c0) {
-                const float inv = rcp(q.r0 + q.rp), ir0 = rcp(q.r0);
-                const float un = fabsf((q.m[0] * So[0] + q.m[1] * So[1] + q.m[2] * So[2]) * iA * inv);
-                const float mm = q.m[0] * q.m[0] + q.m[1] * q.m[1] + q.m[2] * q.m[2];
-                const float pp_ = F.gm1 * (q.Ep - 0.5f * mm * inv), p0 = F.gm1 * q.E0;
-                c0 = sqrtf(F.gam * p0 * ir0);
-                const float dc2 = F.gam * (pp_ * q.r0 - p0 * q.rp) * inv * ir0;
-                const float c = sqrtf(c0 * c0 + dc2);
-                return un + dc2 * rcp(c + c0);
-            };
-            float c0L, c0R;
-            const float eL = excess(s, c0L), eR = excess(r, c0R);
-            // background sound-speed jump c0R - c0L from the FP64 background jump
-            const float dc0 = F.gam * F.gm1 * (dE0 * s.r0 - s.E0 * dr0) * rcp(s.r0 * r.r0 * (c0L + c0R));
-            const float dlam = fmaxf(eL, eR + dc0) - fmaxf(0.0f, dc0);
-            const float lam0 = c0L + fmaxf(0.0f, dc0);
-            const float hl = 0.5f * (lam0 + dlam) * A, hd = 0.5f * dlam * A;
-            const float pR[5] = {r.rp, r.m[0], r.m[1], r.m[2], r.Ep};
-            const float pL[5] = {s.rp, s.m[0], s.m[1], s.m[2], s.Ep};
-            const float dq0[5] = {dr0, 0.0f, 0.0f, 0.0f, dE0};
-            for (int v = 0; v < 5; ++v) phi[v] = 0.5f * (fL[v] + fR[v]) - hl * (pR[v] - pL[v]) - hd * dq0[v];
-            dflux_viscous(s, So, gS0S, F, 0, fvL);
-            // the neighbour stored its flux along its own outward vector (-So)
-            for (int v = 0; v < 5; ++v) phi[v] -= 0.5f * (fvL[v] + (-R.nv[k][v]));
-        } else {
-            // wall: inviscid (0, p' S, 0); viscous wall form
-            const bool outer = ((inf >> 6) - 1) == CHORUS_BC_OUTER;
-            const float mm = s.m[0] * s.m[0] + s.m[1] * s.m[1] + s.m[2] * s.m[2];
-            const float pp = F.gm1 * (s.Ep - 0.5f * mm * rcp(s.r0 + s.rp));
-            float fv[5];
-            dflux_viscous(s, So, gS0S, F, outer ? 2 : 1, fv);
-            phi[0] = 0.0f;
-            for (int a = 0; a < 3; ++a) phi[1 + a] = pp * So[a] - fv[1 + a];
-            phi[4] = -fv[4];
-        }
+        const float h = (l.lk[f] >= 0) ? 0.5f : 0.0f;
         const int fl = m + (N + 1) * pp;
-        for (int v = 0; v < 5; ++v) l.u.ft[d][v][fl] = sg * phi[v];
+        for (int v = 0; v < 5; ++v) l.u.ft[d][v][fl] = sg * (In.ff[k][v] + h * R.nv[k][v]);
     }
     __syncthreads();
     // divergence, source, background residual and stage update
@@ -824,6 +833,7 @@ static MixedBufs bufs_of(const GeoM &g) {
     b.dbg = g.dbg;
     b.gS0 = g.gS0;
     b.R0 = g.R0;
+    b.FF = g.FF;
     return b;
 }
 
