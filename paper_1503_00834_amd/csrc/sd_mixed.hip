@@ -180,7 +180,7 @@ struct MixedLds {
     float g[NGRAD][NP];           // gradients
     union {
         float cs[NFIELD][6][NF2];  // common values (perturbation 0..4, background 5..6)
-        float ft[3][5][NFL];       // transformed flux, written after cs is consumed
+        float ft[5][NFL];          // transformed flux of one direction, written after cs is consumed
     } u;
     int32_t lk[6], inf[6];        // neighbour element and info word per face
 };
@@ -191,8 +191,8 @@ struct Shape {
     static constexpr int IT_SOL = (EPB * NP + NT - 1) / NT;
     static constexpr int IT_FACE = (EPB * 6 * NF2 + NT - 1) / NT;
     static constexpr int IT_FLUX = (EPB * 3 * NFL + NT - 1) / NT;
-    static constexpr int NINT = 3 * (N - 1) * N * N;  // interior flux points per element
-    static constexpr int IT_INT = (EPB * NINT + NT - 1) / NT;
+    static constexpr int NINTD = (N - 1) * N * N;     // interior flux points per element and direction
+    static constexpr int IT_INTD = (EPB * NINTD + NT - 1) / NT;
     static constexpr int MB = 6 * 5 * NF2;             // mailbox floats per element
     static constexpr int DB = 6 * 2 * NF2;
 };
@@ -509,8 +509,8 @@ __global__ __launch_bounds__(NT) void k_pert_begin(OpsF<N> op, GeoF G, const dou
 // viscous-flux difference of the own side at interior interface points
 // along the outward area vector, pushed to the neighbour: TV; and the
 // own-side face flux at every face point: FF (face_flux_own)
-template <int N, int EPB, int NT>
-__global__ __launch_bounds__(NT) void k_grad_mixed(OpsF<N> op, GeoF G, MixedBufs B, PhysParams P,
+template <int N, int EPB, int NT, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_grad_mixed(OpsF<N> op, GeoF G, MixedBufs B, PhysParams P,
                                                    const double *__restrict__ Pq, const float *__restrict__ TQ,
                                                    float *__restrict__ TV) {
     constexpr int NF2 = N * N, NFL = (N + 1) * N * N;
@@ -571,19 +571,19 @@ template <int N, int EPB, int NT>
 struct ResidIn {
     using Sh = Shape<N, EPB, NT>;
     Prologue<N, EPB, NT> R;
-    float Si[Sh::IT_INT][3], gSi[Sh::IT_INT];
+    float Si[3][Sh::IT_INTD][3], gSi[3][Sh::IT_INTD];  // interior flux-point geometry per direction
     float ff[Sh::IT_FACE][5];  // own-side face flux from the gradient pass
 };
 
 // issue every global load of the element block starting at e0.  Interior
-// flux item it: el, d, interior index a = 1..N-1, tangential t1, t2;
-// interface item: el, face f, point pp.
+// flux item it of direction d: el, interior index a = 1..N-1, tangential
+// t1, t2; interface item: el, face f, point pp.
 template <int N, int EPB, int NT>
 __device__ __forceinline__ void resid_load(const GeoF &G, const MixedBufs &B, const double *Pq,
                                            const float *__restrict__ TQ, const float *__restrict__ TV,
                                            const MixedStage &S_, int64_t e0, ResidIn<N, EPB, NT> &In) {
     using Sh = Shape<N, EPB, NT>;
-    constexpr int NP = Sh::NP, NF2 = Sh::NF2, NFL = Sh::NFL, NINT = Sh::NINT;
+    constexpr int NF2 = Sh::NF2, NFL = Sh::NFL, NINTD = Sh::NINTD;
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
         const int it = threadIdx.x + k * NT;
@@ -593,15 +593,17 @@ __device__ __forceinline__ void resid_load(const GeoF &G, const MixedBufs &B, co
         for (int v = 0; v < 5; ++v) In.ff[k][v] = ok ? B.FF[(e * 6 + r / NF2) * 5 * NF2 + v * NF2 + r % NF2] : 0.0f;
     }
 #pragma unroll
-    for (int k = 0; k < Sh::IT_INT; ++k) {
-        const int it = threadIdx.x + k * NT;
-        const int el = it / NINT, r = it % NINT, d = r / ((N - 1) * NF2), q = r % ((N - 1) * NF2);
-        const int fl = 1 + q % (N - 1) + (N + 1) * (q / (N - 1));
-        const int64_t e = e0 + el;
-        const bool ok = it < EPB * NINT && e < G.E;
-        for (int c = 0; c < 3; ++c) In.Si[k][c] = ok ? G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
-        In.gSi[k] = ok ? B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
-    }
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int k = 0; k < Sh::IT_INTD; ++k) {
+            const int it = threadIdx.x + k * NT;
+            const int el = it / NINTD, q = it % NINTD;
+            const int fl = 1 + q % (N - 1) + (N + 1) * (q / (N - 1));
+            const int64_t e = e0 + el;
+            const bool ok = it < EPB * NINTD && e < G.E;
+            for (int c = 0; c < 3; ++c) In.Si[d][k][c] = ok ? G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
+            In.gSi[d][k] = ok ? B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
+        }
     prologue_load<N, EPB, NT>(Pq, B, G, TQ, TV, e0, In.R);
 }
 
@@ -612,47 +614,74 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
                                               const PhysF &F, const MixedStage &S_, int64_t e0,
                                               const ResidIn<N, EPB, NT> &In, MixedLds<N> *L) {
     using Sh = Shape<N, EPB, NT>;
-    constexpr int NP = Sh::NP, NF2 = Sh::NF2, NINT = Sh::NINT;
+    constexpr int NP = Sh::NP, NF2 = Sh::NF2;
     const Prologue<N, EPB, NT> &R = In.R;
     common_values<N, EPB, NT>(op, G, F, e0, L, R);
     __syncthreads();
     gradients<N, EPB, NT>(op, G, e0, L, R.gs);
     __syncthreads();
-    // transformed perturbation flux at the interior flux points
+    // per direction d: transformed perturbation flux at the d-flux points
+    // (interior points here, interface points from the own-side face flux of
+    // the gradient pass plus half the neighbour's viscous flux, stored along
+    // its own outward vector -So), then its derivative added to the
+    // divergence at the solution points
+    float div[Sh::IT_SOL][5];
 #pragma unroll
-    for (int k = 0; k < Sh::IT_INT; ++k) {
-        const int it = threadIdx.x + k * NT;
-        if (it >= EPB * NINT) break;
-        const int el = it / NINT, r = it % NINT, d = r / ((N - 1) * NF2), q = r % ((N - 1) * NF2);
-        const int m = 1 + q % (N - 1), tt = q / (N - 1), t1 = tt % N, t2 = tt / N;
-        if (e0 + el >= G.E) continue;
-        MixedLds<N> &l = L[el];
-        PtState s;
-        state_at<N>(op, l, m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), s);
-        float fi[5], fv[5];
-        dflux_inviscid(s, In.Si[k], F, fi);
-        dflux_viscous(s, In.Si[k], In.gSi[k], F, 0, fv);
-        const int fl = m + (N + 1) * tt;
-        for (int v = 0; v < 5; ++v) l.u.ft[d][v][fl] = fi[v] - fv[v];
-    }
-    // common fluxes at the interface points: own-side part from the gradient
-    // pass plus half the neighbour's viscous flux (stored along its own
-    // outward vector, -So)
+    for (int k = 0; k < Sh::IT_SOL; ++k)
+        for (int v = 0; v < 5; ++v) div[k][v] = 0.0f;
 #pragma unroll
-    for (int k = 0; k < Sh::IT_FACE; ++k) {
-        const int it = threadIdx.x + k * NT;
-        if (it >= EPB * 6 * NF2) break;
-        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
-        if (e0 + el >= G.E) continue;
-        MixedLds<N> &l = L[el];
-        const int d = f >> 1, m = (f & 1) ? N : 0;
-        const float sg = (f & 1) ? 1.0f : -1.0f;
-        const float h = (l.lk[f] >= 0) ? 0.5f : 0.0f;
-        const int fl = m + (N + 1) * pp;
-        for (int v = 0; v < 5; ++v) l.u.ft[d][v][fl] = sg * (In.ff[k][v] + h * R.nv[k][v]);
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int k = 0; k < Sh::IT_INTD; ++k) {
+            const int it = threadIdx.x + k * NT;
+            if (it >= EPB * Sh::NINTD) break;
+            const int el = it / Sh::NINTD, q = it % Sh::NINTD;
+            const int m = 1 + q % (N - 1), tt = q / (N - 1), t1 = tt % N, t2 = tt / N;
+            if (e0 + el >= G.E) continue;
+            MixedLds<N> &l = L[el];
+            PtState s;
+            state_at<N>(op, l, m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), s);
+            float fi[5], fv[5];
+            dflux_inviscid(s, In.Si[d][k], F, fi);
+            dflux_viscous(s, In.Si[d][k], In.gSi[d][k], F, 0, fv);
+            const int fl = m + (N + 1) * tt;
+            for (int v = 0; v < 5; ++v) l.u.ft[v][fl] = fi[v] - fv[v];
+        }
+#pragma unroll
+        for (int k = 0; k < Sh::IT_FACE; ++k) {
+            const int it = threadIdx.x + k * NT;
+            if (it >= EPB * 6 * NF2) break;
+            const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+            if ((f >> 1) != d || e0 + el >= G.E) continue;
+            MixedLds<N> &l = L[el];
+            const int m = (f & 1) ? N : 0;
+            const float sg = (f & 1) ? 1.0f : -1.0f;
+            const float h = (l.lk[f] >= 0) ? 0.5f : 0.0f;
+            const int fl = m + (N + 1) * pp;
+            for (int v = 0; v < 5; ++v) l.u.ft[v][fl] = sg * (In.ff[k][v] + h * R.nv[k][v]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < Sh::IT_SOL; ++k) {
+            const int it = threadIdx.x + k * NT;
+            if (it >= EPB * NP) break;
+            const int el = it / NP, p = it % NP;
+            if (e0 + el >= G.E) continue;
+            const MixedLds<N> &l = L[el];
+            int a, t1, t2;
+            split_sol<N>(d, p, a, t1, t2);
+            const int fb = (N + 1) * (t1 + N * t2);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                float sum = 0.0f;
+#pragma unroll
+                for (int mm = 0; mm <= N; ++mm) sum += op.D[a][mm] * l.u.ft[v][fb + mm];
+                div[k][v] += sum;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    // divergence, source, background residual and stage update
+    // source, background residual and stage update
 #pragma unroll
     for (int k = 0; k < Sh::IT_SOL; ++k) {
         const int it = threadIdx.x + k * NT;
@@ -661,20 +690,6 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
         MixedLds<N> &l = L[el];
-        float div[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            int a, t1, t2;
-            split_sol<N>(d, p, a, t1, t2);
-            const int fb = (N + 1) * (t1 + N * t2);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                float s = 0.0f;
-#pragma unroll
-                for (int mm = 0; mm <= N; ++mm) s += op.D[a][mm] * l.u.ft[d][v][fb + mm];
-                div[v] += s;
-            }
-        }
         // stage-update operands, loaded here rather than held through the flux phase
         const float *gsp = G.solgeo + e * 13 * NP + p;
         const float iJ = gsp[9 * NP];
@@ -697,7 +712,7 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
         float newp[5];
         for (int v = 0; v < 5; ++v) {
             const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
-            const double Rv = (double)r0s[v] + (double)(-div[v] * iJ - M[v]);
+            const double Rv = (double)r0s[v] + (double)(-div[k][v] * iJ - M[v]);
             if (S_.mode == 0) {
                 S_.Pout[gi] = Rv;
             } else {
@@ -812,11 +827,16 @@ __global__ void k_to_float(const double *__restrict__ a, float *__restrict__ b, 
 // ---------------------------------------------------------------------------
 template <int N>
 struct CfgM;
-template <> struct CfgM<2> { static constexpr int EPB = 8, NT = 64, K = 1, MINW = 2; };
-template <> struct CfgM<3> { static constexpr int EPB = 2, NT = 64, K = 1, MINW = 3; };
-template <> struct CfgM<4> { static constexpr int EPB = 1, NT = 64, K = 1, MINW = 3; };
-template <> struct CfgM<5> { static constexpr int EPB = 1, NT = 128, K = 1, MINW = 2; };
-template <> struct CfgM<6> { static constexpr int EPB = 1, NT = 256, K = 1, MINW = 1; };
+// elements per block, threads, element blocks per workgroup, and the
+// minimum waves per SIMD the residual (MINW) and gradient (MINWG) passes are
+// compiled for.  At N = 4 the residual pass runs four waves per SIMD (a few
+// spilled registers cost less than the added latency hiding); the gradient
+// pass stays at three (holding it to 128 registers spills too much).
+template <> struct CfgM<2> { static constexpr int EPB = 8, NT = 64, K = 1, MINW = 2, MINWG = 2; };
+template <> struct CfgM<3> { static constexpr int EPB = 2, NT = 64, K = 1, MINW = 3, MINWG = 3; };
+template <> struct CfgM<4> { static constexpr int EPB = 1, NT = 64, K = 1, MINW = 4, MINWG = 3; };
+template <> struct CfgM<5> { static constexpr int EPB = 1, NT = 128, K = 1, MINW = 2, MINWG = 2; };
+template <> struct CfgM<6> { static constexpr int EPB = 1, NT = 256, K = 1, MINW = 1, MINWG = 1; };
 
 static GeoF geof_of(const GeoM &g) {
     GeoF o;
@@ -850,7 +870,7 @@ static hipError_t grad_mixed_t(const Mesh &m, const GeoM &g, const PhysParams &P
                                float *TV, hipStream_t s) {
     constexpr int EPB = CfgM<N>::EPB, NT = CfgM<N>::NT;
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
-    hipLaunchKernelGGL((k_grad_mixed<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, make_ops_t<float, N>(m.basis),
+    hipLaunchKernelGGL((k_grad_mixed<N, EPB, NT, CfgM<N>::MINWG>), dim3(nb), dim3(NT), 0, s, make_ops_t<float, N>(m.basis),
                        geof_of(g), bufs_of(g), P, Pq, TQ, TV);
     return hipGetLastError();
 }
@@ -861,8 +881,6 @@ static hipError_t resid_mixed_t(const Mesh &m, const GeoM &g, const PhysParams &
     const unsigned nb = (unsigned)((m.E + EPB * K - 1) / (EPB * K));
     static_assert(K >= 1, "at least one element block per workgroup");
     const MixedStage st = a;
-    // at N = 3, 4 the block is held to three waves per SIMD (a few spilled
-    // registers cost less than a third of the latency-hiding waves)
     hipLaunchKernelGGL((k_resid_mixed<N, EPB, NT, K, CfgM<N>::MINW>), dim3(nb), dim3(NT), 0, s,
                        make_ops_t<float, N>(m.basis), geof_of(g), bufs_of(g), P, Pq, TQ, TV, st);
     return hipGetLastError();
