@@ -150,6 +150,24 @@ int chorus_init_polytrope(chorus_mesh_t mesh, double beta, double n_rho, double 
                           double gamma, double R_gas, const double *noise, double amp,
                           double *Q_host, double pars[4]);
 
+/* Almost-flux-balance background (Section 4.3): the polytrope of Section
+ * 4.2 (same units as chorus_init_polytrope) gives the target entropy
+ * gradient Gamma = -(L / (4 pi r^2) + rho_a c_p kappa_r dT_a/dr) /
+ * (rho_a T_a kappa) at which the diffusive flux of Section 2 carries L
+ * outward; the hydrostatic state with that entropy gradient,
+ * d p0/dr = -rho0 g and d rho0/dr = -rho0 (Gamma / c_p + g rho0 /
+ * (gamma p0)), is integrated from the polytrope's mid-layer point (rho0 =
+ * p0 = 1) to both walls.  Q_host [5][E N^3] receives the state at rest;
+ * pars (may be NULL) receives (chi_o, c, alpha, GM, T0 at the outer wall,
+ * bottom flux L / (4 pi R_i^2)) for chorus_physics (GM, T_top, F_bottom).
+ * kappa and kappa_r are the solver's constant diffusivities. */
+typedef struct {
+    double beta, n_rho, poly_n, gamma, R_gas;
+    double luminosity;        /* L in the units of depth 1, rho_c = p_c = 1 */
+    double kappa, kappa_r;
+} chorus_afb_desc;
+int chorus_init_afb(chorus_mesh_t mesh, const chorus_afb_desc *desc, double *Q_host, double pars[6]);
+
 /* Mixed mode: register the background state Q0 (device, [5][E N^3] FP64)
  * and compute its FP64 inviscid residual into the workspace.  Synchronises. */
 int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q0_dev,

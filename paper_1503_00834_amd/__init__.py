@@ -50,6 +50,12 @@ class Hex20Desc(ctypes.Structure):
                 ("order", ctypes.c_int32)]
 
 
+class AfbDesc(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("n_rho", ctypes.c_double), ("poly_n", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("R_gas", ctypes.c_double), ("luminosity", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("kappa_r", ctypes.c_double)]
+
+
 class Physics(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("R_gas", ctypes.c_double), ("GM", ctypes.c_double),
                 ("omega", ctypes.c_double), ("nu", ctypes.c_double), ("kappa", ctypes.c_double),
@@ -93,6 +99,7 @@ _SIGS = {
     "chorus_init_polytrope": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, _P, ctypes.c_double, _P, _P],
     "chorus_set_background": [_P, ctypes.POINTER(Physics), _P, _P, _P],
+    "chorus_init_afb": [_P, ctypes.POINTER(AfbDesc), _P, _P],
     "chorus_sd_residual": [_P, ctypes.POINTER(Physics), _P, _P, _P, _P],
     "chorus_rk_step": [_P, ctypes.POINTER(Physics), _P, ctypes.c_double, ctypes.c_int32, _P, _P],
     "chorus_conserved_sums": [_P, _P, _P, _P, _P],
@@ -202,6 +209,15 @@ class Mesh:
         _check(_lib.chorus_init_polytrope(self.handle, beta, n_rho, poly_n, gamma, R_gas, _ptr(nz), amp,
                                           _ptr(Q), _ptr(pars)), "chorus_init_polytrope")
         return Q, dict(chi_o=pars[0], c=pars[1], alpha=pars[2], GM=pars[3])
+
+    def init_afb(self, beta, n_rho, luminosity, kappa, kappa_r=0.0, poly_n=1.5, gamma=5.0 / 3.0, R_gas=1.0):
+        """Almost-flux-balance background at rest (chorus_init_afb): (Q [5, n],
+        pars with GM, T_top (outer-wall temperature) and F_bottom)."""
+        Q = np.zeros((5, self.n_solpts))
+        pars = np.zeros(6)
+        d = AfbDesc(beta, n_rho, poly_n, gamma, R_gas, luminosity, kappa, kappa_r)
+        _check(_lib.chorus_init_afb(self.handle, ctypes.byref(d), _ptr(Q), _ptr(pars)), "chorus_init_afb")
+        return Q, dict(chi_o=pars[0], c=pars[1], alpha=pars[2], GM=pars[3], T_top=pars[4], F_bottom=pars[5])
 
     def stable_dt(self, phys, Q_host, cfl):
         Qh = np.ascontiguousarray(Q_host, dtype=np.float64)

@@ -497,6 +497,143 @@ int chorus_init_polytrope(chorus_mesh_t mesh, double beta, double n_rho, double 
     return CHORUS_OK;
 }
 
+// Almost-flux-balance background (Section 4.3): from the polytrope
+// (rho_a, p_a, T_a = p_a / (R rho_a)) the target entropy gradient
+//   Gamma(r) = -(L / (4 pi r^2) + rho_a c_p kappa_r dT_a/dr) / (rho_a T_a kappa),
+// the gradient at which the diffusive flux f = -kappa rho T grad S -
+// kappa_r rho c_p grad T (Section 2) carries the luminosity L outward (the
+// printed equation lacks this overall sign; with it L > 0 gives the
+// superadiabatic dS/dr < 0 the section asks for)
+// and then the state equations
+//   dp0/dr = -rho0 g,  d rho0/dr = -rho0 (Gamma / c_p + g rho0 / (gamma p0)),
+// g = GM / r^2, integrated from the polytrope's mid-layer point (chi = 1,
+// rho0 = p0 = 1) out to both walls with classical RK4 on a fine uniform
+// grid; values at the solution points by cubic Hermite interpolation with
+// the ODE's own derivatives.
+namespace {
+struct AfbModel {
+    double c, alpha, n, gamma, R, cp, GM, L, kappa, kappa_r;
+    double chi(double r) const { return c + alpha / r; }
+    double gamma_target(double r) const {
+        const double ch = chi(r);
+        const double rho_a = std::pow(ch, n), T_a = ch / R;
+        const double dTa = -alpha / (r * r) / R;
+        return -(L / (4.0 * M_PI * r * r) + rho_a * cp * kappa_r * dTa) / (rho_a * T_a * kappa);
+    }
+    // d(rho, p)/dr
+    void rhs(double r, const double y[2], double dy[2]) const {
+        const double g = GM / (r * r);
+        dy[1] = -y[0] * g;
+        dy[0] = -y[0] * (gamma_target(r) / cp + g * y[0] / (gamma * y[1]));
+    }
+};
+
+static void rk4_table(const AfbModel &M, double r0, double r1, int steps, std::vector<double> &rr,
+                      std::vector<double> &yy) {
+    const double h = (r1 - r0) / steps;
+    double y[2] = {1.0, 1.0};
+    rr.assign(steps + 1, 0.0);
+    yy.assign(2 * (steps + 1), 0.0);
+    rr[0] = r0;
+    yy[0] = y[0];
+    yy[1] = y[1];
+    for (int k = 0; k < steps; ++k) {
+        const double r = r0 + k * h;
+        double k1[2], k2[2], k3[2], k4[2], t[2];
+        M.rhs(r, y, k1);
+        for (int i = 0; i < 2; ++i) t[i] = y[i] + 0.5 * h * k1[i];
+        M.rhs(r + 0.5 * h, t, k2);
+        for (int i = 0; i < 2; ++i) t[i] = y[i] + 0.5 * h * k2[i];
+        M.rhs(r + 0.5 * h, t, k3);
+        for (int i = 0; i < 2; ++i) t[i] = y[i] + h * k3[i];
+        M.rhs(r + h, t, k4);
+        for (int i = 0; i < 2; ++i) y[i] += h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+        rr[k + 1] = r0 + (k + 1) * h;
+        yy[2 * (k + 1)] = y[0];
+        yy[2 * (k + 1) + 1] = y[1];
+    }
+}
+
+// cubic Hermite interpolation of the table at r (r within the table; the
+// table step may be negative)
+static void hermite(const AfbModel &M, const std::vector<double> &rr, const std::vector<double> &yy, double r,
+                    double out[2]) {
+    const int n = (int)rr.size() - 1;
+    const double h = rr[1] - rr[0];
+    int k = (int)std::floor((r - rr[0]) / h);
+    if (k < 0) k = 0;
+    if (k >= n) k = n - 1;
+    const double s = (r - rr[k]) / h;
+    double d0[2], d1[2];
+    M.rhs(rr[k], &yy[2 * k], d0);
+    M.rhs(rr[k + 1], &yy[2 * (k + 1)], d1);
+    const double h00 = (1 + 2 * s) * (1 - s) * (1 - s), h10 = s * (1 - s) * (1 - s);
+    const double h01 = s * s * (3 - 2 * s), h11 = s * s * (s - 1);
+    for (int i = 0; i < 2; ++i)
+        out[i] = h00 * yy[2 * k + i] + h10 * h * d0[i] + h01 * yy[2 * (k + 1) + i] + h11 * h * d1[i];
+}
+}  // namespace
+
+int chorus_init_afb(chorus_mesh_t mesh, const chorus_afb_desc *desc, double *Q_host, double pars[6]) {
+    Mesh *m = reinterpret_cast<Mesh *>(mesh);
+    if (!m || !desc || !Q_host) {
+        set_error("null argument");
+        return CHORUS_EINVAL;
+    }
+    const chorus_afb_desc &d = *desc;
+    if (!(d.beta > 0.0 && d.beta < 1.0) || !(d.poly_n > 0.0) || !(d.gamma > 1.0) || !(d.R_gas > 0.0) ||
+        !(d.kappa > 0.0) || d.kappa_r < 0.0 || d.luminosity < 0.0) {
+        set_error("afb: need 0 < beta < 1, poly_n > 0, gamma > 1, R_gas > 0, kappa > 0, kappa_r >= 0, L >= 0");
+        return CHORUS_EINVAL;
+    }
+    // the polytrope of Section 4.2 with depth 1 and rho_c = p_c = 1
+    const double ebn = std::exp(d.n_rho / d.poly_n);
+    const double chi_o = (d.beta + 1.0) / (d.beta * ebn + 1.0);
+    const double om = 1.0 - d.beta;
+    AfbModel M;
+    M.c = (2.0 * chi_o - d.beta - 1.0) / om;
+    M.alpha = (1.0 + d.beta) * (1.0 - chi_o) / (om * om);
+    M.n = d.poly_n;
+    M.gamma = d.gamma;
+    M.R = d.R_gas;
+    M.cp = d.gamma * d.R_gas / (d.gamma - 1.0);
+    M.GM = (d.poly_n + 1.0) * M.alpha;  // p_c / rho_c = 1 = GM / ((n+1) alpha d)
+    M.L = d.luminosity;
+    M.kappa = d.kappa;
+    M.kappa_r = d.kappa_r;
+    const double ri = d.beta / om, ro = 1.0 / om, rc = M.alpha / (1.0 - M.c);
+    const int steps = 20000;
+    std::vector<double> r_out, y_out, r_in, y_in;
+    rk4_table(M, rc, ro, steps, r_out, y_out);
+    rk4_table(M, rc, ri, steps, r_in, y_in);
+    const int64_t n = m->E * m->N * m->N * m->N;
+    for (int64_t g = 0; g < n; ++g) {
+        const double *x = &m->xsol[g * 3];
+        const double r = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        double y[2];
+        // both tables interpolate with a signed step (the inward one runs
+        // from rc down to ri)
+        if (r >= rc) hermite(M, r_out, y_out, r, y);
+        else hermite(M, r_in, y_in, r, y);
+        Q_host[g] = y[0];
+        Q_host[n + g] = 0.0;
+        Q_host[2 * n + g] = 0.0;
+        Q_host[3 * n + g] = 0.0;
+        Q_host[4 * n + g] = y[1] / (d.gamma - 1.0);
+    }
+    if (pars) {
+        double yo[2];
+        hermite(M, r_out, y_out, ro, yo);
+        pars[0] = chi_o;
+        pars[1] = M.c;
+        pars[2] = M.alpha;
+        pars[3] = M.GM;
+        pars[4] = yo[1] / (yo[0] * d.R_gas);                  // T0 at the outer wall
+        pars[5] = d.luminosity / (4.0 * M_PI * ri * ri);       // bottom flux L / (4 pi R_i^2)
+    }
+    return CHORUS_OK;
+}
+
 int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q0_dev, void *ws,
                           void *stream) {
     Mesh *m = reinterpret_cast<Mesh *>(mesh);

@@ -524,3 +524,41 @@ def test_angular_momentum_correction_full_tensor(oracle_mod):
             if i != j:
                 Ioff[i, j] = -(wJ * rho * xyz[i] * xyz[j]).sum()
     np.testing.assert_allclose(L2, -Ioff @ dO, rtol=1e-9, atol=1e-14 * np.abs(Ioff).max())
+
+
+# --------------------------------------------------------------------------
+# almost-flux-balance background (Section 4.3)
+# --------------------------------------------------------------------------
+def test_afb_reduces_to_polytrope_without_flux(oracle_mod):
+    """L = 0 and kappa_r = 0: the target gradient vanishes and the
+    hydrostatic isentropic state is the adiabatic polytrope (closed form)."""
+    from oracle import afb
+    r = np.linspace(7 / 3, 10 / 3, 41)
+    rho, p = afb.background(r, 0.7, 1.0, 0.0, 1e-3)
+    _, c, alpha = afb.polytrope_constants(0.7, 1.0, 1.5)
+    chi = c + alpha / r
+    np.testing.assert_allclose(rho, chi ** 1.5, rtol=1e-11)
+    np.testing.assert_allclose(p, chi ** 2.5, rtol=1e-11)
+
+
+def test_afb_flux_balance_and_state_equations(oracle_mod):
+    """The target gradient makes the diffusive flux of the polytrope carry L
+    outward (the anelastic thermal balance, constant r^2 flux); the solved
+    state is hydrostatic with entropy gradient Gamma and superadiabatic."""
+    from oracle import afb
+    L, kap, kr = 3e-3, 1e-3, 1e-5   # radiative flux below L: superadiabatic
+    r = np.linspace(2.4, 3.3, 19)
+    G = afb.target_gradient(r, 0.7, 1.0, L, kap, kr)
+    _, c, alpha = afb.polytrope_constants(0.7, 1.0, 1.5)
+    chi = c + alpha / r
+    flux = -kap * chi ** 1.5 * chi * G - kr * chi ** 1.5 * 2.5 * (-alpha / r ** 2)
+    np.testing.assert_allclose(flux * 4 * np.pi * r ** 2, L, rtol=1e-12)
+    assert (G < 0).all()
+    h = 1e-4
+    rho, p = afb.background(r, 0.7, 1.0, L, kap, kr)
+    rp, pp = afb.background(r + h, 0.7, 1.0, L, kap, kr)
+    rm, pm = afb.background(r - h, 0.7, 1.0, L, kap, kr)
+    GM = 2.5 * alpha
+    np.testing.assert_allclose((pp - pm) / (2 * h), -rho * GM / r ** 2, rtol=1e-7)
+    S = lambda rr, pr: 2.5 * np.log(pr ** 0.6 / rr)   # c_p ln(p^(1/gamma) / rho)
+    np.testing.assert_allclose((S(rp, pp) - S(rm, pm)) / (2 * h), G, rtol=1e-6, atol=1e-9)
