@@ -27,7 +27,11 @@ def build(verbose=False):
     procs = []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc] + hipcc_flags() + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        # the mixed-precision kernels carry perturbation-sized FP32 values
+        # only (no NaN/Inf/signed-zero semantics needed, results held to
+        # 1e-6 of FP64): relaxed FP32 rules there; every other file strict
+        extra = ["-ffast-math"] if src == "sd_mixed.hip" else []
+        cmd = [hipcc] + hipcc_flags() + extra + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd))
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -31,6 +31,7 @@ struct WsLayout {
     size_t tau;  // learned closure: subgrid flux [15][E][NP] FP32 (0 when off)
     // mixed-precision path
     size_t P0, P1, TQm0, TQm1, TVm, bg, dbg, gS0, R0, Q0, FFm;
+    size_t FF64;  // FP64 path: own-side common face flux [E][6][5][NF2]
     size_t P2, P4;  // SSPRK(5,4) on the perturbation
     bool mixed;
     size_t total;
@@ -69,6 +70,7 @@ static WsLayout ws_layout(const Mesh &m) {
     w.R0 = off;   off = align256(off + sizeof(float) * 5 * E * NP);
     w.Q0 = off;   off = align256(off + state);
     w.FFm = off;  off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
+    w.FF64 = off; off = align256(off + sizeof(double) * E * 6 * 5 * NF2);
     w.total = off;
     return w;
 }
@@ -90,7 +92,7 @@ static GeoM geom_of(const Mesh &m, const WsLayout &w, unsigned char *W) {
     return g;
 }
 
-static Geo geo_of(const Mesh &m) {
+static Geo geo_of(const Mesh &m, unsigned char *W) {
     const unsigned char *b = (const unsigned char *)m.dev_image;
     Geo g;
     g.solgeo = (const double *)(b + m.layout.solgeo);
@@ -98,6 +100,7 @@ static Geo geo_of(const Mesh &m) {
     g.link = (const int32_t *)(b + m.layout.link);
     g.info = (const int32_t *)(b + m.layout.info);
     g.E = m.E;
+    g.FF = (double *)(W + ws_layout(m).FF64);
     return g;
 }
 
@@ -660,7 +663,7 @@ int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const 
     chorus_physics p64 = *phys;
     p64.precision = CHORUS_FP64;
     const PhysParams P = params_of(&p64);
-    const Geo G = geo_of(*m);
+    const Geo G = geo_of(*m, (unsigned char *)ws);
     double *R0d = (double *)(W + w.Qs), *TQ = (double *)(W + w.TQ0), *TV = (double *)(W + w.TV);
     if (e == hipSuccess) e = launch_clear_flag(flag, s);
     if (e == hipSuccess) e = launch_trace(*m, G, Q0, TQ, s);
@@ -720,7 +723,7 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
         return CHORUS_OK;
     }
     double *TQ = (double *)(W + w.TQ0), *TV = (double *)(W + w.TV);
-    const Geo G = geo_of(*m);
+    const Geo G = geo_of(*m, (unsigned char *)ws);
     hipError_t e = timed(0, s, [&] { return launch_trace(*m, G, Q_dev, TQ, s); });
     if (e == hipSuccess) e = timed(1, s, [&] { return launch_grad(*m, G, P, Q_dev, TQ, TV, C, s); });
     StageArgs sa{nullptr, dQdt_dev, nullptr, 0.0, 1.0, 0.0, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
@@ -820,7 +823,7 @@ int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev
     double *reg[4] = {Q_dev, (double *)(W + w.Qs), rk54 ? (double *)(W + w.Q2) : nullptr,
                       rk54 ? (double *)(W + w.Q4) : nullptr};
     double *TQb[2] = {(double *)(W + w.TQ0), (double *)(W + w.TQ1)};
-    const Geo G = geo_of(*m);
+    const Geo G = geo_of(*m, (unsigned char *)ws);
     int cur = 0;
     hipError_t e = timed(0, s, [&] { return launch_trace(*m, G, Q_dev, TQb[cur], s); });
     for (int st = 0; st < n_steps && e == hipSuccess; ++st) {
@@ -1028,7 +1031,7 @@ int chorus_closure_features(chorus_mesh_t mesh, const chorus_physics *phys, cons
     }
     const WsLayout w = ws_layout(*m);
     unsigned char *W = (unsigned char *)ws;
-    const Geo G = geo_of(*m);
+    const Geo G = geo_of(*m, (unsigned char *)ws);
     const PhysParams P = params_of(phys);
     hipStream_t s = (hipStream_t)stream;
     double *TQ = (double *)(W + w.TQ0);
@@ -1057,7 +1060,7 @@ int chorus_closure_infer(chorus_mesh_t mesh, const chorus_physics *phys, const d
     }
     const WsLayout w = ws_layout(*m);
     unsigned char *W = (unsigned char *)ws;
-    const Geo G = geo_of(*m);
+    const Geo G = geo_of(*m, (unsigned char *)ws);
     const PhysParams P = params_of(phys);
     hipStream_t s = (hipStream_t)stream;
     double *TQ = (double *)(W + w.TQ0), *TV = (double *)(W + w.TV);

@@ -17,6 +17,8 @@ struct Geo {
     const int32_t *link;    // [E][6]
     const int32_t *info;    // [E][6]
     int64_t E;
+    double *FF;             // [E][6][5][NF2] own-side common face flux along the outward
+                            // area vector (written by the gradient pass, read by the residual pass)
 };
 
 // stage combination of a Shu-Osher Runge-Kutta stage (mode 1):

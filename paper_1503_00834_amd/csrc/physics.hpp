@@ -53,14 +53,16 @@ __device__ __forceinline__ void prim_grad(const T q[5], const T g[5][3], const P
     const T inv = T(1) / o.rho;
     for (int a = 0; a < 3; ++a) o.u[a] = q[1 + a] * inv;
     o.p = gm1 * (q[4] - T(0.5) * (q[1] * o.u[0] + q[2] * o.u[1] + q[3] * o.u[2]));
-    o.Tmp = o.p / (o.rho * R);
+    // one division each for 1/(rho R) and 1/(gamma p), reused below
+    const T irR = T(1) / (o.rho * R), igp = T(1) / (gam * o.p);
+    o.Tmp = o.p * irR;
     const T uu = o.u[0] * o.u[0] + o.u[1] * o.u[1] + o.u[2] * o.u[2];
     for (int c = 0; c < 3; ++c) {
         for (int a = 0; a < 3; ++a) o.du[a][c] = (g[1 + a][c] - o.u[a] * g[0][c]) * inv;
         const T dp = gm1 * (g[4][c] - (o.u[0] * g[1][c] + o.u[1] * g[2][c] + o.u[2] * g[3][c]) +
                             T(0.5) * uu * g[0][c]);
-        o.dS[c] = cp * (dp / (gam * o.p) - g[0][c] * inv);
-        o.dT[c] = (dp - R * o.Tmp * g[0][c]) / (o.rho * R);
+        o.dS[c] = cp * (dp * igp - g[0][c] * inv);
+        o.dT[c] = (dp - R * o.Tmp * g[0][c]) * irR;
     }
 }
 
@@ -100,10 +102,13 @@ __device__ __forceinline__ void flux_rusanov(const T qL[5], const T qR[5], const
     flux_inviscid(qR, S, gm1, fR);
     const T A = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
     const T iA = T(1) / A;
-    const T unL = fabs((qL[1] * S[0] + qL[2] * S[1] + qL[3] * S[2]) * iA / qL[0]);
-    const T unR = fabs((qR[1] * S[0] + qR[2] * S[1] + qR[3] * S[2]) * iA / qR[0]);
-    const T cL = sqrt(gam * pressure_of(qL, gm1) / qL[0]);
-    const T cR = sqrt(gam * pressure_of(qR, gm1) / qR[0]);
+    const T iL = T(1) / qL[0], iR = T(1) / qR[0];
+    const T unL = fabs((qL[1] * S[0] + qL[2] * S[1] + qL[3] * S[2]) * iA * iL);
+    const T unR = fabs((qR[1] * S[0] + qR[2] * S[1] + qR[3] * S[2]) * iA * iR);
+    const T pL = gm1 * (qL[4] - T(0.5) * (qL[1] * qL[1] + qL[2] * qL[2] + qL[3] * qL[3]) * iL);
+    const T pR = gm1 * (qR[4] - T(0.5) * (qR[1] * qR[1] + qR[2] * qR[2] + qR[3] * qR[3]) * iR);
+    const T cL = sqrt(gam * pL * iL);
+    const T cR = sqrt(gam * pR * iR);
     const T lamA = T(0.5) * fmax(unL + cL, unR + cR) * A;
     for (int v = 0; v < 5; ++v) out[v] = T(0.5) * (fL[v] + fR[v]) - lamA * (qR[v] - qL[v]);
 }

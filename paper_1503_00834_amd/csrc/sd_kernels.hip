@@ -217,7 +217,7 @@ __global__ __launch_bounds__(NT) void k_grad(Ops<N> op, Geo G, PhysParams P, con
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
-        if (G.link[e * 6 + f] < 0) continue;
+        const int32_t nb = G.link[e * 6 + f], inf = G.info[e * 6 + f];
         const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
         const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
         double q[5], g[5][3];
@@ -235,20 +235,40 @@ __global__ __launch_bounds__(NT) void k_grad(Ops<N> op, Geo G, PhysParams P, con
         }
         const int fl = m + (N + 1) * (t1 + N * t2);
         const double sg = (f & 1) ? 1.0 : -1.0;
-        double S[3], fv[5];
+        const int bc = (inf >> 6) - 1;
+        double S[3], fv[5], phi[5];
         for (int c = 0; c < 3; ++c) S[c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
-        flux_viscous(q, g, S, P, fv);
-        if constexpr (CL) {
-            // the own-side subgrid flux enters the trace with the sign of -F_v
-            for (int v = 0; v < 5; ++v)
-                for (int c = 0; c < 3; ++c) {
-                    double t = 0.0;
+        if (nb >= 0) {
+            flux_viscous(q, g, S, P, fv);
+            if constexpr (CL) {
+                // the own-side subgrid flux enters the trace with the sign of -F_v
+                for (int v = 0; v < 5; ++v)
+                    for (int c = 0; c < 3; ++c) {
+                        double t = 0.0;
 #pragma unroll
-                    for (int b = 0; b < N; ++b) t += op.I[m][b] * (double)stau[el][v * 3 + c][base + b * st];
-                    fv[v] -= t * S[c];
-                }
+                        for (int b = 0; b < N; ++b) t += op.I[m][b] * (double)stau[el][v * 3 + c][base + b * st];
+                        fv[v] -= t * S[c];
+                    }
+            }
+            for (int v = 0; v < 5; ++v) TV[((e * 6 + f) * 5 + v) * NF2 + pp] = fv[v];
+            // own-side part of the common flux: Rusanov minus half the own
+            // viscous (minus subgrid) flux; the residual pass adds the
+            // neighbour's half from its trace
+            const int f2 = inf & 7, o = (inf >> 3) & 7;
+            const int pn = map_face_point<N>(o, t1, t2);
+            const double *tq = TQ + ((int64_t)nb * 6 + f2) * 5 * NF2;
+            double qn[5];
+            for (int v = 0; v < 5; ++v) qn[v] = tq[v * NF2 + pn];
+            flux_rusanov(q, qn, S, P, phi);
+            for (int v = 0; v < 5; ++v) phi[v] -= 0.5 * fv[v];
+        } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
+            flux_wall(q, g, S, bc == CHORUS_BC_OUTER, P, phi);
+        } else {
+            flux_viscous(q, g, S, P, fv);
+            flux_rusanov(q, P.bc_state, S, P, phi);
+            for (int v = 0; v < 5; ++v) phi[v] -= 0.5 * fv[v];
         }
-        for (int v = 0; v < 5; ++v) TV[((e * 6 + f) * 5 + v) * NF2 + pp] = fv[v];
+        for (int v = 0; v < 5; ++v) G.FF[((e * 6 + f) * 5 + v) * NF2 + pp] = phi[v];
     }
 }
 
@@ -282,12 +302,19 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, co
                                               const double *__restrict__ TQ,
                                               const double *__restrict__ TV, StageArgs S_, ClosureArgs C) {
     constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
+    constexpr int IT_SOL = (EPB * NP + NT - 1) / NT;
     __shared__ double sq[EPB][5][NP];
-    __shared__ double sqs[EPB][6][5][NF2];
     __shared__ double sgr[EPB][15][NP];
-    __shared__ double sft[EPB][5][NFL];
-    __shared__ double sdiv[EPB][5][NP];
+    // the common solution is consumed by the gradients before the first
+    // direction's fluxes are written
+    __shared__ union {
+        double sqs[EPB][6][5][NF2];
+        double sft[EPB][5][NFL];
+    } U;
     __shared__ float stau[CL ? EPB : 1][15][CL ? NP : 1];
+    auto &sqs = U.sqs;
+    auto &sft = U.sft;
+    double div[IT_SOL][5];
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     const double gm1 = P.gamma - 1.0;
     if constexpr (CL) {
@@ -313,6 +340,26 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, co
             const int m = fl % (N + 1), t1 = (fl / (N + 1)) % N, t2 = fl / ((N + 1) * N);
             const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
             double q[5], g[5][3], S[3], F[5];
+            if (m == 0 || m == N) {
+                // interface point: own-side common flux from the gradient pass
+                // plus half the neighbour's viscous flux (stored along its own
+                // outward area vector, -So)
+                const int f = 2 * d + (m == N ? 1 : 0);
+                const double sg = (m == N) ? 1.0 : -1.0;
+                const int pp = t1 + N * t2;
+                const int32_t nb = G.link[e * 6 + f];
+                double phi[5];
+                for (int v = 0; v < 5; ++v) phi[v] = G.FF[((e * 6 + f) * 5 + v) * NF2 + pp];
+                if (nb >= 0) {
+                    const int32_t inf = G.info[e * 6 + f];
+                    const int f2 = inf & 7, o = (inf >> 3) & 7;
+                    const int pn = map_face_point<N>(o, t1, t2);
+                    const double *tv = TV + ((int64_t)nb * 6 + f2) * 5 * NF2;
+                    for (int v = 0; v < 5; ++v) phi[v] += 0.5 * tv[v * NF2 + pn];
+                }
+                for (int v = 0; v < 5; ++v) sft[el][v][fl] = sg * phi[v];
+                continue;
+            }
             for (int v = 0; v < 5; ++v) {
                 double s = 0.0;
 #pragma unroll
@@ -337,50 +384,18 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, co
                         ts[v] += t * S[c];
                     }
             }
-            if (m > 0 && m < N) {
-                double fi[5], fv[5];
-                flux_inviscid(q, S, gm1, fi);
-                flux_viscous(q, g, S, P, fv);
-                for (int v = 0; v < 5; ++v) F[v] = fi[v] - fv[v];
-                if constexpr (CL)
-                    for (int v = 0; v < 5; ++v) F[v] += ts[v];
-            } else {
-                const int f = 2 * d + (m == N ? 1 : 0);
-                const double sg = (m == N) ? 1.0 : -1.0;
-                double So[3] = {sg * S[0], sg * S[1], sg * S[2]}, phi[5];
-                const int32_t nb = G.link[e * 6 + f];
-                const int32_t inf = G.info[e * 6 + f];
-                const int bc = (inf >> 6) - 1;
-                if (nb >= 0) {
-                    const int f2 = inf & 7, o = (inf >> 3) & 7;
-                    const int pn = map_face_point<N>(o, t1, t2);
-                    const double *tq = TQ + ((int64_t)nb * 6 + f2) * 5 * NF2;
-                    const double *tv = TV + ((int64_t)nb * 6 + f2) * 5 * NF2;
-                    double qn[5], fvo[5];
-                    for (int v = 0; v < 5; ++v) qn[v] = tq[v * NF2 + pn];
-                    flux_rusanov(q, qn, So, P, phi);
-                    flux_viscous(q, g, So, P, fvo);
-                    // own subgrid flux along So (ts is along S = sg So)
-                    if constexpr (CL)
-                        for (int v = 0; v < 5; ++v) fvo[v] -= sg * ts[v];
-                    // the neighbour stored its viscous (minus subgrid) flux along
-                    // its own outward area vector, which is -So
-                    for (int v = 0; v < 5; ++v) phi[v] -= 0.5 * (fvo[v] + (-tv[v * NF2 + pn]));
-                } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
-                    flux_wall(q, g, So, bc == CHORUS_BC_OUTER, P, phi);
-                } else {
-                    double fvo[5];
-                    flux_rusanov(q, P.bc_state, So, P, phi);
-                    flux_viscous(q, g, So, P, fvo);
-                    for (int v = 0; v < 5; ++v) phi[v] -= 0.5 * fvo[v];
-                }
-                for (int v = 0; v < 5; ++v) F[v] = sg * phi[v];
-            }
+            double fi[5], fv[5];
+            flux_inviscid(q, S, gm1, fi);
+            flux_viscous(q, g, S, P, fv);
+            for (int v = 0; v < 5; ++v) F[v] = fi[v] - fv[v] + ts[v];
             for (int v = 0; v < 5; ++v) sft[el][v][fl] = F[v];
         }
         __syncthreads();
         // derivative of the flux polynomial along d at the solution points
-        for (int it = threadIdx.x; it < EPB * NP; it += NT) {
+#pragma unroll
+        for (int k = 0; k < IT_SOL; ++k) {
+            const int it = threadIdx.x + k * NT;
+            if (it >= EPB * NP) break;
             const int el = it / NP, p = it % NP;
             int a, t1, t2;
             split_sol<N>(d, p, a, t1, t2);
@@ -389,13 +404,16 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, co
                 double s = 0.0;
 #pragma unroll
                 for (int mm = 0; mm <= N; ++mm) s += op.D[a][mm] * sft[el][v][fb + mm];
-                sdiv[el][v][p] = (d == 0) ? s : sdiv[el][v][p] + s;
+                div[k][v] = (d == 0) ? s : div[k][v] + s;
             }
         }
         __syncthreads();
     }
     // source and output
-    for (int it = threadIdx.x; it < EPB * NP; it += NT) {
+#pragma unroll
+    for (int k = 0; k < IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * NP) break;
         const int el = it / NP, p = it % NP;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
@@ -410,7 +428,7 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, co
         M[3] = rho * g2;
         M[4] = mx * g0 + my * g1 + mz * g2;
         for (int v = 0; v < 5; ++v) {
-            const double R = -sdiv[el][v][p] * iJ - M[v];
+            const double R = -div[k][v] * iJ - M[v];
             const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
             if (S_.mode == 0) {
                 S_.Qout[gi] = R;
