@@ -296,9 +296,12 @@ __device__ __forceinline__ float face_val(const OpsF<N> &op, const float *fld, i
 
 // BR1 common values at the 6 N^2 face points: perturbation (5) and
 // background (rho0, E0)
+// (own face values of the 7 fields at the thread's face items are kept in
+// fo when given: the gradient pass reuses them for its face states)
 template <int N, int EPB, int NT>
 __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, const PhysF &F, int64_t e0,
-                                              MixedLds<N> *L, const Prologue<N, EPB, NT> &R) {
+                                              MixedLds<N> *L, const Prologue<N, EPB, NT> &R,
+                                              float (*fo)[NFIELD] = nullptr) {
     using Sh = Shape<N, EPB, NT>;
     constexpr int NF2 = N * N, NFL = (N + 1) * N * N;
 #pragma unroll
@@ -313,6 +316,11 @@ __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, 
         float pv[5];
         for (int v = 0; v < 5; ++v) pv[v] = face_val<N>(op, l.f[v], f, t1, t2);
         const float r0 = face_val<N>(op, l.f[F_R0], f, t1, t2), E0 = face_val<N>(op, l.f[F_E0], f, t1, t2);
+        if (fo) {
+            for (int v = 0; v < 5; ++v) fo[k][v] = pv[v];
+            fo[k][F_R0] = r0;
+            fo[k][F_E0] = E0;
+        }
         const int32_t nb = l.lk[f], inf = l.inf[f];
         if (nb >= 0) {
             for (int v = 0; v < 5; ++v) l.u.cs[v][f][pp] = 0.5f * (pv[v] + R.nq[k][v]);
@@ -382,10 +390,12 @@ __device__ __forceinline__ void gradients(const OpsF<N> &op, const GeoF &G, int6
     }
 }
 
-// point state at the flux point m of the line (base, st)
+// point state at the flux point m of the line (base, st); with vals given,
+// the 7 field values are taken from there and only the gradients are
+// interpolated
 template <int N>
 __device__ __forceinline__ void state_at(const OpsF<N> &op, const MixedLds<N> &l, int m, int base, int st,
-                                         PtState &s) {
+                                         PtState &s, const float *vals = nullptr) {
     float w[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) w[b] = op.I[m][b];
@@ -395,13 +405,23 @@ __device__ __forceinline__ void state_at(const OpsF<N> &op, const MixedLds<N> &l
         for (int b = 0; b < N; ++b) t += w[b] * fld[base + b * st];
         return t;
     };
-    s.rp = I(l.f[F_RP]);
-    s.m[0] = I(l.f[F_MX]);
-    s.m[1] = I(l.f[F_MY]);
-    s.m[2] = I(l.f[F_MZ]);
-    s.Ep = I(l.f[F_EP]);
-    s.r0 = I(l.f[F_R0]);
-    s.E0 = I(l.f[F_E0]);
+    if (vals) {
+        s.rp = vals[F_RP];
+        s.m[0] = vals[F_MX];
+        s.m[1] = vals[F_MY];
+        s.m[2] = vals[F_MZ];
+        s.Ep = vals[F_EP];
+        s.r0 = vals[F_R0];
+        s.E0 = vals[F_E0];
+    } else {
+        s.rp = I(l.f[F_RP]);
+        s.m[0] = I(l.f[F_MX]);
+        s.m[1] = I(l.f[F_MY]);
+        s.m[2] = I(l.f[F_MZ]);
+        s.Ep = I(l.f[F_EP]);
+        s.r0 = I(l.f[F_R0]);
+        s.E0 = I(l.f[F_E0]);
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         s.grp[c] = I(l.g[3 * F_RP + c]);
@@ -535,7 +555,8 @@ __global__ __launch_bounds__(NT, MINW) void k_grad_mixed(OpsF<N> op, GeoF G, Mix
     prologue_load<N, EPB, NT>(Pq, B, G, TQ, nullptr, e0, R);
     prologue_store<N, EPB, NT>(R, L);
     __syncthreads();
-    common_values<N, EPB, NT>(op, G, F, e0, L, R);
+    float fo[Sh::IT_FACE][NFIELD];
+    common_values<N, EPB, NT>(op, G, F, e0, L, R, fo);
     __syncthreads();
     gradients<N, EPB, NT>(op, G, e0, L, R.gs);
     __syncthreads();
@@ -550,7 +571,7 @@ __global__ __launch_bounds__(NT, MINW) void k_grad_mixed(OpsF<N> op, GeoF G, Mix
         const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
         float fv[5], phi[5];
         PtState st;
-        state_at<N>(op, L[el], m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), st);
+        state_at<N>(op, L[el], m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), st, fo[k]);
         if (nb >= 0) {
             dflux_viscous(st, Sf[k], gSf[k], F, 0, fv);
             const int64_t slot = mailbox_slot<N>(nb, inf, pp);
@@ -829,12 +850,12 @@ template <int N>
 struct CfgM;
 // elements per block, threads, element blocks per workgroup, and the
 // minimum waves per SIMD the residual (MINW) and gradient (MINWG) passes are
-// compiled for.  At N = 4 the residual pass runs four waves per SIMD (a few
-// spilled registers cost less than the added latency hiding); the gradient
-// pass stays at three (holding it to 128 registers spills too much).
+// compiled for.  At N = 4 both run four waves per SIMD (the residual pass
+// with a few spilled registers, which cost less than the added latency
+// hiding).
 template <> struct CfgM<2> { static constexpr int EPB = 8, NT = 64, K = 1, MINW = 2, MINWG = 2; };
 template <> struct CfgM<3> { static constexpr int EPB = 2, NT = 64, K = 1, MINW = 3, MINWG = 3; };
-template <> struct CfgM<4> { static constexpr int EPB = 1, NT = 64, K = 1, MINW = 4, MINWG = 3; };
+template <> struct CfgM<4> { static constexpr int EPB = 1, NT = 64, K = 1, MINW = 4, MINWG = 4; };
 template <> struct CfgM<5> { static constexpr int EPB = 1, NT = 128, K = 1, MINW = 2, MINWG = 2; };
 template <> struct CfgM<6> { static constexpr int EPB = 1, NT = 256, K = 1, MINW = 1, MINWG = 1; };
 
