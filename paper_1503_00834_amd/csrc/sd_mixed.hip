@@ -637,6 +637,16 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
     using Sh = Shape<N, EPB, NT>;
     constexpr int NP = Sh::NP, NF2 = Sh::NF2;
     const Prologue<N, EPB, NT> &R = In.R;
+    // interface fluxes complete as soon as loaded: own-side part plus half
+    // the neighbour's viscous flux (stored along its own outward vector -So)
+    float ffc[Sh::IT_FACE][5];
+#pragma unroll
+    for (int k = 0; k < Sh::IT_FACE; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const int el = (it < EPB * 6 * NF2) ? it / (6 * NF2) : 0, f = (it % (6 * NF2)) / NF2;
+        const float h = (it < EPB * 6 * NF2 && L[el].lk[f] >= 0) ? 0.5f : 0.0f;
+        for (int v = 0; v < 5; ++v) ffc[k][v] = In.ff[k][v] + h * R.nv[k][v];
+    }
     common_values<N, EPB, NT>(op, G, F, e0, L, R);
     __syncthreads();
     gradients<N, EPB, NT>(op, G, e0, L, R.gs);
@@ -677,9 +687,8 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
             MixedLds<N> &l = L[el];
             const int m = (f & 1) ? N : 0;
             const float sg = (f & 1) ? 1.0f : -1.0f;
-            const float h = (l.lk[f] >= 0) ? 0.5f : 0.0f;
             const int fl = m + (N + 1) * pp;
-            for (int v = 0; v < 5; ++v) l.u.ft[v][fl] = sg * (In.ff[k][v] + h * R.nv[k][v]);
+            for (int v = 0; v < 5; ++v) l.u.ft[v][fl] = sg * ffc[k][v];
         }
         __syncthreads();
 #pragma unroll
