@@ -639,13 +639,15 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
     const Prologue<N, EPB, NT> &R = In.R;
     // interface fluxes complete as soon as loaded: own-side part plus half
     // the neighbour's viscous flux (stored along its own outward vector -So)
+    // (the mailbox slot of a boundary face is never written: select, do not
+    // multiply by zero)
     float ffc[Sh::IT_FACE][5];
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
         const int it = threadIdx.x + k * NT;
         const int el = (it < EPB * 6 * NF2) ? it / (6 * NF2) : 0, f = (it % (6 * NF2)) / NF2;
-        const float h = (it < EPB * 6 * NF2 && L[el].lk[f] >= 0) ? 0.5f : 0.0f;
-        for (int v = 0; v < 5; ++v) ffc[k][v] = In.ff[k][v] + h * R.nv[k][v];
+        const bool interior = it < EPB * 6 * NF2 && L[el].lk[f] >= 0;
+        for (int v = 0; v < 5; ++v) ffc[k][v] = interior ? In.ff[k][v] + 0.5f * R.nv[k][v] : In.ff[k][v];
     }
     common_values<N, EPB, NT>(op, G, F, e0, L, R);
     __syncthreads();

@@ -161,3 +161,30 @@ def test_mixed_call_order_errors(ch, oracle_mod, torch_dev):
     with pytest.raises(ch.ChorusError) as ei:
         ch.chorus_sd_residual(cm, other, _dev(torch, Q), R, ws)
     assert ei.value.status == -6
+
+
+def test_results_independent_of_workspace_contents(ch, oracle_mod, torch_dev):
+    """Every workspace value a kernel reads is written first: a workspace
+    filled with NaN bytes gives bit-identical results to a zeroed one, for
+    the FP64 residual, an FP64 and a mixed SSPRK(5,4) step."""
+    torch = torch_dev
+    m, om, Q0, Q, pars = _case(oracle_mod, 3)
+    kw = dict(GM=pars["GM"], omega=1.0, nu=1e-3, kappa=1e-3, T_top=pars["chi_o"], F_bottom=0.01)
+    cm = ch.mesh_from_arrays(m, 3).upload()
+    outs = []
+    for fill in (0, 255):
+        res = []
+        for prec in (ch.CHORUS_FP64, ch.CHORUS_MIXED):
+            phys = ch.physics(precision=prec, integrator=ch.CHORUS_SSPRK54, **kw)
+            ws = cm.workspace(phys).fill_(fill)
+            if prec == ch.CHORUS_MIXED:
+                ch.chorus_set_background(cm, phys, _dev(torch, Q0), ws)
+            R = torch.empty_like(_dev(torch, Q))
+            ch.chorus_sd_residual(cm, phys, _dev(torch, Q), R, ws)
+            Qd = _dev(torch, Q)
+            ch.chorus_rk_step(cm, phys, Qd, 0.01, 2, ws)
+            torch.cuda.synchronize()
+            res += [R.cpu().numpy(), Qd.cpu().numpy()]
+        outs.append(res)
+    for a, b in zip(*outs):
+        assert np.isfinite(a).all() and np.array_equal(a, b)
