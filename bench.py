@@ -151,6 +151,7 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-plain comparison leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB 5 times (HBM counter "
@@ -251,6 +252,22 @@ def main():
                      / (HBM_PEAK_GBS * 1e9)},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in ktimes.items()},
     }
+    if prec == ch.CHORUS_MIXED and not args.no_fp64:
+        # the FP64 plain path on the same workload, for the comparison the
+        # metric names (same step count, after one warm-up step)
+        log("fp64 plain path")
+        p64 = ch.physics(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"],
+                         T_top=pars["chi_o"], precision=ch.CHORUS_FP64)
+        Q64 = torch.from_numpy(Qh).cuda()
+        ch.chorus_rk_step(mesh, p64, Q64, dt, 1, ws, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.chorus_rk_step(mesh, p64, Q64, dt, args.steps, ws, stream)
+        torch.cuda.synchronize()
+        w64 = time.perf_counter() - t0
+        out["fp64_plain"] = {"value": mesh.n_solpts * args.steps / w64, "ms_per_step": w64 / args.steps * 1e3,
+                             "speedup_mixed_over_fp64": w64 / wall}
+        del Q64
     if not args.no_closure:
         log("closure leg")
         out["closure"] = closure_leg()

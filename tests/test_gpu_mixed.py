@@ -52,7 +52,7 @@ def _case(oracle_mod, N, amp=1e-3, vel=1e-3, seed=3):
     return m, om, Q0, Q, pars
 
 
-@pytest.mark.parametrize("N", [3, 4])
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
 def test_mixed_residual_vs_oracle(ch, oracle_mod, torch_dev, N):
     torch = torch_dev
     m, om, Q0, Q, pars = _case(oracle_mod, N)
