@@ -332,34 +332,36 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, co
     __syncthreads();
 #pragma unroll 1
     for (int d = 0; d < 3; ++d) {
-        // transformed flux at the d-flux points
-        for (int it = threadIdx.x; it < EPB * NFL; it += NT) {
-            const int el = it / NFL, fl = it % NFL;
+        // interface points of direction d: own-side common flux from the
+        // gradient pass plus half the neighbour's viscous flux (stored along
+        // its own outward area vector, -So)
+        for (int it = threadIdx.x; it < EPB * 2 * NF2; it += NT) {
+            const int el = it / (2 * NF2), side = (it / NF2) & 1, pp = it % NF2;
             const int64_t e = e0 + el;
             if (e >= G.E) continue;
-            const int m = fl % (N + 1), t1 = (fl / (N + 1)) % N, t2 = fl / ((N + 1) * N);
+            const int f = 2 * d + side, m = side ? N : 0, t1 = pp % N, t2 = pp / N;
+            const double sg = side ? 1.0 : -1.0;
+            const int32_t nb = G.link[e * 6 + f];
+            double phi[5];
+            for (int v = 0; v < 5; ++v) phi[v] = G.FF[((e * 6 + f) * 5 + v) * NF2 + pp];
+            if (nb >= 0) {
+                const int32_t inf = G.info[e * 6 + f];
+                const int f2 = inf & 7, o = (inf >> 3) & 7;
+                const int pn = map_face_point<N>(o, t1, t2);
+                const double *tv = TV + ((int64_t)nb * 6 + f2) * 5 * NF2;
+                for (int v = 0; v < 5; ++v) phi[v] += 0.5 * tv[v * NF2 + pn];
+            }
+            for (int v = 0; v < 5; ++v) sft[el][v][m + (N + 1) * pp] = sg * phi[v];
+        }
+        // interior d-flux points: transformed flux
+        for (int it = threadIdx.x; it < EPB * (N - 1) * NF2; it += NT) {
+            const int el = it / ((N - 1) * NF2), r = it % ((N - 1) * NF2);
+            const int64_t e = e0 + el;
+            if (e >= G.E) continue;
+            const int m = 1 + r % (N - 1), tt = r / (N - 1), t1 = tt % N, t2 = tt / N;
+            const int fl = m + (N + 1) * tt;
             const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
             double q[5], g[5][3], S[3], F[5];
-            if (m == 0 || m == N) {
-                // interface point: own-side common flux from the gradient pass
-                // plus half the neighbour's viscous flux (stored along its own
-                // outward area vector, -So)
-                const int f = 2 * d + (m == N ? 1 : 0);
-                const double sg = (m == N) ? 1.0 : -1.0;
-                const int pp = t1 + N * t2;
-                const int32_t nb = G.link[e * 6 + f];
-                double phi[5];
-                for (int v = 0; v < 5; ++v) phi[v] = G.FF[((e * 6 + f) * 5 + v) * NF2 + pp];
-                if (nb >= 0) {
-                    const int32_t inf = G.info[e * 6 + f];
-                    const int f2 = inf & 7, o = (inf >> 3) & 7;
-                    const int pn = map_face_point<N>(o, t1, t2);
-                    const double *tv = TV + ((int64_t)nb * 6 + f2) * 5 * NF2;
-                    for (int v = 0; v < 5; ++v) phi[v] += 0.5 * tv[v * NF2 + pn];
-                }
-                for (int v = 0; v < 5; ++v) sft[el][v][fl] = sg * phi[v];
-                continue;
-            }
             for (int v = 0; v < 5; ++v) {
                 double s = 0.0;
 #pragma unroll
