@@ -105,7 +105,6 @@ struct GeoM {
     const float *gS0;        // [E][3][NFL] background entropy gradient along the flux metric
     const float *R0;         // [5][E][NP]  background residual
     const double *Q0;        // [5][E][NP]  background state
-    float *FF;               // [E][6][5][NF2] own-side face flux (gradient -> residual pass)
 };
 
 // as StageArgs, on the perturbation P (mode 0 writes dQ/dt to Pout)
@@ -121,10 +120,14 @@ struct MixedStageArgs {
 };
 
 hipError_t launch_pert_begin(const Mesh &m, const GeoM &g, const double *Q, double *Pq, float *TQ, hipStream_t s);
-hipError_t launch_grad_mixed(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
-                             float *TV, hipStream_t s);
-hipError_t launch_resid_mixed(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
-                              const float *TV, const MixedStageArgs &a, hipStream_t s);
+// stage split used by the solver: flux pass (gradients, fluxes, divergence
+// with the own-side face fluxes, source -> dRp [5][E][NP] FP32, own viscous
+// face flux -> neighbour mailbox TV), then lift pass (neighbours' viscous
+// halves, R = R0 + dRp + lift, stage combination, traces -> TQout)
+hipError_t launch_flux_mixed(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
+                             float *TV, float *dRp, hipStream_t s);
+hipError_t launch_lift_mixed(const Mesh &m, const GeoM &g, const double *Pq, const float *TV, const float *dRp,
+                             const MixedStageArgs &a, hipStream_t s);
 hipError_t launch_bg_setup(const Mesh &m, const Geo &G, const double *Q0, const double *TQ0, float *bg, float *dbg,
                            int *flag, hipStream_t s);
 hipError_t launch_bg_entropy(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q0, const double *TQ,

@@ -54,8 +54,6 @@ struct MixedBufs {
     const float *dbg;   // [E][6][2][NF2] neighbour minus own background face trace (rho, E)
     const float *gS0;   // [E][3][NFL]   grad S0 . (|J| grad xi_d) at d-flux points
     const float *R0;    // [5][E][NP]    R(Q0)
-    float *FF;          // [E][6][5][NF2] own-side face flux along the outward area vector
-                        // (written by the gradient pass, read by the residual pass)
 };
 
 struct PhysF {
@@ -110,6 +108,7 @@ __device__ __forceinline__ void dflux_inviscid(const PtState &s, const float S[3
 // (F_v(Q) - F_v(Q0)) . S given gS0S = grad S0 . S.  outer_wall / inner_wall
 // select the wall forms (normal traction only; energy as interior at the
 // outer wall, none at the inner wall where the prescribed flux is in R0).
+template <bool KR = true>
 __device__ __forceinline__ void dflux_viscous(const PtState &s, const float S[3], float gS0S, const PhysF &F,
                                               int wall, float out[5]) {
     const float rho = s.r0 + s.rp, inv = rcp(rho);
@@ -164,8 +163,11 @@ __device__ __forceinline__ void dflux_viscous(const PtState &s, const float S[3]
     const float iR = rcp(F.R);
     const float eS = F.kappa * (pp * gS0S + p * F.cp * dgS) * iR;
     // rho c_p grad T . S difference: c_p/R (grad p' . S - [p grad rho' . S / rho + grad rho0 . S (p/rho - p0/rho0)])
-    const float dpr = (pp * s.r0 - p0 * s.rp) * inv * ir0;
-    const float eT = F.kappa_r * F.cp * iR * (gpS - (p * grpS * inv + gr0S * dpr));
+    float eT = 0.0f;
+    if (KR) {
+        const float dpr = (pp * s.r0 - p0 * s.rp) * inv * ir0;
+        eT = F.kappa_r * F.cp * iR * (gpS - (p * grpS * inv + gr0S * dpr));
+    }
     const float work = (wall == 0) ? (u[0] * tS[0] + u[1] * tS[1] + u[2] * tS[2]) : 0.0f;
     out[4] = work + eS + eT;
 }
@@ -440,6 +442,7 @@ __device__ __forceinline__ void state_at(const OpsF<N> &op, const MixedLds<N> &l
 // jump db) minus half of the own viscous flux fv (the neighbour's half is
 // added by the residual pass from the neighbour's viscous trace).  Wall
 // face: the complete wall flux (inviscid (0, p' So, 0); viscous wall form).
+template <bool KR = true>
 __device__ __forceinline__ void face_flux_own(const PtState &s, const float nq[5], const float db[2], bool interior,
                                               bool outer, const float So[3], float gS0S, const float fv_in[5],
                                               const PhysF &F, float phi[5]) {
@@ -484,7 +487,7 @@ __device__ __forceinline__ void face_flux_own(const PtState &s, const float nq[5
         const float mm = s.m[0] * s.m[0] + s.m[1] * s.m[1] + s.m[2] * s.m[2];
         const float pp = F.gm1 * (s.Ep - 0.5f * mm * rcp(s.r0 + s.rp));
         float fv[5];
-        dflux_viscous(s, So, gS0S, F, outer ? 2 : 1, fv);
+        dflux_viscous<KR>(s, So, gS0S, F, outer ? 2 : 1, fv);
         phi[0] = 0.0f;
         for (int a = 0; a < 3; ++a) phi[1 + a] = pp * So[a] - fv[1 + a];
         phi[4] = -fv[4];
@@ -526,19 +529,30 @@ __global__ __launch_bounds__(NT) void k_pert_begin(OpsF<N> op, GeoF G, const dou
     }
 }
 
-// viscous-flux difference of the own side at interior interface points
-// along the outward area vector, pushed to the neighbour: TV; and the
-// own-side face flux at every face point: FF (face_flux_own)
-template <int N, int EPB, int NT, int MINW>
-__global__ __launch_bounds__(NT, MINW) void k_grad_mixed(OpsF<N> op, GeoF G, MixedBufs B, PhysParams P,
-                                                   const double *__restrict__ Pq, const float *__restrict__ TQ,
-                                                   float *__restrict__ TV) {
-    constexpr int NF2 = N * N, NFL = (N + 1) * N * N;
+// stage combination on P (see MixedStageArgs); mode 0 writes R0 + dR
+using MixedStage = MixedStageArgs;
+
+// ---------------------------------------------------------------------------
+// flux pass + lift pass (the stage split used by the solver)
+// ---------------------------------------------------------------------------
+// Flux pass: every step that needs the gradients, once per stage.  Common
+// values and gradients; at the face points the own viscous flux (pushed to
+// the neighbour's viscous mailbox TV) and the own-side common flux (Rusanov
+// minus half the own viscous flux, or the wall flux); at the interior flux
+// points the transformed flux; the divergence of the flux polynomials with
+// the own-side face fluxes at the line ends; the source.  Output: the
+// partial residual difference dRp = -div/|J| - M [5][E][NP] (FP32), which
+// lacks only the neighbours' viscous halves at interior interfaces.
+template <int N, int EPB, int NT, int MINW, bool KR>
+__global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> op, GeoF G, MixedBufs B, PhysParams P,
+                                                         const double *__restrict__ Pq, const float *__restrict__ TQ,
+                                                         float *__restrict__ TV, float *__restrict__ dRp) {
     using Sh = Shape<N, EPB, NT>;
+    constexpr int NP = Sh::NP, NF2 = Sh::NF2, NFL = Sh::NFL, NINTD = Sh::NINTD;
     __shared__ MixedLds<N> L[EPB];
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     const PhysF F = physf_of(P);
-    // face-point geometry of this thread's face items, loaded up front
+    // every global input of the element block, issued before the first wait
     float Sf[Sh::IT_FACE][3], gSf[Sh::IT_FACE];
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
@@ -551,68 +565,7 @@ __global__ __launch_bounds__(NT, MINW) void k_grad_mixed(OpsF<N> op, GeoF G, Mix
         for (int c = 0; c < 3; ++c) Sf[k][c] = ok ? sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
         gSf[k] = ok ? sg * B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
     }
-    Prologue<N, EPB, NT> R;
-    prologue_load<N, EPB, NT>(Pq, B, G, TQ, nullptr, e0, R);
-    prologue_store<N, EPB, NT>(R, L);
-    __syncthreads();
-    float fo[Sh::IT_FACE][NFIELD];
-    common_values<N, EPB, NT>(op, G, F, e0, L, R, fo);
-    __syncthreads();
-    gradients<N, EPB, NT>(op, G, e0, L, R.gs);
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < Sh::IT_FACE; ++k) {
-        const int it = threadIdx.x + k * NT;
-        if (it >= EPB * 6 * NF2) break;
-        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
-        const int64_t e = e0 + el;
-        if (e >= G.E) continue;
-        const int32_t nb = L[el].lk[f], inf = L[el].inf[f];
-        const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
-        float fv[5], phi[5];
-        PtState st;
-        state_at<N>(op, L[el], m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), st, fo[k]);
-        if (nb >= 0) {
-            dflux_viscous(st, Sf[k], gSf[k], F, 0, fv);
-            const int64_t slot = mailbox_slot<N>(nb, inf, pp);
-            for (int v = 0; v < 5; ++v) TV[slot + v * NF2] = fv[v];
-        }
-        face_flux_own(st, R.nq[k], R.db[k], nb >= 0, ((inf >> 6) - 1) == CHORUS_BC_OUTER, Sf[k], gSf[k], fv, F,
-                      phi);
-        float *ff = B.FF + (e * 6 + f) * 5 * NF2 + pp;
-        for (int v = 0; v < 5; ++v) ff[v * NF2] = phi[v];
-    }
-}
-
-// stage combination on P (see MixedStageArgs); mode 0 writes R0 + dR
-using MixedStage = MixedStageArgs;
-
-// per-thread inputs of one element block for the residual pass
-template <int N, int EPB, int NT>
-struct ResidIn {
-    using Sh = Shape<N, EPB, NT>;
-    Prologue<N, EPB, NT> R;
-    float Si[3][Sh::IT_INTD][3], gSi[3][Sh::IT_INTD];  // interior flux-point geometry per direction
-    float ff[Sh::IT_FACE][5];  // own-side face flux from the gradient pass
-};
-
-// issue every global load of the element block starting at e0.  Interior
-// flux item it of direction d: el, interior index a = 1..N-1, tangential
-// t1, t2; interface item: el, face f, point pp.
-template <int N, int EPB, int NT>
-__device__ __forceinline__ void resid_load(const GeoF &G, const MixedBufs &B, const double *Pq,
-                                           const float *__restrict__ TQ, const float *__restrict__ TV,
-                                           const MixedStage &S_, int64_t e0, ResidIn<N, EPB, NT> &In) {
-    using Sh = Shape<N, EPB, NT>;
-    constexpr int NF2 = Sh::NF2, NFL = Sh::NFL, NINTD = Sh::NINTD;
-#pragma unroll
-    for (int k = 0; k < Sh::IT_FACE; ++k) {
-        const int it = threadIdx.x + k * NT;
-        const int el = it / (6 * NF2), r = it % (6 * NF2);
-        const int64_t e = e0 + el;
-        const bool ok = it < EPB * 6 * NF2 && e < G.E;
-        for (int v = 0; v < 5; ++v) In.ff[k][v] = ok ? B.FF[(e * 6 + r / NF2) * 5 * NF2 + v * NF2 + r % NF2] : 0.0f;
-    }
+    float Si[3][Sh::IT_INTD][3], gSi[3][Sh::IT_INTD];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -622,42 +575,44 @@ __device__ __forceinline__ void resid_load(const GeoF &G, const MixedBufs &B, co
             const int fl = 1 + q % (N - 1) + (N + 1) * (q / (N - 1));
             const int64_t e = e0 + el;
             const bool ok = it < EPB * NINTD && e < G.E;
-            for (int c = 0; c < 3; ++c) In.Si[d][k][c] = ok ? G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
-            In.gSi[d][k] = ok ? B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
+            for (int c = 0; c < 3; ++c) Si[d][k][c] = ok ? G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
+            gSi[d][k] = ok ? B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
         }
-    prologue_load<N, EPB, NT>(Pq, B, G, TQ, TV, e0, In.R);
-}
-
-// the residual pass of one element block from its loaded inputs (the block
-// LDS holds this element block's fields on entry)
-template <int N, int EPB, int NT>
-__device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, const MixedBufs &B, const double *Pq,
-                                              const PhysF &F, const MixedStage &S_, int64_t e0,
-                                              const ResidIn<N, EPB, NT> &In, MixedLds<N> *L) {
-    using Sh = Shape<N, EPB, NT>;
-    constexpr int NP = Sh::NP, NF2 = Sh::NF2;
-    const Prologue<N, EPB, NT> &R = In.R;
-    // interface fluxes complete as soon as loaded: own-side part plus half
-    // the neighbour's viscous flux (stored along its own outward vector -So)
-    // (the mailbox slot of a boundary face is never written: select, do not
-    // multiply by zero)
+    Prologue<N, EPB, NT> R;
+    prologue_load<N, EPB, NT>(Pq, B, G, TQ, nullptr, e0, R);
+    prologue_store<N, EPB, NT>(R, L);
+    __syncthreads();
+    float fo[Sh::IT_FACE][NFIELD];
+    common_values<N, EPB, NT>(op, G, F, e0, L, R, fo);
+    __syncthreads();
+    gradients<N, EPB, NT>(op, G, e0, L, R.gs);
+    __syncthreads();
+    // face points: own viscous flux to the neighbour, own-side common flux
+    // kept in registers for the divergence
     float ffc[Sh::IT_FACE][5];
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
         const int it = threadIdx.x + k * NT;
-        const int el = (it < EPB * 6 * NF2) ? it / (6 * NF2) : 0, f = (it % (6 * NF2)) / NF2;
-        const bool interior = it < EPB * 6 * NF2 && L[el].lk[f] >= 0;
-        for (int v = 0; v < 5; ++v) ffc[k][v] = interior ? In.ff[k][v] + 0.5f * R.nv[k][v] : In.ff[k][v];
+        for (int v = 0; v < 5; ++v) ffc[k][v] = 0.0f;
+        if (it >= EPB * 6 * NF2) break;
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        const int64_t e = e0 + el;
+        if (e >= G.E) continue;
+        const int32_t nb = L[el].lk[f], inf = L[el].inf[f];
+        const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
+        float fv[5];
+        PtState st;
+        state_at<N>(op, L[el], m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), st, fo[k]);
+        if (nb >= 0) {
+            dflux_viscous<KR>(st, Sf[k], gSf[k], F, 0, fv);
+            const int64_t slot = mailbox_slot<N>(nb, inf, pp);
+            for (int v = 0; v < 5; ++v) TV[slot + v * NF2] = fv[v];
+        }
+        face_flux_own<KR>(st, R.nq[k], R.db[k], nb >= 0, ((inf >> 6) - 1) == CHORUS_BC_OUTER, Sf[k], gSf[k], fv, F,
+                      ffc[k]);
     }
-    common_values<N, EPB, NT>(op, G, F, e0, L, R);
-    __syncthreads();
-    gradients<N, EPB, NT>(op, G, e0, L, R.gs);
-    __syncthreads();
-    // per direction d: transformed perturbation flux at the d-flux points
-    // (interior points here, interface points from the own-side face flux of
-    // the gradient pass plus half the neighbour's viscous flux, stored along
-    // its own outward vector -So), then its derivative added to the
-    // divergence at the solution points
+    // per direction d: transformed flux at the d-flux points, then its
+    // derivative added to the divergence at the solution points
     float div[Sh::IT_SOL][5];
 #pragma unroll
     for (int k = 0; k < Sh::IT_SOL; ++k)
@@ -667,16 +622,16 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
 #pragma unroll
         for (int k = 0; k < Sh::IT_INTD; ++k) {
             const int it = threadIdx.x + k * NT;
-            if (it >= EPB * Sh::NINTD) break;
-            const int el = it / Sh::NINTD, q = it % Sh::NINTD;
+            if (it >= EPB * NINTD) break;
+            const int el = it / NINTD, q = it % NINTD;
             const int m = 1 + q % (N - 1), tt = q / (N - 1), t1 = tt % N, t2 = tt / N;
             if (e0 + el >= G.E) continue;
             MixedLds<N> &l = L[el];
             PtState s;
             state_at<N>(op, l, m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), s);
             float fi[5], fv[5];
-            dflux_inviscid(s, In.Si[d][k], F, fi);
-            dflux_viscous(s, In.Si[d][k], In.gSi[d][k], F, 0, fv);
+            dflux_inviscid(s, Si[d][k], F, fi);
+            dflux_viscous<KR>(s, Si[d][k], gSi[d][k], F, 0, fv);
             const int fl = m + (N + 1) * tt;
             for (int v = 0; v < 5; ++v) l.u.ft[v][fl] = fi[v] - fv[v];
         }
@@ -713,7 +668,7 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
         }
         __syncthreads();
     }
-    // source, background residual and stage update
+    // source and output
 #pragma unroll
     for (int k = 0; k < Sh::IT_SOL; ++k) {
         const int it = threadIdx.x + k * NT;
@@ -721,19 +676,10 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
         const int el = it / NP, p = it % NP;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
-        MixedLds<N> &l = L[el];
-        // stage-update operands, loaded here rather than held through the flux phase
+        const MixedLds<N> &l = L[el];
         const float *gsp = G.solgeo + e * 13 * NP + p;
         const float iJ = gsp[9 * NP];
         const float g0 = F.GM * gsp[10 * NP], g1 = F.GM * gsp[11 * NP], g2 = F.GM * gsp[12 * NP];
-        double pin[5], pst[5];
-        float r0s[5];
-        for (int v = 0; v < 5; ++v) {
-            const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
-            r0s[v] = B.R0[gi];
-            pin[v] = Pq[gi];
-            pst[v] = (S_.mode != 0 && S_.c0 != 0.0) ? S_.A[gi] : 0.0;
-        }
         const float rp = l.f[F_RP][p], mx = l.f[F_MX][p], my = l.f[F_MY][p], mz = l.f[F_MZ][p];
         float M[5];
         M[0] = 0.0f;
@@ -741,60 +687,85 @@ __device__ __forceinline__ void resid_compute(const OpsF<N> &op, const GeoF &G, 
         M[2] = rp * g1 + 2.0f * F.om * mx;
         M[3] = rp * g2;
         M[4] = mx * g0 + my * g1 + mz * g2;
-        float newp[5];
+        for (int v = 0; v < 5; ++v) dRp[((int64_t)v * G.E + e) * NP + p] = -div[k][v] * iJ - M[v];
+    }
+}
+
+// Lift pass: the neighbours' viscous halves at the interior interface
+// points enter the divergence through the end columns of the derivative
+// matrix (D[a][0] at the lower, D[a][N] at the upper end of each line);
+// R = R0 + dRp - (1/|J|) * that lift, then the stage combination on P in
+// FP64 and the FP32 face traces of the new P pushed to the neighbours.
+template <int N, int EPB, int NT>
+__global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> op, GeoF G, MixedBufs B, const double *__restrict__ Pq,
+                                                   const float *__restrict__ TV, const float *__restrict__ dRp,
+                                                   MixedStage S_) {
+    constexpr int NP = N * N * N, NF2 = N * N;
+    __shared__ float nv[EPB][6][5][NF2];  // neighbours' viscous flux at own face points, 0 on boundary faces
+    __shared__ float sp[EPB][5][NP];      // new perturbation (FP32) for the traces
+    __shared__ int32_t lk[EPB][6], inf[EPB][6];
+    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    if ((int)threadIdx.x < EPB * 6) {
+        const int el = threadIdx.x / 6, f = threadIdx.x % 6;
+        const bool ok = e0 + el < G.E;
+        lk[el][f] = ok ? G.link[e0 * 6 + threadIdx.x] : -1;
+        inf[el][f] = ok ? G.info[e0 * 6 + threadIdx.x] : 0;
+    }
+    __syncthreads();
+    // the mailbox slot of a boundary face is never written: select, do not
+    // multiply by zero
+    for (int it = threadIdx.x; it < EPB * 6 * 5 * NF2; it += NT) {
+        const int el = it / (30 * NF2), r = it % (30 * NF2), f = r / (5 * NF2);
+        const int64_t e = e0 + el;
+        float val = 0.0f;
+        if (e < G.E && lk[el][f] >= 0) val = TV[e * 30 * NF2 + r];
+        (&nv[el][0][0][0])[r] = val;
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < EPB * NP; it += NT) {
+        const int el = it / NP, p = it % NP;
+        const int64_t e = e0 + el;
+        if (e >= G.E) continue;
+        float corr[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int a, t1, t2;
+            split_sol<N>(d, p, a, t1, t2);
+            const int pp = t1 + N * t2;
+            const float wl = -0.5f * op.D[a][0], wu = 0.5f * op.D[a][N];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) corr[v] += wl * nv[el][2 * d][v][pp] + wu * nv[el][2 * d + 1][v][pp];
+        }
+        const float iJ = G.solgeo[(e * 13 + 9) * NP + p];
+        double newp[5];
         for (int v = 0; v < 5; ++v) {
             const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
-            const double Rv = (double)r0s[v] + (double)(-div[k][v] * iJ - M[v]);
+            const double Rv = (double)B.R0[gi] + (double)dRp[gi] - (double)(iJ * corr[v]);
             if (S_.mode == 0) {
                 S_.Pout[gi] = Rv;
-            } else {
-                if (S_.Tout) {
-                    const double pb = (S_.d0 != 0.0) ? S_.B[gi] : 0.0;
-                    S_.Tout[gi] = S_.d0 * pb + S_.d1 * (pin[v] + S_.d2 * Rv);
-                }
-                const double pv = S_.c0 * pst[v] + S_.c1 * (pin[v] + S_.c2 * Rv);
-                S_.Pout[gi] = pv;
-                newp[v] = (float)pv;
+                continue;
             }
+            const double pin = Pq[gi];
+            if (S_.Tout) {
+                const double pb = (S_.d0 != 0.0) ? S_.B[gi] : 0.0;
+                S_.Tout[gi] = S_.d0 * pb + S_.d1 * (pin + S_.d2 * Rv);
+            }
+            const double pst = (S_.c0 != 0.0) ? S_.A[gi] : 0.0;
+            newp[v] = S_.c0 * pst + S_.c1 * (pin + S_.c2 * Rv);
+            S_.Pout[gi] = newp[v];
         }
         if (S_.mode != 0)
-            for (int v = 0; v < 5; ++v) l.f[v][p] = newp[v];
+            for (int v = 0; v < 5; ++v) sp[el][v][p] = (float)newp[v];
     }
     if (S_.mode == 0 || S_.TQout == nullptr) return;
     __syncthreads();
     for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
         const int64_t e = e0 + el;
-        const int32_t nb = L[el].lk[f];
+        const int32_t nb = lk[el][f];
         if (e >= G.E || nb < 0) continue;
-        float *out = S_.TQout + mailbox_slot<N>(nb, L[el].inf[f], pp);
-        for (int v = 0; v < 5; ++v) out[v * NF2] = face_val<N>(op, L[el].f[v], f, pp % N, pp / N);
-    }
-}
-
-
-// one block processes K consecutive element blocks, loading the next block's
-// inputs while it computes the current one
-template <int N, int EPB, int NT, int K, int MINW>
-__global__ __launch_bounds__(NT, MINW) void k_resid_mixed(OpsF<N> op, GeoF G, MixedBufs B, PhysParams P, const double *Pq,
-                                                    const float *__restrict__ TQ, const float *__restrict__ TV,
-                                                    MixedStage S_) {
-    __shared__ MixedLds<N> L[EPB];
-    const PhysF F = physf_of(P);
-    const int64_t eb = (int64_t)blockIdx.x * EPB * K;
-    ResidIn<N, EPB, NT> cur;
-    resid_load<N, EPB, NT>(G, B, Pq, TQ, TV, S_, eb, cur);
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const int64_t e0 = eb + (int64_t)j * EPB;
-        if (e0 >= G.E) break;
-        prologue_store<N, EPB, NT>(cur.R, L);
-        __syncthreads();
-        ResidIn<N, EPB, NT> nxt;
-        if (j + 1 < K) resid_load<N, EPB, NT>(G, B, Pq, TQ, TV, S_, e0 + EPB, nxt);
-        resid_compute<N, EPB, NT>(op, G, B, Pq, F, S_, e0, cur, L);
-        __syncthreads();
-        if (j + 1 < K) cur = nxt;
+        float *out = S_.TQout + mailbox_slot<N>(nb, inf[el][f], pp);
+        for (int v = 0; v < 5; ++v) out[v * NF2] = face_val<N>(op, sp[el][v], f, pp % N, pp / N);
     }
 }
 
@@ -859,16 +830,19 @@ __global__ void k_to_float(const double *__restrict__ a, float *__restrict__ b, 
 // ---------------------------------------------------------------------------
 template <int N>
 struct CfgM;
-// elements per block, threads, element blocks per workgroup, and the
-// minimum waves per SIMD the residual (MINW) and gradient (MINWG) passes are
-// compiled for.  At N = 4 both run four waves per SIMD (the residual pass
-// with a few spilled registers, which cost less than the added latency
-// hiding).
-template <> struct CfgM<2> { static constexpr int EPB = 8, NT = 64, K = 1, MINW = 2, MINWG = 2; };
-template <> struct CfgM<3> { static constexpr int EPB = 2, NT = 64, K = 1, MINW = 3, MINWG = 3; };
-template <> struct CfgM<4> { static constexpr int EPB = 1, NT = 64, K = 1, MINW = 4, MINWG = 4; };
-template <> struct CfgM<5> { static constexpr int EPB = 1, NT = 128, K = 1, MINW = 2, MINWG = 2; };
-template <> struct CfgM<6> { static constexpr int EPB = 1, NT = 256, K = 1, MINW = 1, MINWG = 1; };
+// elements per block and threads of the element kernels (trace setup,
+// background setup), and the minimum waves per SIMD of the flux pass
+template <> struct CfgM<2> { static constexpr int EPB = 8, NT = 64, MINW = 2; };
+template <> struct CfgM<3> { static constexpr int EPB = 2, NT = 64, MINW = 3; };
+template <> struct CfgM<4> { static constexpr int EPB = 1, NT = 64, MINW = 4; };
+template <> struct CfgM<5> { static constexpr int EPB = 1, NT = 128, MINW = 2; };
+template <> struct CfgM<6> { static constexpr int EPB = 1, NT = 256, MINW = 1; };
+// flux pass (elements per block, threads, minimum waves per SIMD) and lift
+// pass (elements per block, threads)
+template <int N> struct CfgF { static constexpr int EPB = CfgM<N>::EPB, NT = CfgM<N>::NT, MINW = CfgM<N>::MINW; };
+template <> struct CfgF<4> { static constexpr int EPB = 4, NT = 192, MINW = 3; };
+template <int N> struct CfgL { static constexpr int EPB = CfgM<N>::EPB, NT = CfgM<N>::NT; };
+template <> struct CfgL<4> { static constexpr int EPB = 1, NT = 64; };
 
 static GeoF geof_of(const GeoM &g) {
     GeoF o;
@@ -885,7 +859,6 @@ static MixedBufs bufs_of(const GeoM &g) {
     b.dbg = g.dbg;
     b.gS0 = g.gS0;
     b.R0 = g.R0;
-    b.FF = g.FF;
     return b;
 }
 
@@ -898,23 +871,26 @@ static hipError_t pert_begin_t(const Mesh &m, const GeoM &g, const double *Q, do
     return hipGetLastError();
 }
 template <int N>
-static hipError_t grad_mixed_t(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
-                               float *TV, hipStream_t s) {
-    constexpr int EPB = CfgM<N>::EPB, NT = CfgM<N>::NT;
+static hipError_t flux_mixed_t(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
+                               float *TV, float *dRp, hipStream_t s) {
+    constexpr int EPB = CfgF<N>::EPB, NT = CfgF<N>::NT, MINW = CfgF<N>::MINW;
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
-    hipLaunchKernelGGL((k_grad_mixed<N, EPB, NT, CfgM<N>::MINWG>), dim3(nb), dim3(NT), 0, s, make_ops_t<float, N>(m.basis),
-                       geof_of(g), bufs_of(g), P, Pq, TQ, TV);
+    if (P.kappa_r != 0.0)
+        hipLaunchKernelGGL((k_flux_mixed<N, EPB, NT, MINW, true>), dim3(nb), dim3(NT), 0, s,
+                           make_ops_t<float, N>(m.basis), geof_of(g), bufs_of(g), P, Pq, TQ, TV, dRp);
+    else
+        hipLaunchKernelGGL((k_flux_mixed<N, EPB, NT, MINW, false>), dim3(nb), dim3(NT), 0, s,
+                           make_ops_t<float, N>(m.basis), geof_of(g), bufs_of(g), P, Pq, TQ, TV, dRp);
     return hipGetLastError();
 }
 template <int N>
-static hipError_t resid_mixed_t(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq,
-                                const float *TQ, const float *TV, const MixedStageArgs &a, hipStream_t s) {
-    constexpr int EPB = CfgM<N>::EPB, NT = CfgM<N>::NT, K = CfgM<N>::K;
-    const unsigned nb = (unsigned)((m.E + EPB * K - 1) / (EPB * K));
-    static_assert(K >= 1, "at least one element block per workgroup");
+static hipError_t lift_mixed_t(const Mesh &m, const GeoM &g, const double *Pq, const float *TV, const float *dRp,
+                               const MixedStageArgs &a, hipStream_t s) {
+    constexpr int EPB = CfgL<N>::EPB, NT = CfgL<N>::NT;
+    const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
     const MixedStage st = a;
-    hipLaunchKernelGGL((k_resid_mixed<N, EPB, NT, K, CfgM<N>::MINW>), dim3(nb), dim3(NT), 0, s,
-                       make_ops_t<float, N>(m.basis), geof_of(g), bufs_of(g), P, Pq, TQ, TV, st);
+    hipLaunchKernelGGL((k_lift_mixed<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, make_ops_t<float, N>(m.basis),
+                       geof_of(g), bufs_of(g), Pq, TV, dRp, st);
     return hipGetLastError();
 }
 template <int N>
@@ -942,15 +918,15 @@ hipError_t launch_pert_begin(const Mesh &m, const GeoM &g, const double *Q, doub
     CHORUS_DISPATCH_M(m.N, C_)
 #undef C_
 }
-hipError_t launch_grad_mixed(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
-                             float *TV, hipStream_t s) {
-#define C_(n) grad_mixed_t<n>(m, g, P, Pq, TQ, TV, s)
+hipError_t launch_flux_mixed(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
+                             float *TV, float *dRp, hipStream_t s) {
+#define C_(n) flux_mixed_t<n>(m, g, P, Pq, TQ, TV, dRp, s)
     CHORUS_DISPATCH_M(m.N, C_)
 #undef C_
 }
-hipError_t launch_resid_mixed(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
-                              const float *TV, const MixedStageArgs &a, hipStream_t s) {
-#define C_(n) resid_mixed_t<n>(m, g, P, Pq, TQ, TV, a, s)
+hipError_t launch_lift_mixed(const Mesh &m, const GeoM &g, const double *Pq, const float *TV, const float *dRp,
+                             const MixedStageArgs &a, hipStream_t s) {
+#define C_(n) lift_mixed_t<n>(m, g, Pq, TV, dRp, a, s)
     CHORUS_DISPATCH_M(m.N, C_)
 #undef C_
 }
