@@ -31,7 +31,6 @@ struct WsLayout {
     size_t tau;  // learned closure: subgrid flux [15][E][NP] FP32 (0 when off)
     // mixed-precision path
     size_t P0, P1, TQm, TVm, bg, dbg, gS0, R0, Q0;
-    size_t dRm;  // mixed path: partial residual difference of the flux pass [5][E][NP] FP32
     size_t FF64;  // FP64 path: own-side common face flux [E][6][5][NF2]
     size_t P2, P4;  // SSPRK(5,4) on the perturbation
     bool mixed;
@@ -69,7 +68,6 @@ static WsLayout ws_layout(const Mesh &m) {
     w.gS0 = off;  off = align256(off + sizeof(float) * E * 3 * (N + 1) * NF2);
     w.R0 = off;   off = align256(off + sizeof(float) * 5 * E * NP);
     w.Q0 = off;   off = align256(off + state);
-    w.dRm = off;  off = align256(off + sizeof(float) * 5 * E * NP);
     w.FF64 = off; off = align256(off + sizeof(double) * E * 6 * 5 * NF2);
     w.total = off;
     return w;
@@ -713,11 +711,10 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
         const GeoM g = geom_of(*m, w, W);
         double *P0 = (double *)(W + w.P0);
         float *TQm = (float *)(W + w.TQm), *TVm = (float *)(W + w.TVm);
-        float *dR = (float *)(W + w.dRm);
         hipError_t e = timed(0, s, [&] { return launch_pert_begin(*m, g, Q_dev, P0, TQm, s); });
-        if (e == hipSuccess) e = timed(1, s, [&] { return launch_flux_mixed(*m, g, P, P0, TQm, TVm, dR, s); });
         MixedStageArgs a{nullptr, dQdt_dev, nullptr, 0.0, 1.0, 0.0, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
-        if (e == hipSuccess) e = timed(2, s, [&] { return launch_lift_mixed(*m, g, P0, TVm, dR, a, s); });
+        if (e == hipSuccess) e = timed(1, s, [&] { return launch_flux_mixed(*m, g, P, P0, TQm, TVm, a, s); });
+        if (e == hipSuccess) e = timed(2, s, [&] { return launch_lift_mixed(*m, g, TVm, a, s); });
         if (e != hipSuccess) return hip_fail(e, "sd_residual (mixed)");
         if (phys->flags & CHORUS_CHECK_FINITE) return finite_check(*m, P, Q_dev, w, W, s);
         return CHORUS_OK;
@@ -800,18 +797,17 @@ int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev
         // the flux pass reads the Q-trace mailbox and writes the viscous one;
         // the lift pass reads the viscous mailbox and rewrites the Q traces
         // (kernel order separates every read from the next write)
-        float *TQm = (float *)(W + w.TQm), *TVm = (float *)(W + w.TVm), *dR = (float *)(W + w.dRm);
+        float *TQm = (float *)(W + w.TQm), *TVm = (float *)(W + w.TVm);
         hipError_t e = timed(0, s, [&] { return launch_pert_begin(*m, g, Q_dev, reg[0], TQm, s); });
         for (int st = 0; st < n_steps && e == hipSuccess; ++st) {
             for (int k = 0; k < nst && e == hipSuccess; ++k) {
                 const StagePlan &sp = plan[k];
                 const double *pin = reg[sp.in];
-                e = timed(1, s, [&] { return launch_flux_mixed(*m, g, P, pin, TQm, TVm, dR, s); });
-                if (e != hipSuccess) break;
                 MixedStageArgs a{sp.a >= 0 ? reg[sp.a] : nullptr, reg[sp.out], TQm, sp.c0, sp.c1,
                                  sp.c2 * dt, sp.b >= 0 ? reg[sp.b] : nullptr, sp.tout >= 0 ? reg[sp.tout] : nullptr,
                                  sp.d0, sp.d1, sp.d2 * dt, 1};
-                e = timed(2, s, [&] { return launch_lift_mixed(*m, g, pin, TVm, dR, a, s); });
+                e = timed(1, s, [&] { return launch_flux_mixed(*m, g, P, pin, TQm, TVm, a, s); });
+                if (e == hipSuccess) e = timed(2, s, [&] { return launch_lift_mixed(*m, g, TVm, a, s); });
             }
         }
         if (e == hipSuccess) e = launch_pert_end(g.Q0, reg[0], Q_dev, 5 * m->E * m->N * m->N * m->N, s);

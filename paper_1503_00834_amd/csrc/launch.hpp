@@ -121,13 +121,13 @@ struct MixedStageArgs {
 
 hipError_t launch_pert_begin(const Mesh &m, const GeoM &g, const double *Q, double *Pq, float *TQ, hipStream_t s);
 // stage split used by the solver: flux pass (gradients, fluxes, divergence
-// with the own-side face fluxes, source -> dRp [5][E][NP] FP32, own viscous
-// face flux -> neighbour mailbox TV), then lift pass (neighbours' viscous
-// halves, R = R0 + dRp + lift, stage combination, traces -> TQout)
+// with the own-side face fluxes, source; the stage combination with this
+// partial residual into a.Pout / a.Tout; own viscous face flux -> neighbour
+// mailbox TV), then lift pass (neighbours' viscous halves added in place to
+// a.Pout / a.Tout with their stage weights; traces -> a.TQout)
 hipError_t launch_flux_mixed(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
-                             float *TV, float *dRp, hipStream_t s);
-hipError_t launch_lift_mixed(const Mesh &m, const GeoM &g, const double *Pq, const float *TV, const float *dRp,
-                             const MixedStageArgs &a, hipStream_t s);
+                             float *TV, const MixedStageArgs &a, hipStream_t s);
+hipError_t launch_lift_mixed(const Mesh &m, const GeoM &g, const float *TV, const MixedStageArgs &a, hipStream_t s);
 hipError_t launch_bg_setup(const Mesh &m, const Geo &G, const double *Q0, const double *TQ0, float *bg, float *dbg,
                            int *flag, hipStream_t s);
 hipError_t launch_bg_entropy(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q0, const double *TQ,

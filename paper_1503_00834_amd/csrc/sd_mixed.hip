@@ -540,13 +540,15 @@ using MixedStage = MixedStageArgs;
 // the neighbour's viscous mailbox TV) and the own-side common flux (Rusanov
 // minus half the own viscous flux, or the wall flux); at the interior flux
 // points the transformed flux; the divergence of the flux polynomials with
-// the own-side face fluxes at the line ends; the source.  Output: the
-// partial residual difference dRp = -div/|J| - M [5][E][NP] (FP32), which
-// lacks only the neighbours' viscous halves at interior interfaces.
+// the own-side face fluxes at the line ends; the source.  The partial
+// residual Rp = R0 - div/|J| - M, which lacks only the neighbours' viscous
+// halves at interior interfaces, enters the stage combination here (FP64):
+// Pout = c0 A + c1 (P + c2 Rp) (and Tout likewise), or Pout = Rp in
+// residual mode; the lift pass adds the missing part in place.
 template <int N, int EPB, int NT, int MINW, bool KR>
 __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> op, GeoF G, MixedBufs B, PhysParams P,
                                                          const double *__restrict__ Pq, const float *__restrict__ TQ,
-                                                         float *__restrict__ TV, float *__restrict__ dRp) {
+                                                         float *__restrict__ TV, MixedStage S_) {
     using Sh = Shape<N, EPB, NT>;
     constexpr int NP = Sh::NP, NF2 = Sh::NF2, NFL = Sh::NFL, NINTD = Sh::NINTD;
     __shared__ MixedLds<N> L[EPB];
@@ -668,7 +670,29 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> op, GeoF G, Mix
         }
         __syncthreads();
     }
-    // source and output
+    // source, background residual and stage combination: every operand of
+    // the element block loaded first (the outputs may alias the inputs, so
+    // loads issued after a store would wait for it)
+    float r0v[Sh::IT_SOL][5], gq[Sh::IT_SOL][4];
+    double pin[Sh::IT_SOL][5], pst[Sh::IT_SOL][5], pb[Sh::IT_SOL][5];
+    const bool rk = S_.mode != 0;
+    const bool useA = rk && S_.c0 != 0.0, useT = rk && S_.Tout != nullptr, useB = useT && S_.d0 != 0.0;
+#pragma unroll
+    for (int k = 0; k < Sh::IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const int el = it / NP, p = it % NP;
+        const int64_t e = e0 + el;
+        const bool ok = it < EPB * NP && e < G.E;
+        const float *gsp = G.solgeo + e * 13 * NP + p;
+        for (int c = 0; c < 4; ++c) gq[k][c] = ok ? gsp[(9 + c) * NP] : 0.0f;
+        for (int v = 0; v < 5; ++v) {
+            const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
+            r0v[k][v] = ok ? B.R0[gi] : 0.0f;
+            pin[k][v] = (ok && rk) ? Pq[gi] : 0.0;
+            pst[k][v] = (ok && useA) ? S_.A[gi] : 0.0;
+            pb[k][v] = (ok && useB) ? S_.B[gi] : 0.0;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < Sh::IT_SOL; ++k) {
         const int it = threadIdx.x + k * NT;
@@ -677,9 +701,8 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> op, GeoF G, Mix
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
         const MixedLds<N> &l = L[el];
-        const float *gsp = G.solgeo + e * 13 * NP + p;
-        const float iJ = gsp[9 * NP];
-        const float g0 = F.GM * gsp[10 * NP], g1 = F.GM * gsp[11 * NP], g2 = F.GM * gsp[12 * NP];
+        const float iJ = gq[k][0];
+        const float g0 = F.GM * gq[k][1], g1 = F.GM * gq[k][2], g2 = F.GM * gq[k][3];
         const float rp = l.f[F_RP][p], mx = l.f[F_MX][p], my = l.f[F_MY][p], mz = l.f[F_MZ][p];
         float M[5];
         M[0] = 0.0f;
@@ -687,42 +710,84 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> op, GeoF G, Mix
         M[2] = rp * g1 + 2.0f * F.om * mx;
         M[3] = rp * g2;
         M[4] = mx * g0 + my * g1 + mz * g2;
-        for (int v = 0; v < 5; ++v) dRp[((int64_t)v * G.E + e) * NP + p] = -div[k][v] * iJ - M[v];
+        for (int v = 0; v < 5; ++v) {
+            const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
+            const double Rv = (double)r0v[k][v] + (double)(-div[k][v] * iJ - M[v]);
+            if (!rk) {
+                S_.Pout[gi] = Rv;
+                continue;
+            }
+            if (useT) S_.Tout[gi] = S_.d0 * pb[k][v] + S_.d1 * (pin[k][v] + S_.d2 * Rv);
+            S_.Pout[gi] = S_.c0 * pst[k][v] + S_.c1 * (pin[k][v] + S_.c2 * Rv);
+        }
     }
 }
 
 // Lift pass: the neighbours' viscous halves at the interior interface
 // points enter the divergence through the end columns of the derivative
-// matrix (D[a][0] at the lower, D[a][N] at the upper end of each line);
-// R = R0 + dRp - (1/|J|) * that lift, then the stage combination on P in
-// FP64 and the FP32 face traces of the new P pushed to the neighbours.
+// matrix (D[a][0] at the lower, D[a][N] at the upper end of each line); the
+// missing residual part -(1/|J|) * that lift is added in place to the
+// outputs of the flux pass with their stage weights (Pout: c1 c2, Tout:
+// d1 d2; residual mode: 1), and the FP32 face traces of the new P are
+// pushed to the neighbours.
 template <int N, int EPB, int NT>
-__global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> op, GeoF G, MixedBufs B, const double *__restrict__ Pq,
-                                                   const float *__restrict__ TV, const float *__restrict__ dRp,
-                                                   MixedStage S_) {
+__global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> op, GeoF G, const float *__restrict__ TV, MixedStage S_) {
     constexpr int NP = N * N * N, NF2 = N * N;
+    constexpr int IT_MB = (EPB * 30 * NF2 + NT - 1) / NT, IT_SOL = (EPB * NP + NT - 1) / NT;
     __shared__ float nv[EPB][6][5][NF2];  // neighbours' viscous flux at own face points, 0 on boundary faces
     __shared__ float sp[EPB][5][NP];      // new perturbation (FP32) for the traces
     __shared__ int32_t lk[EPB][6], inf[EPB][6];
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    const bool useT = S_.mode != 0 && S_.Tout != nullptr;
+    // every global input first: face links, the viscous mailbox (boundary
+    // slots too: never written, selected away below), outputs of the flux
+    // pass and 1/|J|
+    int32_t rl = -1, ri = 0;
+    if ((int)threadIdx.x < EPB * 6 && e0 + threadIdx.x / 6 < G.E) {
+        rl = G.link[e0 * 6 + threadIdx.x];
+        ri = G.info[e0 * 6 + threadIdx.x];
+    }
+    float mb[IT_MB];
+#pragma unroll
+    for (int k = 0; k < IT_MB; ++k) {
+        const int it = threadIdx.x + k * NT;
+        mb[k] = (it < EPB * 30 * NF2 && e0 + it / (30 * NF2) < G.E) ? TV[e0 * 30 * NF2 + it] : 0.0f;
+    }
+    double po[IT_SOL][5], to[IT_SOL][5];
+    float iJ[IT_SOL];
+#pragma unroll
+    for (int k = 0; k < IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const int el = it / NP, p = it % NP;
+        const int64_t e = e0 + el;
+        const bool ok = it < EPB * NP && e < G.E;
+        iJ[k] = ok ? G.solgeo[(e * 13 + 9) * NP + p] : 0.0f;
+        for (int v = 0; v < 5; ++v) {
+            const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
+            po[k][v] = ok ? S_.Pout[gi] : 0.0;
+            to[k][v] = (ok && useT) ? S_.Tout[gi] : 0.0;
+        }
+    }
     if ((int)threadIdx.x < EPB * 6) {
-        const int el = threadIdx.x / 6, f = threadIdx.x % 6;
-        const bool ok = e0 + el < G.E;
-        lk[el][f] = ok ? G.link[e0 * 6 + threadIdx.x] : -1;
-        inf[el][f] = ok ? G.info[e0 * 6 + threadIdx.x] : 0;
+        lk[threadIdx.x / 6][threadIdx.x % 6] = rl;
+        inf[threadIdx.x / 6][threadIdx.x % 6] = ri;
     }
     __syncthreads();
     // the mailbox slot of a boundary face is never written: select, do not
     // multiply by zero
-    for (int it = threadIdx.x; it < EPB * 6 * 5 * NF2; it += NT) {
+#pragma unroll
+    for (int k = 0; k < IT_MB; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * 30 * NF2) break;
         const int el = it / (30 * NF2), r = it % (30 * NF2), f = r / (5 * NF2);
-        const int64_t e = e0 + el;
-        float val = 0.0f;
-        if (e < G.E && lk[el][f] >= 0) val = TV[e * 30 * NF2 + r];
-        (&nv[el][0][0][0])[r] = val;
+        (&nv[el][0][0][0])[r] = (lk[el][f] >= 0) ? mb[k] : 0.0f;
     }
     __syncthreads();
-    for (int it = threadIdx.x; it < EPB * NP; it += NT) {
+    const double wP = (S_.mode == 0) ? 1.0 : S_.c1 * S_.c2, wT = S_.d1 * S_.d2;
+#pragma unroll
+    for (int k = 0; k < IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * NP) break;
         const int el = it / NP, p = it % NP;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
@@ -736,26 +801,14 @@ __global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> op, GeoF G, MixedBufs
 #pragma unroll
             for (int v = 0; v < 5; ++v) corr[v] += wl * nv[el][2 * d][v][pp] + wu * nv[el][2 * d + 1][v][pp];
         }
-        const float iJ = G.solgeo[(e * 13 + 9) * NP + p];
-        double newp[5];
         for (int v = 0; v < 5; ++v) {
             const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
-            const double Rv = (double)B.R0[gi] + (double)dRp[gi] - (double)(iJ * corr[v]);
-            if (S_.mode == 0) {
-                S_.Pout[gi] = Rv;
-                continue;
-            }
-            const double pin = Pq[gi];
-            if (S_.Tout) {
-                const double pb = (S_.d0 != 0.0) ? S_.B[gi] : 0.0;
-                S_.Tout[gi] = S_.d0 * pb + S_.d1 * (pin + S_.d2 * Rv);
-            }
-            const double pst = (S_.c0 != 0.0) ? S_.A[gi] : 0.0;
-            newp[v] = S_.c0 * pst + S_.c1 * (pin + S_.c2 * Rv);
-            S_.Pout[gi] = newp[v];
+            const double x = -(double)(iJ[k] * corr[v]);
+            const double pv = po[k][v] + wP * x;
+            S_.Pout[gi] = pv;
+            if (useT) S_.Tout[gi] = to[k][v] + wT * x;
+            sp[el][v][p] = (float)pv;
         }
-        if (S_.mode != 0)
-            for (int v = 0; v < 5; ++v) sp[el][v][p] = (float)newp[v];
     }
     if (S_.mode == 0 || S_.TQout == nullptr) return;
     __syncthreads();
@@ -872,25 +925,25 @@ static hipError_t pert_begin_t(const Mesh &m, const GeoM &g, const double *Q, do
 }
 template <int N>
 static hipError_t flux_mixed_t(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
-                               float *TV, float *dRp, hipStream_t s) {
+                               float *TV, const MixedStageArgs &a, hipStream_t s) {
     constexpr int EPB = CfgF<N>::EPB, NT = CfgF<N>::NT, MINW = CfgF<N>::MINW;
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
+    const MixedStage st = a;
     if (P.kappa_r != 0.0)
         hipLaunchKernelGGL((k_flux_mixed<N, EPB, NT, MINW, true>), dim3(nb), dim3(NT), 0, s,
-                           make_ops_t<float, N>(m.basis), geof_of(g), bufs_of(g), P, Pq, TQ, TV, dRp);
+                           make_ops_t<float, N>(m.basis), geof_of(g), bufs_of(g), P, Pq, TQ, TV, st);
     else
         hipLaunchKernelGGL((k_flux_mixed<N, EPB, NT, MINW, false>), dim3(nb), dim3(NT), 0, s,
-                           make_ops_t<float, N>(m.basis), geof_of(g), bufs_of(g), P, Pq, TQ, TV, dRp);
+                           make_ops_t<float, N>(m.basis), geof_of(g), bufs_of(g), P, Pq, TQ, TV, st);
     return hipGetLastError();
 }
 template <int N>
-static hipError_t lift_mixed_t(const Mesh &m, const GeoM &g, const double *Pq, const float *TV, const float *dRp,
-                               const MixedStageArgs &a, hipStream_t s) {
+static hipError_t lift_mixed_t(const Mesh &m, const GeoM &g, const float *TV, const MixedStageArgs &a, hipStream_t s) {
     constexpr int EPB = CfgL<N>::EPB, NT = CfgL<N>::NT;
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
     const MixedStage st = a;
     hipLaunchKernelGGL((k_lift_mixed<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, make_ops_t<float, N>(m.basis),
-                       geof_of(g), bufs_of(g), Pq, TV, dRp, st);
+                       geof_of(g), TV, st);
     return hipGetLastError();
 }
 template <int N>
@@ -919,14 +972,13 @@ hipError_t launch_pert_begin(const Mesh &m, const GeoM &g, const double *Q, doub
 #undef C_
 }
 hipError_t launch_flux_mixed(const Mesh &m, const GeoM &g, const PhysParams &P, const double *Pq, const float *TQ,
-                             float *TV, float *dRp, hipStream_t s) {
-#define C_(n) flux_mixed_t<n>(m, g, P, Pq, TQ, TV, dRp, s)
+                             float *TV, const MixedStageArgs &a, hipStream_t s) {
+#define C_(n) flux_mixed_t<n>(m, g, P, Pq, TQ, TV, a, s)
     CHORUS_DISPATCH_M(m.N, C_)
 #undef C_
 }
-hipError_t launch_lift_mixed(const Mesh &m, const GeoM &g, const double *Pq, const float *TV, const float *dRp,
-                             const MixedStageArgs &a, hipStream_t s) {
-#define C_(n) lift_mixed_t<n>(m, g, Pq, TV, dRp, a, s)
+hipError_t launch_lift_mixed(const Mesh &m, const GeoM &g, const float *TV, const MixedStageArgs &a, hipStream_t s) {
+#define C_(n) lift_mixed_t<n>(m, g, TV, a, s)
     CHORUS_DISPATCH_M(m.N, C_)
 #undef C_
 }
