@@ -201,7 +201,10 @@ struct Shape {
 
 // registers holding one thread's share of an element block's global inputs;
 // everything is issued before the first use so that a block waits for
-// memory once
+// memory once.  Items past the last element (or past the block's item
+// count) load element 0's data through a clamped index: no load is
+// predicated (a guarded load compiles to a branch that waits for it at
+// once) and those items are never stored.
 template <int N, int EPB, int NT>
 struct Prologue {
     using Sh = Shape<N, EPB, NT>;
@@ -209,49 +212,42 @@ struct Prologue {
     float bg[Sh::IT_SOL][2];
     float gs[Sh::IT_SOL][9];
     // neighbour data at this thread's face items (face item it: el, f, pp):
-    // perturbation trace, viscous trace, background jump
-    float nq[Sh::IT_FACE][5], nv[Sh::IT_FACE][5], db[Sh::IT_FACE][2];
+    // perturbation trace, background jump
+    float nq[Sh::IT_FACE][5], db[Sh::IT_FACE][2];
     int32_t lk, inf;
 };
 
-// issue the loads (mailboxes are read as one contiguous block per element;
-// mv only when TV != null)
 template <int N, int EPB, int NT>
 __device__ __forceinline__ void prologue_load(const double *Pq, const MixedBufs &B, const GeoF &G,
-                                              const float *__restrict__ TQ, const float *__restrict__ TV,
-                                              int64_t e0, Prologue<N, EPB, NT> &R) {
+                                              const float *__restrict__ TQ, int64_t e0, Prologue<N, EPB, NT> &R) {
     using Sh = Shape<N, EPB, NT>;
     constexpr int NP = Sh::NP, NF2 = Sh::NF2;
     const int64_t E = G.E;
-    const int64_t nel = (E - e0 < EPB) ? (E - e0) : EPB;
 #pragma unroll
     for (int k = 0; k < Sh::IT_SOL; ++k) {
         const int it = threadIdx.x + k * NT;
         const int el = it / NP, p = it % NP;
-        const int64_t e = e0 + el;
-        const bool ok = it < EPB * NP && e < E;
-        for (int v = 0; v < 5; ++v) R.P[k][v] = ok ? Pq[((int64_t)v * E + e) * NP + p] : 0.0;
-        R.bg[k][0] = ok ? B.bg[(e * 2 + 0) * NP + p] : 1.0f;
-        R.bg[k][1] = ok ? B.bg[(e * 2 + 1) * NP + p] : 1.0f;
-        for (int t = 0; t < 9; ++t) R.gs[k][t] = ok ? G.solgeo[(e * 13 + t) * NP + p] : 1.0f;
+        const int64_t e = (it < EPB * NP && e0 + el < E) ? e0 + el : 0;
+        for (int v = 0; v < 5; ++v) R.P[k][v] = Pq[((int64_t)v * E + e) * NP + p];
+        R.bg[k][0] = B.bg[(e * 2 + 0) * NP + p];
+        R.bg[k][1] = B.bg[(e * 2 + 1) * NP + p];
+        for (int t = 0; t < 9; ++t) R.gs[k][t] = G.solgeo[(e * 13 + t) * NP + p];
     }
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
         const int it = threadIdx.x + k * NT;
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
-        const bool ok = it < EPB * 6 * NF2 && el < nel;
-        const int64_t base = (e0 + el) * 6 + f;
-        for (int v = 0; v < 5; ++v) {
-            R.nq[k][v] = ok ? TQ[(base * 5 + v) * NF2 + pp] : 0.0f;
-            R.nv[k][v] = (ok && TV) ? TV[(base * 5 + v) * NF2 + pp] : 0.0f;
-        }
-        R.db[k][0] = ok ? B.dbg[(base * 2 + 0) * NF2 + pp] : 0.0f;
-        R.db[k][1] = ok ? B.dbg[(base * 2 + 1) * NF2 + pp] : 0.0f;
+        const int64_t e = (it < EPB * 6 * NF2 && e0 + el < E) ? e0 + el : 0;
+        const int64_t base = e * 6 + f;
+        for (int v = 0; v < 5; ++v) R.nq[k][v] = TQ[(base * 5 + v) * NF2 + pp];
+        R.db[k][0] = B.dbg[(base * 2 + 0) * NF2 + pp];
+        R.db[k][1] = B.dbg[(base * 2 + 1) * NF2 + pp];
     }
     const int it = threadIdx.x;
     const bool okl = it < EPB * 6 && e0 + it / 6 < E;
-    R.lk = okl ? G.link[e0 * 6 + it] : -1;
-    R.inf = okl ? G.info[e0 * 6 + it] : 0;
+    const int32_t lk = G.link[okl ? e0 * 6 + it : 0], inf = G.info[okl ? e0 * 6 + it : 0];
+    R.lk = okl ? lk : -1;
+    R.inf = okl ? inf : 0;
 }
 
 // move the prologue registers into the element LDS
@@ -285,6 +281,23 @@ __device__ __forceinline__ int64_t mailbox_slot(int32_t nb, int32_t inf, int pp)
 }
 
 
+// copy the 1D operator tables into LDS: they are indexed with per-lane
+// indices, which from the kernel-argument segment become vector memory
+// loads on the critical path (the caller's first barrier publishes them)
+template <int N, int NT>
+__device__ __forceinline__ void ops_to_lds(const OpsF<N> &src, OpsF<N> &dst) {
+    constexpr int NW = (int)(sizeof(OpsF<N>) / sizeof(float));
+    static_assert(sizeof(OpsF<N>) % sizeof(float) == 0, "float tables");
+    const float *s = reinterpret_cast<const float *>(&src);
+    float *d = reinterpret_cast<float *>(&dst);
+    // constant indices: the values come from scalar registers, no vector
+    // memory wait
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NW; ++i) d[i] = s[i];
+    }
+}
+
 // own face-point interpolation of a field stored in LDS
 template <int N>
 __device__ __forceinline__ float face_val(const OpsF<N> &op, const float *fld, int f, int t1, int t2) {
@@ -303,7 +316,7 @@ __device__ __forceinline__ float face_val(const OpsF<N> &op, const float *fld, i
 template <int N, int EPB, int NT>
 __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, const PhysF &F, int64_t e0,
                                               MixedLds<N> *L, const Prologue<N, EPB, NT> &R,
-                                              float (*fo)[NFIELD] = nullptr) {
+                                              float (*fo)[NFIELD], const float (*Sf)[3]) {
     using Sh = Shape<N, EPB, NT>;
     constexpr int NF2 = N * N, NFL = (N + 1) * N * N;
 #pragma unroll
@@ -331,11 +344,10 @@ __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, 
         } else {
             // wall state in perturbation form: rho' kept, normal momentum
             // removed, pressure kept (outer wall with T_top: p = rho R T_top)
+            // (the normal projection is the same along +-S: the thread's face
+            // area vector Sf serves)
             const bool outer = ((inf >> 6) - 1) == CHORUS_BC_OUTER;
-            const int d = f >> 1, m = (f & 1) ? N : 0;
-            const int fl = m + (N + 1) * (t1 + N * t2);
-            float S[3];
-            for (int c = 0; c < 3; ++c) S[c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+            const float *S = Sf[k];
             const float A2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
             const float mn = (pv[1] * S[0] + pv[2] * S[1] + pv[3] * S[2]) * rcp(A2);
             float mb[3];
@@ -546,26 +558,28 @@ using MixedStage = MixedStageArgs;
 // Pout = c0 A + c1 (P + c2 Rp) (and Tout likewise), or Pout = Rp in
 // residual mode; the lift pass adds the missing part in place.
 template <int N, int EPB, int NT, int MINW, bool KR>
-__global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> op, GeoF G, MixedBufs B, PhysParams P,
+__global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, MixedBufs B, PhysParams P,
                                                          const double *__restrict__ Pq, const float *__restrict__ TQ,
                                                          float *__restrict__ TV, MixedStage S_) {
     using Sh = Shape<N, EPB, NT>;
     constexpr int NP = Sh::NP, NF2 = Sh::NF2, NFL = Sh::NFL, NINTD = Sh::NINTD;
     __shared__ MixedLds<N> L[EPB];
+    __shared__ OpsF<N> op;  // 1D operators (indexed per lane: LDS, not the argument segment)
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     const PhysF F = physf_of(P);
+    ops_to_lds<N, NT>(opa, op);
     // every global input of the element block, issued before the first wait
+    // (unpredicated, clamped indices: see Prologue)
     float Sf[Sh::IT_FACE][3], gSf[Sh::IT_FACE];
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
         const int it = threadIdx.x + k * NT;
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
-        const int64_t e = e0 + el;
-        const bool ok = it < EPB * 6 * NF2 && e < G.E;
+        const int64_t e = (it < EPB * 6 * NF2 && e0 + el < G.E) ? e0 + el : 0;
         const int d = f >> 1, fl = ((f & 1) ? N : 0) + (N + 1) * pp;
         const float sg = (f & 1) ? 1.0f : -1.0f;
-        for (int c = 0; c < 3; ++c) Sf[k][c] = ok ? sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
-        gSf[k] = ok ? sg * B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
+        for (int c = 0; c < 3; ++c) Sf[k][c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+        gSf[k] = sg * B.gS0[(e * 3 + d) * NFL + fl];
     }
     float Si[3][Sh::IT_INTD][3], gSi[3][Sh::IT_INTD];
 #pragma unroll
@@ -575,17 +589,16 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> op, GeoF G, Mix
             const int it = threadIdx.x + k * NT;
             const int el = it / NINTD, q = it % NINTD;
             const int fl = 1 + q % (N - 1) + (N + 1) * (q / (N - 1));
-            const int64_t e = e0 + el;
-            const bool ok = it < EPB * NINTD && e < G.E;
-            for (int c = 0; c < 3; ++c) Si[d][k][c] = ok ? G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl] : 1.0f;
-            gSi[d][k] = ok ? B.gS0[(e * 3 + d) * NFL + fl] : 0.0f;
+            const int64_t e = (it < EPB * NINTD && e0 + el < G.E) ? e0 + el : 0;
+            for (int c = 0; c < 3; ++c) Si[d][k][c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+            gSi[d][k] = B.gS0[(e * 3 + d) * NFL + fl];
         }
     Prologue<N, EPB, NT> R;
-    prologue_load<N, EPB, NT>(Pq, B, G, TQ, nullptr, e0, R);
+    prologue_load<N, EPB, NT>(Pq, B, G, TQ, e0, R);
     prologue_store<N, EPB, NT>(R, L);
     __syncthreads();
     float fo[Sh::IT_FACE][NFIELD];
-    common_values<N, EPB, NT>(op, G, F, e0, L, R, fo);
+    common_values<N, EPB, NT>(op, G, F, e0, L, R, fo, Sf);
     __syncthreads();
     gradients<N, EPB, NT>(op, G, e0, L, R.gs);
     __syncthreads();
@@ -681,16 +694,15 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> op, GeoF G, Mix
     for (int k = 0; k < Sh::IT_SOL; ++k) {
         const int it = threadIdx.x + k * NT;
         const int el = it / NP, p = it % NP;
-        const int64_t e = e0 + el;
-        const bool ok = it < EPB * NP && e < G.E;
+        const int64_t e = (it < EPB * NP && e0 + el < G.E) ? e0 + el : 0;
         const float *gsp = G.solgeo + e * 13 * NP + p;
-        for (int c = 0; c < 4; ++c) gq[k][c] = ok ? gsp[(9 + c) * NP] : 0.0f;
+        for (int c = 0; c < 4; ++c) gq[k][c] = gsp[(9 + c) * NP];
         for (int v = 0; v < 5; ++v) {
             const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
-            r0v[k][v] = ok ? B.R0[gi] : 0.0f;
-            pin[k][v] = (ok && rk) ? Pq[gi] : 0.0;
-            pst[k][v] = (ok && useA) ? S_.A[gi] : 0.0;
-            pb[k][v] = (ok && useB) ? S_.B[gi] : 0.0;
+            r0v[k][v] = B.R0[gi];
+            pin[k][v] = rk ? Pq[gi] : 0.0;
+            pst[k][v] = useA ? S_.A[gi] : 0.0;
+            pb[k][v] = useB ? S_.B[gi] : 0.0;
         }
     }
 #pragma unroll
@@ -731,9 +743,11 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> op, GeoF G, Mix
 // d1 d2; residual mode: 1), and the FP32 face traces of the new P are
 // pushed to the neighbours.
 template <int N, int EPB, int NT>
-__global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> op, GeoF G, const float *__restrict__ TV, MixedStage S_) {
+__global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> opa, GeoF G, const float *__restrict__ TV, MixedStage S_) {
     constexpr int NP = N * N * N, NF2 = N * N;
     constexpr int IT_MB = (EPB * 30 * NF2 + NT - 1) / NT, IT_SOL = (EPB * NP + NT - 1) / NT;
+    __shared__ OpsF<N> op;
+    ops_to_lds<N, NT>(opa, op);
     __shared__ float nv[EPB][6][5][NF2];  // neighbours' viscous flux at own face points, 0 on boundary faces
     __shared__ float sp[EPB][5][NP];      // new perturbation (FP32) for the traces
     __shared__ int32_t lk[EPB][6], inf[EPB][6];
@@ -743,15 +757,20 @@ __global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> op, GeoF G, const flo
     // slots too: never written, selected away below), outputs of the flux
     // pass and 1/|J|
     int32_t rl = -1, ri = 0;
-    if ((int)threadIdx.x < EPB * 6 && e0 + threadIdx.x / 6 < G.E) {
-        rl = G.link[e0 * 6 + threadIdx.x];
-        ri = G.info[e0 * 6 + threadIdx.x];
+    {
+        const bool okl = (int)threadIdx.x < EPB * 6 && e0 + threadIdx.x / 6 < G.E;
+        const int32_t l = G.link[okl ? e0 * 6 + threadIdx.x : 0], i = G.info[okl ? e0 * 6 + threadIdx.x : 0];
+        rl = okl ? l : -1;
+        ri = okl ? i : 0;
     }
+    // (unpredicated loads through clamped indices; items past the end are
+    // never stored)
     float mb[IT_MB];
 #pragma unroll
     for (int k = 0; k < IT_MB; ++k) {
         const int it = threadIdx.x + k * NT;
-        mb[k] = (it < EPB * 30 * NF2 && e0 + it / (30 * NF2) < G.E) ? TV[e0 * 30 * NF2 + it] : 0.0f;
+        const bool ok = it < EPB * 30 * NF2 && e0 + it / (30 * NF2) < G.E;
+        mb[k] = TV[ok ? e0 * 30 * NF2 + it : 0];
     }
     double po[IT_SOL][5], to[IT_SOL][5];
     float iJ[IT_SOL];
@@ -759,13 +778,12 @@ __global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> op, GeoF G, const flo
     for (int k = 0; k < IT_SOL; ++k) {
         const int it = threadIdx.x + k * NT;
         const int el = it / NP, p = it % NP;
-        const int64_t e = e0 + el;
-        const bool ok = it < EPB * NP && e < G.E;
-        iJ[k] = ok ? G.solgeo[(e * 13 + 9) * NP + p] : 0.0f;
+        const int64_t e = (it < EPB * NP && e0 + el < G.E) ? e0 + el : 0;
+        iJ[k] = G.solgeo[(e * 13 + 9) * NP + p];
         for (int v = 0; v < 5; ++v) {
             const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
-            po[k][v] = ok ? S_.Pout[gi] : 0.0;
-            to[k][v] = (ok && useT) ? S_.Tout[gi] : 0.0;
+            po[k][v] = S_.Pout[gi];
+            to[k][v] = useT ? S_.Tout[gi] : 0.0;
         }
     }
     if ((int)threadIdx.x < EPB * 6) {
