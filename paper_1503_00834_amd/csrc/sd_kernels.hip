@@ -125,11 +125,13 @@ __device__ __forceinline__ void gradients(const Ops<N> &op, const Geo &G, int64_
 // ---------------------------------------------------------------------------
 // face traces of Q: TQ[e][f][v][pp]
 template <int N, int EPB, int NT>
-__global__ __launch_bounds__(NT) void k_trace(Ops<N> op, Geo G, const double *__restrict__ Q,
+__global__ __launch_bounds__(NT) void k_trace(Ops<N> opa, Geo G, const double *__restrict__ Q,
                                               double *__restrict__ TQ) {
     constexpr int NP = N * N * N, NF2 = N * N;
     __shared__ double sq[EPB][5][NP];
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    __shared__ Ops<N> op;
+    ops_to_lds(opa, op);
     load_q<N, EPB, NT>(Q, G.E, e0, sq);
     __syncthreads();
     for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
@@ -194,7 +196,7 @@ __device__ __forceinline__ void closure_tau(const ClosureArgs &C, int64_t E, int
 }
 
 template <int N, int EPB, int NT, bool CL>
-__global__ __launch_bounds__(NT) void k_grad(Ops<N> op, Geo G, PhysParams P, const double *__restrict__ Q,
+__global__ __launch_bounds__(NT) void k_grad(Ops<N> opa, Geo G, PhysParams P, const double *__restrict__ Q,
                                              const double *__restrict__ TQ, double *__restrict__ TV,
                                              ClosureArgs C) {
     constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
@@ -203,6 +205,8 @@ __global__ __launch_bounds__(NT) void k_grad(Ops<N> op, Geo G, PhysParams P, con
     __shared__ double sgr[EPB][15][NP];
     __shared__ float stau[CL ? EPB : 1][15][CL ? NP : 1];
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    __shared__ Ops<N> op;
+    ops_to_lds(opa, op);
     load_q<N, EPB, NT>(Q, G.E, e0, sq);
     __syncthreads();
     common_solution<N, EPB, NT>(op, G, P, TQ, e0, sq, sqs);
@@ -274,13 +278,15 @@ __global__ __launch_bounds__(NT) void k_grad(Ops<N> op, Geo G, PhysParams P, con
 
 // raw closure features at the solution points: X[e NP + p][20] = (Q, grad Q)
 template <int N, int EPB, int NT>
-__global__ __launch_bounds__(NT) void k_features(Ops<N> op, Geo G, PhysParams P, const double *__restrict__ Q,
+__global__ __launch_bounds__(NT) void k_features(Ops<N> opa, Geo G, PhysParams P, const double *__restrict__ Q,
                                                  const double *__restrict__ TQ, float *__restrict__ X) {
     constexpr int NP = N * N * N, NF2 = N * N;
     __shared__ double sq[EPB][5][NP];
     __shared__ double sqs[EPB][6][5][NF2];
     __shared__ double sgr[EPB][15][NP];
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    __shared__ Ops<N> op;
+    ops_to_lds(opa, op);
     load_q<N, EPB, NT>(Q, G.E, e0, sq);
     __syncthreads();
     common_solution<N, EPB, NT>(op, G, P, TQ, e0, sq, sqs);
@@ -298,7 +304,7 @@ __global__ __launch_bounds__(NT) void k_features(Ops<N> op, Geo G, PhysParams P,
 
 
 template <int N, int EPB, int NT, bool CL>
-__global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, const double *Q,
+__global__ __launch_bounds__(NT) void k_resid(Ops<N> opa, Geo G, PhysParams P, const double *Q,
                                               const double *__restrict__ TQ,
                                               const double *__restrict__ TV, StageArgs S_, ClosureArgs C) {
     constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
@@ -324,6 +330,8 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, co
             stau[el][k][p] = (e < G.E) ? C.tau[((int64_t)k * G.E + e) * NP + p] : 0.0f;
         }
     }
+    __shared__ Ops<N> op;
+    ops_to_lds(opa, op);
     load_q<N, EPB, NT>(Q, G.E, e0, sq);
     __syncthreads();
     common_solution<N, EPB, NT>(op, G, P, TQ, e0, sq, sqs);
@@ -469,13 +477,15 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> op, Geo G, PhysParams P, co
 // gradients of the FP64 path (S = c_p ln(p^(1/gamma)/rho), p = (gamma-1) E
 // for zero momentum); used by the mixed-precision path
 template <int N, int EPB, int NT>
-__global__ __launch_bounds__(NT) void k_bg_entropy(Ops<N> op, Geo G, PhysParams P, const double *__restrict__ Q0,
+__global__ __launch_bounds__(NT) void k_bg_entropy(Ops<N> opa, Geo G, PhysParams P, const double *__restrict__ Q0,
                                                    const double *__restrict__ TQ, float *__restrict__ out) {
     constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
     __shared__ double sq[EPB][5][NP];
     __shared__ double sqs[EPB][6][5][NF2];
     __shared__ double sgr[EPB][15][NP];
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    __shared__ Ops<N> op;
+    ops_to_lds(opa, op);
     load_q<N, EPB, NT>(Q0, G.E, e0, sq);
     __syncthreads();
     common_solution<N, EPB, NT>(op, G, P, TQ, e0, sq, sqs);

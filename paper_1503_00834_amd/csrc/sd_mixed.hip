@@ -281,23 +281,6 @@ __device__ __forceinline__ int64_t mailbox_slot(int32_t nb, int32_t inf, int pp)
 }
 
 
-// copy the 1D operator tables into LDS: they are indexed with per-lane
-// indices, which from the kernel-argument segment become vector memory
-// loads on the critical path (the caller's first barrier publishes them)
-template <int N, int NT>
-__device__ __forceinline__ void ops_to_lds(const OpsF<N> &src, OpsF<N> &dst) {
-    constexpr int NW = (int)(sizeof(OpsF<N>) / sizeof(float));
-    static_assert(sizeof(OpsF<N>) % sizeof(float) == 0, "float tables");
-    const float *s = reinterpret_cast<const float *>(&src);
-    float *d = reinterpret_cast<float *>(&dst);
-    // constant indices: the values come from scalar registers, no vector
-    // memory wait
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < NW; ++i) d[i] = s[i];
-    }
-}
-
 // own face-point interpolation of a field stored in LDS
 template <int N>
 __device__ __forceinline__ float face_val(const OpsF<N> &op, const float *fld, int f, int t1, int t2) {
@@ -511,11 +494,13 @@ __device__ __forceinline__ void face_flux_own(const PtState &s, const float nq[5
 // ---------------------------------------------------------------------------
 // P = Q - Q0 (FP64) and the FP32 face traces of P
 template <int N, int EPB, int NT>
-__global__ __launch_bounds__(NT) void k_pert_begin(OpsF<N> op, GeoF G, const double *__restrict__ Q,
+__global__ __launch_bounds__(NT) void k_pert_begin(OpsF<N> opa, GeoF G, const double *__restrict__ Q,
                                                    const double *__restrict__ Q0, double *__restrict__ Pq,
                                                    float *__restrict__ TQ) {
     constexpr int NP = N * N * N, NF2 = N * N;
     __shared__ float sp[EPB][5][NP];
+    __shared__ OpsF<N> op;
+    ops_to_lds(opa, op);
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     for (int it = threadIdx.x; it < EPB * 5 * NP; it += NT) {
         const int el = it / (5 * NP), r = it % (5 * NP), v = r / NP, p = r % NP;
@@ -567,7 +552,7 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
     __shared__ OpsF<N> op;  // 1D operators (indexed per lane: LDS, not the argument segment)
     const int64_t e0 = (int64_t)blockIdx.x * EPB;
     const PhysF F = physf_of(P);
-    ops_to_lds<N, NT>(opa, op);
+    ops_to_lds(opa, op);
     // every global input of the element block, issued before the first wait
     // (unpredicated, clamped indices: see Prologue)
     float Sf[Sh::IT_FACE][3], gSf[Sh::IT_FACE];
@@ -747,7 +732,7 @@ __global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> opa, GeoF G, const fl
     constexpr int NP = N * N * N, NF2 = N * N;
     constexpr int IT_MB = (EPB * 30 * NF2 + NT - 1) / NT, IT_SOL = (EPB * NP + NT - 1) / NT;
     __shared__ OpsF<N> op;
-    ops_to_lds<N, NT>(opa, op);
+    ops_to_lds(opa, op);
     __shared__ float nv[EPB][6][5][NF2];  // neighbours' viscous flux at own face points, 0 on boundary faces
     __shared__ float sp[EPB][5][NP];      // new perturbation (FP32) for the traces
     __shared__ int32_t lk[EPB][6], inf[EPB][6];
@@ -851,11 +836,13 @@ __global__ void k_pert_end(const double *__restrict__ Q0, const double *__restri
 // the background face traces across each interface (neighbour minus own,
 // from the FP64 traces TQ0 of Q0, rounded to FP32); a flag if Q0 moves
 template <int N, int EPB, int NT>
-__global__ __launch_bounds__(NT) void k_bg_setup(Ops<N> op, Geo G, const double *__restrict__ Q0,
+__global__ __launch_bounds__(NT) void k_bg_setup(Ops<N> opa, Geo G, const double *__restrict__ Q0,
                                                  const double *__restrict__ TQ0, float *__restrict__ bg,
                                                  float *__restrict__ dbg, int *__restrict__ flag) {
     constexpr int NP = N * N * N, NF2 = N * N;
     __shared__ double s0[EPB][2][NP];
+    __shared__ Ops<N> op;
+    ops_to_lds(opa, op);
     const int64_t e0 = (int64_t)blockIdx.x * EPB, E = G.E;
     for (int it = threadIdx.x; it < EPB * NP; it += NT) {
         const int el = it / NP, p = it % NP;
