@@ -313,7 +313,13 @@ def chorus_kernel_timing(enable):
     _check(_lib.chorus_kernel_timing(1 if enable else 0), "chorus_kernel_timing")
 
 
-KERNEL_KINDS = ("k_trace", "k_grad", "k_resid")
+# kernel kinds of chorus_kernel_times: the face traces that start a call,
+# the first pass of a stage (FP64: gradient pass k_grad; mixed: flux pass
+# k_flux_mixed) and the second pass (FP64: residual pass k_resid; mixed:
+# lift pass k_lift_mixed)
+KERNEL_KINDS = ("trace", "pass1", "pass2")
+KERNEL_NAMES = {"fp64": {"trace": "k_trace", "pass1": "k_grad", "pass2": "k_resid"},
+                "mixed": {"trace": "k_pert_begin", "pass1": "k_flux_mixed", "pass2": "k_lift_mixed"}}
 
 
 def chorus_kernel_times():
