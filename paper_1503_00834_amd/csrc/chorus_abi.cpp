@@ -666,11 +666,14 @@ int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const 
     if (e == hipSuccess) e = launch_trace(*m, G, Q0, TQ, s);
     if (e == hipSuccess) e = launch_bg_setup(*m, G, Q0, TQ, (float *)(W + w.bg), (float *)(W + w.dbg), flag, s);
     if (e == hipSuccess) e = launch_bg_entropy(*m, G, P, Q0, TQ, (float *)(W + w.gS0), s);
-    // R0 = R(Q0), the complete FP64 residual of the background
+    // R0 = R(Q0), the complete FP64 residual of the background (the flux and
+    // lift passes read receiver-indexed traces: a second trace buffer)
     const ClosureArgs C0{nullptr, nullptr};
-    if (e == hipSuccess) e = launch_grad(*m, G, P, Q0, TQ, TV, C0, s);
+    double *TQp = (double *)(W + w.TQ1);
     StageArgs sa{nullptr, R0d, nullptr, 0.0, 1.0, 0.0, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
-    if (e == hipSuccess) e = launch_resid(*m, G, P, Q0, TQ, TV, sa, C0, s);
+    if (e == hipSuccess) e = launch_trace_push(*m, G, Q0, TQp, s);
+    if (e == hipSuccess) e = launch_flux64(*m, G, P, Q0, TQp, TV, sa, C0, s);
+    if (e == hipSuccess) e = launch_lift64(*m, G, TV, sa, s);
     if (e == hipSuccess) e = launch_to_float(R0d, (float *)(W + w.R0), 5 * n, s);
     int h = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -721,10 +724,10 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
     }
     double *TQ = (double *)(W + w.TQ0), *TV = (double *)(W + w.TV);
     const Geo G = geo_of(*m, (unsigned char *)ws);
-    hipError_t e = timed(0, s, [&] { return launch_trace(*m, G, Q_dev, TQ, s); });
-    if (e == hipSuccess) e = timed(1, s, [&] { return launch_grad(*m, G, P, Q_dev, TQ, TV, C, s); });
     StageArgs sa{nullptr, dQdt_dev, nullptr, 0.0, 1.0, 0.0, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
-    if (e == hipSuccess) e = timed(2, s, [&] { return launch_resid(*m, G, P, Q_dev, TQ, TV, sa, C, s); });
+    hipError_t e = timed(0, s, [&] { return launch_trace_push(*m, G, Q_dev, TQ, s); });
+    if (e == hipSuccess) e = timed(1, s, [&] { return launch_flux64(*m, G, P, Q_dev, TQ, TV, sa, C, s); });
+    if (e == hipSuccess) e = timed(2, s, [&] { return launch_lift64(*m, G, TV, sa, s); });
     if (e != hipSuccess) return hip_fail(e, "sd_residual");
     if (phys->flags & CHORUS_CHECK_FINITE) return finite_check(*m, P, Q_dev, w, W, s);
     return CHORUS_OK;
@@ -818,21 +821,21 @@ int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev
     double *TV = (double *)(W + w.TV);
     double *reg[4] = {Q_dev, (double *)(W + w.Qs), rk54 ? (double *)(W + w.Q2) : nullptr,
                       rk54 ? (double *)(W + w.Q4) : nullptr};
-    double *TQb[2] = {(double *)(W + w.TQ0), (double *)(W + w.TQ1)};
+    // the flux pass reads the trace mailbox and writes the viscous one; the
+    // lift pass reads the viscous mailbox and rewrites the traces (kernel
+    // order separates every read from the next write)
+    double *TQ = (double *)(W + w.TQ0);
     const Geo G = geo_of(*m, (unsigned char *)ws);
-    int cur = 0;
-    hipError_t e = timed(0, s, [&] { return launch_trace(*m, G, Q_dev, TQb[cur], s); });
+    hipError_t e = timed(0, s, [&] { return launch_trace_push(*m, G, Q_dev, TQ, s); });
     for (int st = 0; st < n_steps && e == hipSuccess; ++st) {
         for (int k = 0; k < nst && e == hipSuccess; ++k) {
             const StagePlan &sp = plan[k];
             const double *qin = reg[sp.in];
-            e = timed(1, s, [&] { return launch_grad(*m, G, P, qin, TQb[cur], TV, C, s); });
-            if (e != hipSuccess) break;
-            StageArgs sa{sp.a >= 0 ? reg[sp.a] : nullptr, reg[sp.out], TQb[cur ^ 1], sp.c0, sp.c1, sp.c2 * dt,
+            StageArgs sa{sp.a >= 0 ? reg[sp.a] : nullptr, reg[sp.out], TQ, sp.c0, sp.c1, sp.c2 * dt,
                          sp.b >= 0 ? reg[sp.b] : nullptr, sp.tout >= 0 ? reg[sp.tout] : nullptr, sp.d0, sp.d1,
                          sp.d2 * dt, 1};
-            e = timed(2, s, [&] { return launch_resid(*m, G, P, qin, TQb[cur], TV, sa, C, s); });
-            cur ^= 1;
+            e = timed(1, s, [&] { return launch_flux64(*m, G, P, qin, TQ, TV, sa, C, s); });
+            if (e == hipSuccess) e = timed(2, s, [&] { return launch_lift64(*m, G, TV, sa, s); });
         }
     }
     if (e != hipSuccess) return hip_fail(e, "rk_step");

@@ -47,10 +47,20 @@ struct ClosureArgs {
 hipError_t launch_trace(const Mesh &m, const Geo &G, const double *Q, double *TQ, hipStream_t s);
 hipError_t launch_grad(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
                        double *TV, const ClosureArgs &C, hipStream_t s);
-hipError_t launch_resid(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
-                        const double *TV, const StageArgs &sa, const ClosureArgs &C, hipStream_t s);
 hipError_t launch_features(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
                            float *X, hipStream_t s);
+// FP64 stage split used by the solver (mailboxes indexed by the receiving
+// element, face and point): the face traces of Q pushed to the neighbours;
+// the flux pass (gradients, fluxes, divergence with the own-side face
+// fluxes, source, [subgrid flux], the stage combination with this partial
+// residual into sa.Qout / sa.Tout, own viscous face flux -> neighbour
+// mailbox TV); the lift pass (neighbours' viscous halves added in place with
+// the stage weights, traces of the new state -> sa.TQout)
+hipError_t launch_trace_push(const Mesh &m, const Geo &G, const double *Q, double *TQ, hipStream_t s);
+hipError_t launch_flux64(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
+                         double *TV, const StageArgs &sa, const ClosureArgs &C, hipStream_t s);
+hipError_t launch_lift64(const Mesh &m, const Geo &G, const double *TV, const StageArgs &sa, hipStream_t s);
+
 // closure training buffers for a mini-batch of nb samples (rows of 64 or 16)
 struct TrainBufs {
     float *H1, *G1, *H2, *G2, *dZ1, *dZ2;  // [nb][64]: activations, GELU derivatives, gradients

@@ -51,8 +51,30 @@ __device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
     return bf16_bits(lo) | (bf16_bits(hi) << 16);
 }
 
+// erf by the rational approximation 7.1.26 of Abramowitz and Stegun
+// (Handbook of Mathematical Functions, 1964): erf(x) = 1 - t (a1 + t (a2 +
+// t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1 / (1 + p x), x >= 0, odd
+// extension; |error| <= 1.5e-7, far below the bfloat16 rounding (2^-9
+// relative) the activations receive.  One reciprocal, one exponential and
+// five multiply-adds instead of a general-purpose erf.
+__device__ __forceinline__ float erf_as(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+    float poly = fmaf(1.061405429f, t, -1.453152027f);
+    poly = fmaf(poly, t, 1.421413741f);
+    poly = fmaf(poly, t, -0.284496736f);
+    poly = fmaf(poly, t, 0.254829592f);
+    const float y = fmaf(-poly * t, __expf(-ax * ax), 1.0f);
+    return copysignf(y, x);
+}
+
+// GELU x Phi(x): FP32 with the library erf (training), and with the
+// approximation above for the bfloat16 inference
 __device__ __forceinline__ float gelu_f(float z) {
     return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_bf(float z) {
+    return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f));
 }
 
 // K index held by lane group g (= lane / 16), slot i (0..7) of the B
@@ -85,8 +107,8 @@ __device__ __forceinline__ void mlp_eval(const unsigned char *__restrict__ model
             f32x4_t c = {0.f, 0.f, 0.f, 0.f};
             c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8_t, xb[pt]), c, 0, 0, 0);
             const int ks = mt >> 1, half = (mt & 1) * 2;
-            h1[ks][pt][half] = bf16_pair(gelu_f(c[0] + b[0]), gelu_f(c[1] + b[1]));
-            h1[ks][pt][half + 1] = bf16_pair(gelu_f(c[2] + b[2]), gelu_f(c[3] + b[3]));
+            h1[ks][pt][half] = bf16_pair(gelu_bf(c[0] + b[0]), gelu_bf(c[1] + b[1]));
+            h1[ks][pt][half + 1] = bf16_pair(gelu_bf(c[2] + b[2]), gelu_bf(c[3] + b[3]));
         }
     }
     // layer 2
@@ -104,8 +126,8 @@ __device__ __forceinline__ void mlp_eval(const unsigned char *__restrict__ model
             c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, __builtin_bit_cast(bf16x8_t, h1[0][pt]), c, 0, 0, 0);
             c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, __builtin_bit_cast(bf16x8_t, h1[1][pt]), c, 0, 0, 0);
             const int ks = mt >> 1, half = (mt & 1) * 2;
-            h2[ks][pt][half] = bf16_pair(gelu_f(c[0] + b[0]), gelu_f(c[1] + b[1]));
-            h2[ks][pt][half + 1] = bf16_pair(gelu_f(c[2] + b[2]), gelu_f(c[3] + b[3]));
+            h2[ks][pt][half] = bf16_pair(gelu_bf(c[0] + b[0]), gelu_bf(c[1] + b[1]));
+            h2[ks][pt][half + 1] = bf16_pair(gelu_bf(c[2] + b[2]), gelu_bf(c[3] + b[3]));
         }
     }
     // layer 3 (linear) and output scaling

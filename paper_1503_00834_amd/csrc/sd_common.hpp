@@ -77,4 +77,15 @@ __device__ __forceinline__ int map_face_point(int o, int t1, int t2) {
     return u1 + N * u2;
 }
 
+// mailbox slot of face point pp of an element's face (nb, inf = the face's
+// neighbour element and info word): the receiving element's face and point
+// (the orientation map applied), variable 0; variable v is NF2 further on
+template <int N>
+__device__ __forceinline__ int64_t mailbox_slot(int32_t nb, int32_t inf, int pp) {
+    constexpr int NF2 = N * N;
+    const int f2 = inf & 7, o = (inf >> 3) & 7;
+    const int pn = map_face_point<N>(o, pp % N, pp / N);
+    return ((int64_t)nb * 6 + f2) * 5 * NF2 + pn;
+}
+
 }  // namespace chorus

@@ -1,23 +1,26 @@
-// HIP kernels (gfx950) of the spectral-difference residual and the SSP-RK3
-// update (Section 3 of the paper; SSP-RK3 as the explicit integrator).
+// HIP kernels (gfx950) of the FP64 spectral-difference residual and the
+// explicit Runge-Kutta update (Section 3 of the paper).
 //
-// One residual evaluation is split in two element passes because BR1 needs
-// two neighbour exchanges (Section 3, viscous treatment):
+// One stage is split in two element passes because BR1 needs two
+// neighbour exchanges (Section 3, viscous treatment):
 //
-//   k_grad   Q (own element) + neighbours' Q face traces
-//            -> common interface solution, gradients at solution points,
-//               viscous flux of the own side at interior interface points
-//               (written as the viscous face trace TV)
-//   k_resid  Q + neighbours' Q and viscous traces
-//            -> gradients again, fluxes at all flux points, Rusanov + averaged
-//               viscous common fluxes at interfaces, divergence of the flux
-//               polynomials, source, and either dQ/dt or the fused SSP-RK3
-//               stage combination; in RK mode it also writes the face traces
-//               of the new stage value for the next pass.
+//   k_flux64   Q (own element) + neighbours' Q face traces
+//              -> common interface solution, gradients, [learned subgrid
+//                 flux], own-side common fluxes and own viscous face flux
+//                 (pushed to the neighbours), fluxes at the interior flux
+//                 points, divergence, source, and the stage combination with
+//                 this partial residual
+//   k_lift64   neighbours' viscous face fluxes -> the missing residual part
+//              added in place; face traces of the new state pushed to the
+//              neighbours for the next stage.
 //
-// Work mapping: a workgroup of NT threads owns EPB elements; every phase is a
-// strided loop over (element, point) items with all element data staged in
-// LDS.  No atomics: every output is written by exactly one thread in a fixed
+// k_trace / k_grad (traces indexed by their own element, gradient pass
+// with the fused network) serve the closure features, closure inference and
+// the background set-up of the mixed path.
+//
+// Work mapping: a workgroup of NT threads owns EPB elements; every phase is
+// a loop over (element, point) items with all element data staged in LDS.
+// No atomics: every output is written by exactly one thread in a fixed
 // summation order, so results are bitwise run-to-run deterministic.
 #include <hip/hip_runtime.h>
 
@@ -190,7 +193,7 @@ __device__ __forceinline__ void closure_tau(const ClosureArgs &C, int64_t E, int
             const int k = 4 * g + i;
             if (k >= kMlpOut) continue;
             stau[el][k][sp] = out[pt][i];
-            C.tau[((int64_t)k * E + e0 + el) * NP + sp] = out[pt][i];
+            if (C.tau) C.tau[((int64_t)k * E + e0 + el) * NP + sp] = out[pt][i];
         }
     }
 }
@@ -303,12 +306,90 @@ __global__ __launch_bounds__(NT) void k_features(Ops<N> opa, Geo G, PhysParams P
 
 
 
-template <int N, int EPB, int NT, bool CL>
-__global__ __launch_bounds__(NT) void k_resid(Ops<N> opa, Geo G, PhysParams P, const double *Q,
-                                              const double *__restrict__ TQ,
-                                              const double *__restrict__ TV, StageArgs S_, ClosureArgs C) {
-    constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
-    constexpr int IT_SOL = (EPB * NP + NT - 1) / NT;
+// ---------------------------------------------------------------------------
+// flux pass + lift pass (the stage split used by the solver)
+// ---------------------------------------------------------------------------
+// Per stage: the flux pass takes every step that needs the gradients --
+// common interface solution, gradients, [learned subgrid flux], at the face
+// points the own viscous flux (pushed to the neighbour's viscous mailbox)
+// and the own-side common flux (Rusanov minus half the own viscous flux,
+// the wall flux, or the far-field flux), at the interior flux points the
+// transformed flux, the divergence with the own-side face fluxes at the line
+// ends, the source -- and enters the stage combination with this partial
+// residual.  The lift pass adds the neighbours' viscous halves in place and
+// pushes the face traces of the new state to the neighbours' mailboxes.
+// Mailboxes are indexed by the receiving element, face and point (in the
+// receiver's point order), so each element reads its own contiguous block.
+template <int N, int EPB, int NT>
+struct Sh64 {
+    static constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N, NINTD = (N - 1) * N * N;
+    static constexpr int IT_SOL = (EPB * NP + NT - 1) / NT;
+    static constexpr int IT_FACE = (EPB * 6 * NF2 + NT - 1) / NT;
+    static constexpr int IT_INTD = (EPB * NINTD + NT - 1) / NT;
+};
+
+// face traces of the element block's state (LDS) pushed to the neighbours
+template <int N, int EPB, int NT>
+__device__ __forceinline__ void push_traces64(const Ops<N> &op, const Geo &G, int64_t e0, const int32_t (*lk)[6],
+                                              const int32_t (*inf)[6], const double (*sq)[5][N * N * N],
+                                              double *__restrict__ TQout) {
+    constexpr int NF2 = N * N;
+    for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        const int32_t nb = lk[el][f];
+        if (e0 + el >= G.E || nb < 0) continue;
+        const int d = f >> 1, m = (f & 1) ? N : 0;
+        const int base = sol_of<N>(d, 0, pp % N, pp / N), st = stride_of<N>(d);
+        double *out = TQout + mailbox_slot<N>(nb, inf[el][f], pp);
+        for (int v = 0; v < 5; ++v) {
+            double t = 0.0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) t += op.I[m][b] * sq[el][v][base + b * st];
+            out[v * NF2] = t;
+        }
+    }
+}
+
+// face traces of Q pushed to the neighbours' mailboxes (start of a call)
+template <int N, int EPB, int NT>
+__global__ __launch_bounds__(NT) void k_trace_push(Ops<N> opa, Geo G, const double *__restrict__ Q,
+                                                   double *__restrict__ TQ) {
+    constexpr int NP = N * N * N;
+    __shared__ double sq[EPB][5][NP];
+    __shared__ int32_t lk[EPB][6], inf[EPB][6];
+    __shared__ Ops<N> op;
+    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    ops_to_lds(opa, op);
+    load_q<N, EPB, NT>(Q, G.E, e0, sq);
+    if ((int)threadIdx.x < EPB * 6) {
+        const bool ok = e0 + threadIdx.x / 6 < G.E;
+        lk[threadIdx.x / 6][threadIdx.x % 6] = ok ? G.link[e0 * 6 + threadIdx.x] : -1;
+        inf[threadIdx.x / 6][threadIdx.x % 6] = ok ? G.info[e0 * 6 + threadIdx.x] : 0;
+    }
+    __syncthreads();
+    push_traces64<N, EPB, NT>(op, G, e0, lk, inf, sq, TQ);
+}
+
+// line interpolation of an LDS field at flux point m of the line (base, st)
+template <int N, typename T>
+__device__ __forceinline__ double line_interp(const Ops<N> &op, const T *fld, int m, int base, int st) {
+    double t = 0.0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) t += op.I[m][b] * (double)fld[base + b * st];
+    return t;
+}
+
+// PART 0: the flux pass; PART 1: only the learned subgrid flux (common
+// solution, gradients, network -> C.tau); PART 2: the flux pass with the
+// subgrid flux of a preceding PART-1 launch read from C.tau (the network's
+// registers stay out of the flux pass)
+template <int N, int EPB, int NT, int PART>
+__global__ __launch_bounds__(NT) void k_flux64(Ops<N> opa, Geo G, PhysParams P, const double *__restrict__ Q,
+                                               const double *__restrict__ TQ, double *__restrict__ TV,
+                                               StageArgs S_, ClosureArgs C) {
+    constexpr bool CL = PART != 0;
+    using Sh = Sh64<N, EPB, NT>;
+    constexpr int NP = Sh::NP, NF2 = Sh::NF2, NFL = Sh::NFL, NINTD = Sh::NINTD;
     __shared__ double sq[EPB][5][NP];
     __shared__ double sgr[EPB][15][NP];
     // the common solution is consumed by the gradients before the first
@@ -318,118 +399,247 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> opa, Geo G, PhysParams P, c
         double sft[EPB][5][NFL];
     } U;
     __shared__ float stau[CL ? EPB : 1][15][CL ? NP : 1];
-    auto &sqs = U.sqs;
-    auto &sft = U.sft;
-    double div[IT_SOL][5];
-    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    __shared__ int32_t lk[EPB][6], inf[EPB][6];
+    __shared__ Ops<N> op;
+    const int64_t e0 = (int64_t)blockIdx.x * EPB, E = G.E;
     const double gm1 = P.gamma - 1.0;
-    if constexpr (CL) {
+    // every global input of the element block before the first wait;
+    // unpredicated loads through clamped indices (items past the end read
+    // element 0 and are never stored)
+    double qv[Sh::IT_SOL][5], Gm[Sh::IT_SOL][9];
+#pragma unroll
+    for (int k = 0; k < Sh::IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const int el = it / NP, p = it % NP;
+        const int64_t e = (it < EPB * NP && e0 + el < E) ? e0 + el : 0;
+        for (int v = 0; v < 5; ++v) qv[k][v] = Q[((int64_t)v * E + e) * NP + p];
+        for (int t = 0; t < 9; ++t) Gm[k][t] = G.solgeo[(e * 13 + t) * NP + p];
+    }
+    double nq[Sh::IT_FACE][5], Sf[Sh::IT_FACE][3];
+#pragma unroll
+    for (int k = 0; k < Sh::IT_FACE; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        const int64_t e = (it < EPB * 6 * NF2 && e0 + el < E) ? e0 + el : 0;
+        for (int v = 0; v < 5; ++v) nq[k][v] = TQ[((e * 6 + f) * 5 + v) * NF2 + pp];
+        const int d = f >> 1, fl = ((f & 1) ? N : 0) + (N + 1) * pp;
+        const double sg = (f & 1) ? 1.0 : -1.0;
+        for (int c = 0; c < 3; ++c) Sf[k][c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+    }
+    double Si[3][Sh::IT_INTD][3];
+    if constexpr (PART != 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int k = 0; k < Sh::IT_INTD; ++k) {
+                const int it = threadIdx.x + k * NT;
+                const int el = it / NINTD, q = it % NINTD;
+                const int fl = 1 + q % (N - 1) + (N + 1) * (q / (N - 1));
+                const int64_t e = (it < EPB * NINTD && e0 + el < E) ? e0 + el : 0;
+                for (int c = 0; c < 3; ++c) Si[d][k][c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+            }
+    }
+    if constexpr (PART == 2) {
         for (int it = threadIdx.x; it < EPB * 15 * NP; it += NT) {
             const int el = it / (15 * NP), r = it % (15 * NP), k = r / NP, p = r % NP;
-            const int64_t e = e0 + el;
-            stau[el][k][p] = (e < G.E) ? C.tau[((int64_t)k * G.E + e) * NP + p] : 0.0f;
+            const int64_t e = (e0 + el < E) ? e0 + el : 0;
+            stau[el][k][p] = C.tau[((int64_t)k * E + e) * NP + p];
         }
     }
-    __shared__ Ops<N> op;
-    ops_to_lds(opa, op);
-    load_q<N, EPB, NT>(Q, G.E, e0, sq);
-    __syncthreads();
-    common_solution<N, EPB, NT>(op, G, P, TQ, e0, sq, sqs);
-    __syncthreads();
-    gradients<N, EPB, NT>(op, G, e0, sq, sqs, sgr);
-    __syncthreads();
-#pragma unroll 1
-    for (int d = 0; d < 3; ++d) {
-        // interface points of direction d: own-side common flux from the
-        // gradient pass plus half the neighbour's viscous flux (stored along
-        // its own outward area vector, -So)
-        for (int it = threadIdx.x; it < EPB * 2 * NF2; it += NT) {
-            const int el = it / (2 * NF2), side = (it / NF2) & 1, pp = it % NF2;
-            const int64_t e = e0 + el;
-            if (e >= G.E) continue;
-            const int f = 2 * d + side, m = side ? N : 0, t1 = pp % N, t2 = pp / N;
-            const double sg = side ? 1.0 : -1.0;
-            const int32_t nb = G.link[e * 6 + f];
-            double phi[5];
-            for (int v = 0; v < 5; ++v) phi[v] = G.FF[((e * 6 + f) * 5 + v) * NF2 + pp];
-            if (nb >= 0) {
-                const int32_t inf = G.info[e * 6 + f];
-                const int f2 = inf & 7, o = (inf >> 3) & 7;
-                const int pn = map_face_point<N>(o, t1, t2);
-                const double *tv = TV + ((int64_t)nb * 6 + f2) * 5 * NF2;
-                for (int v = 0; v < 5; ++v) phi[v] += 0.5 * tv[v * NF2 + pn];
-            }
-            for (int v = 0; v < 5; ++v) sft[el][v][m + (N + 1) * pp] = sg * phi[v];
+    {
+        const bool okl = (int)threadIdx.x < EPB * 6 && e0 + threadIdx.x / 6 < E;
+        const int32_t l = G.link[okl ? e0 * 6 + threadIdx.x : 0], i = G.info[okl ? e0 * 6 + threadIdx.x : 0];
+        if ((int)threadIdx.x < EPB * 6) {
+            lk[threadIdx.x / 6][threadIdx.x % 6] = okl ? l : -1;
+            inf[threadIdx.x / 6][threadIdx.x % 6] = okl ? i : 0;
         }
-        // interior d-flux points: transformed flux
-        for (int it = threadIdx.x; it < EPB * (N - 1) * NF2; it += NT) {
-            const int el = it / ((N - 1) * NF2), r = it % ((N - 1) * NF2);
-            const int64_t e = e0 + el;
-            if (e >= G.E) continue;
-            const int m = 1 + r % (N - 1), tt = r / (N - 1), t1 = tt % N, t2 = tt / N;
-            const int fl = m + (N + 1) * tt;
-            const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
-            double q[5], g[5][3], S[3], F[5];
+    }
+    ops_to_lds(opa, op);
+#pragma unroll
+    for (int k = 0; k < Sh::IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * NP) break;
+        for (int v = 0; v < 5; ++v) sq[it / NP][v][it % NP] = qv[k][v];
+    }
+    __syncthreads();
+    // common interface solution; the own face values are kept for the
+    // face-flux phase
+    double fo[Sh::IT_FACE][5];
+#pragma unroll
+    for (int k = 0; k < Sh::IT_FACE; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * 6 * NF2) break;
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        if (e0 + el >= E) continue;
+        const int d = f >> 1, m = (f & 1) ? N : 0;
+        const int base = sol_of<N>(d, 0, pp % N, pp / N), st = stride_of<N>(d);
+        for (int v = 0; v < 5; ++v) fo[k][v] = line_interp<N>(op, sq[el][v], m, base, st);
+        const int32_t nb = lk[el][f];
+        const int bc = (inf[el][f] >> 6) - 1;
+        double qs[5];
+        if (nb >= 0) {
+            for (int v = 0; v < 5; ++v) qs[v] = 0.5 * (fo[k][v] + nq[k][v]);
+        } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
+            wall_state(fo[k], Sf[k], bc == CHORUS_BC_OUTER, P, qs);  // (the same along +-S)
+        } else {
+            for (int v = 0; v < 5; ++v) qs[v] = 0.5 * (fo[k][v] + P.bc_state[v]);
+        }
+        for (int v = 0; v < 5; ++v) U.sqs[el][f][v][pp] = qs[v];
+    }
+    __syncthreads();
+    // gradients at the solution points
+#pragma unroll
+    for (int k = 0; k < Sh::IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * NP) break;
+        const int el = it / NP, p = it % NP;
+        double dq[3][5];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int a, t1, t2;
+            split_sol<N>(d, p, a, t1, t2);
+            const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d), pp = t1 + N * t2;
             for (int v = 0; v < 5; ++v) {
-                double s = 0.0;
+                double t = op.D[a][0] * U.sqs[el][2 * d][v][pp] + op.D[a][N] * U.sqs[el][2 * d + 1][v][pp];
 #pragma unroll
-                for (int b = 0; b < N; ++b) s += op.I[m][b] * sq[el][v][base + b * st];
-                q[v] = s;
-                for (int c = 0; c < 3; ++c) {
-                    double t = 0.0;
-#pragma unroll
-                    for (int b = 0; b < N; ++b) t += op.I[m][b] * sgr[el][v * 3 + c][base + b * st];
-                    g[v][c] = t;
-                }
+                for (int b = 0; b < N; ++b) t += op.B[a][b] * sq[el][v][base + b * st];
+                dq[d][v] = t;
             }
-            for (int c = 0; c < 3; ++c) S[c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
-            // learned subgrid flux along S (interpolated like the gradients)
+        }
+        for (int v = 0; v < 5; ++v)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                sgr[el][v * 3 + c][p] = Gm[k][c] * dq[0][v] + Gm[k][3 + c] * dq[1][v] + Gm[k][6 + c] * dq[2][v];
+    }
+    __syncthreads();
+    if constexpr (PART == 1) {
+        // subgrid flux at the solution points -> C.tau
+        closure_tau<N, EPB, NT>(C, E, e0, sq, sgr, stau);
+        return;
+    }
+    // face points: own viscous flux to the neighbour, own-side common flux
+    // kept in registers for the divergence
+    double ffc[Sh::IT_FACE][5];
+#pragma unroll
+    for (int k = 0; k < Sh::IT_FACE; ++k) {
+        const int it = threadIdx.x + k * NT;
+        for (int v = 0; v < 5; ++v) ffc[k][v] = 0.0;
+        if (it >= EPB * 6 * NF2) break;
+        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+        if (e0 + el >= E) continue;
+        const int d = f >> 1, m = (f & 1) ? N : 0;
+        const int base = sol_of<N>(d, 0, pp % N, pp / N), st = stride_of<N>(d);
+        double g[5][3];
+        for (int v = 0; v < 5; ++v)
+            for (int c = 0; c < 3; ++c) g[v][c] = line_interp<N>(op, sgr[el][v * 3 + c], m, base, st);
+        const int32_t nb = lk[el][f];
+        const int bc = (inf[el][f] >> 6) - 1;
+        double fv[5];
+        if (nb >= 0) {
+            flux_viscous(fo[k], g, Sf[k], P, fv);
+            if constexpr (CL) {
+                // the own-side subgrid flux enters the trace with the sign of -F_v
+                for (int v = 0; v < 5; ++v)
+                    for (int c = 0; c < 3; ++c) fv[v] -= line_interp<N>(op, stau[el][v * 3 + c], m, base, st) * Sf[k][c];
+            }
+            double *tv = TV + mailbox_slot<N>(nb, inf[el][f], pp);
+            for (int v = 0; v < 5; ++v) tv[v * NF2] = fv[v];
+            flux_rusanov(fo[k], nq[k], Sf[k], P, ffc[k]);
+            for (int v = 0; v < 5; ++v) ffc[k][v] -= 0.5 * fv[v];
+        } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
+            flux_wall(fo[k], g, Sf[k], bc == CHORUS_BC_OUTER, P, ffc[k]);
+        } else {
+            flux_viscous(fo[k], g, Sf[k], P, fv);
+            flux_rusanov(fo[k], P.bc_state, Sf[k], P, ffc[k]);
+            for (int v = 0; v < 5; ++v) ffc[k][v] -= 0.5 * fv[v];
+        }
+    }
+    // per direction: transformed flux at the d-flux points, its derivative
+    // added to the divergence at the solution points
+    double div[Sh::IT_SOL][5];
+#pragma unroll
+    for (int k = 0; k < Sh::IT_SOL; ++k)
+        for (int v = 0; v < 5; ++v) div[k][v] = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int k = 0; k < Sh::IT_INTD; ++k) {
+            const int it = threadIdx.x + k * NT;
+            if (it >= EPB * NINTD) break;
+            const int el = it / NINTD, q = it % NINTD;
+            const int m = 1 + q % (N - 1), tt = q / (N - 1);
+            if (e0 + el >= E) continue;
+            const int base = sol_of<N>(d, 0, tt % N, tt / N), st = stride_of<N>(d);
+            double qf[5], g[5][3], fi[5], fv[5];
+            for (int v = 0; v < 5; ++v) {
+                qf[v] = line_interp<N>(op, sq[el][v], m, base, st);
+                for (int c = 0; c < 3; ++c) g[v][c] = line_interp<N>(op, sgr[el][v * 3 + c], m, base, st);
+            }
+            flux_inviscid(qf, Si[d][k], gm1, fi);
+            flux_viscous(qf, g, Si[d][k], P, fv);
             double ts[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
             if constexpr (CL) {
                 for (int v = 0; v < 5; ++v)
-                    for (int c = 0; c < 3; ++c) {
-                        double t = 0.0;
-#pragma unroll
-                        for (int b = 0; b < N; ++b) t += op.I[m][b] * (double)stau[el][v * 3 + c][base + b * st];
-                        ts[v] += t * S[c];
-                    }
+                    for (int c = 0; c < 3; ++c) ts[v] += line_interp<N>(op, stau[el][v * 3 + c], m, base, st) * Si[d][k][c];
             }
-            double fi[5], fv[5];
-            flux_inviscid(q, S, gm1, fi);
-            flux_viscous(q, g, S, P, fv);
-            for (int v = 0; v < 5; ++v) F[v] = fi[v] - fv[v] + ts[v];
-            for (int v = 0; v < 5; ++v) sft[el][v][fl] = F[v];
+            const int fl = m + (N + 1) * tt;
+            for (int v = 0; v < 5; ++v) U.sft[el][v][fl] = fi[v] - fv[v] + ts[v];
+        }
+#pragma unroll
+        for (int k = 0; k < Sh::IT_FACE; ++k) {
+            const int it = threadIdx.x + k * NT;
+            if (it >= EPB * 6 * NF2) break;
+            const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
+            if ((f >> 1) != d || e0 + el >= E) continue;
+            const double sg = (f & 1) ? 1.0 : -1.0;
+            const int fl = ((f & 1) ? N : 0) + (N + 1) * pp;
+            for (int v = 0; v < 5; ++v) U.sft[el][v][fl] = sg * ffc[k][v];
         }
         __syncthreads();
-        // derivative of the flux polynomial along d at the solution points
 #pragma unroll
-        for (int k = 0; k < IT_SOL; ++k) {
+        for (int k = 0; k < Sh::IT_SOL; ++k) {
             const int it = threadIdx.x + k * NT;
             if (it >= EPB * NP) break;
             const int el = it / NP, p = it % NP;
             int a, t1, t2;
             split_sol<N>(d, p, a, t1, t2);
             const int fb = (N + 1) * (t1 + N * t2);
-            for (int v = 0; v < 5; ++v) {
-                double s = 0.0;
 #pragma unroll
-                for (int mm = 0; mm <= N; ++mm) s += op.D[a][mm] * sft[el][v][fb + mm];
-                div[k][v] = (d == 0) ? s : div[k][v] + s;
+            for (int v = 0; v < 5; ++v) {
+                double t = 0.0;
+#pragma unroll
+                for (int mm = 0; mm <= N; ++mm) t += op.D[a][mm] * U.sft[el][v][fb + mm];
+                div[k][v] += t;
             }
         }
         __syncthreads();
     }
-    // source and output
+    // source and the stage combination with the partial residual (operands
+    // loaded before the first store: the outputs may alias them)
+    const bool rk = S_.mode != 0;
+    const bool useA = rk && S_.c0 != 0.0, useT = rk && S_.Tout != nullptr, useB = useT && S_.d0 != 0.0;
+    double gq[Sh::IT_SOL][4], av[Sh::IT_SOL][5], bv[Sh::IT_SOL][5];
 #pragma unroll
-    for (int k = 0; k < IT_SOL; ++k) {
+    for (int k = 0; k < Sh::IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const int el = it / NP, p = it % NP;
+        const int64_t e = (it < EPB * NP && e0 + el < E) ? e0 + el : 0;
+        for (int c = 0; c < 4; ++c) gq[k][c] = G.solgeo[(e * 13 + 9 + c) * NP + p];
+        for (int v = 0; v < 5; ++v) {
+            const int64_t gi = ((int64_t)v * E + e) * NP + p;
+            av[k][v] = useA ? S_.A[gi] : 0.0;
+            bv[k][v] = useB ? S_.B[gi] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < Sh::IT_SOL; ++k) {
         const int it = threadIdx.x + k * NT;
         if (it >= EPB * NP) break;
         const int el = it / NP, p = it % NP;
         const int64_t e = e0 + el;
-        if (e >= G.E) continue;
-        const double *gs = G.solgeo + e * 13 * NP + p;
-        const double iJ = gs[9 * NP];
-        const double g0 = P.GM * gs[10 * NP], g1 = P.GM * gs[11 * NP], g2 = P.GM * gs[12 * NP];
+        if (e >= E) continue;
+        const double iJ = gq[k][0];
+        const double g0 = P.GM * gq[k][1], g1 = P.GM * gq[k][2], g2 = P.GM * gq[k][3];
         const double rho = sq[el][0][p], mx = sq[el][1][p], my = sq[el][2][p], mz = sq[el][3][p];
         double M[5];
         M[0] = 0.0;
@@ -439,37 +649,106 @@ __global__ __launch_bounds__(NT) void k_resid(Ops<N> opa, Geo G, PhysParams P, c
         M[4] = mx * g0 + my * g1 + mz * g2;
         for (int v = 0; v < 5; ++v) {
             const double R = -div[k][v] * iJ - M[v];
-            const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
-            if (S_.mode == 0) {
+            const int64_t gi = ((int64_t)v * E + e) * NP + p;
+            if (!rk) {
                 S_.Qout[gi] = R;
-            } else {
-                const double q = sq[el][v][p];
-                if (S_.Tout) {
-                    const double qb = (S_.d0 != 0.0) ? S_.B[gi] : 0.0;
-                    S_.Tout[gi] = S_.d0 * qb + S_.d1 * (q + S_.d2 * R);
-                }
-                const double qa = (S_.c0 != 0.0) ? S_.A[gi] : 0.0;
-                const double qv = S_.c0 * qa + S_.c1 * (q + S_.c2 * R);
-                S_.Qout[gi] = qv;
-                sq[el][v][p] = qv;
+                continue;
             }
+            const double q = sq[el][v][p];
+            if (useT) S_.Tout[gi] = S_.d0 * bv[k][v] + S_.d1 * (q + S_.d2 * R);
+            S_.Qout[gi] = S_.c0 * av[k][v] + S_.c1 * (q + S_.c2 * R);
+        }
+    }
+}
+
+// Lift pass: the neighbours' viscous halves at interior interface points
+// enter the divergence through the end columns of the derivative matrix;
+// -(1/|J|) times that lift is added in place to the flux pass's outputs
+// with their stage weights (Qout: c1 c2, Tout: d1 d2; residual mode: 1);
+// the face traces of the new state are pushed to the neighbours.
+template <int N, int EPB, int NT>
+__global__ __launch_bounds__(NT) void k_lift64(Ops<N> opa, Geo G, const double *__restrict__ TV, StageArgs S_) {
+    constexpr int NP = N * N * N, NF2 = N * N;
+    constexpr int IT_MB = (EPB * 30 * NF2 + NT - 1) / NT, IT_SOL = (EPB * NP + NT - 1) / NT;
+    __shared__ double nv[EPB][6][5][NF2];  // neighbours' viscous flux at own face points, 0 off interfaces
+    __shared__ double sq[EPB][5][NP];      // the new state, for the traces
+    __shared__ int32_t lk[EPB][6], inf[EPB][6];
+    __shared__ Ops<N> op;
+    const int64_t e0 = (int64_t)blockIdx.x * EPB, E = G.E;
+    const bool useT = S_.mode != 0 && S_.Tout != nullptr;
+    // every global input first (unpredicated, clamped; the mailbox slots of
+    // boundary faces are never written and are selected away below)
+    int32_t rl, ri;
+    {
+        const bool okl = (int)threadIdx.x < EPB * 6 && e0 + threadIdx.x / 6 < E;
+        const int32_t l = G.link[okl ? e0 * 6 + threadIdx.x : 0], i = G.info[okl ? e0 * 6 + threadIdx.x : 0];
+        rl = okl ? l : -1;
+        ri = okl ? i : 0;
+    }
+    double mb[IT_MB];
+#pragma unroll
+    for (int k = 0; k < IT_MB; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const bool ok = it < EPB * 30 * NF2 && e0 + it / (30 * NF2) < E;
+        mb[k] = TV[ok ? e0 * 30 * NF2 + it : 0];
+    }
+    double qo[IT_SOL][5], to[IT_SOL][5], iJ[IT_SOL];
+#pragma unroll
+    for (int k = 0; k < IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const int el = it / NP, p = it % NP;
+        const int64_t e = (it < EPB * NP && e0 + el < E) ? e0 + el : 0;
+        iJ[k] = G.solgeo[(e * 13 + 9) * NP + p];
+        for (int v = 0; v < 5; ++v) {
+            const int64_t gi = ((int64_t)v * E + e) * NP + p;
+            qo[k][v] = S_.Qout[gi];
+            to[k][v] = useT ? S_.Tout[gi] : 0.0;
+        }
+    }
+    ops_to_lds(opa, op);
+    if ((int)threadIdx.x < EPB * 6) {
+        lk[threadIdx.x / 6][threadIdx.x % 6] = rl;
+        inf[threadIdx.x / 6][threadIdx.x % 6] = ri;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IT_MB; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * 30 * NF2) break;
+        const int el = it / (30 * NF2), r = it % (30 * NF2), f = r / (5 * NF2);
+        (&nv[el][0][0][0])[r] = (lk[el][f] >= 0) ? mb[k] : 0.0;
+    }
+    __syncthreads();
+    const double wP = (S_.mode == 0) ? 1.0 : S_.c1 * S_.c2, wT = S_.d1 * S_.d2;
+#pragma unroll
+    for (int k = 0; k < IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        if (it >= EPB * NP) break;
+        const int el = it / NP, p = it % NP;
+        const int64_t e = e0 + el;
+        if (e >= E) continue;
+        double corr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int a, t1, t2;
+            split_sol<N>(d, p, a, t1, t2);
+            const int pp = t1 + N * t2;
+            const double wl = -0.5 * op.D[a][0], wu = 0.5 * op.D[a][N];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) corr[v] += wl * nv[el][2 * d][v][pp] + wu * nv[el][2 * d + 1][v][pp];
+        }
+        for (int v = 0; v < 5; ++v) {
+            const int64_t gi = ((int64_t)v * E + e) * NP + p;
+            const double x = -iJ[k] * corr[v];
+            const double qn = qo[k][v] + wP * x;
+            S_.Qout[gi] = qn;
+            if (useT) S_.Tout[gi] = to[k][v] + wT * x;
+            sq[el][v][p] = qn;
         }
     }
     if (S_.mode == 0 || S_.TQout == nullptr) return;
     __syncthreads();
-    for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
-        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
-        const int64_t e = e0 + el;
-        if (e >= G.E) continue;
-        const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
-        const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
-        for (int v = 0; v < 5; ++v) {
-            double s = 0.0;
-#pragma unroll
-            for (int b = 0; b < N; ++b) s += op.I[m][b] * sq[el][v][base + b * st];
-            S_.TQout[((e * 6 + f) * 5 + v) * NF2 + pp] = s;
-        }
-    }
+    push_traces64<N, EPB, NT>(op, G, e0, lk, inf, sq, S_.TQout);
 }
 
 // entropy gradient of a state at rest along the flux-point metric:
@@ -679,21 +958,50 @@ static hipError_t launch_grad_t(const Mesh &m, const Geo &G, const PhysParams &P
     return hipGetLastError();
 }
 
+// flux/lift passes: elements per block / threads per block for each order
 template <int N>
-static hipError_t launch_resid_t(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q,
-                                 const double *TQ, const double *TV, const StageArgs &sa, const ClosureArgs &C,
-                                 hipStream_t s) {
-    constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
-    const Ops<N> op = make_ops<N>(m.basis);
+struct Cfg64 {
+    static constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
+};
+
+template <int N>
+static hipError_t launch_trace_push_t(const Mesh &m, const Geo &G, const double *Q, double *TQ, hipStream_t s) {
+    constexpr int EPB = Cfg64<N>::EPB, NT = Cfg64<N>::NT;
+    const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
+    hipLaunchKernelGGL((k_trace_push<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, Q, TQ);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_flux64_t(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q,
+                                  const double *TQ, double *TV, const StageArgs &sa, const ClosureArgs &C,
+                                  hipStream_t s) {
+    constexpr int EPB = Cfg64<N>::EPB, NT = Cfg64<N>::NT;
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
     if (C.model) {
-        if constexpr (N == 3)
-            hipLaunchKernelGGL((k_resid<N, EPB, NT, true>), dim3(nb), dim3(NT), 0, s, op, G, P, Q, TQ, TV, sa, C);
-        else
+        // the network's pass, then the flux pass reading its subgrid flux
+        if constexpr (N == 3) {
+            hipLaunchKernelGGL((k_flux64<N, EPB, NT, 1>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, P, Q,
+                               TQ, TV, sa, C);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_flux64<N, EPB, NT, 2>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, P, Q,
+                               TQ, TV, sa, C);
+        } else {
             return hipErrorInvalidValue;
+        }
     } else {
-        hipLaunchKernelGGL((k_resid<N, EPB, NT, false>), dim3(nb), dim3(NT), 0, s, op, G, P, Q, TQ, TV, sa, C);
+        hipLaunchKernelGGL((k_flux64<N, EPB, NT, 0>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, P, Q, TQ,
+                           TV, sa, C);
     }
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_lift64_t(const Mesh &m, const Geo &G, const double *TV, const StageArgs &sa, hipStream_t s) {
+    constexpr int EPB = Cfg64<N>::EPB, NT = Cfg64<N>::NT;
+    const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
+    hipLaunchKernelGGL((k_lift64<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, TV, sa);
     return hipGetLastError();
 }
 
@@ -728,9 +1036,19 @@ hipError_t launch_grad(const Mesh &m, const Geo &G, const PhysParams &P, const d
     CHORUS_DISPATCH(m.N, C_)
 #undef C_
 }
-hipError_t launch_resid(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
-                        const double *TV, const StageArgs &sa, const ClosureArgs &C, hipStream_t s) {
-#define C_(n) launch_resid_t<n>(m, G, P, Q, TQ, TV, sa, C, s)
+hipError_t launch_trace_push(const Mesh &m, const Geo &G, const double *Q, double *TQ, hipStream_t s) {
+#define C_(n) launch_trace_push_t<n>(m, G, Q, TQ, s)
+    CHORUS_DISPATCH(m.N, C_)
+#undef C_
+}
+hipError_t launch_flux64(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
+                         double *TV, const StageArgs &sa, const ClosureArgs &C, hipStream_t s) {
+#define C_(n) launch_flux64_t<n>(m, G, P, Q, TQ, TV, sa, C, s)
+    CHORUS_DISPATCH(m.N, C_)
+#undef C_
+}
+hipError_t launch_lift64(const Mesh &m, const Geo &G, const double *TV, const StageArgs &sa, hipStream_t s) {
+#define C_(n) launch_lift64_t<n>(m, G, TV, sa, s)
     CHORUS_DISPATCH(m.N, C_)
 #undef C_
 }

@@ -270,17 +270,6 @@ __device__ __forceinline__ void prologue_store(const Prologue<N, EPB, NT> &R, Mi
     }
 }
 
-// push a value of own face point (f, pp) into the neighbour's mailbox at the
-// neighbour's point index (no-op on boundary faces)
-template <int N>
-__device__ __forceinline__ int64_t mailbox_slot(int32_t nb, int32_t inf, int pp) {
-    constexpr int NF2 = N * N;
-    const int f2 = inf & 7, o = (inf >> 3) & 7;
-    const int pn = map_face_point<N>(o, pp % N, pp / N);
-    return ((int64_t)nb * 6 + f2) * 5 * NF2 + pn;
-}
-
-
 // own face-point interpolation of a field stored in LDS
 template <int N>
 __device__ __forceinline__ float face_val(const OpsF<N> &op, const float *fld, int f, int t1, int t2) {
