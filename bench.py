@@ -98,7 +98,7 @@ def closure_leg(panel_n=32, radial_n=16):
     network, and the resolved order-6 run on the same mesh, per unit
     simulated time.  The network's matrix-core rate is its algorithmic
     flops (2 (20*64 + 64*64 + 64*15) = 12,672 per point) over the extra
-    time the fused gradient pass takes."""
+    time its pass adds to the first pass of a stage."""
     from paper_1503_00834_amd import closure
     c = closure.cost_per_time(panel_n, radial_n, kernel_times=True)
     g_cl = c["closure"]["kernel_ms_per_launch"]["pass1"]
@@ -112,7 +112,8 @@ def closure_leg(panel_n=32, radial_n=16):
             "grad_kernel_ms": {"closure": g_cl, "plain": g_pl},
             "mlp": {"bound": "mfma", "achieved": flops / dt_mlp / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
                     "frac": flops / dt_mlp / 1e12 / 2500.0, "alg_flops_per_launch": flops,
-                    "note": "network time = fused gradient pass minus the plain one"}}
+                    "note": "network time = the network pass plus the order-3 flux pass, minus the plain "
+                            "order-3 flux pass"}}
 
 
 def large_leg(ch, workload="sun_332k_N4", steps=10):
