@@ -314,11 +314,11 @@ def chorus_kernel_timing(enable):
 
 
 # kernel kinds of chorus_kernel_times: the face traces that start a call,
-# the first pass of a stage (FP64: gradient pass k_grad; mixed: flux pass
-# k_flux_mixed) and the second pass (FP64: residual pass k_resid; mixed:
+# the first pass of a stage (FP64: flux pass k_flux64; mixed: flux pass
+# k_flux_mixed) and the second pass (FP64: lift pass k_lift64; mixed:
 # lift pass k_lift_mixed)
 KERNEL_KINDS = ("trace", "pass1", "pass2")
-KERNEL_NAMES = {"fp64": {"trace": "k_trace", "pass1": "k_grad", "pass2": "k_resid"},
+KERNEL_NAMES = {"fp64": {"trace": "k_trace_push", "pass1": "k_flux64", "pass2": "k_lift64"},
                 "mixed": {"trace": "k_pert_begin", "pass1": "k_flux_mixed", "pass2": "k_lift_mixed"}}
 
 

@@ -963,6 +963,7 @@ template <int N>
 struct Cfg64 {
     static constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
 };
+template <> struct Cfg64<4> { static constexpr int EPB = 1, NT = 64; };
 
 template <int N>
 static hipError_t launch_trace_push_t(const Mesh &m, const Geo &G, const double *Q, double *TQ, hipStream_t s) {
