@@ -89,7 +89,11 @@ typedef struct {
  * rho nu; diffusive energy flux f = -kappa rho T grad S - kappa_r rho c_p
  * grad T; walls impermeable and stress-free (Section 5) with f.r_hat =
  * F_bottom at the inner wall and T = T_top at the outer wall (T_top <= 0:
- * interior temperature kept). */
+ * interior temperature kept).  The radiative diffusivity may vary with
+ * radius as in the solar benchmark (Section 7.3, a quadratic in r):
+ * kappa_r(r) = kappa_r + kappa_r1 r + kappa_r2 r^2, evaluated at the radius
+ * of each flux point (kappa_r1 = kappa_r2 = 0: constant).  It must not be
+ * negative anywhere on the mesh (CHORUS_EINVAL). */
 typedef struct {
     double gamma, R_gas, GM, omega, nu, kappa, kappa_r, T_top, F_bottom;
     double bc_state[5];       /* state for CHORUS_BC_STATE faces              */
@@ -102,6 +106,7 @@ typedef struct {
                                  CHORUS_SSPRK54                               */
     const void *closure_model;/* device image from chorus_closure_pack when
                                  closure == CHORUS_CLOSURE_MLP, else ignored   */
+    double kappa_r1, kappa_r2;/* radial terms of kappa_r(r) (see above)      */
 } chorus_physics;
 
 /* Build a cubed-sphere shell mesh (host only). */
@@ -160,11 +165,14 @@ int chorus_init_polytrope(chorus_mesh_t mesh, double beta, double n_rho, double 
  * p0 = 1) to both walls.  Q_host [5][E N^3] receives the state at rest;
  * pars (may be NULL) receives (chi_o, c, alpha, GM, T0 at the outer wall,
  * bottom flux L / (4 pi R_i^2)) for chorus_physics (GM, T_top, F_bottom).
- * kappa and kappa_r are the solver's constant diffusivities. */
+ * kappa is the solver's constant entropy diffusivity; kappa_r(r) =
+ * kappa_r + kappa_r1 r + kappa_r2 r^2 its radiative diffusivity (as in
+ * chorus_physics). */
 typedef struct {
     double beta, n_rho, poly_n, gamma, R_gas;
     double luminosity;        /* L in the units of depth 1, rho_c = p_c = 1 */
     double kappa, kappa_r;
+    double kappa_r1, kappa_r2;
 } chorus_afb_desc;
 int chorus_init_afb(chorus_mesh_t mesh, const chorus_afb_desc *desc, double *Q_host, double pars[6]);
 

@@ -77,14 +77,18 @@ class OraPhys(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("R_gas", ctypes.c_double), ("GM", ctypes.c_double),
                 ("omega", ctypes.c_double), ("nu", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("kappa_r", ctypes.c_double), ("T_top", ctypes.c_double),
-                ("F_bottom", ctypes.c_double), ("bc_state", ctypes.c_double * 5)]
+                ("F_bottom", ctypes.c_double), ("bc_state", ctypes.c_double * 5),
+                ("kappa_r1", ctypes.c_double), ("kappa_r2", ctypes.c_double)]
 
 
 def phys(gamma=5.0 / 3.0, R_gas=1.0, GM=0.0, omega=0.0, nu=0.0, kappa=0.0, kappa_r=0.0,
-         T_top=0.0, F_bottom=0.0, bc_state=(1.0, 0.0, 0.0, 0.0, 1.5)):
+         T_top=0.0, F_bottom=0.0, bc_state=(1.0, 0.0, 0.0, 0.0, 1.5), kappa_r1=0.0, kappa_r2=0.0):
+    """Physics of the oracle; the radiative diffusivity at radius r is
+    kappa_r + kappa_r1 r + kappa_r2 r^2."""
     p = OraPhys()
     p.gamma, p.R_gas, p.GM, p.omega = gamma, R_gas, GM, omega
     p.nu, p.kappa, p.kappa_r, p.T_top, p.F_bottom = nu, kappa, kappa_r, T_top, F_bottom
+    p.kappa_r1, p.kappa_r2 = kappa_r1, kappa_r2
     for i in range(5):
         p.bc_state[i] = bc_state[i]
     return p

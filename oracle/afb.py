@@ -7,7 +7,9 @@ mid-layer point chi = 1 (so T_c = 1 / R and GM = (n + 1) alpha):
 Target entropy gradient (Eq. target_entropy, with the overall sign that
 makes the diffusive flux f = -kappa rho T grad S - kappa_r rho c_p grad T of
 Section 2 carry the luminosity outward):
-    Gamma = -(L / (4 pi r^2) + rho_a c_p kappa_r dT_a/dr) / (rho_a T_a kappa).
+    Gamma = -(L / (4 pi r^2) + rho_a c_p kappa_r dT_a/dr) / (rho_a T_a kappa),
+with kappa_r(r) = kappa_r + kappa_r1 r + kappa_r2 r^2 (constant unless the
+quadratic terms are given: the solar case of Section 7.3).
 State equations (Eq. state_equations), integrated from r_c (chi = 1) with
 rho0 = p0 = 1 by scipy's DOP853 at tight tolerances:
     Gamma / c_p = -(rho0'/rho0 + g rho0 / (gamma p0)),  p0' = -rho0 g,
@@ -25,17 +27,20 @@ def polytrope_constants(beta, n_rho, poly_n):
     return chi_o, c, alpha
 
 
-def target_gradient(r, beta, n_rho, luminosity, kappa, kappa_r=0.0, poly_n=1.5, gamma=5.0 / 3.0, R_gas=1.0):
+def target_gradient(r, beta, n_rho, luminosity, kappa, kappa_r=0.0, poly_n=1.5, gamma=5.0 / 3.0, R_gas=1.0,
+                    kappa_r1=0.0, kappa_r2=0.0):
     _, c, alpha = polytrope_constants(beta, n_rho, poly_n)
     chi = c + alpha / r
     rho_a = chi ** poly_n
     T_a = chi / R_gas
     dT_a = -alpha / r ** 2 / R_gas
     cp = gamma * R_gas / (gamma - 1.0)
-    return -(luminosity / (4.0 * math.pi * r ** 2) + rho_a * cp * kappa_r * dT_a) / (rho_a * T_a * kappa)
+    kr = kappa_r + kappa_r1 * r + kappa_r2 * r * r
+    return -(luminosity / (4.0 * math.pi * r ** 2) + rho_a * cp * kr * dT_a) / (rho_a * T_a * kappa)
 
 
-def background(r, beta, n_rho, luminosity, kappa, kappa_r=0.0, poly_n=1.5, gamma=5.0 / 3.0, R_gas=1.0):
+def background(r, beta, n_rho, luminosity, kappa, kappa_r=0.0, poly_n=1.5, gamma=5.0 / 3.0, R_gas=1.0,
+               kappa_r1=0.0, kappa_r2=0.0):
     """(rho0, p0) at the radii r (any shape)."""
     from scipy.integrate import solve_ivp
     _, c, alpha = polytrope_constants(beta, n_rho, poly_n)
@@ -46,7 +51,7 @@ def background(r, beta, n_rho, luminosity, kappa, kappa_r=0.0, poly_n=1.5, gamma
     def f(x, y):
         rho, p = y
         g = GM / x ** 2
-        G = target_gradient(x, beta, n_rho, luminosity, kappa, kappa_r, poly_n, gamma, R_gas)
+        G = target_gradient(x, beta, n_rho, luminosity, kappa, kappa_r, poly_n, gamma, R_gas, kappa_r1, kappa_r2)
         return [-rho * (G / cp + g * rho / (gamma * p)), -rho * g]
 
     r = np.asarray(r, dtype=np.float64)

@@ -22,7 +22,9 @@
  *   - M uses g_vec = +GM x / r^3 (outward components of the magnitude), so
  *     that -M reproduces rho g and rho u.g of Eqs. 2-3; Coriolis as printed.
  *   - energy component of F_v is u.tau - f (Eq. 3), f = -kappa rho T grad S
- *     - kappa_r rho c_p grad T.
+ *     - kappa_r rho c_p grad T; kappa_r may vary with radius as a quadratic
+ *     in r (the solar case of Section 7.3), evaluated at the radius of each
+ *     flux point given by the element map.
  *   - Rusanov wave speed max(|u_L.n| + c_L, |u_R.n| + c_R); one common flux
  *     per face point, shared by both sides.
  *   - BR1: gradients of the conserved variables from the flux-point values
@@ -212,6 +214,7 @@ struct ora_mesh {
     double *jac;   /* [E][np] */
     double *met;   /* [E][np][3 d][3 c]  exact |J| grad xi_d */
     double *metf;  /* [E][3 d][nfl][3 c] curl-form |J| grad xi_d at d-flux points */
+    double *rflux; /* [E][3 d][nfl] radius |x| at the d-flux points (from the map) */
     int *bc;       /* [E][6] */
     long *nbr_e;   /* [E][6] */
     int *nbr_f;    /* [E][6] */
@@ -283,7 +286,7 @@ void ora_mesh_free(ora_mesh *m)
 {
     if (!m)
         return;
-    free(m->xsol); free(m->jac); free(m->met); free(m->metf); free(m->bc);
+    free(m->xsol); free(m->jac); free(m->met); free(m->metf); free(m->rflux); free(m->bc);
     free(m->nbr_e); free(m->nbr_f); free(m->nbr_p);
     free(m->Qf); free(m->Qs); free(m->grad); free(m->gradf); free(m->Ft);
     free(m->k1); free(m->k2);
@@ -312,6 +315,7 @@ ora_mesh *ora_mesh_new(int N, long n_nodes, const double *xyz, long n_elems,
     m->jac = malloc(sizeof(double) * E * m->np);
     m->met = malloc(sizeof(double) * E * m->np * 9);
     m->metf = malloc(sizeof(double) * E * 3 * m->nfl * 3);
+    m->rflux = malloc(sizeof(double) * E * 3 * m->nfl);
     m->bc = malloc(sizeof(int) * E * 6);
     m->nbr_e = malloc(sizeof(long) * E * 6);
     m->nbr_f = malloc(sizeof(int) * E * 6);
@@ -445,6 +449,21 @@ ora_mesh *ora_mesh_new(int N, long n_nodes, const double *xyz, long n_elems,
                         o[2] = dx[0][d1] * dx[1][d2] - dx[1][d1] * dx[0][d2];
                     }
                 }
+        /* radius at the d-flux points: reference coordinate xf[a] along d,
+         * solution-point coordinates along the other two axes */
+        for (int d = 0; d < 3; ++d)
+            for (int t2 = 0; t2 < N; ++t2)
+                for (int t1 = 0; t1 < N; ++t1)
+                    for (int a = 0; a <= N; ++a) {
+                        int idx[3];
+                        dir_ijk(d, a, t1, t2, idx);
+                        double r[3], x[3], dx[3][3];
+                        for (int t = 0; t < 3; ++t)
+                            r[t] = (t == d) ? m->xf[idx[t]] : m->xs[idx[t]];
+                        map_eval(nodes, r, x, dx);
+                        m->rflux[(e * 3 + d) * m->nfl + fl_index(m, a, t1, t2)]
+                            = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                    }
         /* curl form: W^(n)_i = x_l d x_m / d xi_i, (n, m, l) cyclic, sampled
          * on the lattice with solution points along i and flux points along
          * the other two axes */
@@ -591,9 +610,17 @@ static void stress(const ora_phys *ph, const prim_grad *pg, double tau[3][3])
             tau[a][b] = mu * (pg->du[a][b] + pg->du[b][a]) - (a == b ? 2.0 / 3.0 * mu * div : 0.0);
 }
 
-/* (F_v, G_v, H_v) . S, energy component u.tau.S - f.S */
+/* radiative diffusivity at radius r: the constant, or the quadratic in r
+ * of the solar case (Section 7.3) */
+static double kappa_r_at(const ora_phys *ph, double r)
+{
+    return ph->kappa_r + ph->kappa_r1 * r + ph->kappa_r2 * r * r;
+}
+
+/* (F_v, G_v, H_v) . S, energy component u.tau.S - f.S; kr = kappa_r at the
+ * point */
 static void viscous_flux(const ora_phys *ph, const double q[5], const double g[5][3], const double S[3],
-                         double out[5])
+                         double kr, double out[5])
 {
     prim_grad pg;
     primitive_gradients(ph, q, g, &pg);
@@ -610,7 +637,7 @@ static void viscous_flux(const ora_phys *ph, const double q[5], const double g[5
     out[2] = tS[1];
     out[3] = tS[2];
     out[4] = pg.u[0] * tS[0] + pg.u[1] * tS[1] + pg.u[2] * tS[2]
-           + ph->kappa * pg.rho * pg.T * dSS + ph->kappa_r * pg.rho * cp * dTS;
+           + ph->kappa * pg.rho * pg.T * dSS + kr * pg.rho * cp * dTS;
 }
 
 /* Rusanov common inviscid flux along S (outward from the L side) */
@@ -848,7 +875,7 @@ void ora_residual_sgs(const ora_mesh *m, const ora_phys *ph, const double *Q, co
                         }
                         const double *S = &m->metf[((e * 3 + d) * nfl + fi) * 3];
                         inviscid_flux(ph, q, S, fi_);
-                        viscous_flux(ph, q, g, S, fv);
+                        viscous_flux(ph, q, g, S, kappa_r_at(ph, m->rflux[(e * 3 + d) * nfl + fi]), fv);
                         for (int v = 0; v < 5; ++v) {
                             FT(d, e, v, fi) = fi_[v] - fv[v];
                             if (sgsf)
@@ -893,8 +920,8 @@ void ora_residual_sgs(const ora_mesh *m, const ora_phys *ph, const double *Q, co
                                 gR[v][c] = GF(d2, e2, v, c, fi2);
                         }
                         rusanov(ph, qL, qR, S, phi);
-                        viscous_flux(ph, qL, gL, S, fvL);
-                        viscous_flux(ph, qR, gR, S, fvR);
+                        viscous_flux(ph, qL, gL, S, kappa_r_at(ph, m->rflux[(e * 3 + d) * nfl + fi]), fvL);
+                        viscous_flux(ph, qR, gR, S, kappa_r_at(ph, m->rflux[((long)e2 * 3 + d2) * nfl + fi2]), fvR);
                         for (int v = 0; v < 5; ++v)
                             phi[v] -= 0.5 * (fvL[v] + fvR[v]);
                         if (sgsf)
@@ -922,7 +949,8 @@ void ora_residual_sgs(const ora_mesh *m, const ora_phys *ph, const double *Q, co
                             double cp = ph->gamma * ph->R_gas / (ph->gamma - 1.0);
                             double dSS = pg.dS[0] * S[0] + pg.dS[1] * S[1] + pg.dS[2] * S[2];
                             double dTS = pg.dT[0] * S[0] + pg.dT[1] * S[1] + pg.dT[2] * S[2];
-                            energy_v = ph->kappa * pg.rho * pg.T * dSS + ph->kappa_r * pg.rho * cp * dTS;
+                            energy_v = ph->kappa * pg.rho * pg.T * dSS
+                                     + kappa_r_at(ph, m->rflux[(e * 3 + d) * nfl + fi]) * pg.rho * cp * dTS;
                         }
                         phi[0] = 0.0;
                         for (int a = 0; a < 3; ++a)
@@ -931,7 +959,7 @@ void ora_residual_sgs(const ora_mesh *m, const ora_phys *ph, const double *Q, co
                     } else {
                         double fvL[5];
                         rusanov(ph, qL, ph->bc_state, S, phi);
-                        viscous_flux(ph, qL, gL, S, fvL);
+                        viscous_flux(ph, qL, gL, S, kappa_r_at(ph, m->rflux[(e * 3 + d) * nfl + fi]), fvL);
                         for (int v = 0; v < 5; ++v)
                             phi[v] -= 0.5 * fvL[v];
                     }

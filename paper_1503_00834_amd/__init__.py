@@ -53,7 +53,8 @@ class Hex20Desc(ctypes.Structure):
 class AfbDesc(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("n_rho", ctypes.c_double), ("poly_n", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("R_gas", ctypes.c_double), ("luminosity", ctypes.c_double),
-                ("kappa", ctypes.c_double), ("kappa_r", ctypes.c_double)]
+                ("kappa", ctypes.c_double), ("kappa_r", ctypes.c_double),
+                ("kappa_r1", ctypes.c_double), ("kappa_r2", ctypes.c_double)]
 
 
 class Physics(ctypes.Structure):
@@ -62,17 +63,19 @@ class Physics(ctypes.Structure):
                 ("kappa_r", ctypes.c_double), ("T_top", ctypes.c_double), ("F_bottom", ctypes.c_double),
                 ("bc_state", ctypes.c_double * 5), ("precision", ctypes.c_int32),
                 ("closure", ctypes.c_int32), ("flags", ctypes.c_int32), ("integrator", ctypes.c_int32),
-                ("closure_model", ctypes.c_void_p)]
+                ("closure_model", ctypes.c_void_p), ("kappa_r1", ctypes.c_double), ("kappa_r2", ctypes.c_double)]
 
 
 def physics(gamma=5.0 / 3.0, R_gas=1.0, GM=0.0, omega=0.0, nu=0.0, kappa=0.0, kappa_r=0.0, T_top=0.0,
             F_bottom=0.0, bc_state=(1.0, 0.0, 0.0, 0.0, 1.5), precision=CHORUS_FP64, closure=0, flags=0,
-            closure_model=None, integrator=CHORUS_SSPRK3):
+            closure_model=None, integrator=CHORUS_SSPRK3, kappa_r1=0.0, kappa_r2=0.0):
     """chorus_physics; closure_model: a ClosureModel (or a device address)
-    used when closure == CHORUS_CLOSURE_MLP."""
+    used when closure == CHORUS_CLOSURE_MLP; the radiative diffusivity at
+    radius r is kappa_r + kappa_r1 r + kappa_r2 r^2."""
     p = Physics()
     p.gamma, p.R_gas, p.GM, p.omega, p.nu = gamma, R_gas, GM, omega, nu
     p.kappa, p.kappa_r, p.T_top, p.F_bottom = kappa, kappa_r, T_top, F_bottom
+    p.kappa_r1, p.kappa_r2 = kappa_r1, kappa_r2
     for i in range(5):
         p.bc_state[i] = bc_state[i]
     p.precision, p.closure, p.flags, p.integrator = precision, closure, flags, integrator
@@ -210,12 +213,13 @@ class Mesh:
                                           _ptr(Q), _ptr(pars)), "chorus_init_polytrope")
         return Q, dict(chi_o=pars[0], c=pars[1], alpha=pars[2], GM=pars[3])
 
-    def init_afb(self, beta, n_rho, luminosity, kappa, kappa_r=0.0, poly_n=1.5, gamma=5.0 / 3.0, R_gas=1.0):
+    def init_afb(self, beta, n_rho, luminosity, kappa, kappa_r=0.0, poly_n=1.5, gamma=5.0 / 3.0, R_gas=1.0,
+                 kappa_r1=0.0, kappa_r2=0.0):
         """Almost-flux-balance background at rest (chorus_init_afb): (Q [5, n],
         pars with GM, T_top (outer-wall temperature) and F_bottom)."""
         Q = np.zeros((5, self.n_solpts))
         pars = np.zeros(6)
-        d = AfbDesc(beta, n_rho, poly_n, gamma, R_gas, luminosity, kappa, kappa_r)
+        d = AfbDesc(beta, n_rho, poly_n, gamma, R_gas, luminosity, kappa, kappa_r, kappa_r1, kappa_r2)
         _check(_lib.chorus_init_afb(self.handle, ctypes.byref(d), _ptr(Q), _ptr(pars)), "chorus_init_afb")
         return Q, dict(chi_o=pars[0], c=pars[1], alpha=pars[2], GM=pars[3], T_top=pars[4], F_bottom=pars[5])
 

@@ -86,6 +86,7 @@ static GeoM geom_of(const Mesh &m, const WsLayout &w, unsigned char *W) {
     g.gS0 = (const float *)(W + w.gS0);
     g.R0 = (const float *)(W + w.R0);
     g.Q0 = (const double *)(W + w.Q0);
+    g.rflux32 = (const float *)(b + m.layout.rflux32);
     return g;
 }
 
@@ -98,6 +99,7 @@ static Geo geo_of(const Mesh &m, unsigned char *W) {
     g.info = (const int32_t *)(b + m.layout.info);
     g.E = m.E;
     g.FF = (double *)(W + ws_layout(m).FF64);
+    g.rflux = (const double *)(b + m.layout.rflux);
     return g;
 }
 
@@ -161,7 +163,8 @@ static int check_mixed(const Mesh &m, const chorus_physics *p, const void *ws) {
     }
     const chorus_physics &b = m.bg_phys;
     if (b.gamma != p->gamma || b.R_gas != p->R_gas || b.GM != p->GM || b.omega != p->omega || b.nu != p->nu ||
-        b.kappa != p->kappa || b.kappa_r != p->kappa_r || b.T_top != p->T_top || b.F_bottom != p->F_bottom) {
+        b.kappa != p->kappa || b.kappa_r != p->kappa_r || b.kappa_r1 != p->kappa_r1 ||
+        b.kappa_r2 != p->kappa_r2 || b.T_top != p->T_top || b.F_bottom != p->F_bottom) {
         set_error("mixed precision: the physics must match the one passed to chorus_set_background");
         return CHORUS_ESTATE;
     }
@@ -181,7 +184,31 @@ static PhysParams params_of(const chorus_physics *p) {
     P.F_bottom = p->F_bottom;
     for (int v = 0; v < 5; ++v) P.bc_state[v] = p->bc_state[v];
     P.cp = p->gamma * p->R_gas / (p->gamma - 1.0);
+    P.kappa_r1 = p->kappa_r1;
+    P.kappa_r2 = p->kappa_r2;
     return P;
+}
+
+// the radiative diffusivity kappa_r(r) (a quadratic) must not be negative
+// at any flux-point radius of the mesh: checked at both ends of the radius
+// range and at the vertex when it lies inside
+static int check_kappa_r(const Mesh &m, const chorus_physics *p) {
+    if (!std::isfinite(p->kappa_r1) || !std::isfinite(p->kappa_r2)) {
+        set_error("physics: kappa_r1 and kappa_r2 must be finite");
+        return CHORUS_EINVAL;
+    }
+    if (p->kappa_r1 == 0.0 && p->kappa_r2 == 0.0) return CHORUS_OK;
+    const PhysParams P = params_of(p);
+    double lo = std::min(kappa_r_at(P, m.rflux_min), kappa_r_at(P, m.rflux_max));
+    if (p->kappa_r2 != 0.0) {
+        const double rv = -p->kappa_r1 / (2.0 * p->kappa_r2);
+        if (rv > m.rflux_min && rv < m.rflux_max) lo = std::min(lo, kappa_r_at(P, rv));
+    }
+    if (!(lo >= 0.0)) {
+        set_error("physics: kappa_r(r) = kappa_r + kappa_r1 r + kappa_r2 r^2 is negative on the mesh");
+        return CHORUS_EINVAL;
+    }
+    return CHORUS_OK;
 }
 
 static int check_ready(const Mesh *m) {
@@ -499,7 +526,7 @@ int chorus_init_polytrope(chorus_mesh_t mesh, double beta, double n_rho, double 
 
 // Almost-flux-balance background (Section 4.3): from the polytrope
 // (rho_a, p_a, T_a = p_a / (R rho_a)) the target entropy gradient
-//   Gamma(r) = -(L / (4 pi r^2) + rho_a c_p kappa_r dT_a/dr) / (rho_a T_a kappa),
+//   Gamma(r) = -(L / (4 pi r^2) + rho_a c_p kappa_r(r) dT_a/dr) / (rho_a T_a kappa),
 // the gradient at which the diffusive flux f = -kappa rho T grad S -
 // kappa_r rho c_p grad T (Section 2) carries the luminosity L outward (the
 // printed equation lacks this overall sign; with it L > 0 gives the
@@ -512,13 +539,14 @@ int chorus_init_polytrope(chorus_mesh_t mesh, double beta, double n_rho, double 
 // the ODE's own derivatives.
 namespace {
 struct AfbModel {
-    double c, alpha, n, gamma, R, cp, GM, L, kappa, kappa_r;
+    double c, alpha, n, gamma, R, cp, GM, L, kappa, kappa_r, kappa_r1, kappa_r2;
     double chi(double r) const { return c + alpha / r; }
     double gamma_target(double r) const {
         const double ch = chi(r);
         const double rho_a = std::pow(ch, n), T_a = ch / R;
         const double dTa = -alpha / (r * r) / R;
-        return -(L / (4.0 * M_PI * r * r) + rho_a * cp * kappa_r * dTa) / (rho_a * T_a * kappa);
+        const double kr = kappa_r + r * (kappa_r1 + r * kappa_r2);
+        return -(L / (4.0 * M_PI * r * r) + rho_a * cp * kr * dTa) / (rho_a * T_a * kappa);
     }
     // d(rho, p)/dr
     void rhs(double r, const double y[2], double dy[2]) const {
@@ -582,7 +610,8 @@ int chorus_init_afb(chorus_mesh_t mesh, const chorus_afb_desc *desc, double *Q_h
     }
     const chorus_afb_desc &d = *desc;
     if (!(d.beta > 0.0 && d.beta < 1.0) || !(d.poly_n > 0.0) || !(d.gamma > 1.0) || !(d.R_gas > 0.0) ||
-        !(d.kappa > 0.0) || d.kappa_r < 0.0 || d.luminosity < 0.0) {
+        !(d.kappa > 0.0) || d.kappa_r < 0.0 || d.luminosity < 0.0 || !std::isfinite(d.kappa_r1) ||
+        !std::isfinite(d.kappa_r2)) {
         set_error("afb: need 0 < beta < 1, poly_n > 0, gamma > 1, R_gas > 0, kappa > 0, kappa_r >= 0, L >= 0");
         return CHORUS_EINVAL;
     }
@@ -601,6 +630,8 @@ int chorus_init_afb(chorus_mesh_t mesh, const chorus_afb_desc *desc, double *Q_h
     M.L = d.luminosity;
     M.kappa = d.kappa;
     M.kappa_r = d.kappa_r;
+    M.kappa_r1 = d.kappa_r1;
+    M.kappa_r2 = d.kappa_r2;
     const double ri = d.beta / om, ro = 1.0 / om, rc = M.alpha / (1.0 - M.c);
     const int steps = 20000;
     std::vector<double> r_out, y_out, r_in, y_in;
@@ -640,6 +671,8 @@ int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const 
     int rc = check_ready(m);
     if (rc) return rc;
     rc = check_phys(phys);
+    if (rc) return rc;
+    rc = check_kappa_r(*m, phys);
     if (rc) return rc;
     if (!Q0_dev || !ws) {
         set_error("null device pointer");
@@ -695,6 +728,8 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
     int rc = check_ready(m);
     if (rc) return rc;
     rc = check_phys(phys);
+    if (rc) return rc;
+    rc = check_kappa_r(*m, phys);
     if (rc) return rc;
     if (!Q_dev || !dQdt_dev || !ws) {
         set_error("null device pointer");
@@ -774,6 +809,8 @@ int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev
     int rc = check_ready(m);
     if (rc) return rc;
     rc = check_phys(phys);
+    if (rc) return rc;
+    rc = check_kappa_r(*m, phys);
     if (rc) return rc;
     if (!Q_dev || !ws || n_steps < 0 || !std::isfinite(dt)) {
         set_error("rk_step: null pointer, negative step count or non-finite dt");

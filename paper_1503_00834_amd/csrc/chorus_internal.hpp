@@ -43,6 +43,8 @@ struct DeviceLayout {
     size_t solgeo32 = 0;   // f32 copy of solgeo (mixed mode)
     size_t fluxgeo32 = 0;  // f32 copy of fluxgeo (mixed mode)
     size_t xsol = 0;       // f64 [E][3][NP]: solution-point coordinates
+    size_t rflux = 0;      // f64 [E][3 d][NFL]: radius at the d-flux points
+    size_t rflux32 = 0;    // f32 copy of rflux (mixed mode)
     size_t total = 0;
 };
 
@@ -60,6 +62,8 @@ struct Mesh {
     std::vector<double> jac;        // [E][NP]
     std::vector<double> met;        // [E][NP][3][3]
     std::vector<double> metf;       // [E][3][NFL][3]  (interface ends made antisymmetric)
+    std::vector<double> rflux;      // [E][3][NFL] radius at the d-flux points
+    double rflux_min = 0.0, rflux_max = 0.0;
     int64_t n_faces = 0, n_wall_faces = 0;
     DeviceLayout layout;
     std::vector<unsigned char> image;  // host copy of the device image

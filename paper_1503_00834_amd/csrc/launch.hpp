@@ -18,7 +18,8 @@ struct Geo {
     const int32_t *info;    // [E][6]
     int64_t E;
     double *FF;             // [E][6][5][NF2] own-side common face flux along the outward
-                            // area vector (written by the gradient pass, read by the residual pass)
+                            // area vector (written by the gradient pass)
+    const double *rflux;    // [E][3][NFL] radius at the d-flux points
 };
 
 // stage combination of a Shu-Osher Runge-Kutta stage (mode 1):
@@ -115,6 +116,7 @@ struct GeoM {
     const float *gS0;        // [E][3][NFL] background entropy gradient along the flux metric
     const float *R0;         // [5][E][NP]  background residual
     const double *Q0;        // [5][E][NP]  background state
+    const float *rflux32;    // [E][3][NFL] radius at the d-flux points
 };
 
 // as StageArgs, on the perturbation P (mode 0 writes dQ/dt to Pout)

@@ -439,9 +439,22 @@ static int build_geometry(Mesh &m) {
                     for (int t = 0; t < 3; ++t) r[t] = (t == i) ? b.xs[idx[t]] : b.xf[idx[t]];
                     w_pts[i * NW + a0 + L * (a1 + L * a2)] = r;
                 }
-    Table ts, tw;
+    // d-flux points: flux coordinate along d, solution coordinates along the
+    // other two axes (index a + (N+1)(t1 + N t2))
+    std::vector<std::array<double, 3>> f_pts(3 * NFL);
+    for (int d = 0; d < 3; ++d)
+        for (int fl = 0; fl < NFL; ++fl) {
+            int a = fl % L, t1 = (fl / L) % N, t2 = fl / (L * N);
+            std::array<double, 3> r;
+            int t = 0;
+            for (int ax = 0; ax < 3; ++ax) r[ax] = (ax == d) ? b.xf[a] : b.xs[(t++ == 0) ? t1 : t2];
+            f_pts[d * NFL + fl] = r;
+        }
+    Table ts, tw, tf;
     tabulate(sol_pts, ts);
     tabulate(w_pts, tw);
+    tabulate(f_pts, tf);
+    m.rflux.assign(E * 3 * NFL, 0.0);
     m.xsol.assign(E * NP * 3, 0.0);
     m.jac.assign(E * NP, 0.0);
     m.met.assign(E * NP * 9, 0.0);
@@ -475,6 +488,12 @@ static int build_geometry(Mesh &m) {
                 o[1] = J[2][d1] * J[0][d2] - J[0][d1] * J[2][d2];
                 o[2] = J[0][d1] * J[1][d2] - J[1][d1] * J[0][d2];
             }
+        }
+        for (int q = 0; q < 3 * NFL; ++q) {
+            double x[3] = {0, 0, 0};
+            for (int n = 0; n < 20; ++n)
+                for (int c = 0; c < 3; ++c) x[c] += tf.val[q * 20 + n] * X[n][c];
+            m.rflux[e * 3 * NFL + q] = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
         }
         // W[n][i] on lattice i
         std::vector<double> W(9 * NW, 0.0);
@@ -524,6 +543,11 @@ static int build_geometry(Mesh &m) {
         set_error("non-positive Jacobian at a solution point");
         return CHORUS_EMESH;
     }
+    m.rflux_min = m.rflux_max = m.rflux.empty() ? 0.0 : m.rflux[0];
+    for (double r : m.rflux) {
+        m.rflux_min = std::min(m.rflux_min, r);
+        m.rflux_max = std::max(m.rflux_max, r);
+    }
     // antisymmetric interface area vectors
     for (int64_t e = 0; e < E; ++e)
         for (int f = 0; f < 6; ++f) {
@@ -563,6 +587,8 @@ static void build_image(Mesh &m) {
     L.solgeo32 = off;  off = align256(off + sizeof(float) * E * 13 * NP);
     L.fluxgeo32 = off; off = align256(off + sizeof(float) * E * 9 * NFL);
     L.xsol = off;      off = align256(off + sizeof(double) * E * 3 * NP);
+    L.rflux = off;     off = align256(off + sizeof(double) * E * 3 * NFL);
+    L.rflux32 = off;   off = align256(off + sizeof(float) * E * 3 * NFL);
     L.total = off;
     m.image.assign(L.total, 0);
     double *sg = (double *)(m.image.data() + L.solgeo);
@@ -601,6 +627,12 @@ static void build_image(Mesh &m) {
     }
     for (int64_t t = 0; t < E * 13 * NP; ++t) sg32[t] = (float)sg[t];
     for (int64_t t = 0; t < E * 9 * NFL; ++t) fg32[t] = (float)fg[t];
+    double *rf = (double *)(m.image.data() + L.rflux);
+    float *rf32 = (float *)(m.image.data() + L.rflux32);
+    for (int64_t t = 0; t < E * 3 * NFL; ++t) {
+        rf[t] = m.rflux[t];
+        rf32[t] = (float)m.rflux[t];
+    }
 }
 
 int finish_mesh(Mesh &m) {

@@ -15,7 +15,13 @@ struct PhysParams {
     double gamma, R_gas, GM, omega, nu, kappa, kappa_r, T_top, F_bottom;
     double bc_state[5];
     double cp;  // gamma R / (gamma - 1)
+    double kappa_r1, kappa_r2;  // kappa_r(r) = kappa_r + kappa_r1 r + kappa_r2 r^2
 };
+
+// radiative diffusivity at radius r
+__host__ __device__ __forceinline__ double kappa_r_at(const PhysParams &P, double r) {
+    return P.kappa_r + r * (P.kappa_r1 + r * P.kappa_r2);
+}
 
 template <typename T>
 __device__ __forceinline__ T pressure_of(const T q[5], T gm1) {
@@ -67,10 +73,11 @@ __device__ __forceinline__ void prim_grad(const T q[5], const T g[5][3], const P
 }
 
 // viscous flux along S: (0, tau.S, u.tau.S - f.S), tau = mu (grad u + grad u^T
-// - 2/3 div u I), mu = rho nu, -f = kappa rho T grad S + kappa_r rho c_p grad T
+// - 2/3 div u I), mu = rho nu, -f = kappa rho T grad S + kr rho c_p grad T
+// (kr: the radiative diffusivity at the point)
 template <typename T>
 __device__ __forceinline__ void flux_viscous(const T q[5], const T g[5][3], const T S[3],
-                                             const PhysParams &P, T out[5]) {
+                                             const PhysParams &P, T kr, T out[5]) {
     PrimGrad<T> pg;
     prim_grad(q, g, P, pg);
     const T mu = pg.rho * T(P.nu);
@@ -88,7 +95,7 @@ __device__ __forceinline__ void flux_viscous(const T q[5], const T g[5][3], cons
     out[2] = tS[1];
     out[3] = tS[2];
     out[4] = pg.u[0] * tS[0] + pg.u[1] * tS[1] + pg.u[2] * tS[2] +
-             T(P.kappa) * pg.rho * pg.Tmp * dSS + T(P.kappa_r) * pg.rho * T(P.cp) * dTS;
+             T(P.kappa) * pg.rho * pg.Tmp * dSS + kr * pg.rho * T(P.cp) * dTS;
 }
 
 // Rusanov common flux along S (outward from the qL side), wave speed
@@ -131,9 +138,10 @@ __device__ __forceinline__ void wall_state(const T q[5], const T S[3], bool oute
 // total wall flux along the outward S: inviscid (0, p S, 0) with the interior
 // p (V_r = 0); viscous: normal traction only (stress free), energy f.S =
 // F_bottom |S| at the inner wall, interior diffusive flux at the outer wall
+// (kr: the radiative diffusivity at the point)
 template <typename T>
 __device__ __forceinline__ void flux_wall(const T q[5], const T g[5][3], const T S[3], bool outer,
-                                          const PhysParams &P, T out[5]) {
+                                          const PhysParams &P, T kr, T out[5]) {
     PrimGrad<T> pg;
     prim_grad(q, g, P, pg);
     const T mu = pg.rho * T(P.nu);
@@ -148,7 +156,7 @@ __device__ __forceinline__ void flux_wall(const T q[5], const T g[5][3], const T
     if (outer) {
         const T dSS = pg.dS[0] * S[0] + pg.dS[1] * S[1] + pg.dS[2] * S[2];
         const T dTS = pg.dT[0] * S[0] + pg.dT[1] * S[1] + pg.dT[2] * S[2];
-        ev = T(P.kappa) * pg.rho * pg.Tmp * dSS + T(P.kappa_r) * pg.rho * T(P.cp) * dTS;
+        ev = T(P.kappa) * pg.rho * pg.Tmp * dSS + kr * pg.rho * T(P.cp) * dTS;
     } else {
         ev = T(P.F_bottom) * sqrt(A2);
     }

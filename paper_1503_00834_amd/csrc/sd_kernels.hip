@@ -245,8 +245,9 @@ __global__ __launch_bounds__(NT) void k_grad(Ops<N> opa, Geo G, PhysParams P, co
         const int bc = (inf >> 6) - 1;
         double S[3], fv[5], phi[5];
         for (int c = 0; c < 3; ++c) S[c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+        const double kr = kappa_r_at(P, G.rflux[(e * 3 + d) * NFL + fl]);
         if (nb >= 0) {
-            flux_viscous(q, g, S, P, fv);
+            flux_viscous(q, g, S, P, kr, fv);
             if constexpr (CL) {
                 // the own-side subgrid flux enters the trace with the sign of -F_v
                 for (int v = 0; v < 5; ++v)
@@ -269,9 +270,9 @@ __global__ __launch_bounds__(NT) void k_grad(Ops<N> opa, Geo G, PhysParams P, co
             flux_rusanov(q, qn, S, P, phi);
             for (int v = 0; v < 5; ++v) phi[v] -= 0.5 * fv[v];
         } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
-            flux_wall(q, g, S, bc == CHORUS_BC_OUTER, P, phi);
+            flux_wall(q, g, S, bc == CHORUS_BC_OUTER, P, kr, phi);
         } else {
-            flux_viscous(q, g, S, P, fv);
+            flux_viscous(q, g, S, P, kr, fv);
             flux_rusanov(q, P.bc_state, S, P, phi);
             for (int v = 0; v < 5; ++v) phi[v] -= 0.5 * fv[v];
         }
@@ -383,7 +384,9 @@ __device__ __forceinline__ double line_interp(const Ops<N> &op, const T *fld, in
 // solution, gradients, network -> C.tau); PART 2: the flux pass with the
 // subgrid flux of a preceding PART-1 launch read from C.tau (the network's
 // registers stay out of the flux pass)
-template <int N, int EPB, int NT, int PART>
+// RAD: radiative diffusivity varying with radius (radius of each flux point
+// read with its geometry), else the constant P.kappa_r
+template <int N, int EPB, int NT, int PART, bool RAD>
 __global__ __launch_bounds__(NT) void k_flux64(Ops<N> opa, Geo G, PhysParams P, const double *__restrict__ Q,
                                                const double *__restrict__ TQ, double *__restrict__ TV,
                                                StageArgs S_, ClosureArgs C) {
@@ -415,7 +418,8 @@ __global__ __launch_bounds__(NT) void k_flux64(Ops<N> opa, Geo G, PhysParams P, 
         for (int v = 0; v < 5; ++v) qv[k][v] = Q[((int64_t)v * E + e) * NP + p];
         for (int t = 0; t < 9; ++t) Gm[k][t] = G.solgeo[(e * 13 + t) * NP + p];
     }
-    double nq[Sh::IT_FACE][5], Sf[Sh::IT_FACE][3];
+    // radiative diffusivity at the face and interior flux points
+    double nq[Sh::IT_FACE][5], Sf[Sh::IT_FACE][3], krf[Sh::IT_FACE];
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
         const int it = threadIdx.x + k * NT;
@@ -425,8 +429,9 @@ __global__ __launch_bounds__(NT) void k_flux64(Ops<N> opa, Geo G, PhysParams P, 
         const int d = f >> 1, fl = ((f & 1) ? N : 0) + (N + 1) * pp;
         const double sg = (f & 1) ? 1.0 : -1.0;
         for (int c = 0; c < 3; ++c) Sf[k][c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+        krf[k] = RAD ? G.rflux[(e * 3 + d) * NFL + fl] : P.kappa_r;
     }
-    double Si[3][Sh::IT_INTD][3];
+    double Si[3][Sh::IT_INTD][3], kri[3][Sh::IT_INTD];
     if constexpr (PART != 1) {
 #pragma unroll
         for (int d = 0; d < 3; ++d)
@@ -437,6 +442,7 @@ __global__ __launch_bounds__(NT) void k_flux64(Ops<N> opa, Geo G, PhysParams P, 
                 const int fl = 1 + q % (N - 1) + (N + 1) * (q / (N - 1));
                 const int64_t e = (it < EPB * NINTD && e0 + el < E) ? e0 + el : 0;
                 for (int c = 0; c < 3; ++c) Si[d][k][c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+                kri[d][k] = RAD ? G.rflux[(e * 3 + d) * NFL + fl] : P.kappa_r;
             }
     }
     if constexpr (PART == 2) {
@@ -534,9 +540,10 @@ __global__ __launch_bounds__(NT) void k_flux64(Ops<N> opa, Geo G, PhysParams P, 
             for (int c = 0; c < 3; ++c) g[v][c] = line_interp<N>(op, sgr[el][v * 3 + c], m, base, st);
         const int32_t nb = lk[el][f];
         const int bc = (inf[el][f] >> 6) - 1;
+        const double kr = RAD ? kappa_r_at(P, krf[k]) : krf[k];
         double fv[5];
         if (nb >= 0) {
-            flux_viscous(fo[k], g, Sf[k], P, fv);
+            flux_viscous(fo[k], g, Sf[k], P, kr, fv);
             if constexpr (CL) {
                 // the own-side subgrid flux enters the trace with the sign of -F_v
                 for (int v = 0; v < 5; ++v)
@@ -547,9 +554,9 @@ __global__ __launch_bounds__(NT) void k_flux64(Ops<N> opa, Geo G, PhysParams P, 
             flux_rusanov(fo[k], nq[k], Sf[k], P, ffc[k]);
             for (int v = 0; v < 5; ++v) ffc[k][v] -= 0.5 * fv[v];
         } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
-            flux_wall(fo[k], g, Sf[k], bc == CHORUS_BC_OUTER, P, ffc[k]);
+            flux_wall(fo[k], g, Sf[k], bc == CHORUS_BC_OUTER, P, kr, ffc[k]);
         } else {
-            flux_viscous(fo[k], g, Sf[k], P, fv);
+            flux_viscous(fo[k], g, Sf[k], P, kr, fv);
             flux_rusanov(fo[k], P.bc_state, Sf[k], P, ffc[k]);
             for (int v = 0; v < 5; ++v) ffc[k][v] -= 0.5 * fv[v];
         }
@@ -576,7 +583,7 @@ __global__ __launch_bounds__(NT) void k_flux64(Ops<N> opa, Geo G, PhysParams P, 
                 for (int c = 0; c < 3; ++c) g[v][c] = line_interp<N>(op, sgr[el][v * 3 + c], m, base, st);
             }
             flux_inviscid(qf, Si[d][k], gm1, fi);
-            flux_viscous(qf, g, Si[d][k], P, fv);
+            flux_viscous(qf, g, Si[d][k], P, RAD ? kappa_r_at(P, kri[d][k]) : kri[d][k], fv);
             double ts[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
             if constexpr (CL) {
                 for (int v = 0; v < 5; ++v)
@@ -979,21 +986,29 @@ static hipError_t launch_flux64_t(const Mesh &m, const Geo &G, const PhysParams 
                                   hipStream_t s) {
     constexpr int EPB = Cfg64<N>::EPB, NT = Cfg64<N>::NT;
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
+    const bool rad = P.kappa_r1 != 0.0 || P.kappa_r2 != 0.0;
     if (C.model) {
         // the network's pass, then the flux pass reading its subgrid flux
         if constexpr (N == 3) {
-            hipLaunchKernelGGL((k_flux64<N, EPB, NT, 1>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, P, Q,
-                               TQ, TV, sa, C);
+            hipLaunchKernelGGL((k_flux64<N, EPB, NT, 1, false>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G,
+                               P, Q, TQ, TV, sa, C);
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_flux64<N, EPB, NT, 2>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, P, Q,
-                               TQ, TV, sa, C);
+            if (rad)
+                hipLaunchKernelGGL((k_flux64<N, EPB, NT, 2, true>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis),
+                                   G, P, Q, TQ, TV, sa, C);
+            else
+                hipLaunchKernelGGL((k_flux64<N, EPB, NT, 2, false>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis),
+                                   G, P, Q, TQ, TV, sa, C);
         } else {
             return hipErrorInvalidValue;
         }
+    } else if (rad) {
+        hipLaunchKernelGGL((k_flux64<N, EPB, NT, 0, true>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, P, Q,
+                           TQ, TV, sa, C);
     } else {
-        hipLaunchKernelGGL((k_flux64<N, EPB, NT, 0>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, P, Q, TQ,
-                           TV, sa, C);
+        hipLaunchKernelGGL((k_flux64<N, EPB, NT, 0, false>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, P, Q,
+                           TQ, TV, sa, C);
     }
     return hipGetLastError();
 }

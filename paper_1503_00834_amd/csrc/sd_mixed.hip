@@ -47,6 +47,7 @@ struct GeoF {
     const int32_t *link;   // [E][6]
     const int32_t *info;   // [E][6]
     int64_t E;
+    const float *rflux;    // [E][3][NFL] radius at the d-flux points
 };
 
 struct MixedBufs {
@@ -58,6 +59,7 @@ struct MixedBufs {
 
 struct PhysF {
     float gm1, gam, R, cp, GM, om, nu, kappa, kappa_r, RT_top;  // RT_top <= 0: off
+    float kappa_r1, kappa_r2;                                    // kappa_r(r) = kappa_r + kappa_r1 r + kappa_r2 r^2
 };
 
 __device__ __forceinline__ PhysF physf_of(const PhysParams &P) {
@@ -72,7 +74,20 @@ __device__ __forceinline__ PhysF physf_of(const PhysParams &P) {
     f.kappa = (float)P.kappa;
     f.kappa_r = (float)P.kappa_r;
     f.RT_top = (P.T_top > 0.0) ? (float)(P.R_gas * P.T_top) : -1.0f;
+    f.kappa_r1 = (float)P.kappa_r1;
+    f.kappa_r2 = (float)P.kappa_r2;
     return f;
+}
+
+// radiative-diffusivity variants of the flux pass: none, constant, radial
+enum { KR_NONE = 0, KR_CONST = 1, KR_RADIAL = 2 };
+
+// radiative diffusivity at a flux point from the value read with its
+// geometry (the radius for KR_RADIAL)
+template <int KR>
+__device__ __forceinline__ float kr_of(const PhysF &F, float loaded) {
+    if constexpr (KR == KR_RADIAL) return F.kappa_r + loaded * (F.kappa_r1 + loaded * F.kappa_r2);
+    else return F.kappa_r;
 }
 
 // LDS field slots at solution points: perturbation (5), background (2)
@@ -108,9 +123,10 @@ __device__ __forceinline__ void dflux_inviscid(const PtState &s, const float S[3
 // (F_v(Q) - F_v(Q0)) . S given gS0S = grad S0 . S.  outer_wall / inner_wall
 // select the wall forms (normal traction only; energy as interior at the
 // outer wall, none at the inner wall where the prescribed flux is in R0).
-template <bool KR = true>
+// (kr: the radiative diffusivity at the point, used unless KR == KR_NONE)
+template <int KR>
 __device__ __forceinline__ void dflux_viscous(const PtState &s, const float S[3], float gS0S, const PhysF &F,
-                                              int wall, float out[5]) {
+                                              float kr, int wall, float out[5]) {
     const float rho = s.r0 + s.rp, inv = rcp(rho);
     const float u[3] = {s.m[0] * inv, s.m[1] * inv, s.m[2] * inv};
     float grho[3], du[3][3];
@@ -164,9 +180,9 @@ __device__ __forceinline__ void dflux_viscous(const PtState &s, const float S[3]
     const float eS = F.kappa * (pp * gS0S + p * F.cp * dgS) * iR;
     // rho c_p grad T . S difference: c_p/R (grad p' . S - [p grad rho' . S / rho + grad rho0 . S (p/rho - p0/rho0)])
     float eT = 0.0f;
-    if (KR) {
+    if constexpr (KR != KR_NONE) {
         const float dpr = (pp * s.r0 - p0 * s.rp) * inv * ir0;
-        eT = F.kappa_r * F.cp * iR * (gpS - (p * grpS * inv + gr0S * dpr));
+        eT = kr * F.cp * iR * (gpS - (p * grpS * inv + gr0S * dpr));
     }
     const float work = (wall == 0) ? (u[0] * tS[0] + u[1] * tS[1] + u[2] * tS[2]) : 0.0f;
     out[4] = work + eS + eT;
@@ -426,10 +442,10 @@ __device__ __forceinline__ void state_at(const OpsF<N> &op, const MixedLds<N> &l
 // jump db) minus half of the own viscous flux fv (the neighbour's half is
 // added by the residual pass from the neighbour's viscous trace).  Wall
 // face: the complete wall flux (inviscid (0, p' So, 0); viscous wall form).
-template <bool KR = true>
+template <int KR>
 __device__ __forceinline__ void face_flux_own(const PtState &s, const float nq[5], const float db[2], bool interior,
-                                              bool outer, const float So[3], float gS0S, const float fv_in[5],
-                                              const PhysF &F, float phi[5]) {
+                                              bool outer, const float So[3], float gS0S, float kr,
+                                              const float fv_in[5], const PhysF &F, float phi[5]) {
     if (interior) {
         PtState r = s;
         r.rp = nq[0];
@@ -471,7 +487,7 @@ __device__ __forceinline__ void face_flux_own(const PtState &s, const float nq[5
         const float mm = s.m[0] * s.m[0] + s.m[1] * s.m[1] + s.m[2] * s.m[2];
         const float pp = F.gm1 * (s.Ep - 0.5f * mm * rcp(s.r0 + s.rp));
         float fv[5];
-        dflux_viscous<KR>(s, So, gS0S, F, outer ? 2 : 1, fv);
+        dflux_viscous<KR>(s, So, gS0S, F, kr, outer ? 2 : 1, fv);
         phi[0] = 0.0f;
         for (int a = 0; a < 3; ++a) phi[1 + a] = pp * So[a] - fv[1 + a];
         phi[4] = -fv[4];
@@ -531,7 +547,7 @@ using MixedStage = MixedStageArgs;
 // halves at interior interfaces, enters the stage combination here (FP64):
 // Pout = c0 A + c1 (P + c2 Rp) (and Tout likewise), or Pout = Rp in
 // residual mode; the lift pass adds the missing part in place.
-template <int N, int EPB, int NT, int MINW, bool KR>
+template <int N, int EPB, int NT, int MINW, int KR>
 __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, MixedBufs B, PhysParams P,
                                                          const double *__restrict__ Pq, const float *__restrict__ TQ,
                                                          float *__restrict__ TV, MixedStage S_) {
@@ -544,7 +560,7 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
     ops_to_lds(opa, op);
     // every global input of the element block, issued before the first wait
     // (unpredicated, clamped indices: see Prologue)
-    float Sf[Sh::IT_FACE][3], gSf[Sh::IT_FACE];
+    float Sf[Sh::IT_FACE][3], gSf[Sh::IT_FACE], krf[Sh::IT_FACE];
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
         const int it = threadIdx.x + k * NT;
@@ -554,8 +570,9 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
         const float sg = (f & 1) ? 1.0f : -1.0f;
         for (int c = 0; c < 3; ++c) Sf[k][c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
         gSf[k] = sg * B.gS0[(e * 3 + d) * NFL + fl];
+        krf[k] = (KR == KR_RADIAL) ? G.rflux[(e * 3 + d) * NFL + fl] : 0.0f;
     }
-    float Si[3][Sh::IT_INTD][3], gSi[3][Sh::IT_INTD];
+    float Si[3][Sh::IT_INTD][3], gSi[3][Sh::IT_INTD], kri[3][Sh::IT_INTD];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -566,6 +583,7 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
             const int64_t e = (it < EPB * NINTD && e0 + el < G.E) ? e0 + el : 0;
             for (int c = 0; c < 3; ++c) Si[d][k][c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
             gSi[d][k] = B.gS0[(e * 3 + d) * NFL + fl];
+            kri[d][k] = (KR == KR_RADIAL) ? G.rflux[(e * 3 + d) * NFL + fl] : 0.0f;
         }
     Prologue<N, EPB, NT> R;
     prologue_load<N, EPB, NT>(Pq, B, G, TQ, e0, R);
@@ -592,13 +610,14 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
         float fv[5];
         PtState st;
         state_at<N>(op, L[el], m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), st, fo[k]);
+        const float kr = kr_of<KR>(F, krf[k]);
         if (nb >= 0) {
-            dflux_viscous<KR>(st, Sf[k], gSf[k], F, 0, fv);
+            dflux_viscous<KR>(st, Sf[k], gSf[k], F, kr, 0, fv);
             const int64_t slot = mailbox_slot<N>(nb, inf, pp);
             for (int v = 0; v < 5; ++v) TV[slot + v * NF2] = fv[v];
         }
-        face_flux_own<KR>(st, R.nq[k], R.db[k], nb >= 0, ((inf >> 6) - 1) == CHORUS_BC_OUTER, Sf[k], gSf[k], fv, F,
-                      ffc[k]);
+        face_flux_own<KR>(st, R.nq[k], R.db[k], nb >= 0, ((inf >> 6) - 1) == CHORUS_BC_OUTER, Sf[k], gSf[k], kr, fv,
+                          F, ffc[k]);
     }
     // per direction d: transformed flux at the d-flux points, then its
     // derivative added to the divergence at the solution points
@@ -620,7 +639,7 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
             state_at<N>(op, l, m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), s);
             float fi[5], fv[5];
             dflux_inviscid(s, Si[d][k], F, fi);
-            dflux_viscous<KR>(s, Si[d][k], gSi[d][k], F, 0, fv);
+            dflux_viscous<KR>(s, Si[d][k], gSi[d][k], F, kr_of<KR>(F, kri[d][k]), 0, fv);
             const int fl = m + (N + 1) * tt;
             for (int v = 0; v < 5; ++v) l.u.ft[v][fl] = fi[v] - fv[v];
         }
@@ -898,6 +917,7 @@ static GeoF geof_of(const GeoM &g) {
     o.link = g.link;
     o.info = g.info;
     o.E = g.E;
+    o.rflux = g.rflux32;
     return o;
 }
 static MixedBufs bufs_of(const GeoM &g) {
@@ -923,11 +943,14 @@ static hipError_t flux_mixed_t(const Mesh &m, const GeoM &g, const PhysParams &P
     constexpr int EPB = CfgF<N>::EPB, NT = CfgF<N>::NT, MINW = CfgF<N>::MINW;
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
     const MixedStage st = a;
-    if (P.kappa_r != 0.0)
-        hipLaunchKernelGGL((k_flux_mixed<N, EPB, NT, MINW, true>), dim3(nb), dim3(NT), 0, s,
+    if (P.kappa_r1 != 0.0 || P.kappa_r2 != 0.0)
+        hipLaunchKernelGGL((k_flux_mixed<N, EPB, NT, MINW, KR_RADIAL>), dim3(nb), dim3(NT), 0, s,
+                           make_ops_t<float, N>(m.basis), geof_of(g), bufs_of(g), P, Pq, TQ, TV, st);
+    else if (P.kappa_r != 0.0)
+        hipLaunchKernelGGL((k_flux_mixed<N, EPB, NT, MINW, KR_CONST>), dim3(nb), dim3(NT), 0, s,
                            make_ops_t<float, N>(m.basis), geof_of(g), bufs_of(g), P, Pq, TQ, TV, st);
     else
-        hipLaunchKernelGGL((k_flux_mixed<N, EPB, NT, MINW, false>), dim3(nb), dim3(NT), 0, s,
+        hipLaunchKernelGGL((k_flux_mixed<N, EPB, NT, MINW, KR_NONE>), dim3(nb), dim3(NT), 0, s,
                            make_ops_t<float, N>(m.basis), geof_of(g), bufs_of(g), P, Pq, TQ, TV, st);
     return hipGetLastError();
 }

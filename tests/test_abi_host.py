@@ -130,24 +130,26 @@ def test_closure_host_errors():
     h = (ctypes.c_double * 4)(1e-3, 0.9, 0.999, 1e-8)
     assert L.chorus_closure_train(None, None, 10, None, 1, 1, None, None, None, 0, h, None, None, 0,
                                   None) == -1
-    assert ctypes.sizeof(ch.Physics) == 14 * 8 + 4 * 4 + 8
+    assert ctypes.sizeof(ch.Physics) == 16 * 8 + 4 * 4 + 8
 
 
-@pytest.mark.parametrize("L,kr", [(0.0, 0.0), (3e-3, 1e-5), (1e-2, 0.0)])
-def test_afb_background_matches_oracle(L, kr):
+@pytest.mark.parametrize("L,kr,kr1,kr2", [(0.0, 0.0, 0.0, 0.0), (3e-3, 1e-5, 0.0, 0.0), (1e-2, 0.0, 0.0, 0.0),
+                                           (3e-3, 1e-5, 2e-5, -3e-6)])
+def test_afb_background_matches_oracle(L, kr, kr1, kr2):
     """chorus_init_afb (RK4 table + Hermite) against the oracle's DOP853
-    solve at every solution point of a small shell."""
+    solve at every solution point of a small shell (constant and
+    radius-dependent radiative diffusivity)."""
     import paper_1503_00834_amd as ch
     from oracle import afb
     m = ch.chorus_mesh_create(3, 2, 3, 7 / 3, 10 / 3)
-    Q, pars = m.init_afb(0.7, 1.0, L, 1e-3, kappa_r=kr)
+    Q, pars = m.init_afb(0.7, 1.0, L, 1e-3, kappa_r=kr, kappa_r1=kr1, kappa_r2=kr2)
     xyz, _ = m.solpts()
     r = np.sqrt((xyz ** 2).sum(0))
-    rho, p = afb.background(r, 0.7, 1.0, L, 1e-3, kr)
+    rho, p = afb.background(r, 0.7, 1.0, L, 1e-3, kr, kappa_r1=kr1, kappa_r2=kr2)
     np.testing.assert_allclose(Q[0], rho, rtol=1e-10)
     np.testing.assert_allclose(Q[4], p / (2.0 / 3.0), rtol=1e-10)
     assert np.all(Q[1:4] == 0.0)
     ro = 10 / 3
-    rho_o, p_o = afb.background(np.array([ro]), 0.7, 1.0, L, 1e-3, kr)
+    rho_o, p_o = afb.background(np.array([ro]), 0.7, 1.0, L, 1e-3, kr, kappa_r1=kr1, kappa_r2=kr2)
     assert abs(pars["T_top"] - p_o[0] / rho_o[0]) < 1e-10
     assert abs(pars["F_bottom"] - L / (4 * np.pi * (7 / 3) ** 2)) < 1e-15

@@ -74,6 +74,37 @@ def test_mixed_residual_vs_oracle(ch, oracle_mod, torch_dev, N):
         assert err <= tol, (v, err, tol)
 
 
+@pytest.mark.parametrize("N", [3, 4])
+def test_mixed_residual_radial_kappa_r(ch, oracle_mod, torch_dev, N):
+    """The mixed path with a radius-dependent radiative diffusivity (solar
+    case, Section 7.3), to the tolerance of the constant case."""
+    torch = torch_dev
+    m, om, Q0, Q, pars = _case(oracle_mod, N)
+    kw = dict(GM=pars["GM"], omega=1.0, nu=1e-3, kappa=1e-3, kappa_r=1e-4, T_top=pars["chi_o"], F_bottom=0.01,
+              kappa_r1=3e-4, kappa_r2=1e-4)
+    phys = ch.physics(precision=ch.CHORUS_MIXED, **kw)
+    cm = ch.mesh_from_arrays(m, N).upload()
+    ws = cm.workspace(phys)
+    ch.chorus_set_background(cm, phys, _dev(torch, Q0), ws)
+    R = torch.empty_like(_dev(torch, Q))
+    ch.chorus_sd_residual(cm, phys, _dev(torch, Q), R, ws)
+    torch.cuda.synchronize()
+    Rg = R.cpu().numpy()
+    op = oracle_mod.phys(**kw)
+    Rr = om.residual(op, Q).reshape(5, -1)
+    Rb = om.residual(op, Q0).reshape(5, -1)
+    for v in range(5):
+        err = np.linalg.norm(Rg[v] - Rr[v])
+        tol = 2e-5 * np.linalg.norm(Rr[v] - Rb[v]) + 1e-6 * np.linalg.norm(Rb[v])
+        assert err <= tol, (v, err, tol)
+    # the radial terms matter at this tolerance
+    kw0 = dict(kw, kappa_r1=0.0, kappa_r2=0.0)
+    Rr0 = om.residual(oracle_mod.phys(**kw0), Q).reshape(5, -1)
+    Rb0 = om.residual(oracle_mod.phys(**kw0), Q0).reshape(5, -1)
+    d = np.linalg.norm((Rr[4] - Rb[4]) - (Rr0[4] - Rb0[4]))
+    assert d > 10 * (2e-5 * np.linalg.norm(Rr[4] - Rb[4]) + 1e-6 * np.linalg.norm(Rb[4])), d
+
+
 def test_mixed_background_is_steady_part(ch, oracle_mod, torch_dev):
     """At Q = Q0 the mixed residual is the background residual plus the
     (FP32) viscous residual of Q0, i.e. the FP64 residual of Q0 to FP32

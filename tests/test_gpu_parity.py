@@ -61,7 +61,7 @@ def assert_parity(R_gpu, R_ref, R_pert, what, rel=1e-12):
 def ora_phys(oracle_mod, p):
     return oracle_mod.phys(gamma=p.gamma, R_gas=p.R_gas, GM=p.GM, omega=p.omega, nu=p.nu, kappa=p.kappa,
                            kappa_r=p.kappa_r, T_top=p.T_top, F_bottom=p.F_bottom,
-                           bc_state=tuple(p.bc_state))
+                           bc_state=tuple(p.bc_state), kappa_r1=p.kappa_r1, kappa_r2=p.kappa_r2)
 
 
 def gpu_residual(ch, torch, cm, phys, Q):
@@ -95,6 +95,35 @@ def test_residual_parity_shell(ch, oracle_mod, torch_dev, N):
     op = ora_phys(oracle_mod, phys)
     Rp = perturbed_oracle(oracle_mod, m, N).residual(op, ulp_perturb(Q))
     assert_parity(R, om.residual(op, Q), Rp, "shell N=%d" % N)
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_residual_parity_radial_kappa_r(ch, oracle_mod, torch_dev, N):
+    """Radiative diffusivity varying with radius (solar case, Section 7.3):
+    kappa_r(r) = kappa_r + kappa_r1 r + kappa_r2 r^2 at each flux point's
+    radius; the radial terms change the residual by far more than the
+    tolerance."""
+    m, om, Q, phys = shell_case(oracle_mod, ch, 3, 2, N)
+    phys.kappa_r1, phys.kappa_r2 = 3e-4, 1e-4
+    cm = ch.mesh_from_arrays(m, N).upload()
+    R = gpu_residual(ch, torch_dev, cm, phys, Q)
+    op = ora_phys(oracle_mod, phys)
+    Rr = om.residual(op, Q)
+    Rp = perturbed_oracle(oracle_mod, m, N).residual(op, ulp_perturb(Q))
+    assert_parity(R, Rr, Rp, "radial kappa_r N=%d" % N)
+    phys.kappa_r1, phys.kappa_r2 = 0.0, 0.0
+    R0 = om.residual(ora_phys(oracle_mod, phys), Q).reshape(5, -1)
+    assert np.linalg.norm(Rr.reshape(5, -1)[4] - R0[4]) > 1e-6 * np.linalg.norm(R0[4])
+
+
+def test_negative_radial_kappa_r_rejected(ch, oracle_mod, torch_dev):
+    """kappa_r(r) negative somewhere on the mesh: CHORUS_EINVAL, nothing run."""
+    m, om, Q, phys = shell_case(oracle_mod, ch, 2, 1, 3)
+    cm = ch.mesh_from_arrays(m, 3).upload()
+    phys.kappa_r, phys.kappa_r1 = 1e-4, -1e-3  # negative near the outer wall
+    with pytest.raises(ch.ChorusError) as ei:
+        gpu_residual(ch, torch_dev, cm, phys, Q)
+    assert ei.value.status == -1
 
 
 def test_residual_parity_c1_config(ch, oracle_mod, torch_dev):

@@ -392,6 +392,57 @@ def test_entropy_diffusion_converges(oracle_mod, which):
     assert errs[1] < 0.05 and errs[1] < errs[0] / 2.0, errs
 
 
+def _radial_conduction_state(om, T0, T1, p, gam, R_gas):
+    xyz, wJ = om.solpts()
+    r = np.sqrt((xyz ** 2).sum(0))
+    T = T0 + T1 * r
+    rho = p / (R_gas * T)
+    z = np.zeros_like(rho)
+    Q = np.stack([rho, z, z, z, np.full_like(rho, p / (gam - 1))]).reshape(5, om.E, om.np)
+    return Q, r, T, wJ
+
+
+def test_radial_kappa_r_conduction_converges(oracle_mod):
+    """Radiative diffusivity varying with radius (the solar case, Section
+    7.3: a quadratic in r), kappa_r(r) = k0 + k1 r + k2 r^2, at rest with
+    uniform p and T = T0 + T1 r, no gravity: the energy equation of Section 2
+    gives dE/dt = (1/r^2) d/dr (r^2 kappa_r(r) rho c_p dT/dr), rho = p/(R T).
+    The residual on the elements off the walls converges to it with the
+    order (a constant kappa_r, or kappa_r taken at the wrong radius, gives an
+    O(1) error); the momentum residual vanishes (the density residual does
+    not: Rusanov dissipation acts on the interface jumps of rho)."""
+    gam, R_gas, p = 5.0 / 3.0, 1.0, 1.0
+    cp = gam * R_gas / (gam - 1.0)
+    k0, k1, k2, T0, T1 = 0.05, 0.03, 0.02, 1.0, 0.3
+    ri, ro, nr = 1.0, 2.0, 4
+    errs = []
+    for N in (3, 4, 5):
+        om = oracle_mod.OracleMesh(cubed_sphere_shell(2, nr, ri, ro), N)
+        Q, r, T, wJ = _radial_conduction_state(om, T0, T1, p, gam, R_gas)
+        R = om.residual(oracle_mod.phys(kappa_r=k0, kappa_r1=k1, kappa_r2=k2), Q).reshape(5, -1)
+        kr, dkr = k0 + k1 * r + k2 * r * r, k1 + 2.0 * k2 * r
+        c = cp * T1 * p / R_gas
+        want = c * ((2.0 * r * kr + r * r * dkr) / T - r * r * kr * T1 / T ** 2) / (r * r)
+        layer = np.floor((r.reshape(om.E, om.np).mean(1) - ri) / (ro - ri) * nr).astype(int)
+        sel = np.repeat((layer >= 1) & (layer <= nr - 2), om.np)
+        err = R[4][sel] - want[sel]
+        errs.append(math.sqrt((wJ[sel] * err ** 2).sum() / (wJ[sel] * want[sel] ** 2).sum()))
+        assert np.abs(R[1:4]).max() < 1e-10 * p  # metric identity: roundoff of the pressure flux
+    assert errs[2] < 2e-3 and errs[2] < errs[0] / 5.0, errs
+
+
+def test_radial_kappa_r_reduces_to_constant(oracle_mod):
+    """kappa_r1 = kappa_r2 = 0 gives the constant-diffusivity residual
+    exactly, and a nonzero quadratic changes it."""
+    om = oracle_mod.OracleMesh(cubed_sphere_shell(2, 2, 1.0, 2.0), 3)
+    Q, r, T, wJ = _radial_conduction_state(om, 1.0, 0.3, 1.0, 5.0 / 3.0, 1.0)
+    a = om.residual(oracle_mod.phys(kappa_r=0.1), Q)
+    b = om.residual(oracle_mod.phys(kappa_r=0.1, kappa_r1=0.0, kappa_r2=0.0), Q)
+    c = om.residual(oracle_mod.phys(kappa_r=0.1, kappa_r1=0.01), Q)
+    assert np.array_equal(a, b)
+    assert np.abs(c[4] - a[4]).max() > 1e-4 * np.abs(a[4]).max()
+
+
 # --------------------------------------------------------------------------
 # five-stage fourth-order SSP Runge-Kutta (the paper's integrator)
 # --------------------------------------------------------------------------
