@@ -153,3 +153,26 @@ def test_afb_background_matches_oracle(L, kr, kr1, kr2):
     rho_o, p_o = afb.background(np.array([ro]), 0.7, 1.0, L, 1e-3, kr, kappa_r1=kr1, kappa_r2=kr2)
     assert abs(pars["T_top"] - p_o[0] / rho_o[0]) < 1e-10
     assert abs(pars["F_bottom"] - L / (4 * np.pi * (7 / 3) ** 2)) < 1e-15
+
+
+def test_solar_radiative_diffusivity():
+    """The solar benchmark's radiative diffusivity (Section 7.3) mapped to
+    the solver's units: proportional to the printed quadratic at the
+    dimensional radii of Table 2's shell, positive over the shell, and with
+    lambda such that the almost-flux-balance entropy gradient vanishes at the
+    inner wall (the radiative flux carries L there)."""
+    import paper_1503_00834_amd as ch
+    from oracle import afb
+    beta, n_rho, L = 0.73, 3.0, 2e-3
+    k0, k1, k2 = ch.solar_radiative_diffusivity(beta, n_rho, L)
+    c0, c1, c2 = 1.5600975e8, -4.5631718e7, 3.3370368e6
+    ri, ro = beta / (1 - beta), 1 / (1 - beta)
+    rs = np.linspace(ri, ro, 7)
+    kr = k0 + k1 * rs + k2 * rs ** 2
+    w = rs * 1.74e10 / 1e10
+    printed = c0 + c1 * w + c2 * w * w
+    np.testing.assert_allclose(kr / kr[0], printed / printed[0], rtol=1e-12)
+    assert (kr > 0).all()
+    G = afb.target_gradient(ri, beta, n_rho, L, 1e-3, k0, kappa_r1=k1, kappa_r2=k2)
+    G_mid = afb.target_gradient(0.5 * (ri + ro), beta, n_rho, L, 1e-3, k0, kappa_r1=k1, kappa_r2=k2)
+    assert abs(G) < 1e-12 * abs(G_mid) and G_mid != 0.0
