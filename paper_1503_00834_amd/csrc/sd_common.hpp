@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 #include "chorus_internal.hpp"
 
 namespace chorus {
@@ -75,6 +77,19 @@ __device__ __forceinline__ int map_face_point(int o, int t1, int t2) {
     if (o & 2) u1 = N - 1 - u1;
     if (o & 1) u2 = N - 1 - u2;
     return u1 + N * u2;
+}
+
+// Global access at a base pointer plus a small per-lane offset in elements
+// (its byte offset fits 32 bits).  With a block-uniform base the address is
+// a scalar base plus a 32-bit vector offset: no 64-bit vector arithmetic per
+// access.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T *base, uint32_t i) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st_off(T *base, uint32_t i, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + i * (uint32_t)sizeof(T)) = v;
 }
 
 // mailbox slot of face point pp of an element's face (nb, inf = the face's

@@ -683,19 +683,21 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
     double pin[Sh::IT_SOL][5], pst[Sh::IT_SOL][5], pb[Sh::IT_SOL][5];
     const bool rk = S_.mode != 0;
     const bool useA = rk && S_.c0 != 0.0, useT = rk && S_.Tout != nullptr, useB = useT && S_.d0 != 0.0;
+    // (block-uniform bases, per-lane offsets clamped to the last element)
+    const int elmax = (G.E - 1 - e0 < EPB - 1) ? (int)(G.E - 1 - e0) : EPB - 1;
+    const float *sgb = G.solgeo + e0 * 13 * NP;
 #pragma unroll
     for (int k = 0; k < Sh::IT_SOL; ++k) {
         const int it = threadIdx.x + k * NT;
-        const int el = it / NP, p = it % NP;
-        const int64_t e = (it < EPB * NP && e0 + el < G.E) ? e0 + el : 0;
-        const float *gsp = G.solgeo + e * 13 * NP + p;
-        for (int c = 0; c < 4; ++c) gq[k][c] = gsp[(9 + c) * NP];
+        const int el = min(it / NP, elmax), p = it % NP;
+        for (int c = 0; c < 4; ++c) gq[k][c] = ld_off(sgb, (uint32_t)((el * 13 + 9 + c) * NP + p));
+        const uint32_t o = (uint32_t)(el * NP + p);
         for (int v = 0; v < 5; ++v) {
-            const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
-            r0v[k][v] = B.R0[gi];
-            pin[k][v] = rk ? Pq[gi] : 0.0;
-            pst[k][v] = useA ? S_.A[gi] : 0.0;
-            pb[k][v] = useB ? S_.B[gi] : 0.0;
+            const int64_t vb = ((int64_t)v * G.E + e0) * NP;
+            r0v[k][v] = ld_off(B.R0 + vb, o);
+            pin[k][v] = rk ? ld_off(Pq + vb, o) : 0.0;
+            pst[k][v] = useA ? ld_off(S_.A + vb, o) : 0.0;
+            pb[k][v] = useB ? ld_off(S_.B + vb, o) : 0.0;
         }
     }
 #pragma unroll
@@ -703,8 +705,7 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
         const int it = threadIdx.x + k * NT;
         if (it >= EPB * NP) break;
         const int el = it / NP, p = it % NP;
-        const int64_t e = e0 + el;
-        if (e >= G.E) continue;
+        if (el > elmax) continue;
         const MixedLds<N> &l = L[el];
         const float iJ = gq[k][0];
         const float g0 = F.GM * gq[k][1], g1 = F.GM * gq[k][2], g2 = F.GM * gq[k][3];
@@ -715,15 +716,16 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
         M[2] = rp * g1 + 2.0f * F.om * mx;
         M[3] = rp * g2;
         M[4] = mx * g0 + my * g1 + mz * g2;
+        const uint32_t o = (uint32_t)(el * NP + p);
         for (int v = 0; v < 5; ++v) {
-            const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
+            const int64_t vb = ((int64_t)v * G.E + e0) * NP;
             const double Rv = (double)r0v[k][v] + (double)(-div[k][v] * iJ - M[v]);
             if (!rk) {
-                S_.Pout[gi] = Rv;
+                st_off(S_.Pout + vb, o, Rv);
                 continue;
             }
-            if (useT) S_.Tout[gi] = S_.d0 * pb[k][v] + S_.d1 * (pin[k][v] + S_.d2 * Rv);
-            S_.Pout[gi] = S_.c0 * pst[k][v] + S_.c1 * (pin[k][v] + S_.c2 * Rv);
+            if (useT) st_off(S_.Tout + vb, o, S_.d0 * pb[k][v] + S_.d1 * (pin[k][v] + S_.d2 * Rv));
+            st_off(S_.Pout + vb, o, S_.c0 * pst[k][v] + S_.c1 * (pin[k][v] + S_.c2 * Rv));
         }
     }
 }
