@@ -55,14 +55,18 @@ __device__ __forceinline__ void ops_to_lds(const OpsT<T, N> &src, OpsT<T, N> &ds
     }
 }
 
-// line through solution point (a along d; t1 < t2 the tangential indices)
-template <int N>
-__device__ __forceinline__ int sol_of(int d, int a, int t1, int t2) {
-    return d == 0 ? a + N * (t1 + N * t2) : (d == 1 ? t1 + N * (a + N * t2) : t1 + N * (t2 + N * a));
-}
+// line through solution point (a along d; t1 < t2 the tangential indices).
+// Written with arithmetic selects: d is often lane dependent (face points),
+// and nested conditionals on it compiled to divergent branches recomputed
+// for every field.
 template <int N>
 __device__ __forceinline__ int stride_of(int d) {
-    return d == 0 ? 1 : (d == 1 ? N : N * N);
+    return (d == 0) ? 1 : ((d == 1) ? N : N * N);
+}
+template <int N>
+__device__ __forceinline__ int sol_of(int d, int a, int t1, int t2) {
+    const int s1 = (d == 0) ? N : 1, s2 = (d == 2) ? N : N * N;
+    return a * stride_of<N>(d) + t1 * s1 + t2 * s2;
 }
 template <int N>
 __device__ __forceinline__ void split_sol(int d, int p, int &a, int &t1, int &t2) {

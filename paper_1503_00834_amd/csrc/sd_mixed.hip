@@ -286,11 +286,10 @@ __device__ __forceinline__ void prologue_store(const Prologue<N, EPB, NT> &R, Mi
     }
 }
 
-// own face-point interpolation of a field stored in LDS
+// interpolation of a field stored in LDS at flux point m of the line
+// (base, st)
 template <int N>
-__device__ __forceinline__ float face_val(const OpsF<N> &op, const float *fld, int f, int t1, int t2) {
-    const int d = f >> 1, m = (f & 1) ? N : 0;
-    const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
+__device__ __forceinline__ float line_val(const OpsF<N> &op, const float *fld, int m, int base, int st) {
     float s = 0.0f;
 #pragma unroll
     for (int b = 0; b < N; ++b) s += op.I[m][b] * fld[base + b * st];
@@ -316,9 +315,10 @@ __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, 
         if (e >= G.E) continue;
         MixedLds<N> &l = L[el];
         const int t1 = pp % N, t2 = pp / N;
+        const int d = f >> 1, m = (f & 1) ? N : 0, base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
         float pv[5];
-        for (int v = 0; v < 5; ++v) pv[v] = face_val<N>(op, l.f[v], f, t1, t2);
-        const float r0 = face_val<N>(op, l.f[F_R0], f, t1, t2), E0 = face_val<N>(op, l.f[F_E0], f, t1, t2);
+        for (int v = 0; v < 5; ++v) pv[v] = line_val<N>(op, l.f[v], m, base, st);
+        const float r0 = line_val<N>(op, l.f[F_R0], m, base, st), E0 = line_val<N>(op, l.f[F_E0], m, base, st);
         if (fo) {
             for (int v = 0; v < 5; ++v) fo[k][v] = pv[v];
             fo[k][F_R0] = r0;
@@ -527,7 +527,8 @@ __global__ __launch_bounds__(NT) void k_pert_begin(OpsF<N> opa, GeoF G, const do
         const int32_t nb = G.link[e * 6 + f];
         if (nb < 0) continue;
         const int64_t slot = mailbox_slot<N>(nb, G.info[e * 6 + f], pp);
-        for (int v = 0; v < 5; ++v) TQ[slot + v * NF2] = face_val<N>(op, sp[el][v], f, pp % N, pp / N);
+        const int d = f >> 1, m = (f & 1) ? N : 0, base = sol_of<N>(d, 0, pp % N, pp / N), st = stride_of<N>(d);
+        for (int v = 0; v < 5; ++v) TQ[slot + v * NF2] = line_val<N>(op, sp[el][v], m, base, st);
     }
 }
 
@@ -831,7 +832,8 @@ __global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> opa, GeoF G, const fl
         const int32_t nb = lk[el][f];
         if (e >= G.E || nb < 0) continue;
         float *out = S_.TQout + mailbox_slot<N>(nb, inf[el][f], pp);
-        for (int v = 0; v < 5; ++v) out[v * NF2] = face_val<N>(op, sp[el][v], f, pp % N, pp / N);
+        const int d = f >> 1, m = (f & 1) ? N : 0, base = sol_of<N>(d, 0, pp % N, pp / N), st = stride_of<N>(d);
+        for (int v = 0; v < 5; ++v) out[v * NF2] = line_val<N>(op, sp[el][v], m, base, st);
     }
 }
 
