@@ -30,7 +30,7 @@ struct WsLayout {
     size_t Q2, Q4;  // SSPRK(5,4): extra stage registers (FP64 path), 0 otherwise
     size_t tau;  // learned closure: subgrid flux [15][E][NP] FP32 (0 when off)
     // mixed-precision path
-    size_t P0, P1, TQm, TVm, bg, dbg, gS0, R0, Q0;
+    size_t P0, P1, TQm, TVm, bg, dbg, gS0, R0, Q0, gbg;
     size_t FF64;  // FP64 path: own-side common face flux [E][6][5][NF2]
     size_t P2, P4;  // SSPRK(5,4) on the perturbation
     bool mixed;
@@ -66,6 +66,7 @@ static WsLayout ws_layout(const Mesh &m) {
     w.bg = off;   off = align256(off + sizeof(float) * E * 2 * NP);
     w.dbg = off;  off = align256(off + sizeof(float) * E * 6 * 2 * NF2);
     w.gS0 = off;  off = align256(off + sizeof(float) * E * 3 * (N + 1) * NF2);
+    w.gbg = off;  off = align256(off + sizeof(float) * E * 6 * NP);
     w.R0 = off;   off = align256(off + sizeof(float) * 5 * E * NP);
     w.Q0 = off;   off = align256(off + state);
     w.FF64 = off; off = align256(off + sizeof(double) * E * 6 * 5 * NF2);
@@ -84,6 +85,7 @@ static GeoM geom_of(const Mesh &m, const WsLayout &w, unsigned char *W) {
     g.bg = (const float *)(W + w.bg);
     g.dbg = (const float *)(W + w.dbg);
     g.gS0 = (const float *)(W + w.gS0);
+    g.gbg = (const float *)(W + w.gbg);
     g.R0 = (const float *)(W + w.R0);
     g.Q0 = (const double *)(W + w.Q0);
     g.rflux32 = (const float *)(b + m.layout.rflux32);
@@ -698,7 +700,7 @@ int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const 
     if (e == hipSuccess) e = launch_clear_flag(flag, s);
     if (e == hipSuccess) e = launch_trace(*m, G, Q0, TQ, s);
     if (e == hipSuccess) e = launch_bg_setup(*m, G, Q0, TQ, (float *)(W + w.bg), (float *)(W + w.dbg), flag, s);
-    if (e == hipSuccess) e = launch_bg_entropy(*m, G, P, Q0, TQ, (float *)(W + w.gS0), s);
+    if (e == hipSuccess) e = launch_bg_entropy(*m, G, P, Q0, TQ, (float *)(W + w.gS0), (float *)(W + w.gbg), s);
     // R0 = R(Q0), the complete FP64 residual of the background (the flux and
     // lift passes read receiver-indexed traces: a second trace buffer)
     const ClosureArgs C0{nullptr, nullptr};

@@ -764,7 +764,8 @@ __global__ __launch_bounds__(NT) void k_lift64(Ops<N> opa, Geo G, const double *
 // for zero momentum); used by the mixed-precision path
 template <int N, int EPB, int NT>
 __global__ __launch_bounds__(NT) void k_bg_entropy(Ops<N> opa, Geo G, PhysParams P, const double *__restrict__ Q0,
-                                                   const double *__restrict__ TQ, float *__restrict__ out) {
+                                                   const double *__restrict__ TQ, float *__restrict__ out,
+                                                   float *__restrict__ gout) {
     constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
     __shared__ double sq[EPB][5][NP];
     __shared__ double sqs[EPB][6][5][NF2];
@@ -778,6 +779,14 @@ __global__ __launch_bounds__(NT) void k_bg_entropy(Ops<N> opa, Geo G, PhysParams
     __syncthreads();
     gradients<N, EPB, NT>(op, G, e0, sq, sqs, sgr);
     __syncthreads();
+    // gradients of rho0 (components 0..2) and E0 (3..5) at the solution
+    // points: gout[e][6][NP]
+    for (int it = threadIdx.x; it < EPB * 6 * NP; it += NT) {
+        const int el = it / (6 * NP), r = it % (6 * NP), k = r / NP, p = r % NP;
+        const int64_t e = e0 + el;
+        if (e >= G.E) continue;
+        gout[(e * 6 + k) * NP + p] = (float)sgr[el][(k < 3 ? 0 : 12) + k % 3][p];
+    }
     const double gm1 = P.gamma - 1.0;
     for (int it = threadIdx.x; it < EPB * 3 * NFL; it += NT) {
         const int el = it / (3 * NFL), r = it % (3 * NFL), d = r / NFL, fl = r % NFL;
@@ -1077,17 +1086,17 @@ hipError_t launch_features(const Mesh &m, const Geo &G, const PhysParams &P, con
 
 template <int N>
 static hipError_t launch_bg_entropy_t(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q0,
-                                      const double *TQ, float *out, hipStream_t s) {
+                                      const double *TQ, float *out, float *gout, hipStream_t s) {
     constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
     const Ops<N> op = make_ops<N>(m.basis);
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
-    hipLaunchKernelGGL((k_bg_entropy<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, op, G, P, Q0, TQ, out);
+    hipLaunchKernelGGL((k_bg_entropy<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, op, G, P, Q0, TQ, out, gout);
     return hipGetLastError();
 }
 
 hipError_t launch_bg_entropy(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q0, const double *TQ,
-                             float *out, hipStream_t s) {
-#define C_(n) launch_bg_entropy_t<n>(m, G, P, Q0, TQ, out, s)
+                             float *out, float *gout, hipStream_t s) {
+#define C_(n) launch_bg_entropy_t<n>(m, G, P, Q0, TQ, out, gout, s)
     CHORUS_DISPATCH(m.N, C_)
 #undef C_
 }

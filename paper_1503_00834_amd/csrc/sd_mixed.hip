@@ -55,6 +55,7 @@ struct MixedBufs {
     const float *dbg;   // [E][6][2][NF2] neighbour minus own background face trace (rho, E)
     const float *gS0;   // [E][3][NFL]   grad S0 . (|J| grad xi_d) at d-flux points
     const float *R0;    // [5][E][NP]    R(Q0)
+    const float *gbg;   // [E][6][NP]    grad rho0, grad E0 at the solution points (from FP64, once)
 };
 
 struct PhysF {
@@ -197,7 +198,7 @@ struct MixedLds {
     float f[NFIELD][NP];          // perturbation + background fields
     float g[NGRAD][NP];           // gradients
     union {
-        float cs[NFIELD][6][NF2];  // common values (perturbation 0..4, background 5..6)
+        float cs[5][6][NF2];       // common values of the perturbation
         float ft[5][NFL];          // transformed flux of one direction, written after cs is consumed
     } u;
     int32_t lk[6], inf[6];        // neighbour element and info word per face
@@ -227,6 +228,7 @@ struct Prologue {
     double P[Sh::IT_SOL][5];
     float bg[Sh::IT_SOL][2];
     float gs[Sh::IT_SOL][9];
+    float gb[Sh::IT_SOL][6];  // background gradients
     // neighbour data at this thread's face items (face item it: el, f, pp):
     // perturbation trace, background jump
     float nq[Sh::IT_FACE][5], db[Sh::IT_FACE][2];
@@ -248,6 +250,7 @@ __device__ __forceinline__ void prologue_load(const double *Pq, const MixedBufs 
         R.bg[k][0] = B.bg[(e * 2 + 0) * NP + p];
         R.bg[k][1] = B.bg[(e * 2 + 1) * NP + p];
         for (int t = 0; t < 9; ++t) R.gs[k][t] = G.solgeo[(e * 13 + t) * NP + p];
+        for (int t = 0; t < 6; ++t) R.gb[k][t] = B.gbg[(e * 6 + t) * NP + p];
     }
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
@@ -279,6 +282,10 @@ __device__ __forceinline__ void prologue_store(const Prologue<N, EPB, NT> &R, Mi
         for (int v = 0; v < 5; ++v) L[el].f[v][p] = (float)R.P[k][v];
         L[el].f[F_R0][p] = R.bg[k][0];
         L[el].f[F_E0][p] = R.bg[k][1];
+        for (int c = 0; c < 3; ++c) {
+            L[el].g[3 * F_R0 + c][p] = R.gb[k][c];
+            L[el].g[3 * F_E0 + c][p] = R.gb[k][3 + c];
+        }
     }
     if ((int)threadIdx.x < EPB * 6) {
         L[threadIdx.x / 6].lk[threadIdx.x % 6] = R.lk;
@@ -296,10 +303,10 @@ __device__ __forceinline__ float line_val(const OpsF<N> &op, const float *fld, i
     return s;
 }
 
-// BR1 common values at the 6 N^2 face points: perturbation (5) and
-// background (rho0, E0)
-// (own face values of the 7 fields at the thread's face items are kept in
-// fo when given: the gradient pass reuses them for its face states)
+// BR1 common values of the perturbation at the 6 N^2 face points (the
+// background's gradients are computed once, in FP64, at set-up); the own
+// face values of the 7 fields at the thread's face items are kept in fo when
+// given: the face-flux phase reuses them
 template <int N, int EPB, int NT>
 __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, const PhysF &F, int64_t e0,
                                               MixedLds<N> *L, const Prologue<N, EPB, NT> &R,
@@ -327,8 +334,6 @@ __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, 
         const int32_t nb = l.lk[f], inf = l.inf[f];
         if (nb >= 0) {
             for (int v = 0; v < 5; ++v) l.u.cs[v][f][pp] = 0.5f * (pv[v] + R.nq[k][v]);
-            l.u.cs[F_R0][f][pp] = r0 + 0.5f * R.db[k][0];
-            l.u.cs[F_E0][f][pp] = E0 + 0.5f * R.db[k][1];
         } else {
             // wall state in perturbation form: rho' kept, normal momentum
             // removed, pressure kept (outer wall with T_top: p = rho R T_top)
@@ -349,13 +354,12 @@ __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, 
             l.u.cs[0][f][pp] = pv[0];
             for (int a = 0; a < 3; ++a) l.u.cs[1 + a][f][pp] = mb[a];
             l.u.cs[4][f][pp] = Eb;
-            l.u.cs[F_R0][f][pp] = r0;
-            l.u.cs[F_E0][f][pp] = (outer && F.RT_top > 0.0f) ? r0 * F.RT_top * igm1 : E0;
         }
     }
 }
 
-// gradients of the 7 fields at the solution points
+// gradients of the 5 perturbation fields at the solution points (those of
+// the background are loaded)
 template <int N, int EPB, int NT>
 __device__ __forceinline__ void gradients(const OpsF<N> &op, const GeoF &G, int64_t e0, MixedLds<N> *L,
                                           const float (*gsol)[9]) {
@@ -370,14 +374,14 @@ __device__ __forceinline__ void gradients(const OpsF<N> &op, const GeoF &G, int6
         if (e >= G.E) continue;
         MixedLds<N> &l = L[el];
         const float *Gm = gsol[k];
-        float dq[3][NFIELD];
+        float dq[3][5];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             int a, t1, t2;
             split_sol<N>(d, p, a, t1, t2);
             const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d), pp = t1 + N * t2;
 #pragma unroll
-            for (int v = 0; v < NFIELD; ++v) {
+            for (int v = 0; v < 5; ++v) {
                 float s = op.D[a][0] * l.u.cs[v][2 * d][pp] + op.D[a][N] * l.u.cs[v][2 * d + 1][pp];
 #pragma unroll
                 for (int b = 0; b < N; ++b) s += op.B[a][b] * l.f[v][base + b * st];
@@ -385,7 +389,7 @@ __device__ __forceinline__ void gradients(const OpsF<N> &op, const GeoF &G, int6
             }
         }
 #pragma unroll
-        for (int v = 0; v < NFIELD; ++v)
+        for (int v = 0; v < 5; ++v)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 l.g[3 * v + c][p] = Gm[c] * dq[0][v] + Gm[3 + c] * dq[1][v] + Gm[6 + c] * dq[2][v];
@@ -930,6 +934,7 @@ static MixedBufs bufs_of(const GeoM &g) {
     b.dbg = g.dbg;
     b.gS0 = g.gS0;
     b.R0 = g.R0;
+    b.gbg = g.gbg;
     return b;
 }
 
