@@ -329,6 +329,16 @@ struct Sh64 {
     static constexpr int IT_INTD = (EPB * NINTD + NT - 1) / NT;
 };
 
+// launch shape of the flux/lift passes per order: elements per block,
+// threads, minimum waves per SIMD of the flux pass
+template <int N>
+struct Cfg64;
+template <> struct Cfg64<2> { static constexpr int EPB = 8, NT = 64, MINW = 1; };
+template <> struct Cfg64<3> { static constexpr int EPB = 2, NT = 64, MINW = 1; };
+template <> struct Cfg64<4> { static constexpr int EPB = 1, NT = 64, MINW = 1; };
+template <> struct Cfg64<5> { static constexpr int EPB = 1, NT = 128, MINW = 1; };
+template <> struct Cfg64<6> { static constexpr int EPB = 1, NT = 256, MINW = 1; };
+
 // face traces of the element block's state (LDS) pushed to the neighbours
 template <int N, int EPB, int NT>
 __device__ __forceinline__ void push_traces64(const Ops<N> &op, const Geo &G, int64_t e0, const int32_t (*lk)[6],
@@ -387,7 +397,7 @@ __device__ __forceinline__ double line_interp(const Ops<N> &op, const T *fld, in
 // RAD: radiative diffusivity varying with radius (radius of each flux point
 // read with its geometry), else the constant P.kappa_r
 template <int N, int EPB, int NT, int PART, bool RAD>
-__global__ __launch_bounds__(NT) void k_flux64(Ops<N> opa, Geo G, PhysParams P, const double *__restrict__ Q,
+__global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G, PhysParams P, const double *__restrict__ Q,
                                                const double *__restrict__ TQ, double *__restrict__ TV,
                                                StageArgs S_, ClosureArgs C) {
     constexpr bool CL = PART != 0;
@@ -975,11 +985,7 @@ static hipError_t launch_grad_t(const Mesh &m, const Geo &G, const PhysParams &P
 }
 
 // flux/lift passes: elements per block / threads per block for each order
-template <int N>
-struct Cfg64 {
-    static constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
-};
-template <> struct Cfg64<4> { static constexpr int EPB = 1, NT = 64; };
+
 
 template <int N>
 static hipError_t launch_trace_push_t(const Mesh &m, const Geo &G, const double *Q, double *TQ, hipStream_t s) {
