@@ -31,7 +31,6 @@ struct WsLayout {
     size_t tau;  // learned closure: subgrid flux [15][E][NP] FP32 (0 when off)
     // mixed-precision path
     size_t P0, P1, TQm, TVm, bg, dbg, gS0, R0, Q0, gbg;
-    size_t FF64;  // FP64 path: own-side common face flux [E][6][5][NF2]
     size_t P2, P4;  // SSPRK(5,4) on the perturbation
     bool mixed;
     size_t total;
@@ -69,7 +68,6 @@ static WsLayout ws_layout(const Mesh &m) {
     w.gbg = off;  off = align256(off + sizeof(float) * E * 6 * NP);
     w.R0 = off;   off = align256(off + sizeof(float) * 5 * E * NP);
     w.Q0 = off;   off = align256(off + state);
-    w.FF64 = off; off = align256(off + sizeof(double) * E * 6 * 5 * NF2);
     w.total = off;
     return w;
 }
@@ -100,7 +98,6 @@ static Geo geo_of(const Mesh &m, unsigned char *W) {
     g.link = (const int32_t *)(b + m.layout.link);
     g.info = (const int32_t *)(b + m.layout.info);
     g.E = m.E;
-    g.FF = (double *)(W + ws_layout(m).FF64);
     g.rflux = (const double *)(b + m.layout.rflux);
     return g;
 }
@@ -1103,8 +1100,8 @@ int chorus_closure_infer(chorus_mesh_t mesh, const chorus_physics *phys, const d
     hipStream_t s = (hipStream_t)stream;
     double *TQ = (double *)(W + w.TQ0), *TV = (double *)(W + w.TV);
     const ClosureArgs C{(const unsigned char *)phys->closure_model, sgs_dev};
-    hipError_t e = launch_trace(*m, G, Q_dev, TQ, s);
-    if (e == hipSuccess) e = launch_grad(*m, G, P, Q_dev, TQ, TV, C, s);
+    hipError_t e = launch_trace_push(*m, G, Q_dev, TQ, s);
+    if (e == hipSuccess) e = launch_closure_tau(*m, G, P, Q_dev, TQ, C, s);
     if (e != hipSuccess) return hip_fail(e, "closure_infer");
     return CHORUS_OK;
 }

@@ -17,8 +17,6 @@ struct Geo {
     const int32_t *link;    // [E][6]
     const int32_t *info;    // [E][6]
     int64_t E;
-    double *FF;             // [E][6][5][NF2] own-side common face flux along the outward
-                            // area vector (written by the gradient pass)
     const double *rflux;    // [E][3][NFL] radius at the d-flux points
 };
 
@@ -42,12 +40,14 @@ struct StageArgs {
 struct ClosureArgs {
     const unsigned char *model;  // packed BF16 network image
     float *tau;                  // [15][E][NP] subgrid flux at the solution points (written by
-                                 // the gradient pass, read by the residual pass)
+                                 // the network-only flux pass, read by the flux pass)
 };
 
 hipError_t launch_trace(const Mesh &m, const Geo &G, const double *Q, double *TQ, hipStream_t s);
-hipError_t launch_grad(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
-                       double *TV, const ClosureArgs &C, hipStream_t s);
+// learned subgrid flux at the solution points -> C.tau (order 3; traces from
+// launch_trace_push in TQ)
+hipError_t launch_closure_tau(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
+                              const ClosureArgs &C, hipStream_t s);
 hipError_t launch_features(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
                            float *X, hipStream_t s);
 // FP64 stage split used by the solver (mailboxes indexed by the receiving

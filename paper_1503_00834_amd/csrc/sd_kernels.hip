@@ -14,9 +14,9 @@
 //              added in place; face traces of the new state pushed to the
 //              neighbours for the next stage.
 //
-// k_trace / k_grad (traces indexed by their own element, gradient pass
-// with the fused network) serve the closure features, closure inference and
-// the background set-up of the mixed path.
+// k_trace (traces indexed by their own element) serves the closure features
+// and the background set-up of the mixed path; the flux pass's network-only
+// variant serves closure inference.
 //
 // Work mapping: a workgroup of NT threads owns EPB elements; every phase is
 // a loop over (element, point) items with all element data staged in LDS.
@@ -152,8 +152,6 @@ __global__ __launch_bounds__(NT) void k_trace(Ops<N> opa, Geo G, const double *_
     }
 }
 
-// viscous flux of the own side at interior interface points, along the
-// outward area vector: TV[e][f][v][pp]
 // learned subgrid flux at the solution points of the block's elements (one
 // wave, all points in 16-point tiles): features (Q, grad Q) -> network ->
 // stau (LDS) and tau[k][E][NP] (global)
@@ -195,88 +193,6 @@ __device__ __forceinline__ void closure_tau(const ClosureArgs &C, int64_t E, int
             stau[el][k][sp] = out[pt][i];
             if (C.tau) C.tau[((int64_t)k * E + e0 + el) * NP + sp] = out[pt][i];
         }
-    }
-}
-
-template <int N, int EPB, int NT, bool CL>
-__global__ __launch_bounds__(NT) void k_grad(Ops<N> opa, Geo G, PhysParams P, const double *__restrict__ Q,
-                                             const double *__restrict__ TQ, double *__restrict__ TV,
-                                             ClosureArgs C) {
-    constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
-    __shared__ double sq[EPB][5][NP];
-    __shared__ double sqs[EPB][6][5][NF2];
-    __shared__ double sgr[EPB][15][NP];
-    __shared__ float stau[CL ? EPB : 1][15][CL ? NP : 1];
-    const int64_t e0 = (int64_t)blockIdx.x * EPB;
-    __shared__ Ops<N> op;
-    ops_to_lds(opa, op);
-    load_q<N, EPB, NT>(Q, G.E, e0, sq);
-    __syncthreads();
-    common_solution<N, EPB, NT>(op, G, P, TQ, e0, sq, sqs);
-    __syncthreads();
-    gradients<N, EPB, NT>(op, G, e0, sq, sqs, sgr);
-    __syncthreads();
-    if constexpr (CL) {
-        closure_tau<N, EPB, NT>(C, G.E, e0, sq, sgr, stau);
-        __syncthreads();
-    }
-    for (int it = threadIdx.x; it < EPB * 6 * NF2; it += NT) {
-        const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
-        const int64_t e = e0 + el;
-        if (e >= G.E) continue;
-        const int32_t nb = G.link[e * 6 + f], inf = G.info[e * 6 + f];
-        const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
-        const int base = sol_of<N>(d, 0, t1, t2), st = stride_of<N>(d);
-        double q[5], g[5][3];
-        for (int v = 0; v < 5; ++v) {
-            double s = 0.0;
-#pragma unroll
-            for (int b = 0; b < N; ++b) s += op.I[m][b] * sq[el][v][base + b * st];
-            q[v] = s;
-            for (int c = 0; c < 3; ++c) {
-                double t = 0.0;
-#pragma unroll
-                for (int b = 0; b < N; ++b) t += op.I[m][b] * sgr[el][v * 3 + c][base + b * st];
-                g[v][c] = t;
-            }
-        }
-        const int fl = m + (N + 1) * (t1 + N * t2);
-        const double sg = (f & 1) ? 1.0 : -1.0;
-        const int bc = (inf >> 6) - 1;
-        double S[3], fv[5], phi[5];
-        for (int c = 0; c < 3; ++c) S[c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
-        const double kr = kappa_r_at(P, G.rflux[(e * 3 + d) * NFL + fl]);
-        if (nb >= 0) {
-            flux_viscous(q, g, S, P, kr, fv);
-            if constexpr (CL) {
-                // the own-side subgrid flux enters the trace with the sign of -F_v
-                for (int v = 0; v < 5; ++v)
-                    for (int c = 0; c < 3; ++c) {
-                        double t = 0.0;
-#pragma unroll
-                        for (int b = 0; b < N; ++b) t += op.I[m][b] * (double)stau[el][v * 3 + c][base + b * st];
-                        fv[v] -= t * S[c];
-                    }
-            }
-            for (int v = 0; v < 5; ++v) TV[((e * 6 + f) * 5 + v) * NF2 + pp] = fv[v];
-            // own-side part of the common flux: Rusanov minus half the own
-            // viscous (minus subgrid) flux; the residual pass adds the
-            // neighbour's half from its trace
-            const int f2 = inf & 7, o = (inf >> 3) & 7;
-            const int pn = map_face_point<N>(o, t1, t2);
-            const double *tq = TQ + ((int64_t)nb * 6 + f2) * 5 * NF2;
-            double qn[5];
-            for (int v = 0; v < 5; ++v) qn[v] = tq[v * NF2 + pn];
-            flux_rusanov(q, qn, S, P, phi);
-            for (int v = 0; v < 5; ++v) phi[v] -= 0.5 * fv[v];
-        } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
-            flux_wall(q, g, S, bc == CHORUS_BC_OUTER, P, kr, phi);
-        } else {
-            flux_viscous(q, g, S, P, kr, fv);
-            flux_rusanov(q, P.bc_state, S, P, phi);
-            for (int v = 0; v < 5; ++v) phi[v] -= 0.5 * fv[v];
-        }
-        for (int v = 0; v < 5; ++v) G.FF[((e * 6 + f) * 5 + v) * NF2 + pp] = phi[v];
     }
 }
 
@@ -968,26 +884,6 @@ static hipError_t launch_trace_t(const Mesh &m, const Geo &G, const double *Q, d
 }
 
 template <int N>
-static hipError_t launch_grad_t(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q,
-                                const double *TQ, double *TV, const ClosureArgs &C, hipStream_t s) {
-    constexpr int EPB = Cfg<N>::EPB, NT = Cfg<N>::NT;
-    const Ops<N> op = make_ops<N>(m.basis);
-    const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
-    if (C.model) {
-        if constexpr (N == 3)
-            hipLaunchKernelGGL((k_grad<N, EPB, NT, true>), dim3(nb), dim3(NT), 0, s, op, G, P, Q, TQ, TV, C);
-        else
-            return hipErrorInvalidValue;
-    } else {
-        hipLaunchKernelGGL((k_grad<N, EPB, NT, false>), dim3(nb), dim3(NT), 0, s, op, G, P, Q, TQ, TV, C);
-    }
-    return hipGetLastError();
-}
-
-// flux/lift passes: elements per block / threads per block for each order
-
-
-template <int N>
 static hipError_t launch_trace_push_t(const Mesh &m, const Geo &G, const double *Q, double *TQ, hipStream_t s) {
     constexpr int EPB = Cfg64<N>::EPB, NT = Cfg64<N>::NT;
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
@@ -1061,9 +957,24 @@ hipError_t launch_trace(const Mesh &m, const Geo &G, const double *Q, double *TQ
     CHORUS_DISPATCH(m.N, C_)
 #undef C_
 }
-hipError_t launch_grad(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
-                       double *TV, const ClosureArgs &C, hipStream_t s) {
-#define C_(n) launch_grad_t<n>(m, G, P, Q, TQ, TV, C, s)
+template <int N>
+static hipError_t launch_closure_tau_t(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q,
+                                       const double *TQ, const ClosureArgs &C, hipStream_t s) {
+    if constexpr (N == 3) {
+        constexpr int EPB = Cfg64<N>::EPB, NT = Cfg64<N>::NT;
+        const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
+        const StageArgs none{nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
+        hipLaunchKernelGGL((k_flux64<N, EPB, NT, 1, false>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, P, Q,
+                           TQ, nullptr, none, C);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_closure_tau(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
+                              const ClosureArgs &C, hipStream_t s) {
+#define C_(n) launch_closure_tau_t<n>(m, G, P, Q, TQ, C, s)
     CHORUS_DISPATCH(m.N, C_)
 #undef C_
 }
