@@ -65,7 +65,7 @@ static WsLayout ws_layout(const Mesh &m) {
     w.bg = off;   off = align256(off + sizeof(float) * E * 2 * NP);
     w.dbg = off;  off = align256(off + sizeof(float) * E * 6 * 2 * NF2);
     w.gS0 = off;  off = align256(off + sizeof(float) * E * 3 * (N + 1) * NF2);
-    w.gbg = off;  off = align256(off + sizeof(float) * E * 6 * NP);
+    w.gbg = off;  off = align256(off + sizeof(float) * E * 3 * NP);
     w.R0 = off;   off = align256(off + sizeof(float) * 5 * E * NP);
     w.Q0 = off;   off = align256(off + state);
     w.total = off;

@@ -115,7 +115,7 @@ struct GeoM {
     const float *dbg;        // [E][6][2][NF2] neighbour minus own background face trace
     const float *gS0;        // [E][3][NFL] background entropy gradient along the flux metric
     const float *R0;         // [5][E][NP]  background residual
-    const float *gbg;        // [E][6][NP]  grad rho0 (0..2), grad E0 (3..5) at the solution points
+    const float *gbg;        // [E][3][NP]  grad rho0 at the solution points
     const double *Q0;        // [5][E][NP]  background state
     const float *rflux32;    // [E][3][NFL] radius at the d-flux points
 };
@@ -144,7 +144,7 @@ hipError_t launch_lift_mixed(const Mesh &m, const GeoM &g, const float *TV, cons
 hipError_t launch_bg_setup(const Mesh &m, const Geo &G, const double *Q0, const double *TQ0, float *bg, float *dbg,
                            int *flag, hipStream_t s);
 // background entropy gradient along the flux-point metric (out) and the
-// gradients of rho0 and E0 at the solution points (gout [E][6][NP])
+// gradient of rho0 at the solution points (gout [E][3][NP])
 hipError_t launch_bg_entropy(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q0, const double *TQ,
                              float *out, float *gout, hipStream_t s);
 hipError_t launch_pert_end(const double *Q0, const double *Pq, double *Q, int64_t n, hipStream_t s);

@@ -705,13 +705,12 @@ __global__ __launch_bounds__(NT) void k_bg_entropy(Ops<N> opa, Geo G, PhysParams
     __syncthreads();
     gradients<N, EPB, NT>(op, G, e0, sq, sqs, sgr);
     __syncthreads();
-    // gradients of rho0 (components 0..2) and E0 (3..5) at the solution
-    // points: gout[e][6][NP]
-    for (int it = threadIdx.x; it < EPB * 6 * NP; it += NT) {
-        const int el = it / (6 * NP), r = it % (6 * NP), k = r / NP, p = r % NP;
+    // gradient of rho0 at the solution points: gout[e][3][NP]
+    for (int it = threadIdx.x; it < EPB * 3 * NP; it += NT) {
+        const int el = it / (3 * NP), r = it % (3 * NP), k = r / NP, p = r % NP;
         const int64_t e = e0 + el;
         if (e >= G.E) continue;
-        gout[(e * 6 + k) * NP + p] = (float)sgr[el][(k < 3 ? 0 : 12) + k % 3][p];
+        gout[(e * 3 + k) * NP + p] = (float)sgr[el][k][p];
     }
     const double gm1 = P.gamma - 1.0;
     for (int it = threadIdx.x; it < EPB * 3 * NFL; it += NT) {

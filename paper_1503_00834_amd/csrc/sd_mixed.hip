@@ -55,11 +55,11 @@ struct MixedBufs {
     const float *dbg;   // [E][6][2][NF2] neighbour minus own background face trace (rho, E)
     const float *gS0;   // [E][3][NFL]   grad S0 . (|J| grad xi_d) at d-flux points
     const float *R0;    // [5][E][NP]    R(Q0)
-    const float *gbg;   // [E][6][NP]    grad rho0, grad E0 at the solution points (from FP64, once)
+    const float *gbg;   // [E][3][NP]    grad rho0 at the solution points (from FP64, once)
 };
 
 struct PhysF {
-    float gm1, gam, R, cp, GM, om, nu, kappa, kappa_r, RT_top;  // RT_top <= 0: off
+    float gm1, gam, R, cp, icp, GM, om, nu, kappa, kappa_r, RT_top;  // RT_top <= 0: off
     float kappa_r1, kappa_r2;                                    // kappa_r(r) = kappa_r + kappa_r1 r + kappa_r2 r^2
 };
 
@@ -69,6 +69,7 @@ __device__ __forceinline__ PhysF physf_of(const PhysParams &P) {
     f.gam = (float)P.gamma;
     f.R = (float)P.R_gas;
     f.cp = (float)P.cp;
+    f.icp = (float)(1.0 / P.cp);
     f.GM = (float)P.GM;
     f.om = (float)P.omega;
     f.nu = (float)P.nu;
@@ -93,14 +94,16 @@ __device__ __forceinline__ float kr_of(const PhysF &F, float loaded) {
 
 // LDS field slots at solution points: perturbation (5), background (2)
 enum { F_RP = 0, F_MX = 1, F_MY = 2, F_MZ = 3, F_EP = 4, F_R0 = 5, F_E0 = 6, NFIELD = 7 };
-// gradient slots: field f, component c at slot 3 f + c
-constexpr int NGRAD = 3 * NFIELD;
+// gradient slots: field f, component c at slot 3 f + c (the perturbation
+// fields and rho0; grad E0 enters only along S, through the background
+// entropy gradient: see dflux_viscous)
+constexpr int NGRAD = 3 * (F_R0 + 1);
 
 // point state at a flux point: background and perturbation values and
 // gradients (full gradient = background + perturbation)
 struct PtState {
     float r0, E0, rp, m[3], Ep;          // values
-    float gr0[3], gE0[3];                // background gradients
+    float gr0[3];                        // background density gradient
     float grp[3], gm[3][3], gEp[3];      // perturbation gradients
 };
 
@@ -164,18 +167,18 @@ __device__ __forceinline__ void dflux_viscous(const PtState &s, const float S[3]
     const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const float pp = F.gm1 * (s.Ep - 0.5f * uu * rho);
     const float p0 = F.gm1 * s.E0, p = p0 + pp;
-    float gpS = 0.0f, grpS = 0.0f, gr0S = 0.0f, gp0S = 0.0f;
+    float gpS = 0.0f, grpS = 0.0f, gr0S = 0.0f;
     for (int c = 0; c < 3; ++c) {
         const float gp = F.gm1 * (s.gEp[c] - (u[0] * s.gm[0][c] + u[1] * s.gm[1][c] + u[2] * s.gm[2][c]) +
                                   0.5f * uu * grho[c]);
         gpS += gp * S[c];
         grpS += s.grp[c] * S[c];
         gr0S += s.gr0[c] * S[c];
-        gp0S += F.gm1 * s.gE0[c] * S[c];
     }
-    // (grad S - grad S0).S / c_p
+    // (grad S - grad S0).S / c_p with grad p0 . S / p0 = gamma (gS0S / c_p
+    // + grad rho0 . S / rho0), the background entropy gradient's definition
     const float igp = rcp(F.gam * p), ir0 = rcp(s.r0);
-    const float dgS = igp * (gpS - gp0S * pp * rcp(p0)) - inv * (grpS - gr0S * s.rp * ir0);
+    const float dgS = igp * (gpS - F.gam * pp * (gS0S * F.icp + gr0S * ir0)) - inv * (grpS - gr0S * s.rp * ir0);
     // rho T grad S . S - rho0 T0 grad S0 . S = (p' gS0S + p c_p dgS) / R
     const float iR = rcp(F.R);
     const float eS = F.kappa * (pp * gS0S + p * F.cp * dgS) * iR;
@@ -228,7 +231,7 @@ struct Prologue {
     double P[Sh::IT_SOL][5];
     float bg[Sh::IT_SOL][2];
     float gs[Sh::IT_SOL][9];
-    float gb[Sh::IT_SOL][6];  // background gradients
+    float gb[Sh::IT_SOL][3];  // background density gradient
     // neighbour data at this thread's face items (face item it: el, f, pp):
     // perturbation trace, background jump
     float nq[Sh::IT_FACE][5], db[Sh::IT_FACE][2];
@@ -250,7 +253,7 @@ __device__ __forceinline__ void prologue_load(const double *Pq, const MixedBufs 
         R.bg[k][0] = B.bg[(e * 2 + 0) * NP + p];
         R.bg[k][1] = B.bg[(e * 2 + 1) * NP + p];
         for (int t = 0; t < 9; ++t) R.gs[k][t] = G.solgeo[(e * 13 + t) * NP + p];
-        for (int t = 0; t < 6; ++t) R.gb[k][t] = B.gbg[(e * 6 + t) * NP + p];
+        for (int t = 0; t < 3; ++t) R.gb[k][t] = B.gbg[(e * 3 + t) * NP + p];
     }
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
@@ -282,10 +285,7 @@ __device__ __forceinline__ void prologue_store(const Prologue<N, EPB, NT> &R, Mi
         for (int v = 0; v < 5; ++v) L[el].f[v][p] = (float)R.P[k][v];
         L[el].f[F_R0][p] = R.bg[k][0];
         L[el].f[F_E0][p] = R.bg[k][1];
-        for (int c = 0; c < 3; ++c) {
-            L[el].g[3 * F_R0 + c][p] = R.gb[k][c];
-            L[el].g[3 * F_E0 + c][p] = R.gb[k][3 + c];
-        }
+        for (int c = 0; c < 3; ++c) L[el].g[3 * F_R0 + c][p] = R.gb[k][c];
     }
     if ((int)threadIdx.x < EPB * 6) {
         L[threadIdx.x / 6].lk[threadIdx.x % 6] = R.lk;
@@ -436,7 +436,6 @@ __device__ __forceinline__ void state_at(const OpsF<N> &op, const MixedLds<N> &l
         s.gm[2][c] = I(l.g[3 * F_MZ + c]);
         s.gEp[c] = I(l.g[3 * F_EP + c]);
         s.gr0[c] = I(l.g[3 * F_R0 + c]);
-        s.gE0[c] = I(l.g[3 * F_E0 + c]);
     }
 }
 
