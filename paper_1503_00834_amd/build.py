@@ -31,6 +31,11 @@ def build(verbose=False):
         # only (no NaN/Inf/signed-zero semantics needed, results held to
         # 1e-6 of FP64): relaxed FP32 rules there; every other file strict
         extra = ["-ffast-math"] if src == "sd_mixed.hip" else []
+        # the closure network's matrix-core accumulators in ordinary vector
+        # registers, which its activations read directly (no accumulator-
+        # register copies)
+        if src == "sd_kernels.hip":
+            extra += ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
         cmd = [hipcc] + hipcc_flags() + extra + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd))

@@ -40,41 +40,40 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
-// float -> bfloat16 bits, round to nearest even
-__device__ __forceinline__ uint32_t bf16_bits(float x) {
-    uint32_t u = __builtin_bit_cast(uint32_t, x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return u >> 16;
-}
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 
+// two floats -> two bfloat16 (low half: lo), round to nearest even: one
+// packed conversion instruction on gfx950
 __device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
-    return bf16_bits(lo) | (bf16_bits(hi) << 16);
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
 }
 
-// erf by the rational approximation 7.1.26 of Abramowitz and Stegun
-// (Handbook of Mathematical Functions, 1964): erf(x) = 1 - t (a1 + t (a2 +
-// t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1 / (1 + p x), x >= 0, odd
-// extension; |error| <= 1.5e-7, far below the bfloat16 rounding (2^-9
-// relative) the activations receive.  One reciprocal, one exponential and
-// five multiply-adds instead of a general-purpose erf.
-__device__ __forceinline__ float erf_as(float x) {
-    const float ax = fabsf(x);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
-    float poly = fmaf(1.061405429f, t, -1.453152027f);
-    poly = fmaf(poly, t, 1.421413741f);
-    poly = fmaf(poly, t, -0.284496736f);
-    poly = fmaf(poly, t, 0.254829592f);
-    const float y = fmaf(-poly * t, __expf(-ax * ax), 1.0f);
-    return copysignf(y, x);
-}
-
-// GELU x Phi(x): FP32 with the library erf (training), and with the
-// approximation above for the bfloat16 inference
+// GELU z Phi(z), Phi(z) = (1 + erf(z / sqrt 2)) / 2: FP32 with the library
+// erf (training).
 __device__ __forceinline__ float gelu_f(float z) {
     return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
 }
+
+// The same for the bfloat16 inference, with erf by the rational
+// approximation 7.1.26 of Abramowitz and Stegun (Handbook of Mathematical
+// Functions, 1964): erf(x) = 1 - q, q = t (a1 + t (a2 + t (a3 + t (a4 +
+// t a5)))) exp(-x^2), t = 1 / (1 + p x) for x >= 0 (odd extension),
+// |error| <= 1.5e-7, far below the bfloat16 rounding (2^-9 relative) the
+// activations receive.  With x = |z| / sqrt 2 the odd extension folds into
+// z Phi(z) = max(z, 0) - |z| q / 2: one reciprocal, one exponential, four
+// multiply-adds for the polynomial (coefficients halved) and four more
+// operations, no sign handling.
 __device__ __forceinline__ float gelu_bf(float z) {
-    return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f));
+    const float az = fabsf(z);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, az, 1.0f));
+    float h = fmaf(0.5f * 1.061405429f, t, 0.5f * -1.453152027f);
+    h = fmaf(h, t, 0.5f * 1.421413741f);
+    h = fmaf(h, t, 0.5f * -0.284496736f);
+    h = fmaf(h, t, 0.5f * 0.254829592f);
+    // exp(-z^2 / 2) as a power of two
+    const float e = __builtin_amdgcn_exp2f(z * z * (-0.5f * 1.4426950408889634f));
+    return fmaf(-az, h * t * e, fmaxf(z, 0.0f));
 }
 
 // K index held by lane group g (= lane / 16), slot i (0..7) of the B
@@ -99,16 +98,16 @@ __device__ __forceinline__ void mlp_eval(const unsigned char *__restrict__ model
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         const bf16x8_t a = __builtin_bit_cast(bf16x8_t, fr[mt * 64 + lane]);
-        float b[4];
+        f32x4_t b;  // bias as the accumulator's initial value
 #pragma unroll
         for (int i = 0; i < 4; ++i) b[i] = fl[kMlpB1 + 16 * mt + 4 * g + i];
 #pragma unroll
         for (int pt = 0; pt < NPT; ++pt) {
-            f32x4_t c = {0.f, 0.f, 0.f, 0.f};
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8_t, xb[pt]), c, 0, 0, 0);
+            const f32x4_t c =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8_t, xb[pt]), b, 0, 0, 0);
             const int ks = mt >> 1, half = (mt & 1) * 2;
-            h1[ks][pt][half] = bf16_pair(gelu_bf(c[0] + b[0]), gelu_bf(c[1] + b[1]));
-            h1[ks][pt][half + 1] = bf16_pair(gelu_bf(c[2] + b[2]), gelu_bf(c[3] + b[3]));
+            h1[ks][pt][half] = bf16_pair(gelu_bf(c[0]), gelu_bf(c[1]));
+            h1[ks][pt][half + 1] = bf16_pair(gelu_bf(c[2]), gelu_bf(c[3]));
         }
     }
     // layer 2
@@ -117,17 +116,16 @@ __device__ __forceinline__ void mlp_eval(const unsigned char *__restrict__ model
     for (int mt = 0; mt < 4; ++mt) {
         const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, fr[(4 + 2 * mt) * 64 + lane]);
         const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, fr[(5 + 2 * mt) * 64 + lane]);
-        float b[4];
+        f32x4_t b;
 #pragma unroll
         for (int i = 0; i < 4; ++i) b[i] = fl[kMlpB2 + 16 * mt + 4 * g + i];
 #pragma unroll
         for (int pt = 0; pt < NPT; ++pt) {
-            f32x4_t c = {0.f, 0.f, 0.f, 0.f};
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, __builtin_bit_cast(bf16x8_t, h1[0][pt]), c, 0, 0, 0);
+            f32x4_t c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, __builtin_bit_cast(bf16x8_t, h1[0][pt]), b, 0, 0, 0);
             c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, __builtin_bit_cast(bf16x8_t, h1[1][pt]), c, 0, 0, 0);
             const int ks = mt >> 1, half = (mt & 1) * 2;
-            h2[ks][pt][half] = bf16_pair(gelu_bf(c[0] + b[0]), gelu_bf(c[1] + b[1]));
-            h2[ks][pt][half + 1] = bf16_pair(gelu_bf(c[2] + b[2]), gelu_bf(c[3] + b[3]));
+            h2[ks][pt][half] = bf16_pair(gelu_bf(c[0]), gelu_bf(c[1]));
+            h2[ks][pt][half + 1] = bf16_pair(gelu_bf(c[2]), gelu_bf(c[3]));
         }
     }
     // layer 3 (linear) and output scaling
