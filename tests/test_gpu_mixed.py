@@ -154,6 +154,85 @@ def test_mixed_100_steps_vs_fp64_full_workload(ch, torch_dev):
     assert max(rel) <= 1e-6, rel
 
 
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_mixed_ragged_last_block(ch, oracle_mod, torch_dev, N):
+    """162 hexes: the last element block of the flux pass is partly empty
+    (4 elements per block at N = 4, 8 at N = 2; 162 = 40 * 4 + 2 = 20 * 8 + 2);
+    residual and two SSP-RK3 steps against the oracle."""
+    torch = torch_dev
+    beta, n_rho = 0.7, 1.0
+    ri, ro = beta / (1 - beta), 1 / (1 - beta)
+    m = cubed_sphere_shell(3, 3, ri, ro)
+    om = oracle_mod.OracleMesh(m, N)
+    assert om.E == 162
+    Q0, pars = om.polytrope(beta, n_rho)
+    Q, _ = om.polytrope(beta, n_rho, noise=uniform_noise(om.n_solpts, 9), amp=1e-3)
+    rng = np.random.default_rng(10)
+    Q[1:4] = 1e-3 * Q[0] * rng.uniform(-1, 1, size=Q[1:4].shape)
+    Q[4] += 0.5 * (Q[1:4] ** 2).sum(0) / Q[0]
+    kw = dict(GM=pars["GM"], omega=1.0, nu=1e-3, kappa=1e-3, kappa_r=1e-4, T_top=pars["chi_o"], F_bottom=0.01)
+    phys = ch.physics(precision=ch.CHORUS_MIXED, **kw)
+    cm = ch.mesh_from_arrays(m, N).upload()
+    ws = cm.workspace(phys)
+    ch.chorus_set_background(cm, phys, _dev(torch, Q0), ws)
+    R = torch.empty_like(_dev(torch, Q))
+    ch.chorus_sd_residual(cm, phys, _dev(torch, Q), R, ws)
+    Qd = _dev(torch, Q)
+    dt = 0.01
+    ch.chorus_rk_step(cm, phys, Qd, dt, 2, ws)
+    torch.cuda.synchronize()
+    Rg, Qg = R.cpu().numpy(), Qd.cpu().numpy()
+    op = oracle_mod.phys(**kw)
+    Rr = om.residual(op, Q).reshape(5, -1)
+    Rb = om.residual(op, Q0).reshape(5, -1)
+    Qr = om.rk3(op, Q, dt, 2).reshape(5, -1)
+    Qs = Q.reshape(5, -1)
+    for v in range(5):
+        err = np.linalg.norm(Rg[v] - Rr[v])
+        assert err <= 2e-5 * np.linalg.norm(Rr[v] - Rb[v]) + 1e-6 * np.linalg.norm(Rb[v]), (v, err)
+        # the last block's two elements are checked on their own too
+        last = slice((om.E - 2) * om.np, om.E * om.np)
+        assert np.abs(Rg[v, last] - Rr[v, last]).max() <= 1e-4 * np.abs(Rr[v] - Rb[v]).max() + \
+            1e-6 * np.abs(Rb[v]).max(), v
+        errq = np.linalg.norm(Qg[v] - Qr[v])
+        assert errq <= 2e-5 * np.linalg.norm(Qr[v] - Qs[v]) + 1e-13 * np.linalg.norm(Qr[v]), (v, errq)
+
+
+@pytest.mark.timeout(600)
+def test_mixed_vs_fp64_largest_workload(ch, torch_dev):
+    """The metric's gate on the largest shell (331,776 hexes, N = 4, 21.2M
+    DOFs): three SSP-RK3 steps of the mixed path against the FP64 path."""
+    torch = torch_dev
+    cfg = CONFIGS["sun_332k_N4"]
+    ri, ro = shell_params_from_config(cfg)
+    cm = ch.chorus_mesh_create(cfg["panel_n"], cfg["radial_n"], 4, ri, ro).upload()
+    print("sun_332k_N4: mesh built", flush=True)
+    Qh, pars = cm.init_polytrope(cfg["beta"], cfg["n_rho"], noise=uniform_noise(cm.n_solpts, cfg["seed"]),
+                                 amp=1e-4)
+    Q0h, _ = cm.init_polytrope(cfg["beta"], cfg["n_rho"])
+    kw = dict(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"], T_top=pars["chi_o"])
+    p64 = ch.physics(**kw)
+    pmx = ch.physics(precision=ch.CHORUS_MIXED, **kw)
+    dt = cm.stable_dt(p64, Qh, cfg["cfl"])
+    Qa = torch.from_numpy(Qh).cuda()
+    ws = cm.workspace(p64)
+    ch.chorus_rk_step(cm, p64, Qa, dt, 3, ws)
+    torch.cuda.synchronize()
+    del ws
+    wsm = cm.workspace(pmx)
+    ch.chorus_set_background(cm, pmx, torch.from_numpy(Q0h).cuda(), wsm)
+    Qb = torch.from_numpy(Qh).cuda()
+    ch.chorus_rk_step(cm, pmx, Qb, dt, 3, wsm)
+    torch.cuda.synchronize()
+    Qs = torch.from_numpy(Qh).cuda()
+    for v in range(5):
+        d = torch.linalg.vector_norm(Qb[v] - Qa[v]).item()
+        a = torch.linalg.vector_norm(Qa[v]).item()
+        ch_ = torch.linalg.vector_norm(Qa[v] - Qs[v]).item()
+        print("sun_332k_N4 variable %d: |mixed - fp64| / |fp64| = %.2e, / |change| = %.2e" % (v, d / a, d / ch_))
+        assert np.isfinite(d) and d <= 1e-6 * a, (v, d, a)
+
+
 def test_mixed_deterministic_and_mass(ch, oracle_mod, torch_dev):
     torch = torch_dev
     m, om, Q0, Q, pars = _case(oracle_mod, 3)
