@@ -153,6 +153,37 @@ def test_residual_parity_periodic_box_all_orders(ch, oracle_mod, torch_dev, N):
     assert_parity(R, om.residual(op, Qo), Rp, "box N=%d" % N)
 
 
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("dims", [(1, 1, 1), (1, 1, 3)])
+def test_residual_parity_fewer_elements_than_a_block(ch, oracle_mod, torch_dev, N, dims):
+    """One element (far-field faces all round) and three elements (periodic
+    along z): fewer elements than one block of the flux pass holds at N = 2
+    (8) and a ragged last block at N = 3 (2 per block); residual and three
+    RK3 steps."""
+    m = box_mesh(*dims, lengths=(1.0, 1.0, float(dims[2])), periodic=(False, False, dims[2] > 1))
+    om = oracle_mod.OracleMesh(m, N)
+    xyz, _ = om.solpts()
+    x, y, z = xyz
+    Q = np.stack([1 + 0.2 * np.sin(2 * np.pi * (x + y)), 0.3 + 0.1 * np.cos(2 * np.pi * z / dims[2]),
+                  -0.2 + 0.05 * np.sin(2 * np.pi * x), 0.1 * np.cos(2 * np.pi * y), 2.5 + 0.1 * np.sin(2 * np.pi * z)])
+    phys = ch.physics(GM=1.0, omega=0.5, nu=1e-2, kappa=1e-2, kappa_r=1e-3,
+                      bc_state=[1.0, 0.3, -0.2, 0.1, 2.5])
+    cm = ch.mesh_from_arrays(m, N).upload()
+    R = gpu_residual(ch, torch_dev, cm, phys, Q)
+    op = ora_phys(oracle_mod, phys)
+    Qo = Q.reshape(5, om.E, om.np)
+    Rp = perturbed_oracle(oracle_mod, m, N).residual(op, ulp_perturb(Qo))
+    assert_parity(R, om.residual(op, Qo), Rp, "E=%d N=%d" % (om.E, N))
+    torch = torch_dev
+    Qd = torch.from_numpy(np.ascontiguousarray(Q.reshape(5, -1))).cuda()
+    ch.chorus_rk_step(cm, phys, Qd, 1e-3, 3, cm.workspace(phys))
+    torch.cuda.synchronize()
+    Qr = om.rk3(op, Qo, 1e-3, 3).reshape(5, -1)
+    Qp = perturbed_oracle(oracle_mod, m, N).rk3(op, ulp_perturb(Qo), 1e-3, 3).reshape(5, -1)
+    Q0 = Q.reshape(5, -1)
+    assert_parity(Qd.cpu().numpy() - Q0, Qr - Q0, Qp - Q0, "rk3 E=%d N=%d" % (om.E, N))
+
+
 @pytest.mark.parametrize("rot", [0, 3, 7, 13, 22])
 def test_residual_parity_orientations(ch, oracle_mod, torch_dev, rot):
     m = two_element_mesh(rot)
