@@ -244,6 +244,16 @@ __device__ __forceinline__ void prologue_load(const double *Pq, const MixedBufs 
     using Sh = Shape<N, EPB, NT>;
     constexpr int NP = Sh::NP, NF2 = Sh::NF2;
     const int64_t E = G.E;
+    // issued in the order of first use, so that each phase waits only for
+    // its own inputs: links, the LDS fields, the neighbour traces (common
+    // values)
+    {
+        const int it = threadIdx.x;
+        const bool okl = it < EPB * 6 && e0 + it / 6 < E;
+        const int32_t lk = G.link[okl ? e0 * 6 + it : 0], inf = G.info[okl ? e0 * 6 + it : 0];
+        R.lk = okl ? lk : -1;
+        R.inf = okl ? inf : 0;
+    }
 #pragma unroll
     for (int k = 0; k < Sh::IT_SOL; ++k) {
         const int it = threadIdx.x + k * NT;
@@ -252,7 +262,6 @@ __device__ __forceinline__ void prologue_load(const double *Pq, const MixedBufs 
         for (int v = 0; v < 5; ++v) R.P[k][v] = Pq[((int64_t)v * E + e) * NP + p];
         R.bg[k][0] = B.bg[(e * 2 + 0) * NP + p];
         R.bg[k][1] = B.bg[(e * 2 + 1) * NP + p];
-        for (int t = 0; t < 9; ++t) R.gs[k][t] = G.solgeo[(e * 13 + t) * NP + p];
         for (int t = 0; t < 3; ++t) R.gb[k][t] = B.gbg[(e * 3 + t) * NP + p];
     }
 #pragma unroll
@@ -265,11 +274,20 @@ __device__ __forceinline__ void prologue_load(const double *Pq, const MixedBufs 
         R.db[k][0] = B.dbg[(base * 2 + 0) * NF2 + pp];
         R.db[k][1] = B.dbg[(base * 2 + 1) * NF2 + pp];
     }
-    const int it = threadIdx.x;
-    const bool okl = it < EPB * 6 && e0 + it / 6 < E;
-    const int32_t lk = G.link[okl ? e0 * 6 + it : 0], inf = G.info[okl ? e0 * 6 + it : 0];
-    R.lk = okl ? lk : -1;
-    R.inf = okl ? inf : 0;
+}
+
+// the solution-point metrics (first used by the gradients)
+template <int N, int EPB, int NT>
+__device__ __forceinline__ void prologue_load_metrics(const GeoF &G, int64_t e0, Prologue<N, EPB, NT> &R) {
+    using Sh = Shape<N, EPB, NT>;
+    constexpr int NP = Sh::NP;
+#pragma unroll
+    for (int k = 0; k < Sh::IT_SOL; ++k) {
+        const int it = threadIdx.x + k * NT;
+        const int el = it / NP, p = it % NP;
+        const int64_t e = (it < EPB * NP && e0 + el < G.E) ? e0 + el : 0;
+        for (int t = 0; t < 9; ++t) R.gs[k][t] = G.solgeo[(e * 13 + t) * NP + p];
+    }
 }
 
 // move the prologue registers into the element LDS
@@ -337,8 +355,8 @@ __device__ __forceinline__ void common_values(const OpsF<N> &op, const GeoF &G, 
         } else {
             // wall state in perturbation form: rho' kept, normal momentum
             // removed, pressure kept (outer wall with T_top: p = rho R T_top)
-            // (the normal projection is the same along +-S: the thread's face
-            // area vector Sf serves)
+            // (the normal projection is the same along +-S: the thread's
+            // flux-point metric Sf serves)
             const bool outer = ((inf >> 6) - 1) == CHORUS_BC_OUTER;
             const float *S = Sf[k];
             const float A2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
@@ -563,7 +581,9 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
     const PhysF F = physf_of(P);
     ops_to_lds(opa, op);
     // every global input of the element block, issued before the first wait
-    // (unpredicated, clamped indices: see Prologue)
+    // (unpredicated, clamped indices: see Prologue), in the order of first use
+    Prologue<N, EPB, NT> R;
+    prologue_load<N, EPB, NT>(Pq, B, G, TQ, e0, R);
     float Sf[Sh::IT_FACE][3], gSf[Sh::IT_FACE], krf[Sh::IT_FACE];
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
@@ -571,11 +591,12 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
         const int el = it / (6 * NF2), r = it % (6 * NF2), f = r / NF2, pp = r % NF2;
         const int64_t e = (it < EPB * 6 * NF2 && e0 + el < G.E) ? e0 + el : 0;
         const int d = f >> 1, fl = ((f & 1) ? N : 0) + (N + 1) * pp;
-        const float sg = (f & 1) ? 1.0f : -1.0f;
-        for (int c = 0; c < 3; ++c) Sf[k][c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
-        gSf[k] = sg * B.gS0[(e * 3 + d) * NFL + fl];
+        // along +xi_d here; the face phase turns them outward
+        for (int c = 0; c < 3; ++c) Sf[k][c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+        gSf[k] = B.gS0[(e * 3 + d) * NFL + fl];
         krf[k] = (KR == KR_RADIAL) ? G.rflux[(e * 3 + d) * NFL + fl] : 0.0f;
     }
+    prologue_load_metrics<N, EPB, NT>(G, e0, R);
     float Si[3][Sh::IT_INTD][3], gSi[3][Sh::IT_INTD], kri[3][Sh::IT_INTD];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -589,8 +610,6 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
             gSi[d][k] = B.gS0[(e * 3 + d) * NFL + fl];
             kri[d][k] = (KR == KR_RADIAL) ? G.rflux[(e * 3 + d) * NFL + fl] : 0.0f;
         }
-    Prologue<N, EPB, NT> R;
-    prologue_load<N, EPB, NT>(Pq, B, G, TQ, e0, R);
     prologue_store<N, EPB, NT>(R, L);
     __syncthreads();
     float fo[Sh::IT_FACE][NFIELD];
@@ -611,16 +630,18 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
         if (e >= G.E) continue;
         const int32_t nb = L[el].lk[f], inf = L[el].inf[f];
         const int d = f >> 1, m = (f & 1) ? N : 0, t1 = pp % N, t2 = pp / N;
+        const float sg = (f & 1) ? 1.0f : -1.0f;
+        const float So[3] = {sg * Sf[k][0], sg * Sf[k][1], sg * Sf[k][2]}, gSo = sg * gSf[k];
         float fv[5];
         PtState st;
         state_at<N>(op, L[el], m, sol_of<N>(d, 0, t1, t2), stride_of<N>(d), st, fo[k]);
         const float kr = kr_of<KR>(F, krf[k]);
         if (nb >= 0) {
-            dflux_viscous<KR>(st, Sf[k], gSf[k], F, kr, 0, fv);
+            dflux_viscous<KR>(st, So, gSo, F, kr, 0, fv);
             const int64_t slot = mailbox_slot<N>(nb, inf, pp);
             for (int v = 0; v < 5; ++v) TV[slot + v * NF2] = fv[v];
         }
-        face_flux_own<KR>(st, R.nq[k], R.db[k], nb >= 0, ((inf >> 6) - 1) == CHORUS_BC_OUTER, Sf[k], gSf[k], kr, fv,
+        face_flux_own<KR>(st, R.nq[k], R.db[k], nb >= 0, ((inf >> 6) - 1) == CHORUS_BC_OUTER, So, gSo, kr, fv,
                           F, ffc[k]);
     }
     // per direction d: transformed flux at the d-flux points, then its
