@@ -650,6 +650,16 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
 #pragma unroll
     for (int k = 0; k < Sh::IT_SOL; ++k)
         for (int v = 0; v < 5; ++v) div[k][v] = 0.0f;
+    // operands of the source and the stage combination, loaded before the
+    // last divergence so that it covers their latency (every one before the
+    // first store: the outputs may alias the inputs, and a load issued after
+    // a store would wait for it); block-uniform bases, per-lane offsets
+    // clamped to the last element
+    float r0v[Sh::IT_SOL][5], gq[Sh::IT_SOL][4];
+    double pin[Sh::IT_SOL][5], pst[Sh::IT_SOL][5], pb[Sh::IT_SOL][5];
+    const bool rk = S_.mode != 0;
+    const bool useA = rk && S_.c0 != 0.0, useT = rk && S_.Tout != nullptr, useB = useT && S_.d0 != 0.0;
+    const int elmax = (G.E - 1 - e0 < EPB - 1) ? (int)(G.E - 1 - e0) : EPB - 1;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
 #pragma unroll
@@ -681,6 +691,23 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
             for (int v = 0; v < 5; ++v) l.u.ft[v][fl] = sg * ffc[k][v];
         }
         __syncthreads();
+        if (d == 2) {
+            const float *sgb = G.solgeo + e0 * 13 * NP;
+#pragma unroll
+            for (int k = 0; k < Sh::IT_SOL; ++k) {
+                const int it = threadIdx.x + k * NT;
+                const int el = min(it / NP, elmax), p = it % NP;
+                for (int c = 0; c < 4; ++c) gq[k][c] = ld_off(sgb, (uint32_t)((el * 13 + 9 + c) * NP + p));
+                const uint32_t o = (uint32_t)(el * NP + p);
+                for (int v = 0; v < 5; ++v) {
+                    const int64_t vb = ((int64_t)v * G.E + e0) * NP;
+                    r0v[k][v] = ld_off(B.R0 + vb, o);
+                    pin[k][v] = rk ? ld_off(Pq + vb, o) : 0.0;
+                    pst[k][v] = useA ? ld_off(S_.A + vb, o) : 0.0;
+                    pb[k][v] = useB ? ld_off(S_.B + vb, o) : 0.0;
+                }
+            }
+        }
 #pragma unroll
         for (int k = 0; k < Sh::IT_SOL; ++k) {
             const int it = threadIdx.x + k * NT;
@@ -701,30 +728,8 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
         }
         __syncthreads();
     }
-    // source, background residual and stage combination: every operand of
-    // the element block loaded first (the outputs may alias the inputs, so
-    // loads issued after a store would wait for it)
-    float r0v[Sh::IT_SOL][5], gq[Sh::IT_SOL][4];
-    double pin[Sh::IT_SOL][5], pst[Sh::IT_SOL][5], pb[Sh::IT_SOL][5];
-    const bool rk = S_.mode != 0;
-    const bool useA = rk && S_.c0 != 0.0, useT = rk && S_.Tout != nullptr, useB = useT && S_.d0 != 0.0;
-    // (block-uniform bases, per-lane offsets clamped to the last element)
-    const int elmax = (G.E - 1 - e0 < EPB - 1) ? (int)(G.E - 1 - e0) : EPB - 1;
-    const float *sgb = G.solgeo + e0 * 13 * NP;
-#pragma unroll
-    for (int k = 0; k < Sh::IT_SOL; ++k) {
-        const int it = threadIdx.x + k * NT;
-        const int el = min(it / NP, elmax), p = it % NP;
-        for (int c = 0; c < 4; ++c) gq[k][c] = ld_off(sgb, (uint32_t)((el * 13 + 9 + c) * NP + p));
-        const uint32_t o = (uint32_t)(el * NP + p);
-        for (int v = 0; v < 5; ++v) {
-            const int64_t vb = ((int64_t)v * G.E + e0) * NP;
-            r0v[k][v] = ld_off(B.R0 + vb, o);
-            pin[k][v] = rk ? ld_off(Pq + vb, o) : 0.0;
-            pst[k][v] = useA ? ld_off(S_.A + vb, o) : 0.0;
-            pb[k][v] = useB ? ld_off(S_.B + vb, o) : 0.0;
-        }
-    }
+    // source, background residual and stage combination (operands loaded
+    // during the last direction's divergence)
 #pragma unroll
     for (int k = 0; k < Sh::IT_SOL; ++k) {
         const int it = threadIdx.x + k * NT;
