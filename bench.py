@@ -151,6 +151,51 @@ def large_leg(ch, workload="sun_332k_N4", steps=10):
             "path_hbm_frac": value * alg_bytes_per_stage_point(N, "mixed") * 3.0 / (HBM_PEAK_GBS * 1e9)}
 
 
+def next_rows_leg(ch, mesh, cfg, pars, Qh, Q0h, dt, ws, steps=10):
+    """The rows built after the hot path, on the same workload and mixed
+    path: the paper's five-stage fourth-order SSP integrator (DOF-updates/s,
+    one update = one five-stage step), the solar radius-dependent radiative
+    diffusivity (SSP-RK3 DOF-updates/s with the radial variant of the flux
+    pass), and the angular-momentum correction (six fixed-order sums and the
+    rigid-rotation removal, wall time per call including its host sync)."""
+    import torch
+    out = {}
+    kw = dict(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"], T_top=pars["chi_o"],
+              precision=ch.CHORUS_MIXED)
+
+    def run(phys):
+        ch.chorus_set_background(mesh, phys, torch.from_numpy(Q0h).cuda(), ws)
+        Q = torch.from_numpy(Qh).cuda()
+        ch.chorus_rk_step(mesh, phys, Q, dt, 1, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.chorus_rk_step(mesh, phys, Q, dt, steps, ws)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if not bool(torch.isfinite(Q).all()):
+            raise RuntimeError("state became non-finite")
+        return {"value": mesh.n_solpts * steps / wall, "ms_per_step": wall / steps * 1e3, "steps": steps}, Q
+
+    r54, _ = run(ch.physics(integrator=ch.CHORUS_SSPRK54, **kw))
+    out["ssprk54"] = dict(r54, unit="DOF-updates/s (five-stage steps)")
+    k0, k1, k2 = ch.solar_radiative_diffusivity(cfg["beta"], cfg["n_rho"], 2e-3, poly_n=cfg["poly_n"])
+    rkr, Q = run(ch.physics(kappa_r=k0, kappa_r1=k1, kappa_r2=k2, **kw))
+    out["radial_kappa_r"] = dict(rkr, unit="DOF-updates/s", kappa_r=[k0, k1, k2])
+    ch.chorus_am_correct(mesh, Q, ws)
+    n = 20
+    t0 = time.perf_counter()
+    for _ in range(n):
+        ch.chorus_am_correct(mesh, Q, ws)
+    wall = (time.perf_counter() - t0) / n
+    # per call and point: the sums read the coordinates, the weight, density
+    # and momentum (8 doubles); the update reads the coordinates, density,
+    # momentum and energy (8) and writes momentum and energy (4)
+    nbytes = mesh.n_solpts * 8 * (8 + 8 + 4)
+    out["am_correct"] = {"us_per_call": wall * 1e6, "hbm_GBs_incl_sync": nbytes / wall / 1e9}
+    del Q
+    return out
+
+
 def cpu_baseline(cfg, budget_s=15.0):
     """The CPU oracle on the same workload for a bounded number of steps."""
     import oracle
@@ -189,6 +234,8 @@ def main():
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-plain comparison leg")
     ap.add_argument("--no-large", action="store_true", help="skip the 331,776-hex shell leg")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the leg of the five-stage integrator, radial kappa_r and angular-momentum correction")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB 5 times (HBM counter "
@@ -311,6 +358,10 @@ def main():
         out["fp64_plain"] = {"value": mesh.n_solpts * args.steps / w64, "ms_per_step": w64 / args.steps * 1e3,
                              "speedup_mixed_over_fp64": w64 / wall}
         del Q64
+    if prec == ch.CHORUS_MIXED and not args.no_next:
+        log("five-stage integrator, radial kappa_r, angular-momentum leg")
+        out["next_rows"] = next_rows_leg(ch, mesh, cfg, pars, Qh, Q0h, dt, ws)
+        torch.cuda.synchronize()
     if prec == ch.CHORUS_MIXED and not args.no_large:
         log("large-shell leg")
         del Q, ws
