@@ -305,9 +305,8 @@ def main():
     dof_updates = mesh.n_solpts * args.steps
     value = dof_updates / wall
     # dominant kernel: the pass with the longer average launch (the flux pass
-    # of the mixed path, the residual pass of the FP64 path); it carries the
-    # line operators and pointwise fluxes, so the stage's algorithmic flops
-    # and bytes are set against its launch time
+    # of either path); it carries the line operators and pointwise fluxes, so
+    # the stage's algorithmic flops and bytes are set against its launch time
     per_launch = {k: ktimes[k][0] / max(ktimes[k][1], 1) for k in ("pass1", "pass2")}
     dom = max(per_launch, key=per_launch.get)
     kname = ch.KERNEL_NAMES[args.precision][dom]

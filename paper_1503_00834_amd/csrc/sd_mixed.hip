@@ -461,7 +461,7 @@ __device__ __forceinline__ void state_at(const OpsF<N> &op, const MixedLds<N> &l
 // along the outward area vector So.  Interior face: the Rusanov flux of the
 // own state s and the neighbour state (perturbation trace nq, background
 // jump db) minus half of the own viscous flux fv (the neighbour's half is
-// added by the residual pass from the neighbour's viscous trace).  Wall
+// added by the lift pass from the neighbour's viscous trace).  Wall
 // face: the complete wall flux (inviscid (0, p' So, 0); viscous wall form).
 template <int KR>
 __device__ __forceinline__ void face_flux_own(const PtState &s, const float nq[5], const float db[2], bool interior,
