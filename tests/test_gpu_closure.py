@@ -17,7 +17,7 @@ Tolerances:
 import numpy as np
 import pytest
 
-from chorus_inputs import cubed_sphere_shell, mlp_init, random_velocity, uniform_noise
+from chorus_inputs import box_mesh, cubed_sphere_shell, mlp_init, random_velocity, uniform_noise
 
 pytestmark = pytest.mark.gpu
 
@@ -147,6 +147,55 @@ def test_closure_residual_matches_oracle(ch, cl, oracle_mod, torch_dev):
         err = np.linalg.norm(Rg[v] - R_cl[v])
         assert err <= 2e-3 * d + 1e-11 * np.linalg.norm(R_cl[v]), (v, err, d)
     # the closure changes the residual by far more than the tolerance
+    assert np.linalg.norm(R_cl[1:] - R_pl[1:]) > 1e-3 * np.linalg.norm(R_pl[1:])
+
+
+def test_closure_odd_element_count(ch, cl, oracle_mod, torch_dev):
+    """27 hexes (a curved periodic box): the network pass's last block of
+    two elements holds one; inference and the closure residual against the
+    oracle, to the tolerances above."""
+    torch = torch_dev
+    m = box_mesh(3, 3, 3, periodic=(True,) * 3, curve=0.03)
+    om = oracle_mod.OracleMesh(m, 3)
+    assert om.E == 27
+    xyz, _ = om.solpts()
+    x, y, z = xyz
+    rho = 1 + 0.2 * np.sin(2 * np.pi * (x + y))
+    u = np.stack([0.3 * np.cos(2 * np.pi * z), -0.2 * np.sin(2 * np.pi * x), 0.25 * np.cos(2 * np.pi * y)])
+    Q = np.stack([rho, rho * u[0], rho * u[1], rho * u[2],
+                  2.5 + 0.1 * np.sin(2 * np.pi * z) + 0.5 * rho * (u ** 2).sum(0)]).reshape(5, om.E, om.np)
+    kw = dict(nu=1e-3, kappa=1e-3)
+    ph_o = oracle_mod.phys(**kw)
+    raw = cl.features(om, ph_o, Q)
+    params = mlp_init(14) * 1.5
+    norm = _norm_from(cl, raw)
+    norm[40:43] = 0.0
+    norm[55:58] = 0.0
+    want = cl.infer_bf16(params, norm, raw)
+    model = ch.chorus_closure_pack(_dev(torch, params, torch.float32), _dev(torch, norm, torch.float32))
+    phys = ch.physics(closure=ch.CHORUS_CLOSURE_MLP, closure_model=model, **kw)
+    cm = ch.mesh_from_arrays(m, 3).upload()
+    ws = cm.workspace(phys)
+    sgs = torch.zeros((15, cm.n_solpts), dtype=torch.float32, device="cuda")
+    ch.chorus_closure_infer(cm, phys, _dev(torch, Q.reshape(5, -1)), sgs, ws)
+    R = torch.empty((5, cm.n_solpts), dtype=torch.float64, device="cuda")
+    ch.chorus_sd_residual(cm, phys, _dev(torch, Q.reshape(5, -1)), R, ws)
+    torch.cuda.synchronize()
+    got = sgs.cpu().numpy().T.astype(np.float64)
+    for k in range(3, 15):
+        scale = np.abs(want[:, k]).max()
+        assert np.linalg.norm(got[:, k] - want[:, k]) <= 1e-3 * np.linalg.norm(want[:, k]) + 1e-7 * scale, k
+        # the last element (alone in its block) on its own
+        last = slice((om.E - 1) * om.np, om.E * om.np)
+        assert np.abs(got[last, k] - want[last, k]).max() <= 2e-2 * scale, k
+    tau = cl.sgs_field(om, ph_o, Q, params, norm)
+    R_cl = om.residual(ph_o, Q, tau)
+    R_pl = om.residual(ph_o, Q)
+    Rg = R.cpu().numpy().reshape(5, om.E, om.np)
+    for v in range(5):
+        d = np.linalg.norm(R_cl[v] - R_pl[v])
+        err = np.linalg.norm(Rg[v] - R_cl[v])
+        assert err <= 2e-3 * d + 1e-11 * np.linalg.norm(R_cl[v]), (v, err, d)
     assert np.linalg.norm(R_cl[1:] - R_pl[1:]) > 1e-3 * np.linalg.norm(R_pl[1:])
 
 
