@@ -196,6 +196,49 @@ def next_rows_leg(ch, mesh, cfg, pars, Qh, Q0h, dt, ws, steps=10):
     return out
 
 
+def size_sweep(ch):
+    """DOF-updates/s of both paths (SSP-RK3) on cubed-sphere shells of the
+    benchmark's stratification (beta 0.75, N_rho 3) from 288 to 331,776
+    hexes at N = 4: where the GPU fills."""
+    import torch
+    rows = []
+    for panel_n, radial_n in ((4, 3), (8, 4), (12, 6), (24, 12), (48, 24)):
+        beta, n_rho = 0.75, 3.0
+        ri, ro = beta / (1 - beta), 1 / (1 - beta)
+        mesh = ch.chorus_mesh_create(panel_n, radial_n, 4, ri, ro).upload()
+        Qh, pars = mesh.init_polytrope(beta, n_rho, noise=uniform_noise_of(mesh.n_solpts), amp=1e-4)
+        Q0h, _ = mesh.init_polytrope(beta, n_rho)
+        steps = max(5, min(200, int(4e7 / mesh.n_solpts)))
+        row = {"hexes": mesh.n_elems, "dofs": mesh.n_solpts, "steps": steps}
+        for name, prec in (("mixed", ch.CHORUS_MIXED), ("fp64", ch.CHORUS_FP64)):
+            phys = ch.physics(GM=pars["GM"], omega=1.0, nu=2e-4, kappa=2e-4, T_top=pars["chi_o"], precision=prec)
+            dt = mesh.stable_dt(phys, Qh, 0.5)
+            ws = mesh.workspace(phys)
+            if prec == ch.CHORUS_MIXED:
+                ch.chorus_set_background(mesh, phys, torch.from_numpy(Q0h).cuda(), ws)
+            Q = torch.from_numpy(Qh).cuda()
+            ch.chorus_rk_step(mesh, phys, Q, dt, 2, ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ch.chorus_rk_step(mesh, phys, Q, dt, steps, ws)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            if not bool(torch.isfinite(Q).all()):
+                raise RuntimeError("state became non-finite")
+            row[name] = mesh.n_solpts * steps / wall
+            del Q, ws
+        log("size sweep: %s" % row)
+        rows.append(row)
+        del mesh
+        torch.cuda.empty_cache()
+    return rows
+
+
+def uniform_noise_of(n):
+    from chorus_inputs import uniform_noise
+    return uniform_noise(n, 0)
+
+
 def cpu_baseline(cfg, budget_s=15.0):
     """The CPU oracle on the same workload for a bounded number of steps."""
     import oracle
@@ -237,6 +280,8 @@ def main():
     ap.add_argument("--no-next", action="store_true",
                     help="skip the leg of the five-stage integrator, radial kappa_r and angular-momentum correction")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="only measure both paths on shells from 288 to 331,776 hexes (one JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB 5 times (HBM counter "
                          "calibration under rocprofv3 --pmc)")
@@ -262,6 +307,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}))
+        return
+    if args.size_sweep:
+        print(json.dumps({"size_sweep": size_sweep(ch), "unit": "DOF-updates/s", "integrator": "SSP-RK3",
+                          "order": 4, "data": "synthetic"}), flush=True)
         return
     cfg = CONFIGS[args.workload]
     N = cfg["order"]
