@@ -226,12 +226,12 @@ int chorus_stable_dt(chorus_mesh_t mesh, const chorus_physics *phys, const doubl
  * recorded on the launch stream (no extra work is launched).
  * chorus_kernel_times waits for the recorded events and returns, per kernel
  * kind, the summed milliseconds and launch counts, then clears the record.
- * Kinds: 0 the face traces that start a call (FP64: trace kernel; mixed:
- * perturbation set-up); 1 the first pass of a stage (FP64: gradients and
- * viscous face traces; mixed: the flux pass -- gradients, fluxes,
- * divergence, source, stage combination); 2 the second pass (FP64: residual
- * and stage update; mixed: the lift pass -- neighbours' viscous halves and
- * the next face traces).  Not thread-safe; process-wide. */
+ * Kinds: 0 the face traces that start a call (FP64: trace push; mixed:
+ * perturbation set-up and its traces); 1 the first pass of a stage, the flux
+ * pass (common values, gradients, fluxes, divergence, source, stage
+ * combination); 2 the second pass, the lift pass (the neighbours' viscous
+ * halves added in place, the next face traces pushed).  Both precisions
+ * have the same two passes.  Not thread-safe; process-wide. */
 int chorus_kernel_timing(int enable);
 int chorus_kernel_times(double ms[3], int64_t counts[3]);
 
