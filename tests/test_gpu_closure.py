@@ -232,6 +232,42 @@ def test_closure_rk_steps_match_oracle(ch, cl, oracle_mod, torch_dev):
         assert np.linalg.norm(got[v] - q[v]) <= 2e-3 * dq + 1e-13 * np.linalg.norm(q[v]), v
 
 
+def test_closure_ssp54_step_matches_oracle(ch, cl, oracle_mod, torch_dev):
+    """One step of the five-stage SSP method with the closure re-evaluated at
+    every stage (the oracle's Shu-Osher table, stage sums written out)."""
+    torch = torch_dev
+    m, om, pars, Q = _shell_case(oracle_mod, seed=9)
+    kw = dict(GM=pars["GM"], omega=1.0, nu=1e-3, kappa=1e-3)
+    ph_o = oracle_mod.phys(**kw)
+    raw = cl.features(om, ph_o, Q)
+    params = mlp_init(15)
+    norm = _norm_from(cl, raw)
+    norm[40:43] = 0.0
+    norm[55:58] = 0.0
+    dt = 3e-3
+    alpha, beta = oracle_mod.ssp54_table()
+
+    def R(q):
+        return om.residual(ph_o, q, cl.sgs_field(om, ph_o, q, params, norm))
+    u = [Q.copy()]
+    L = []
+    for i in range(5):
+        L.append(R(u[i]))
+        u.append(sum(alpha[i, k] * u[k] + dt * beta[i, k] * L[k] for k in range(i + 1)))
+    q = u[5]
+    model = ch.chorus_closure_pack(_dev(torch, params, torch.float32), _dev(torch, norm, torch.float32))
+    phys = ch.physics(closure=ch.CHORUS_CLOSURE_MLP, closure_model=model, integrator=ch.CHORUS_SSPRK54, **kw)
+    cm = ch.mesh_from_arrays(m, 3).upload()
+    ws = cm.workspace(phys)
+    Qd = _dev(torch, Q.reshape(5, -1))
+    ch.chorus_rk_step(cm, phys, Qd, dt, 1, ws)
+    torch.cuda.synchronize()
+    got = Qd.cpu().numpy().reshape(5, om.E, om.np)
+    for v in range(5):
+        dq = np.linalg.norm(q[v] - Q[v])
+        assert np.linalg.norm(got[v] - q[v]) <= 2e-3 * dq + 1e-13 * np.linalg.norm(q[v]), v
+
+
 @pytest.mark.parametrize("n", [64, 300])
 def test_grad_matches_oracle(ch, cl, torch_dev, n):
     torch = torch_dev
