@@ -154,6 +154,37 @@ def test_mixed_100_steps_vs_fp64_full_workload(ch, torch_dev):
     assert max(rel) <= 1e-6, rel
 
 
+def test_mixed_vs_fp64_radial_kappa_r_full_workload(ch, torch_dev):
+    """The metric's gate with the solar radius-dependent radiative
+    diffusivity (Section 7.3) on the benchmark workload: 30 SSP-RK3 steps of
+    the mixed path against the FP64 path."""
+    torch = torch_dev
+    cfg = CONFIGS["jupiter_41k_N4"]
+    ri, ro = shell_params_from_config(cfg)
+    cm = ch.chorus_mesh_create(cfg["panel_n"], cfg["radial_n"], 4, ri, ro).upload()
+    Qh, pars = cm.init_polytrope(cfg["beta"], cfg["n_rho"], noise=uniform_noise(cm.n_solpts, cfg["seed"]),
+                                 amp=1e-4)
+    Q0h, _ = cm.init_polytrope(cfg["beta"], cfg["n_rho"])
+    k0, k1, k2 = ch.solar_radiative_diffusivity(cfg["beta"], cfg["n_rho"], 2e-3)
+    kw = dict(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"], T_top=pars["chi_o"],
+              kappa_r=k0, kappa_r1=k1, kappa_r2=k2)
+    p64 = ch.physics(**kw)
+    pmx = ch.physics(precision=ch.CHORUS_MIXED, **kw)
+    dt = cm.stable_dt(p64, Qh, cfg["cfl"])
+    Qa = torch.from_numpy(Qh).cuda()
+    ch.chorus_rk_step(cm, p64, Qa, dt, 30, cm.workspace(p64))
+    wsm = cm.workspace(pmx)
+    ch.chorus_set_background(cm, pmx, torch.from_numpy(Q0h).cuda(), wsm)
+    Qb = torch.from_numpy(Qh).cuda()
+    ch.chorus_rk_step(cm, pmx, Qb, dt, 30, wsm)
+    torch.cuda.synchronize()
+    A, B = Qa.cpu().numpy(), Qb.cpu().numpy()
+    assert np.isfinite(A).all() and np.isfinite(B).all()
+    rel = [np.linalg.norm(B[v] - A[v]) / np.linalg.norm(A[v]) for v in range(5)]
+    print("mixed vs fp64, radial kappa_r, 30 steps: rel", rel)
+    assert max(rel) <= 1e-6, rel
+
+
 @pytest.mark.parametrize("N", [2, 3, 4])
 def test_mixed_ragged_last_block(ch, oracle_mod, torch_dev, N):
     """162 hexes: the last element block of the flux pass is partly empty
