@@ -99,8 +99,31 @@ def closure_leg(panel_n=32, radial_n=16):
     simulated time.  The network's matrix-core rate is its algorithmic
     flops (2 (20*64 + 64*64 + 64*15) = 12,672 per point) over the extra
     time its pass adds to the first pass of a stage."""
+    import torch
     from paper_1503_00834_amd import closure
+    from chorus_inputs import mlp_init
     c = closure.cost_per_time(panel_n, radial_n, kernel_times=True)
+    # training (FP32, one thread per sample): Adam iterations on synthetic
+    # normalised samples, batch 4,096; about 3 x 12,672 flops per sample
+    # (forward, and a backward twice its size)
+    n, batch, iters = 1 << 20, 4096, 200
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.randn((n, 20), generator=gen, device="cuda", dtype=torch.float32)
+    Y = torch.randn((n, 15), generator=gen, device="cuda", dtype=torch.float32)
+    idx = torch.randint(0, n, (iters * batch,), generator=gen, device="cuda", dtype=torch.int32)
+    P = torch.as_tensor(mlp_init(0), dtype=torch.float32).cuda()
+    M, V = torch.zeros_like(P), torch.zeros_like(P)
+    losses = torch.zeros(iters, dtype=torch.float32, device="cuda")
+    from paper_1503_00834_amd import closure_train_workspace, chorus_closure_train
+    ws = closure_train_workspace(batch)
+    chorus_closure_train(X, Y, idx, batch, 10, P, M, V, 0, (1e-3, 0.9, 0.999, 1e-8), losses, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chorus_closure_train(X, Y, idx, batch, iters, P, M, V, 10, (1e-3, 0.9, 0.999, 1e-8), losses, ws)
+    torch.cuda.synchronize()
+    wt = time.perf_counter() - t0
+    train_sps = iters * batch / wt
+    del X, Y, idx, ws
     g_cl = c["closure"]["kernel_ms_per_launch"]["pass1"]
     g_pl = c["plain"]["kernel_ms_per_launch"]["pass1"]
     flops = 12672.0 * c["closure"]["points"]
@@ -113,7 +136,10 @@ def closure_leg(panel_n=32, radial_n=16):
             "mlp": {"bound": "mfma", "achieved": flops / dt_mlp / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
                     "frac": flops / dt_mlp / 1e12 / 2500.0, "alg_flops_per_launch": flops,
                     "note": "network time = the network pass plus the order-3 flux pass, minus the plain "
-                            "order-3 flux pass"}}
+                            "order-3 flux pass"},
+            "training": {"samples_per_s": train_sps, "batch": batch, "iters": iters,
+                         "achieved": train_sps * 3 * 12672.0 / 1e12, "unit": "TFLOP/s (FP32 vector)",
+                         "peak": 157.3}}
 
 
 def large_leg(ch, workload="sun_332k_N4", steps=10):
