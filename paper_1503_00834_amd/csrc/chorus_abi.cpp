@@ -1122,7 +1122,7 @@ static TrainLayout train_layout(int64_t B) {
     L.dZ2 = off; off = align256(off + row);
     L.dY = off;  off = align256(off + sizeof(float) * 16 * (size_t)B);
     L.lossv = off; off = align256(off + sizeof(float) * (size_t)B);
-    L.part = off;  off = align256(off + sizeof(float) * kMlpParams * (size_t)((B + 63) / 64));
+    L.part = off;  off = align256(off + sizeof(float) * (kMlpParams + 1) * (size_t)((B + 63) / 64));
     L.grad = off;  off = align256(off + sizeof(float) * kMlpParams);
     L.total = off;
     return L;

@@ -6,13 +6,15 @@
 //
 // Training is a sequence of small fixed-order kernels (no atomics), so a
 // run is bitwise reproducible:
-//   k_fwd_bwd    one thread per sample: forward pass, loss terms, and the
-//                pre-activation gradients dZ1, dZ2, dY (activations and
-//                GELU derivatives kept per sample, [t][64] rows)
-//   k_wgrad      one thread per (parameter, chunk of 64 samples): partial
-//                sums of the outer products
-//   k_wgrad_sum  chunk partials summed in chunk order
-//   k_loss       sum of the per-sample losses, fixed tree
+//   k_fwd_bwd    a block of eight waves per 64 samples (lane = sample, wave
+//                = an eighth of the hidden units of every layer): forward
+//                pass, loss terms, and the pre-activation gradients dZ1,
+//                dZ2, dY (activations and GELU derivatives kept per sample,
+//                [t][64] rows)
+//   k_wgrad      one thread per (parameter or loss, chunk of 64 samples):
+//                partial sums of the outer products and of the losses
+//   k_wgrad_sum  chunk partials summed
+// (every sum in a fixed order: four interleaved running sums, then pairwise)
 //   k_adam       Adam update (Kingma & Ba 2015) with bias correction
 #include <hip/hip_runtime.h>
 
@@ -79,127 +81,173 @@ __device__ __forceinline__ float gelu_prime_f(float z) {
     return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
-__global__ __launch_bounds__(64) void k_fwd_bwd(const float *__restrict__ X, const float *__restrict__ Y,
-                                                const int32_t *__restrict__ idx, int64_t base, int nb,
-                                                const float *__restrict__ W, TrainBufs T) {
-    const int t = blockIdx.x * 64 + threadIdx.x;
-    if (t >= nb) return;
-    const int64_t s = idx ? (int64_t)idx[base + t] : base + t;
+constexpr int kTrainWaves = 8;  // waves per 64 samples in the forward/backward pass
+
+__global__ __launch_bounds__(64 * kTrainWaves) void k_fwd_bwd(const float *__restrict__ X, const float *__restrict__ Y,
+                                                 const int32_t *__restrict__ idx, int64_t base, int nb,
+                                                 const float *__restrict__ W, TrainBufs T) {
+    constexpr int NW = kTrainWaves, QU = kMlpHid / NW;  // hidden units per wave
+    __shared__ float sh1[kMlpHid][64];              // h1[unit][sample]
+    __shared__ float syq[NW][kMlpOut][64];          // layer-3 sums over each wave's units
+    __shared__ float sdz2[kMlpHid][64];             // dz2[unit][sample]
+    const int lane = threadIdx.x & 63;
+    const int q = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int t = blockIdx.x * 64 + lane;
+    const bool ok = t < nb;
+    // lanes past the batch compute on its first sample and store nothing
+    const int64_t s = idx ? (int64_t)idx[base + (ok ? t : 0)] : base + (ok ? t : 0);
     float x[kMlpIn];
 #pragma unroll
     for (int i = 0; i < kMlpIn; ++i) x[i] = X[s * kMlpIn + i];
     float *H1 = T.H1 + (int64_t)t * 64, *G1 = T.G1 + (int64_t)t * 64;
     float *H2 = T.H2 + (int64_t)t * 64, *G2 = T.G2 + (int64_t)t * 64;
-    float h1[kMlpHid];
+    // layer 1, this wave's units
+    float g1[QU];
 #pragma unroll
-    for (int j = 0; j < kMlpHid; ++j) {
+    for (int jj = 0; jj < QU; ++jj) {
+        const int j = QU * q + jj;
         float z = W[kB1 + j];
 #pragma unroll
         for (int i = 0; i < kMlpIn; ++i) z += W[kW1 + j * kMlpIn + i] * x[i];
-        h1[j] = gelu_f(z);
-        H1[j] = h1[j];
-        G1[j] = gelu_prime_f(z);
+        const float h = gelu_f(z);
+        g1[jj] = gelu_prime_f(z);
+        sh1[j][lane] = h;
+        if (ok) {
+            H1[j] = h;
+            G1[j] = g1[jj];
+        }
     }
-    float y[kMlpOut];
+    __syncthreads();
+    // layer 2, this wave's units, and their share of layer 3
+    float g2[QU], yq[kMlpOut];
 #pragma unroll
-    for (int k = 0; k < kMlpOut; ++k) y[k] = W[kB3 + k];
+    for (int k = 0; k < kMlpOut; ++k) yq[k] = 0.0f;
 #pragma unroll 4
-    for (int j = 0; j < kMlpHid; ++j) {
+    for (int jj = 0; jj < QU; ++jj) {
+        const int j = QU * q + jj;
         float z = W[kB2 + j];
 #pragma unroll
-        for (int k = 0; k < kMlpHid; ++k) z += W[kW2 + j * kMlpHid + k] * h1[k];
+        for (int k = 0; k < kMlpHid; ++k) z += W[kW2 + j * kMlpHid + k] * sh1[k][lane];
         const float h = gelu_f(z);
-        H2[j] = h;
-        G2[j] = gelu_prime_f(z);
+        g2[jj] = gelu_prime_f(z);
+        if (ok) {
+            H2[j] = h;
+            G2[j] = g2[jj];
+        }
 #pragma unroll
-        for (int k = 0; k < kMlpOut; ++k) y[k] += W[kW3 + k * kMlpHid + j] * h;
+        for (int k = 0; k < kMlpOut; ++k) yq[k] += W[kW3 + k * kMlpHid + j] * h;
     }
+#pragma unroll
+    for (int k = 0; k < kMlpOut; ++k) syq[q][k][lane] = yq[k];
+    __syncthreads();
+    // outputs, loss and dY (every wave forms them for its own backward pass)
     float l = 0.0f, dy[kMlpOut];
     const float sc = 2.0f / ((float)T.n_mean * (float)kMlpOut);
 #pragma unroll
     for (int k = 0; k < kMlpOut; ++k) {
-        const float e = y[k] - Y[s * kMlpOut + k];
+        float p[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) p[w] = syq[w][k][lane];
+#pragma unroll
+        for (int h = NW / 2; h > 0; h /= 2)  // pairwise, fixed order
+#pragma unroll
+            for (int w = 0; w < h; ++w) p[w] += p[w + h];
+        const float y = W[kB3 + k] + p[0];
+        const float e = y - Y[s * kMlpOut + k];
         l += e * e;
         dy[k] = sc * e;
-        T.dY[(int64_t)t * 16 + k] = dy[k];
     }
-    T.lossv[t] = l;
-    // back through layers 3 and 2: dZ2_j = (sum_k W3[k][j] dY_k) gelu'(z2_j),
-    // dH1_k = sum_j W2[j][k] dZ2_j
-    float dh1[kMlpHid];
+    if (q == 0 && ok) {
 #pragma unroll
-    for (int k = 0; k < kMlpHid; ++k) dh1[k] = 0.0f;
+        for (int k = 0; k < kMlpOut; ++k) T.dY[(int64_t)t * 16 + k] = dy[k];
+        T.lossv[t] = l;
+    }
+    // back through layer 3 to this wave's layer-2 units:
+    // dZ2_j = (sum_k W3[k][j] dY_k) gelu'(z2_j)
     float *dZ2 = T.dZ2 + (int64_t)t * 64, *dZ1 = T.dZ1 + (int64_t)t * 64;
-#pragma unroll 4
-    for (int j = 0; j < kMlpHid; ++j) {
+#pragma unroll
+    for (int jj = 0; jj < QU; ++jj) {
+        const int j = QU * q + jj;
         float a = 0.0f;
 #pragma unroll
         for (int k = 0; k < kMlpOut; ++k) a += W[kW3 + k * kMlpHid + j] * dy[k];
-        const float dz = a * G2[j];
-        dZ2[j] = dz;
-#pragma unroll
-        for (int k = 0; k < kMlpHid; ++k) dh1[k] += W[kW2 + j * kMlpHid + k] * dz;
+        const float dz = a * g2[jj];
+        sdz2[j][lane] = dz;
+        if (ok) dZ2[j] = dz;
     }
+    __syncthreads();
+    // back through layer 2 to this wave's layer-1 units:
+    // dZ1_k = (sum_j W2[j][k] dZ2_j) gelu'(z1_k)
+#pragma unroll 4
+    for (int kk = 0; kk < QU; ++kk) {
+        const int k = QU * q + kk;
+        float dh = 0.0f;
 #pragma unroll
-    for (int k = 0; k < kMlpHid; ++k) dZ1[k] = dh1[k] * G1[k];
+        for (int j = 0; j < kMlpHid; ++j) dh += W[kW2 + j * kMlpHid + k] * sdz2[j][lane];
+        if (ok) dZ1[k] = dh * g1[kk];
+    }
+}
+
+// sum of f(t) for t0 <= t < t1 in a fixed order: four interleaved running
+// sums (t = t0 + 4u + r in sum r), combined pairwise
+template <typename Fn>
+__device__ __forceinline__ float fixed_sum(int t0, int t1, Fn f) {
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    int t = t0;
+    for (; t + 3 < t1; t += 4) {
+        a0 += f(t);
+        a1 += f(t + 1);
+        a2 += f(t + 2);
+        a3 += f(t + 3);
+    }
+    if (t < t1) a0 += f(t);
+    if (t + 1 < t1) a1 += f(t + 1);
+    if (t + 2 < t1) a2 += f(t + 2);
+    return (a0 + a1) + (a2 + a3);
 }
 
 // partial sums over chunk c (samples 64c .. 64c+63) of each parameter's
-// gradient: part[c][q]
+// gradient and (q = kMlpParams) of the losses: part[c][q]
 __global__ __launch_bounds__(64) void k_wgrad(const float *__restrict__ X, const int32_t *__restrict__ idx,
                                               int64_t base, int nb, TrainBufs T) {
     const int q = blockIdx.x * 64 + threadIdx.x, c = blockIdx.y;
-    if (q >= kMlpParams) return;
+    if (q > kMlpParams) return;
     const int t0 = 64 * c, t1 = min(nb, t0 + 64);
-    float s = 0.0f;
-    if (q < kB1) {
+    float s;
+    if (q == kMlpParams) {
+        s = fixed_sum(t0, t1, [&](int t) { return T.lossv[t]; });
+    } else if (q < kB1) {
         const int j = q / kMlpIn, i = q % kMlpIn;
-        for (int t = t0; t < t1; ++t) {
+        s = fixed_sum(t0, t1, [&](int t) {
             const int64_t smp = idx ? (int64_t)idx[base + t] : base + t;
-            s += T.dZ1[(int64_t)t * 64 + j] * X[smp * kMlpIn + i];
-        }
+            return T.dZ1[(int64_t)t * 64 + j] * X[smp * kMlpIn + i];
+        });
     } else if (q < kW2) {
         const int j = q - kB1;
-        for (int t = t0; t < t1; ++t) s += T.dZ1[(int64_t)t * 64 + j];
+        s = fixed_sum(t0, t1, [&](int t) { return T.dZ1[(int64_t)t * 64 + j]; });
     } else if (q < kB2) {
         const int j = (q - kW2) / kMlpHid, k = (q - kW2) % kMlpHid;
-        for (int t = t0; t < t1; ++t) s += T.dZ2[(int64_t)t * 64 + j] * T.H1[(int64_t)t * 64 + k];
+        s = fixed_sum(t0, t1, [&](int t) { return T.dZ2[(int64_t)t * 64 + j] * T.H1[(int64_t)t * 64 + k]; });
     } else if (q < kW3) {
         const int j = q - kB2;
-        for (int t = t0; t < t1; ++t) s += T.dZ2[(int64_t)t * 64 + j];
+        s = fixed_sum(t0, t1, [&](int t) { return T.dZ2[(int64_t)t * 64 + j]; });
     } else if (q < kB3) {
         const int k = (q - kW3) / kMlpHid, j = (q - kW3) % kMlpHid;
-        for (int t = t0; t < t1; ++t) s += T.dY[(int64_t)t * 16 + k] * T.H2[(int64_t)t * 64 + j];
+        s = fixed_sum(t0, t1, [&](int t) { return T.dY[(int64_t)t * 16 + k] * T.H2[(int64_t)t * 64 + j]; });
     } else {
         const int k = q - kB3;
-        for (int t = t0; t < t1; ++t) s += T.dY[(int64_t)t * 16 + k];
+        s = fixed_sum(t0, t1, [&](int t) { return T.dY[(int64_t)t * 16 + k]; });
     }
-    T.part[(int64_t)c * kMlpParams + q] = s;
+    T.part[(int64_t)c * (kMlpParams + 1) + q] = s;
 }
 
-__global__ __launch_bounds__(64) void k_wgrad_sum(int nchunk, const float *__restrict__ part,
-                                                  float *__restrict__ grad) {
+__global__ __launch_bounds__(64) void k_wgrad_sum(int nchunk, const float *__restrict__ part, int64_t n_mean,
+                                                  float *__restrict__ grad, float *__restrict__ loss) {
     const int q = blockIdx.x * 64 + threadIdx.x;
-    if (q >= kMlpParams) return;
-    float s = 0.0f;
-    for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * kMlpParams + q];
-    grad[q] = s;
-}
-
-// loss = sum_t lossv[t] / (n_mean * 15): each lane sums a fixed strided
-// subset, then a fixed LDS tree
-__global__ __launch_bounds__(64) void k_loss(const float *__restrict__ lossv, int nb, int64_t n_mean,
-                                             float *__restrict__ out) {
-    __shared__ float red[64];
-    float s = 0.0f;
-    for (int t = threadIdx.x; t < nb; t += 64) s += lossv[t];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 32; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = red[0] / ((float)n_mean * (float)kMlpOut);
+    if (q > kMlpParams) return;
+    const float s = fixed_sum(0, nchunk, [&](int c) { return part[(int64_t)c * (kMlpParams + 1) + q]; });
+    if (q < kMlpParams) grad[q] = s;
+    else loss[0] = s / ((float)n_mean * (float)kMlpOut);
 }
 
 __global__ __launch_bounds__(64) void k_adam(float *__restrict__ W, float *__restrict__ m, float *__restrict__ v,
@@ -291,17 +339,14 @@ hipError_t launch_pack(const float *W, const float *norm, unsigned char *model, 
 hipError_t launch_train_grad(const float *X, const float *Y, const int32_t *idx, int64_t base, int nb,
                              const float *W, const TrainBufs &T, float *grad, float *loss, hipStream_t s) {
     const int nchunk = (nb + 63) / 64;
-    hipLaunchKernelGGL(k_fwd_bwd, dim3(nchunk), dim3(64), 0, s, X, Y, idx, base, nb, W, T);
+    hipLaunchKernelGGL(k_fwd_bwd, dim3(nchunk), dim3(64 * kTrainWaves), 0, s, X, Y, idx, base, nb, W, T);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad, dim3((kMlpParams + 63) / 64, nchunk), dim3(64), 0, s, X, idx, base, nb, T);
+    hipLaunchKernelGGL(k_wgrad, dim3((kMlpParams + 1 + 63) / 64, nchunk), dim3(64), 0, s, X, idx, base, nb, T);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad_sum, dim3((kMlpParams + 63) / 64), dim3(64), 0, s, nchunk, (const float *)T.part,
-                       grad);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_loss, dim3(1), dim3(64), 0, s, (const float *)T.lossv, nb, T.n_mean, loss);
+    hipLaunchKernelGGL(k_wgrad_sum, dim3((kMlpParams + 1 + 63) / 64), dim3(64), 0, s, nchunk,
+                       (const float *)T.part, T.n_mean, grad, loss);
     return hipGetLastError();
 }
 

@@ -67,7 +67,7 @@ struct TrainBufs {
     float *H1, *G1, *H2, *G2, *dZ1, *dZ2;  // [nb][64]: activations, GELU derivatives, gradients
     float *dY;                             // [nb][16]
     float *lossv;                          // [nb]
-    float *part;                           // [ceil(nb/64)][6479] chunk partial gradients
+    float *part;                           // [ceil(nb/64)][6480] chunk partial gradients and losses
     int64_t n_mean;                        // samples the loss is averaged over
 };
 
