@@ -154,11 +154,10 @@ __global__ __launch_bounds__(NT) void k_trace(Ops<N> opa, Geo G, const double *_
 
 // learned subgrid flux at the solution points of the block's elements (one
 // wave, all points in 16-point tiles): features (Q, grad Q) -> network ->
-// stau (LDS) and tau[k][E][NP] (global)
+// tau[k][E][NP] (global)
 template <int N, int EPB, int NT>
 __device__ __forceinline__ void closure_tau(const ClosureArgs &C, int64_t E, int64_t e0,
-                                            double (*sq)[5][N * N * N], double (*sgr)[15][N * N * N],
-                                            float (*stau)[15][N * N * N]) {
+                                            double (*sq)[5][N * N * N], double (*sgr)[15][N * N * N]) {
     constexpr int NP = N * N * N, NPTS = EPB * NP, NPT = (NPTS + 15) / 16;
     static_assert(NT == 64, "the closure runs one wave per block");
     const int lane = threadIdx.x, g = lane >> 4;
@@ -190,8 +189,7 @@ __device__ __forceinline__ void closure_tau(const ClosureArgs &C, int64_t E, int
         for (int i = 0; i < 4; ++i) {
             const int k = 4 * g + i;
             if (k >= kMlpOut) continue;
-            stau[el][k][sp] = out[pt][i];
-            if (C.tau) C.tau[((int64_t)k * E + e0 + el) * NP + sp] = out[pt][i];
+            C.tau[((int64_t)k * E + e0 + el) * NP + sp] = out[pt][i];
         }
     }
 }
@@ -327,7 +325,7 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
         double sqs[EPB][6][5][NF2];
         double sft[EPB][5][NFL];
     } U;
-    __shared__ float stau[CL ? EPB : 1][15][CL ? NP : 1];
+    __shared__ float stau[PART == 2 ? EPB : 1][15][PART == 2 ? NP : 1];  // subgrid flux read back (PART 2)
     __shared__ int32_t lk[EPB][6], inf[EPB][6];
     __shared__ Ops<N> op;
     const int64_t e0 = (int64_t)blockIdx.x * EPB, E = G.E;
@@ -446,7 +444,7 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
     __syncthreads();
     if constexpr (PART == 1) {
         // subgrid flux at the solution points -> C.tau
-        closure_tau<N, EPB, NT>(C, E, e0, sq, sgr, stau);
+        closure_tau<N, EPB, NT>(C, E, e0, sq, sgr);
         return;
     }
     // face points: own viscous flux to the neighbour, own-side common flux
