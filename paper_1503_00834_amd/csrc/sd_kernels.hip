@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "launch.hpp"
 #include "mlp_bf16.hpp"
@@ -155,9 +156,9 @@ __global__ __launch_bounds__(NT) void k_trace(Ops<N> opa, Geo G, const double *_
 // learned subgrid flux at the solution points of the block's elements (one
 // wave, all points in 16-point tiles): features (Q, grad Q) -> network ->
 // tau[k][E][NP] (global)
-template <int N, int EPB, int NT>
+template <int N, int EPB, int NT, typename GT>
 __device__ __forceinline__ void closure_tau(const ClosureArgs &C, int64_t E, int64_t e0,
-                                            double (*sq)[5][N * N * N], double (*sgr)[15][N * N * N]) {
+                                            double (*sq)[5][N * N * N], GT (*sgr)[15][N * N * N]) {
     constexpr int NP = N * N * N, NPTS = EPB * NP, NPT = (NPTS + 15) / 16;
     static_assert(NT == 64, "the closure runs one wave per block");
     const int lane = threadIdx.x, g = lane >> 4;
@@ -173,7 +174,7 @@ __device__ __forceinline__ void closure_tau(const ClosureArgs &C, int64_t E, int
             const int f = 8 * g + i;
             double raw = 0.0;
             if (ok && f < 5) raw = sq[el][f][sp];
-            else if (ok && f < 20) raw = sgr[el][f - 5][sp];
+            else if (ok && f < 20) raw = (double)sgr[el][f - 5][sp];
             x[i] = (ok && f < 20) ? mlp_norm_feature(C.model, f, raw) : 0.0f;
         }
         xb[pt] = u32x4_t{bf16_pair(x[0], x[1]), bf16_pair(x[2], x[3]), bf16_pair(x[4], x[5]), bf16_pair(x[6], x[7])};
@@ -318,7 +319,10 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
     using Sh = Sh64<N, EPB, NT>;
     constexpr int NP = Sh::NP, NF2 = Sh::NF2, NFL = Sh::NFL, NINTD = Sh::NINTD;
     __shared__ double sq[EPB][5][NP];
-    __shared__ double sgr[EPB][15][NP];
+    // gradients at the solution points (the network-only pass keeps them in
+    // FP32: they are network inputs, rounded to bfloat16 after
+    // normalisation)
+    __shared__ std::conditional_t<PART == 1, float, double> sgr[EPB][15][NP];
     // the common solution is consumed by the gradients before the first
     // direction's fluxes are written
     __shared__ union {
