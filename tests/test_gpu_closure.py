@@ -4,7 +4,8 @@ Tolerances:
   * bfloat16 inference: the oracle follows the kernel's precision steps
     (normalised features, weights and hidden activations rounded to
     bfloat16, nearest-even) but sums in FP64 and uses the FP64 erf; the
-    kernel sums in FP32 with the FP32 erff.  A hidden activation whose FP32
+    kernel sums in FP32 with an FP32 erf approximation (|error| <= 1.5e-7)
+    and holds the gradient features in FP32 before normalising them.  A hidden activation whose FP32
     and FP64 values straddle a bfloat16 rounding boundary differs by one
     bfloat16 ulp (2^-8 relative); these are rare (~1e-7 / 4e-3 per value),
     so the output error is held to 1e-3 of the output norm per component,
