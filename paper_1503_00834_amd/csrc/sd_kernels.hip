@@ -609,7 +609,11 @@ __global__ __launch_bounds__(NT) void k_lift64(Ops<N> opa, Geo G, const double *
     __shared__ double sq[EPB][5][NP];      // the new state, for the traces
     __shared__ int32_t lk[EPB][6], inf[EPB][6];
     __shared__ Ops<N> op;
-    const int64_t e0 = (int64_t)blockIdx.x * EPB, E = G.E;
+    // blocks walk the elements from the last to the first: the flux pass
+    // before ran from the first to the last, so the first blocks here read
+    // its latest writes, which are still in the memory-side cache; the next
+    // flux pass starts where this pass ends, for the same reason
+    const int64_t e0 = (int64_t)(gridDim.x - 1 - blockIdx.x) * EPB, E = G.E;
     const bool useT = S_.mode != 0 && S_.Tout != nullptr;
     // every global input first (unpredicated, clamped; the mailbox slots of
     // boundary faces are never written and are selected away below)

@@ -776,7 +776,11 @@ __global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> opa, GeoF G, const fl
     __shared__ float nv[EPB][6][5][NF2];  // neighbours' viscous flux at own face points, 0 on boundary faces
     __shared__ float sp[EPB][5][NP];      // new perturbation (FP32) for the traces
     __shared__ int32_t lk[EPB][6], inf[EPB][6];
-    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    // blocks walk the elements from the last to the first: the flux pass
+    // before ran from the first to the last, so the first blocks here read
+    // its latest writes, which are still in the memory-side cache; the next
+    // flux pass starts where this pass ends, for the same reason
+    const int64_t e0 = (int64_t)(gridDim.x - 1 - blockIdx.x) * EPB;
     const bool useT = S_.mode != 0 && S_.Tout != nullptr;
     // every global input first: face links, the viscous mailbox (boundary
     // slots too: never written, selected away below), outputs of the flux
