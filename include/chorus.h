@@ -177,7 +177,12 @@ typedef struct {
 int chorus_init_afb(chorus_mesh_t mesh, const chorus_afb_desc *desc, double *Q_host, double pars[6]);
 
 /* Mixed mode: register the background state Q0 (device, [5][E N^3] FP64)
- * and compute its FP64 inviscid residual into the workspace.  Synchronises. */
+ * and compute, once, its complete FP64 residual R(Q0) and the background
+ * arrays into the workspace.  Synchronises.  Q0 must be at rest (zero
+ * momentum; CHORUS_EINVAL otherwise); CHORUS_BC_STATE faces are not
+ * supported (CHORUS_ENOTSUP).  A failed call leaves no background
+ * registered: chorus_rk_step and chorus_sd_residual in mixed precision
+ * then return CHORUS_ESTATE until a call succeeds. */
 int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q0_dev,
                           void *ws, void *stream);
 

@@ -682,6 +682,11 @@ int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const 
             set_error("mixed precision supports interior and wall faces only");
             return CHORUS_ENOTSUP;
         }
+    // the workspace's background arrays are rewritten from here on: until
+    // this call succeeds no background is registered (a failed call leaves
+    // none, not the previous one half overwritten)
+    m->bg_ready = false;
+    m->bg_ws = nullptr;
     const WsLayout w = ws_layout(*m);
     unsigned char *W = (unsigned char *)ws;
     hipStream_t s = (hipStream_t)stream;

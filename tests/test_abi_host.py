@@ -51,6 +51,30 @@ def test_errors_are_reported(ch):
     assert ei.value.status == -2
 
 
+
+def test_empty_and_degenerate_meshes_rejected(ch):
+    """Empty meshes, orders outside 2..6 and degenerate shells are argument
+    errors (CHORUS_EINVAL) reported on the host, before any device work."""
+    bad_shells = [(0, 2, 3, 2.0, 3.0), (2, 0, 3, 2.0, 3.0), (2, 2, 3, 0.0, 3.0), (2, 2, 3, 3.0, 3.0),
+                  (2, 2, 3, 3.0, 2.0), (2, 2, 3, float("nan"), 3.0), (2, 2, 1, 2.0, 3.0), (2, 2, 7, 2.0, 3.0)]
+    for args in bad_shells:
+        with pytest.raises(ch.ChorusError) as ei:
+            ch.chorus_mesh_create(*args)
+        assert ei.value.status == -1, args
+    m = box_mesh(2, 2, 2)
+    with pytest.raises(ch.ChorusError) as ei:
+        ch.chorus_mesh_create_hex20(m.xyz, m.elem20[:0], m.face_bc[:0], 3)
+    assert ei.value.status == -1
+    for order in (1, 7):
+        with pytest.raises(ch.ChorusError) as ei:
+            ch.chorus_mesh_create_hex20(m.xyz, m.elem20, m.face_bc, order)
+        assert ei.value.status == -1, order
+    # the smallest valid meshes: one shell element per panel and layer, one hex
+    sm = ch.chorus_mesh_create(1, 1, 2, 2.0, 3.0)
+    assert sm.n_solpts == 6 * 8
+    one = box_mesh(1, 1, 1)
+    assert ch.chorus_mesh_create_hex20(one.xyz, one.elem20, one.face_bc, 2).n_solpts == 8
+
 @pytest.mark.parametrize("N", [3, 4])
 def test_geometry_matches_oracle(ch, oracle_mod, N):
     m = cubed_sphere_shell(3, 2, 7.0 / 3.0, 10.0 / 3.0)

@@ -253,6 +253,47 @@ def test_check_finite_flag(ch, oracle_mod, torch_dev):
     assert ei.value.status == -5
 
 
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_rk_step_argument_edges(ch, oracle_mod, torch_dev, precision):
+    """Zero steps leave the state bitwise unchanged; a negative step count or
+    a non-finite dt is an argument error (CHORUS_EINVAL) that leaves the
+    state untouched; the mixed path without a background for this workspace
+    is a call-order error (CHORUS_ESTATE)."""
+    torch = torch_dev
+    m, om, Q, phys = shell_case(oracle_mod, ch, 2, 2, 4)
+    if precision == "mixed":
+        phys.precision = ch.CHORUS_MIXED
+    cm = ch.mesh_from_arrays(m, 4).upload()
+    ws = cm.workspace(phys)
+    Qd = torch.from_numpy(np.ascontiguousarray(Q.reshape(5, -1))).cuda()
+    if precision == "mixed":
+        with pytest.raises(ch.ChorusError) as ei:
+            ch.chorus_rk_step(cm, phys, Qd, 0.01, 1, ws)
+        assert ei.value.status == -6
+        Q0 = torch.from_numpy(np.ascontiguousarray(om.polytrope(0.7, 1.0)[0].reshape(5, -1))).cuda()
+        ch.chorus_set_background(cm, phys, Q0, ws)
+        # a background with momentum is rejected and unregisters the previous one
+        with pytest.raises(ch.ChorusError) as ei:
+            ch.chorus_set_background(cm, phys, Qd.clone(), ws)
+        assert ei.value.status == -1
+        with pytest.raises(ch.ChorusError) as ei:
+            ch.chorus_rk_step(cm, phys, Qd, 0.01, 1, ws)
+        assert ei.value.status == -6
+        ch.chorus_set_background(cm, phys, Q0, ws)
+    ch.chorus_rk_step(cm, phys, Qd, 0.01, 0, ws)
+    for n, dt in ((-1, 0.01), (1, float("nan")), (1, float("inf"))):
+        with pytest.raises(ch.ChorusError) as ei:
+            ch.chorus_rk_step(cm, phys, Qd, dt, n, ws)
+        assert ei.value.status == -1, (n, dt)
+    torch.cuda.synchronize()
+    assert np.array_equal(Qd.cpu().numpy(), Q.reshape(5, -1))
+    # and a real step after the rejected calls still runs
+    ch.chorus_rk_step(cm, phys, Qd, 0.01, 1, ws)
+    torch.cuda.synchronize()
+    out = Qd.cpu().numpy()
+    assert np.isfinite(out).all() and not np.array_equal(out, Q.reshape(5, -1))
+
 def test_full_size_jupiter_workload(ch, oracle_mod, torch_dev):
     """The benchmark workload at full size (41,472 hexes, N=4, 2.65M DOFs),
     built the way bench.py builds it (library shell generator), against the
