@@ -73,7 +73,11 @@ __device__ __forceinline__ float gelu_bf(float z) {
     h = fmaf(h, t, 0.5f * 0.254829592f);
     // exp(-z^2 / 2) as a power of two
     const float e = __builtin_amdgcn_exp2f(z * z * (-0.5f * 1.4426950408889634f));
-    return fmaf(-az, h * t * e, fmaxf(z, 0.0f));
+    // max(z, 0) as a signed-integer max of the bit pattern (a negative float
+    // is a negative integer): the same value for every non-NaN z, one
+    // instruction, where a float max of an accumulator first canonicalises it
+    const float zp = __builtin_bit_cast(float, max(__builtin_bit_cast(int, z), 0));
+    return fmaf(-az, h * t * e, zp);
 }
 
 // K index held by lane group g (= lane / 16), slot i (0..7) of the B
