@@ -242,6 +242,43 @@ def test_linear_velocity_viscous_exact(oracle_mod):
     assert np.abs(R_v[1:4]).max() > 1e-8
 
 
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_linear_velocity_and_pressure_euler_exact(oracle_mod, N):
+    """u = U + A x, p = p0 + b.x, uniform rho, no viscosity, gravity or
+    rotation, on an affine box: Q is at most quadratic in x and every flux
+    (rho u u + p I, (E + p) u) at most cubic, so at N >= 3 the flux
+    polynomials and the (continuous) interface fluxes are exact and the SD
+    residual of an interior element is the exact Euler dQ/dt (Section 2):
+        d rho/dt = -rho tr A
+        d m/dt   = -rho (A u + u tr A) - b
+        d E/dt   = -(u.grad E + (E + p) tr A + u.b),  grad E = b/(gamma-1) + rho A^T u.
+    Pins the inviscid momentum and energy fluxes with their pressure terms
+    (an energy flux E u instead of (E + p) u, a pressure without its
+    gamma - 1 factor or a transposed velocity gradient all fail)."""
+    m = box_mesh(3, 3, 3, lengths=(1.0, 1.2, 0.9), origin=(-0.5, -0.6, -0.45))
+    om = oracle_mod.OracleMesh(m, N)
+    xyz, _ = om.solpts()
+    A = np.array([[0.3, -0.2, 0.5], [0.1, -0.4, 0.25], [-0.3, 0.2, 0.15]])
+    U = np.array([0.2, -0.1, 0.05])
+    b = np.array([0.3, -0.5, 0.2])
+    rho, p0, gam = 1.3, 2.0, 5.0 / 3.0
+    u = U[:, None] + A @ xyz
+    p = p0 + b @ xyz
+    E = p / (gam - 1) + 0.5 * rho * (u ** 2).sum(0)
+    Q = np.concatenate([np.full((1, xyz.shape[1]), rho), rho * u, E[None]]).reshape(5, om.E, om.np)
+    R = om.residual(oracle_mod.phys(gamma=gam), Q).reshape(5, -1)
+    trA = np.trace(A)
+    gradE = b[:, None] / (gam - 1) + rho * (A.T @ u)
+    exact = np.concatenate([np.full((1, xyz.shape[1]), -rho * trA),
+                            -rho * (A @ u + u * trA) - b[:, None],
+                            -((u * gradE).sum(0) + (E + p) * trA + b @ u)[None]])
+    centre = 1 + 3 * (1 + 3 * 1)
+    sl = slice(centre * om.np, (centre + 1) * om.np)
+    for v in range(5):
+        np.testing.assert_allclose(R[v, sl], exact[v, sl], rtol=1e-11, atol=1e-11 * np.abs(exact[v]).max(),
+                                   err_msg="variable %d" % v)
+
 def _density_wave(om, t, amp=0.2, u=(0.5, 0.3, 0.2), p=1.0, gam=5.0 / 3.0):
     xyz, _ = om.solpts()
     k = 2 * np.pi * np.ones(3)
