@@ -327,6 +327,39 @@ def test_rusanov_dissipates(oracle_mod):
     assert all(b < a for a, b in zip(norms, norms[1:])), norms
 
 
+
+@pytest.mark.parametrize("w", [0.0, 0.4])
+def test_rusanov_dissipation_coefficient(oracle_mod, w):
+    """Two contact discontinuities in a periodic box: density rho_L for
+    x < 1/2 and rho_R above, uniform pressure and velocity (w, 0, 0).  Inside
+    each element the state is constant, so the residual comes from the
+    interface fluxes alone, and the scheme's discrete conservation makes the
+    quadrature sum of the mass residual over the rho_L half equal to minus
+    its net outflow: with the Rusanov flux at both x-interfaces (the central
+    parts cancel),
+        d/dt int_{x < 1/2} rho = lambda (rho_R - rho_L) A,
+    lambda = |w| + max(c_L, c_R), A the area of one x-interface (Section 3's
+    interface flux; the planes x = 0 and 1/2 stay flat under the box's
+    curvature field).  Fails for a wave speed without the sound speed, the
+    mean instead of the larger speed, or a missing 1/2."""
+    Ly, Lz, gam, p = 0.8, 0.6, 5.0 / 3.0, 1.2
+    m = box_mesh(4, 3, 3, lengths=(1.0, Ly, Lz), periodic=(True,) * 3, curve=0.02)
+    om = oracle_mod.OracleMesh(m, 3)
+    xyz, wJ = om.solpts()
+    rL, rR = 0.7, 1.6
+    cx = xyz[0].reshape(om.E, om.np).mean(1)
+    left = np.repeat(cx < 0.5, om.np)
+    rho = np.where(left, rL, rR)
+    z = np.zeros_like(rho)
+    Q = np.stack([rho, rho * w, z, z, p / (gam - 1) + 0.5 * rho * w * w]).reshape(5, om.E, om.np)
+    R = om.residual(oracle_mod.phys(gamma=gam), Q).reshape(5, -1)
+    lam = abs(w) + max(math.sqrt(gam * p / rL), math.sqrt(gam * p / rR))
+    expect = lam * (rR - rL) * Ly * Lz
+    got = (wJ * R[0])[left].sum()
+    assert abs(got - expect) <= 1e-12 * abs(expect), (got, expect)
+    # the rho_R half loses exactly that mass
+    assert abs((wJ * R[0])[~left].sum() + expect) <= 1e-12 * abs(expect)
+
 def test_rk3_linear_amplification(oracle_mod):
     """Uniform state with only Coriolis: a linear ODE whose exact SSP-RK3
     update is the polynomial 1 + z + z^2/2 + z^3/6 of dt L."""
