@@ -153,6 +153,75 @@ def test_residual_parity_periodic_box_all_orders(ch, oracle_mod, torch_dev, N):
     assert_parity(R, om.residual(op, Qo), Rp, "box N=%d" % N)
 
 
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_linear_velocity_and_pressure_euler_exact_gpu(ch, oracle_mod, torch_dev, N):
+    """Closed-form pin of the FP64 kernels, no oracle values: u = U + A x,
+    p = p0 + b.x, uniform rho on an affine box (every flux at most cubic,
+    exact at N >= 3), so the residual of the interior element is the exact
+    Euler dQ/dt of Section 2 (the same state as the oracle's pin)."""
+    m = box_mesh(3, 3, 3, lengths=(1.0, 1.2, 0.9), origin=(-0.5, -0.6, -0.45))
+    cm = ch.mesh_from_arrays(m, N).upload()
+    xyz, _ = cm.solpts()
+    A = np.array([[0.3, -0.2, 0.5], [0.1, -0.4, 0.25], [-0.3, 0.2, 0.15]])
+    U = np.array([0.2, -0.1, 0.05])
+    b = np.array([0.3, -0.5, 0.2])
+    rho, p0, gam = 1.3, 2.0, 5.0 / 3.0
+    u = U[:, None] + A @ xyz
+    p = p0 + b @ xyz
+    E = p / (gam - 1) + 0.5 * rho * (u ** 2).sum(0)
+    Q = np.concatenate([np.full((1, xyz.shape[1]), rho), rho * u, E[None]])
+    R = gpu_residual(ch, torch_dev, cm, ch.physics(gamma=gam), Q)
+    trA = np.trace(A)
+    gradE = b[:, None] / (gam - 1) + rho * (A.T @ u)
+    exact = np.concatenate([np.full((1, xyz.shape[1]), -rho * trA),
+                            -rho * (A @ u + u * trA) - b[:, None],
+                            -((u * gradE).sum(0) + (E + p) * trA + b @ u)[None]])
+    NP = N ** 3
+    sl = slice(13 * NP, 14 * NP)  # the centre element of the 3 x 3 x 3 box
+    for v in range(5):
+        np.testing.assert_allclose(R[v, sl], exact[v, sl], rtol=1e-11, atol=1e-11 * np.abs(exact[v]).max(),
+                                   err_msg="variable %d" % v)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("w", [0.0, 0.4])
+def test_rusanov_dissipation_coefficient_gpu(ch, oracle_mod, torch_dev, precision, w):
+    """Closed-form pin of the interface flux of both paths, no oracle values:
+    two contact discontinuities in a periodic box (density rho_L for x < 1/2,
+    rho_R above, uniform p and velocity (w, 0, 0)); by discrete conservation
+    the quadrature sum of the mass residual over the rho_L half is
+    lambda (rho_R - rho_L) A with lambda = |w| + max(c_L, c_R) (the oracle's
+    pin, same state).  Mixed path: background at rest with the same
+    pressure, so the FP32 part carries the whole jump; bound 1e-6 relative."""
+    torch = torch_dev
+    Ly, Lz, gam, p = 0.8, 0.6, 5.0 / 3.0, 1.2
+    N = 4
+    m = box_mesh(4, 3, 3, lengths=(1.0, Ly, Lz), periodic=(True,) * 3, curve=0.02)
+    cm = ch.mesh_from_arrays(m, N).upload()
+    xyz, wJ = cm.solpts()
+    rL, rR = 0.7, 1.6
+    left = np.repeat(xyz[0].reshape(-1, N ** 3).mean(1) < 0.5, N ** 3)
+    rho = np.where(left, rL, rR)
+    z = np.zeros_like(rho)
+    Q = np.stack([rho, rho * w, z, z, p / (gam - 1) + 0.5 * rho * w * w])
+    prec = ch.CHORUS_MIXED if precision == "mixed" else ch.CHORUS_FP64
+    phys = ch.physics(gamma=gam, precision=prec)
+    ws = cm.workspace(phys)
+    if prec == ch.CHORUS_MIXED:
+        Q0 = np.stack([np.ones_like(rho), z, z, z, np.full_like(rho, p / (gam - 1))])
+        ch.chorus_set_background(cm, phys, torch.from_numpy(np.ascontiguousarray(Q0)).cuda(), ws)
+    Qd = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+    Rd = torch.empty_like(Qd)
+    ch.chorus_sd_residual(cm, phys, Qd, Rd, ws)
+    torch.cuda.synchronize()
+    R = Rd.cpu().numpy()
+    lam = abs(w) + max(np.sqrt(gam * p / rL), np.sqrt(gam * p / rR))
+    expect = lam * (rR - rL) * Ly * Lz
+    tol = (1e-12 if precision == "fp64" else 1e-6) * abs(expect)
+    assert abs((wJ * R[0])[left].sum() - expect) <= tol, ((wJ * R[0])[left].sum(), expect)
+    assert abs((wJ * R[0])[~left].sum() + expect) <= tol
+
 @pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("dims", [(1, 1, 1), (1, 1, 3)])
 def test_residual_parity_fewer_elements_than_a_block(ch, oracle_mod, torch_dev, N, dims):
