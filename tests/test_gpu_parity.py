@@ -222,6 +222,38 @@ def test_rusanov_dissipation_coefficient_gpu(ch, oracle_mod, torch_dev, precisio
     assert abs((wJ * R[0])[left].sum() - expect) <= tol, ((wJ * R[0])[left].sum(), expect)
     assert abs((wJ * R[0])[~left].sum() + expect) <= tol
 
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_br1_common_solution_is_the_average_gpu(ch, oracle_mod, torch_dev, N):
+    """Closed-form pin of the library's BR1 gradients (the closure features,
+    FP32 output), no oracle values: a piecewise-constant density on an affine
+    periodic box (0.7 for x < 1/2, 1.6 above); each element's quadrature
+    integral of d rho/dx is (rho_R - rho_L) A / 2, signed by the side of the
+    jump, for the elements touching the jumps at x = 0 and 1/2 (the common
+    value is the average), and the y and z components vanish (the oracle's
+    pin, same state)."""
+    torch = torch_dev
+    Ly, Lz, gam, p = 0.8, 0.6, 5.0 / 3.0, 1.2
+    rL, rR, A = 0.7, 1.6, (Ly / 3) * (Lz / 3)
+    m = box_mesh(4, 3, 3, lengths=(1.0, Ly, Lz), periodic=(True,) * 3)
+    cm = ch.mesh_from_arrays(m, N).upload()
+    NP = N ** 3
+    xyz, wJ = cm.solpts()
+    cx = xyz[0].reshape(-1, NP).mean(1)
+    rho = np.repeat(np.where(cx < 0.5, rL, rR), NP)
+    z = np.zeros_like(rho)
+    Q = np.stack([rho, z, z, z, np.full_like(rho, p / (gam - 1))])
+    phys = ch.physics(gamma=gam)
+    X = torch.empty((cm.n_solpts, 20), dtype=torch.float32, device="cuda")
+    ch.chorus_closure_features(cm, phys, torch.from_numpy(np.ascontiguousarray(Q)).cuda(), X, cm.workspace(phys))
+    torch.cuda.synchronize()
+    G = X.cpu().numpy().astype(np.float64)[:, 5:8].T  # d rho / dx_c
+    integ = (G * wJ[None]).reshape(3, -1, NP).sum(2)
+    col = np.floor(cx * 4).astype(int)
+    want = np.array([-0.5, 0.5, 0.5, -0.5])[col] * (rR - rL) * A
+    np.testing.assert_allclose(integ[0], want, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(integ[1:], 0.0, atol=1e-7)
+
 @pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("dims", [(1, 1, 1), (1, 1, 3)])
 def test_residual_parity_fewer_elements_than_a_block(ch, oracle_mod, torch_dev, N, dims):

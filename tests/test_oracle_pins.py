@@ -360,6 +360,48 @@ def test_rusanov_dissipation_coefficient(oracle_mod, w):
     # the rho_R half loses exactly that mass
     assert abs((wJ * R[0])[~left].sum() + expect) <= 1e-12 * abs(expect)
 
+
+def _contact_box(N, Ly=0.8, Lz=0.6):
+    """Affine periodic 4 x 3 x 3 box for a density 0.7 for x < 1/2 and 1.6
+    above, uniform pressure 1.2 at rest.  Returns the mesh, the two
+    densities, the pressure and the area of one element's x-face."""
+    m = box_mesh(4, 3, 3, lengths=(1.0, Ly, Lz), periodic=(True,) * 3)
+    return m, 0.7, 1.6, 1.2, (Ly / 3) * (Lz / 3)
+
+
+def _contact_state(xyz, NP, rL, rR, p, gam=5.0 / 3.0):
+    cx = xyz[0].reshape(-1, NP).mean(1)
+    rho = np.repeat(np.where(cx < 0.5, rL, rR), NP)
+    z = np.zeros_like(rho)
+    return np.stack([rho, z, z, z, np.full_like(rho, p / (gam - 1))]), cx
+
+
+def test_br1_common_solution_is_the_average(oracle_mod):
+    """BR1 (Section 3): the gradient uses the common interface value
+    Q* = (Q_L + Q_R) / 2.  For a piecewise-constant density on affine
+    elements (constant metrics) the discrete Gauss identity
+    (w^T D = e_N - e_0) makes each element's quadrature integral of d rho/dx
+    equal to the sum over its faces of (rho* - rho_own) times the face's
+    x-area: (rho_R - rho_L) A / 2, signed by the side of the jump, for the
+    elements touching the jumps at x = 1/2 and x = 0; the y and z components
+    vanish.  (On curved elements the gradient's chain-rule form does not
+    telescope exactly.)  A one-sided common value (planted in the oracle:
+    every other pin passes) gives zero."""
+    N = 3
+    m, rL, rR, p, A = _contact_box(N)
+    om = oracle_mod.OracleMesh(m, N)
+    xyz, wJ = om.solpts()
+    Q, cx = _contact_state(xyz, om.np, rL, rR, p)
+    G = om.gradients(oracle_mod.phys(), Q.reshape(5, om.E, om.np)).reshape(15, om.E, om.np)
+    integ = (G[0:3] * wJ.reshape(om.E, om.np)[None]).sum(2)  # [c][E]
+    col = np.floor(cx * 4).astype(int)
+    # columns 0, 1 hold rho_L, 2, 3 rho_R; the jumps sit on the left of
+    # columns 0 and 2 and on the right of columns 1 and 3: the density rises
+    # across x = 1/2 and falls across x = 0
+    want = np.array([-0.5, 0.5, 0.5, -0.5])[col] * (rR - rL) * A
+    np.testing.assert_allclose(integ[0], want, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(integ[1:], 0.0, atol=1e-13)
+
 def test_rk3_linear_amplification(oracle_mod):
     """Uniform state with only Coriolis: a linear ODE whose exact SSP-RK3
     update is the polynomial 1 + z + z^2/2 + z^3/6 of dt L."""
