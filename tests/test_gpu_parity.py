@@ -254,6 +254,42 @@ def test_br1_common_solution_is_the_average_gpu(ch, oracle_mod, torch_dev, N):
     np.testing.assert_allclose(integ[0], want, rtol=1e-5, atol=1e-7)
     np.testing.assert_allclose(integ[1:], 0.0, atol=1e-7)
 
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_bottom_flux_enters_through_the_inner_wall_gpu(ch, oracle_mod, torch_dev, precision):
+    """Closed-form pin of the inner-wall energy flux on both paths (the
+    oracle's pin, same state): for a polytrope at rest with kappa =
+    kappa_r = 0 the quadrature sum of the change of the energy residual
+    caused by F_bottom is F_bottom times the inner wall's area (4 pi R_i^2
+    within the hex20 surface approximation) and mass and momentum do not
+    change.  Mixed path: the state is its own background, so the prescribed
+    flux sits in the FP64 background residual."""
+    torch = torch_dev
+    beta = 0.7
+    ri, ro = beta / (1 - beta), 1 / (1 - beta)
+    m = cubed_sphere_shell(4, 2, ri, ro)
+    om = oracle_mod.OracleMesh(m, 3)
+    Q, pars = om.polytrope(beta, 1.0)
+    cm = ch.mesh_from_arrays(m, 3).upload()
+    _, wJ = cm.solpts()
+    prec = ch.CHORUS_MIXED if precision == "mixed" else ch.CHORUS_FP64
+    f = 0.37
+    Qd = torch.from_numpy(np.ascontiguousarray(Q.reshape(5, -1))).cuda()
+    out = []
+    for fb in (f, 0.0):
+        phys = ch.physics(GM=pars["GM"], nu=1e-3, F_bottom=fb, precision=prec)
+        ws = cm.workspace(phys)
+        if prec == ch.CHORUS_MIXED:
+            ch.chorus_set_background(cm, phys, Qd, ws)
+        R = torch.empty_like(Qd)
+        ch.chorus_sd_residual(cm, phys, Qd, R, ws)
+        torch.cuda.synchronize()
+        out.append(R.cpu().numpy())
+    dE = (wJ * (out[0][4] - out[1][4])).sum()
+    assert abs(dE / (f * 4 * np.pi * ri ** 2) - 1.0) < 2e-3, dE / (f * 4 * np.pi * ri ** 2)
+    scale = np.abs(out[1][:4]).max()
+    assert np.abs(out[0][:4] - out[1][:4]).max() <= 1e-12 * scale
+
 @pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("dims", [(1, 1, 1), (1, 1, 3)])
 def test_residual_parity_fewer_elements_than_a_block(ch, oracle_mod, torch_dev, N, dims):

@@ -402,6 +402,28 @@ def test_br1_common_solution_is_the_average(oracle_mod):
     np.testing.assert_allclose(integ[0], want, rtol=1e-12, atol=1e-13)
     np.testing.assert_allclose(integ[1:], 0.0, atol=1e-13)
 
+
+def test_bottom_flux_enters_through_the_inner_wall(oracle_mod):
+    """Section 5's prescribed energy flux F_bottom at the inner wall heats the
+    shell from below: for a polytrope at rest with kappa = kappa_r = 0 no
+    other energy flux is non-zero, so by discrete conservation the
+    quadrature sum of the change of the energy residual caused by F_bottom
+    is F_bottom times the inner wall's area (4 pi R_i^2 up to the hex20
+    surface approximation), positive, and mass and momentum do not change.
+    (A flipped sign, planted in the oracle, passes every other pin.)"""
+    beta = 0.7
+    ri, ro = beta / (1 - beta), 1 / (1 - beta)
+    om = oracle_mod.OracleMesh(cubed_sphere_shell(4, 2, ri, ro), 3)
+    _, wJ = om.solpts()
+    Q, pars = om.polytrope(beta, 1.0)
+    f = 0.37
+    R1 = om.residual(oracle_mod.phys(GM=pars["GM"], nu=1e-3, F_bottom=f), Q).reshape(5, -1)
+    R0 = om.residual(oracle_mod.phys(GM=pars["GM"], nu=1e-3, F_bottom=0.0), Q).reshape(5, -1)
+    dE = (wJ * (R1[4] - R0[4])).sum()
+    area = 4 * math.pi * ri ** 2
+    assert abs(dE / (f * area) - 1.0) < 2e-3, dE / (f * area)
+    assert np.abs(R1[:4] - R0[:4]).max() == 0.0
+
 def test_rk3_linear_amplification(oracle_mod):
     """Uniform state with only Coriolis: a linear ODE whose exact SSP-RK3
     update is the polynomial 1 + z + z^2/2 + z^3/6 of dt L."""
