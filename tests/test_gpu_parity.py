@@ -290,6 +290,40 @@ def test_bottom_flux_enters_through_the_inner_wall_gpu(ch, oracle_mod, torch_dev
     scale = np.abs(out[1][:4]).max()
     assert np.abs(out[0][:4] - out[1][:4]).max() <= 1e-12 * scale
 
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_outer_wall_temperature_enters_the_gradient_gpu(ch, oracle_mod, torch_dev, N):
+    """Closed-form pin of the library's outer-wall state (the oracle's pin,
+    same state, through the BR1 gradients of the closure features): on an
+    affine box walled all round (outer walls) with a uniform state at rest,
+    each element's quadrature integral of dE/dx_c is the sum over its wall
+    faces of (E_b - E) n_c A, E_b = rho R T_top / (gamma - 1); the density
+    and momentum gradients vanish."""
+    torch = torch_dev
+    gam, rho, p, T_top = 5.0 / 3.0, 1.1, 1.3, 0.9
+    lengths = (1.0, 1.2, 0.9)
+    m = box_mesh(3, 3, 3, lengths=lengths, bc=2)
+    cm = ch.mesh_from_arrays(m, N).upload()
+    NP = N ** 3
+    xyz, wJ = cm.solpts()
+    n = xyz.shape[1]
+    Q = np.stack([np.full(n, rho), np.zeros(n), np.zeros(n), np.zeros(n), np.full(n, p / (gam - 1))])
+    phys = ch.physics(gamma=gam, T_top=T_top)
+    X = torch.empty((n, 20), dtype=torch.float32, device="cuda")
+    ch.chorus_closure_features(cm, phys, torch.from_numpy(np.ascontiguousarray(Q)).cuda(), X, cm.workspace(phys))
+    torch.cuda.synchronize()
+    G = X.cpu().numpy().astype(np.float64)[:, 5:20].T
+    integ = (G * wJ[None]).reshape(15, -1, NP).sum(2)
+    cent = xyz.reshape(3, -1, NP).mean(2)
+    Eb, E = rho * T_top / (gam - 1), p / (gam - 1)
+    h = np.asarray(lengths) / 3
+    want = np.zeros((3, cent.shape[1]))
+    for c in range(3):
+        idx = np.floor(cent[c] / h[c]).astype(int)
+        want[c] = ((idx == 2).astype(float) - (idx == 0).astype(float)) * (Eb - E) * np.prod(h) / h[c]
+    np.testing.assert_allclose(integ[12:15], want, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(integ[0:12], 0.0, atol=1e-7)
+
 @pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("dims", [(1, 1, 1), (1, 1, 3)])
 def test_residual_parity_fewer_elements_than_a_block(ch, oracle_mod, torch_dev, N, dims):

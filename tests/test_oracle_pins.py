@@ -424,6 +424,46 @@ def test_bottom_flux_enters_through_the_inner_wall(oracle_mod):
     assert abs(dE / (f * area) - 1.0) < 2e-3, dE / (f * area)
     assert np.abs(R1[:4] - R0[:4]).max() == 0.0
 
+
+def _wall_box_case(gam=5.0 / 3.0):
+    """Affine 3 x 3 x 3 box whose boundary faces are all outer walls, uniform
+    state at rest (rho 1.1, p 1.3), wall temperature T_top = 0.9."""
+    m = box_mesh(3, 3, 3, lengths=(1.0, 1.2, 0.9), bc=2)
+    return m, 1.1, 1.3, 0.9, gam
+
+
+def _wall_box_expected(cent, lengths, rho, p, T_top, gam):
+    """Per element and direction: sum over its wall faces of (E_b - E) n_c A."""
+    Eb, E = rho * T_top / (gam - 1), p / (gam - 1)
+    h = np.asarray(lengths) / 3
+    want = np.zeros((3, cent.shape[1]))
+    for c in range(3):
+        area = np.prod(h) / h[c]
+        idx = np.floor(cent[c] / h[c]).astype(int)
+        want[c] = ((idx == 2).astype(float) - (idx == 0).astype(float)) * (Eb - E) * area
+    return want
+
+
+def test_outer_wall_temperature_enters_the_gradient(oracle_mod):
+    """Section 5's fixed temperature at the outer wall: the BR1 wall state
+    takes T = T_top (density kept, normal momentum removed).  On an affine
+    box walled all round with a uniform state at rest, each element's
+    quadrature integral of dE/dx_c is the sum over its wall faces of
+    (E_b - E) n_c A with E_b = rho R T_top / (gamma - 1) (discrete Gauss
+    identity), and the density and momentum gradients vanish.  (Ignoring
+    T_top, planted in the oracle, passes every other pin.)"""
+    m, rho, p, T_top, gam = _wall_box_case()
+    om = oracle_mod.OracleMesh(m, 3)
+    xyz, wJ = om.solpts()
+    n = xyz.shape[1]
+    Q = np.stack([np.full(n, rho), np.zeros(n), np.zeros(n), np.zeros(n), np.full(n, p / (gam - 1))])
+    G = om.gradients(oracle_mod.phys(gamma=gam, T_top=T_top), Q.reshape(5, om.E, om.np)).reshape(15, om.E, om.np)
+    integ = (G * wJ.reshape(om.E, om.np)[None]).sum(2)  # [3 v + c][E]
+    cent = xyz.reshape(3, om.E, om.np).mean(2)
+    want = _wall_box_expected(cent, (1.0, 1.2, 0.9), rho, p, T_top, gam)
+    np.testing.assert_allclose(integ[12:15], want, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(integ[0:12], 0.0, atol=1e-13)
+
 def test_rk3_linear_amplification(oracle_mod):
     """Uniform state with only Coriolis: a linear ODE whose exact SSP-RK3
     update is the polynomial 1 + z + z^2/2 + z^3/6 of dt L."""
