@@ -17,9 +17,11 @@ Boundary tags: -1 interior, 1 inner sphere wall, 2 outer sphere wall,
 3 far-field state boundary.
 """
 from .meshes import (HEX20_LOCAL, Hex20Mesh, cubed_sphere_shell, box_mesh,
-                     two_element_mesh, shell_params_from_config,
+                     two_element_mesh, warped_slab_mesh, walled_slab_mesh,
+                     shell_params_from_config,
                      uniform_noise, mlp_init, random_velocity, CONFIGS)
 
 __all__ = ["HEX20_LOCAL", "Hex20Mesh", "cubed_sphere_shell", "box_mesh",
-           "two_element_mesh", "shell_params_from_config", "uniform_noise",
+           "two_element_mesh", "warped_slab_mesh",
+           "walled_slab_mesh", "shell_params_from_config", "uniform_noise",
            "mlp_init", "random_velocity", "CONFIGS"]

@@ -212,6 +212,36 @@ def box_mesh(nx, ny, nz, lengths=(1.0, 1.0, 1.0), periodic=(False, False, False)
                                periodic=tuple(periodic), curve=curve))
 
 
+def warped_slab_mesh(n, length, amp, nz=3):
+    """Periodic slab of n x n x nz hex20 elements, [0, L]^2 x [0, nz L / n],
+    with every node displaced in x and y by the smooth periodic field
+        dx = dy = amp * L * sin(2 pi x / L) sin(2 pi y / L)
+    (z unchanged): the elements are curved, the map is one fixed smooth
+    field under refinement in x and y, and the slab stays periodic.  nz must
+    be at least 3 (with two layers the two z-faces of an element would carry
+    the same periodic corner set)."""
+    if nz < 3:
+        raise ValueError("nz >= 3 (periodic face matching)")
+    L = float(length)
+    m = box_mesh(n, n, nz, lengths=(L, L, nz * L / n), periodic=(True, True, True))
+    xyz = m.xyz.copy()
+    s = np.sin(2 * math.pi * xyz[:, 0] / L) * np.sin(2 * math.pi * xyz[:, 1] / L)
+    xyz[:, 0] += amp * L * s
+    xyz[:, 1] += amp * L * s
+    return Hex20Mesh(xyz=xyz, elem20=m.elem20, face_bc=m.face_bc, match_id=m.match_id,
+                     meta=dict(kind="warped_slab", n=n, length=L, amp=amp, nz=nz))
+
+
+def walled_slab_mesh(nx, ny, nz, lengths, bc_low, bc_high):
+    """Affine box, periodic in y and z, with boundary tag bc_low on its
+    x = 0 faces and bc_high on its x = L faces."""
+    m = box_mesh(nx, ny, nz, lengths=lengths, periodic=(False, True, True), bc=bc_low)
+    fb = m.face_bc.copy()
+    fb[fb[:, 1] == bc_low, 1] = bc_high
+    return Hex20Mesh(xyz=m.xyz, elem20=m.elem20, face_bc=fb, match_id=m.match_id,
+                     meta=dict(m.meta, walls=(bc_low, bc_high)))
+
+
 def _proper_rotations():
     """The 24 orientation-preserving signed permutation matrices."""
     import itertools
