@@ -12,6 +12,9 @@ perturbation part of the oracle residual, R(Q) - R(Q0):
 2e-5 covers FP32 rounding (6e-8) amplified by the derivative operators'
 cancellation (3(N+1) terms with |D| up to ~10, factor <= ~200 at N <= 4);
 the second term is the FP32 rounding of the stored background residual.
+The same check is made element by element in the max norm (bound 1e-4 of
+the largest perturbation residual plus 1e-6 of the largest background
+residual), and every case prints its achieved errors.
 """
 import numpy as np
 import pytest
@@ -52,6 +55,24 @@ def _case(oracle_mod, N, amp=1e-3, vel=1e-3, seed=3):
     return m, om, Q0, Q, pars
 
 
+def assert_mixed(Rg, Rr, Rb, what):
+    """Mixed residual Rg against the oracle's R(Q) (Rr) with R(Q0) = Rb: L2
+    and max norm per variable, printed."""
+    fails = []
+    for v in range(5):
+        d = Rg[v] - Rr[v]
+        err, errm = np.linalg.norm(d), np.abs(d).max()
+        pert, pertm = np.linalg.norm(Rr[v] - Rb[v]), np.abs(Rr[v] - Rb[v]).max()
+        tol = 2e-5 * pert + 1e-6 * np.linalg.norm(Rb[v])
+        tolm = 1e-4 * pertm + 1e-6 * np.abs(Rb[v]).max()
+        print("%s var %d: L2 err/|R - R0| %.2e (tol %.2e), max err/max|R - R0| %.2e (tol %.2e)" % (
+            what, v, err / max(pert, 1e-300), tol / max(pert, 1e-300), errm / max(pertm, 1e-300),
+            tolm / max(pertm, 1e-300)))
+        if not (err <= tol and errm <= tolm):
+            fails.append((v, err, tol, errm, tolm))
+    assert not fails, (what, fails)
+
+
 @pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
 def test_mixed_residual_vs_oracle(ch, oracle_mod, torch_dev, N):
     torch = torch_dev
@@ -68,16 +89,13 @@ def test_mixed_residual_vs_oracle(ch, oracle_mod, torch_dev, N):
     op = oracle_mod.phys(**kw)
     Rr = om.residual(op, Q).reshape(5, -1)
     Rb = om.residual(op, Q0).reshape(5, -1)
-    for v in range(5):
-        err = np.linalg.norm(Rg[v] - Rr[v])
-        tol = 2e-5 * np.linalg.norm(Rr[v] - Rb[v]) + 1e-6 * np.linalg.norm(Rb[v])
-        assert err <= tol, (v, err, tol)
+    assert_mixed(Rg, Rr, Rb, "mixed N=%d" % N)
 
 
 @pytest.mark.parametrize("N", [3, 4])
 def test_mixed_residual_radial_kappa_r(ch, oracle_mod, torch_dev, N):
     """The mixed path with a radius-dependent radiative diffusivity (solar
-    case, Section 7.3), to the tolerance of the constant case."""
+    case, Section 7.4), to the tolerance of the constant case."""
     torch = torch_dev
     m, om, Q0, Q, pars = _case(oracle_mod, N)
     kw = dict(GM=pars["GM"], omega=1.0, nu=1e-3, kappa=1e-3, kappa_r=1e-4, T_top=pars["chi_o"], F_bottom=0.01,
@@ -93,10 +111,7 @@ def test_mixed_residual_radial_kappa_r(ch, oracle_mod, torch_dev, N):
     op = oracle_mod.phys(**kw)
     Rr = om.residual(op, Q).reshape(5, -1)
     Rb = om.residual(op, Q0).reshape(5, -1)
-    for v in range(5):
-        err = np.linalg.norm(Rg[v] - Rr[v])
-        tol = 2e-5 * np.linalg.norm(Rr[v] - Rb[v]) + 1e-6 * np.linalg.norm(Rb[v])
-        assert err <= tol, (v, err, tol)
+    assert_mixed(Rg, Rr, Rb, "mixed radial kappa_r N=%d" % N)
     # the radial terms matter at this tolerance
     kw0 = dict(kw, kappa_r1=0.0, kappa_r2=0.0)
     Rr0 = om.residual(oracle_mod.phys(**kw0), Q).reshape(5, -1)
@@ -156,7 +171,7 @@ def test_mixed_100_steps_vs_fp64_full_workload(ch, torch_dev):
 
 def test_mixed_vs_fp64_radial_kappa_r_full_workload(ch, torch_dev):
     """The metric's gate with the solar radius-dependent radiative
-    diffusivity (Section 7.3) on the benchmark workload: 30 SSP-RK3 steps of
+    diffusivity (Section 7.4) on the benchmark workload: 30 SSP-RK3 steps of
     the mixed path against the FP64 path."""
     torch = torch_dev
     cfg = CONFIGS["jupiter_41k_N4"]
@@ -218,9 +233,8 @@ def test_mixed_ragged_last_block(ch, oracle_mod, torch_dev, N):
     Rb = om.residual(op, Q0).reshape(5, -1)
     Qr = om.rk3(op, Q, dt, 2).reshape(5, -1)
     Qs = Q.reshape(5, -1)
+    assert_mixed(Rg, Rr, Rb, "mixed ragged N=%d" % N)
     for v in range(5):
-        err = np.linalg.norm(Rg[v] - Rr[v])
-        assert err <= 2e-5 * np.linalg.norm(Rr[v] - Rb[v]) + 1e-6 * np.linalg.norm(Rb[v]), (v, err)
         # the last block's two elements are checked on their own too
         last = slice((om.E - 2) * om.np, om.E * om.np)
         assert np.abs(Rg[v, last] - Rr[v, last]).max() <= 1e-4 * np.abs(Rr[v] - Rb[v]).max() + \
@@ -232,7 +246,9 @@ def test_mixed_ragged_last_block(ch, oracle_mod, torch_dev, N):
 @pytest.mark.timeout(600)
 def test_mixed_vs_fp64_largest_workload(ch, torch_dev):
     """The metric's gate on the largest shell (331,776 hexes, N = 4, 21.2M
-    DOFs): three SSP-RK3 steps of the mixed path against the FP64 path."""
+    DOFs) at its configured length: 200 SSP-RK3 steps of the mixed path
+    against the FP64 path, relative L2 error per variable <= 1e-6 (also
+    printed relative to the change from the start state)."""
     torch = torch_dev
     cfg = CONFIGS["sun_332k_N4"]
     ri, ro = shell_params_from_config(cfg)
@@ -247,13 +263,15 @@ def test_mixed_vs_fp64_largest_workload(ch, torch_dev):
     dt = cm.stable_dt(p64, Qh, cfg["cfl"])
     Qa = torch.from_numpy(Qh).cuda()
     ws = cm.workspace(p64)
-    ch.chorus_rk_step(cm, p64, Qa, dt, 3, ws)
+    STEPS = 200
+    ch.chorus_rk_step(cm, p64, Qa, dt, STEPS, ws)
     torch.cuda.synchronize()
+    print("sun_332k_N4: %d FP64 steps done" % STEPS, flush=True)
     del ws
     wsm = cm.workspace(pmx)
     ch.chorus_set_background(cm, pmx, torch.from_numpy(Q0h).cuda(), wsm)
     Qb = torch.from_numpy(Qh).cuda()
-    ch.chorus_rk_step(cm, pmx, Qb, dt, 3, wsm)
+    ch.chorus_rk_step(cm, pmx, Qb, dt, STEPS, wsm)
     torch.cuda.synchronize()
     Qs = torch.from_numpy(Qh).cuda()
     for v in range(5):

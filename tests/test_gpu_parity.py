@@ -1,15 +1,17 @@
 """GPU parity of the FP64 SD residual and SSP-RK3 update against the CPU
-oracle, through the C-ABI.
+oracle, through the C-ABI, element by element.
 
-Tolerance (FP64 mode): per conserved variable v,
-    ||R_gpu,v - R_oracle,v||_2 <= max(1e-12 ||R_oracle,v||_2, 8 * floor_v)
-where floor_v is the oracle's own rounding sensitivity: the change of its
-output when every state value and every node coordinate is perturbed by one
-unit in the last place (random signs).  The GPU library computes the same
-geometry, 1D operators and fluxes with its own code, a different summation
-order and fused multiply-adds: rounding-level perturbations of that size.
-The floor dominates only where the output cancels strongly (high order N,
-hydrostatic momentum); elsewhere the 1e-12 relative bound applies.
+Tolerance (FP64 mode): per conserved variable v, in the L2 norm over all
+points and in the max norm,
+    ||R_gpu,v - R_oracle,v|| <= max(1e-12 ||R_oracle,v||, K * floor_v)
+where floor_v is the oracle's own rounding sensitivity in the same norm:
+the change of its output when every state value and every node coordinate
+is perturbed by one unit in the last place (random signs).  The GPU library
+computes the same geometry, 1D operators and fluxes with its own code, a
+different summation order and fused multiply-adds: rounding-level
+perturbations of that size.  K = 2 unless a case lists its measured factor
+(FLOOR_FACTOR below).  Every case prints its achieved error relative to the
+reference norm and to the floor, and which bound applied.
 """
 import numpy as np
 import pytest
@@ -46,16 +48,29 @@ def perturbed_oracle(oracle_mod, mesh, N, seed=11):
     return oracle_mod.OracleMesh(m2, N)
 
 
-def assert_parity(R_gpu, R_ref, R_pert, what, rel=1e-12):
+FLOOR_FACTOR = 2.0
+
+
+def assert_parity(R_gpu, R_ref, R_pert, what, rel=1e-12, factor=None):
+    """Per variable: L2 and max-norm error within max(rel * |R_ref|,
+    factor * floor) of the same norm; prints the achieved errors."""
+    factor = FLOOR_FACTOR if factor is None else factor
     R_gpu = R_gpu.reshape(5, -1)
     R_ref = R_ref.reshape(5, -1)
-    floor = np.linalg.norm((R_pert.reshape(5, -1) - R_ref), axis=1)
+    dp = R_pert.reshape(5, -1) - R_ref
+    d = R_gpu - R_ref
+    fails = []
     for v in range(5):
-        err = np.linalg.norm(R_gpu[v] - R_ref[v])
-        ref = np.linalg.norm(R_ref[v])
-        tol = max(rel * ref, 8.0 * floor[v], 1e-300)
-        assert err <= tol, "%s var %d: err %.3e tol %.3e (ref %.3e floor %.3e)" % (
-            what, v, err, tol, ref, floor[v])
+        for norm, f in (("L2", lambda a: float(np.linalg.norm(a))), ("max", lambda a: float(np.abs(a).max()))):
+            err, ref, floor = f(d[v]), f(R_ref[v]), f(dp[v])
+            tol = max(rel * ref, factor * floor, 1e-300)
+            bound = "1e-12 rel" if rel * ref >= factor * floor else "%g x floor" % factor
+            print("%s var %d %s: err/ref %.2e err/floor %.2f (bound %s)" % (
+                what, v, norm, err / max(ref, 1e-300), err / max(floor, 1e-300), bound))
+            if not err <= tol:
+                fails.append("%s var %d %s: err %.3e tol %.3e (ref %.3e floor %.3e)" % (
+                    what, v, norm, err, tol, ref, floor))
+    assert not fails, "; ".join(fails)
 
 
 def ora_phys(oracle_mod, p):
@@ -99,7 +114,7 @@ def test_residual_parity_shell(ch, oracle_mod, torch_dev, N):
 
 @pytest.mark.parametrize("N", [3, 4])
 def test_residual_parity_radial_kappa_r(ch, oracle_mod, torch_dev, N):
-    """Radiative diffusivity varying with radius (solar case, Section 7.3):
+    """Radiative diffusivity varying with radius (solar case, Section 7.4):
     kappa_r(r) = kappa_r + kappa_r1 r + kappa_r2 r^2 at each flux point's
     radius; the radial terms change the residual by far more than the
     tolerance."""
@@ -324,6 +339,130 @@ def test_outer_wall_temperature_enters_the_gradient_gpu(ch, oracle_mod, torch_de
     np.testing.assert_allclose(integ[12:15], want, rtol=1e-5, atol=1e-7)
     np.testing.assert_allclose(integ[0:12], 0.0, atol=1e-7)
 
+def gpu_residual_prec(ch, torch, cm, phys, Q, Q0=None):
+    """Residual on either path; the mixed path takes the background Q0 (a
+    state at rest)."""
+    Qd = torch.from_numpy(np.ascontiguousarray(Q.reshape(5, -1))).cuda()
+    ws = cm.workspace(phys)
+    if phys.precision == ch.CHORUS_MIXED:
+        ch.chorus_set_background(cm, phys, torch.from_numpy(np.ascontiguousarray(Q0.reshape(5, -1))).cuda(), ws)
+    R = torch.empty_like(Qd)
+    ch.chorus_sd_residual(cm, phys, Qd, R, ws)
+    torch.cuda.synchronize()
+    return R.cpu().numpy()
+
+
+def uniform_rest(n, rho, p, gam):
+    z = np.zeros(n)
+    return np.stack([np.full(n, rho), z, z, z, np.full(n, p / (gam - 1))])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("N", [3, 4])
+@pytest.mark.parametrize("bc", [1, 2])
+def test_stress_free_wall_traction_gpu(ch, oracle_mod, torch_dev, precision, N, bc):
+    """Closed-form pin of the stress-free walls (Section 5) on both paths,
+    no oracle values (the oracle's pin, same state): on the affine slab
+    walled in x with u = (c x (L - x), a x, b x) at uniform rho and p, each
+    element's quadrature integral of the viscous residual R(nu) - R(0) is
+    the divergence theorem for tau and u.tau plus, on the wall elements,
+    the dropped tangential traction and viscous work.  Mixed path: the
+    background is the uniform state at rest, so the FP32 part carries the
+    whole velocity field; bound 1e-5 of the largest integral."""
+    from chorus_inputs import walled_slab_mesh
+    import closed_forms as cf
+    m = walled_slab_mesh(cf.SLAB["nx"], cf.SLAB["ny"], cf.SLAB["nz"], cf.SLAB["lengths"], bc, bc)
+    cm = ch.mesh_from_arrays(m, N).upload()
+    xyz, wJ = cm.solpts()
+    t = cf.TRACTION
+    prec = ch.CHORUS_MIXED if precision == "mixed" else ch.CHORUS_FP64
+    Q = cf.traction_state(xyz)
+    Q0 = uniform_rest(xyz.shape[1], t["rho"], t["p"], t["gamma"])
+    R1 = gpu_residual_prec(ch, torch_dev, cm, ch.physics(gamma=t["gamma"], nu=t["nu"], precision=prec), Q, Q0)
+    R0 = gpu_residual_prec(ch, torch_dev, cm, ch.physics(gamma=t["gamma"], precision=prec), Q, Q0)
+    integ = ((R1 - R0) * wJ[None]).reshape(5, -1, N ** 3).sum(2)
+    want = cf.traction_expected(xyz, N ** 3)
+    rel = 1e-11 if precision == "fp64" else 1e-5
+    scale = np.abs(want[1:]).max()
+    err = np.abs(integ[1:] - want[1:]).max()
+    print("traction %s N=%d bc=%d: max |err| / scale = %.2e (bound %.0e)" % (precision, N, bc, err / scale, rel))
+    assert err <= rel * scale
+    assert np.abs(integ[0]).max() <= rel * scale
+    for wrong in ("full", "none"):
+        assert np.abs(cf.traction_expected(xyz, N ** 3, wall=wrong) - want).max() > 100 * rel * scale
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("N", [3, 4])
+def test_wall_energy_fluxes_gpu(ch, oracle_mod, torch_dev, precision, N):
+    """Closed-form pin of the wall energy fluxes (Section 5) on both paths
+    (the oracle's pin, same state): on the affine slab with the inner wall
+    at x = 0 and the outer wall at x = L, at rest with rho and p linear in
+    x, each element's quadrature integral of the energy residual's
+    diffusive part is the conductive flux through its x-faces, F_bottom
+    entering through the inner wall and the interior flux leaving through
+    the outer wall (T_top = the interior wall temperature).  Mixed path:
+    the background is the uniform state (r0, p0) at rest; bound 1e-5."""
+    from chorus_inputs import walled_slab_mesh
+    import closed_forms as cf
+    m = walled_slab_mesh(cf.SLAB["nx"], cf.SLAB["ny"], cf.SLAB["nz"], cf.SLAB["lengths"], 1, 2)
+    cm = ch.mesh_from_arrays(m, N).upload()
+    xyz, wJ = cm.solpts()
+    t = cf.CONDUCTION
+    prec = ch.CHORUS_MIXED if precision == "mixed" else ch.CHORUS_FP64
+    Q = cf.conduction_state(xyz)
+    Q0 = uniform_rest(xyz.shape[1], t["r0"], t["p0"], t["gamma"])
+    kw = dict(gamma=t["gamma"], R_gas=t["R_gas"], T_top=cf.conduction_T_top(), precision=prec)
+    R1 = gpu_residual_prec(ch, torch_dev, cm, ch.physics(kappa=t["kappa"], kappa_r=t["kappa_r"],
+                                                         F_bottom=t["F_bottom"], **kw), Q, Q0)
+    R0 = gpu_residual_prec(ch, torch_dev, cm, ch.physics(**kw), Q, Q0)
+    integ = ((R1 - R0) * wJ[None]).reshape(5, -1, N ** 3).sum(2)
+    want = cf.conduction_expected(xyz, N ** 3)
+    rel = 1e-11 if precision == "fp64" else 1e-5
+    scale = np.abs(want).max()
+    err = np.abs(integ[4] - want).max()
+    print("wall energy %s N=%d: max |err| / scale = %.2e (bound %.0e)" % (precision, N, err / scale, rel))
+    assert err <= rel * scale
+    assert np.abs(integ[:4]).max() <= rel * scale
+    for wrong in ("adiabatic", "flipped"):
+        assert np.abs(cf.conduction_expected(xyz, N ** 3, outer=wrong) - want).max() > 100 * rel * scale
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_design_order_isentropic_vortex_gpu(ch, oracle_mod, torch_dev, precision):
+    """Design order of the library's nonlinear inviscid scheme on both paths
+    (the oracle's pin, same runs): the isentropic vortex advected on curved
+    periodic slabs, error at t = 1 over the vortex disc at h = L/12 and
+    L/24; rate > N - 0.5 for N = 2, 4 and > 2.4 for N = 3.  Mixed path: the
+    background is the uniform far-field state at rest, so the vortex and
+    the mean flow are the FP32 perturbation."""
+    from chorus_inputs import warped_slab_mesh
+    import closed_forms as cf
+    torch = torch_dev
+    v = cf.VORTEX
+    prec = ch.CHORUS_MIXED if precision == "mixed" else ch.CHORUS_FP64
+    phys = ch.physics(gamma=v["gamma"], precision=prec)
+
+    def run(N, n):
+        cm = ch.mesh_from_arrays(warped_slab_mesh(n, v["length"], v["amp"]), N).upload()
+        xyz, wJ = cm.solpts()
+        ws = cm.workspace(phys)
+        if prec == ch.CHORUS_MIXED:
+            Q0 = uniform_rest(xyz.shape[1], 1.0, 1.0, v["gamma"])
+            ch.chorus_set_background(cm, phys, torch.from_numpy(Q0).cuda(), ws)
+        Qd = torch.from_numpy(np.ascontiguousarray(cf.vortex_state(xyz, 0.0))).cuda()
+        steps = cf.vortex_steps(N, n)
+        ch.chorus_rk_step(cm, phys, Qd, v["t_end"] / steps, steps, ws)
+        torch.cuda.synchronize()
+        return cf.vortex_errors(Qd.cpu().numpy(), xyz, wJ)
+
+    for N, bound in ((2, 1.5), (3, 2.4), (4, 3.5)):
+        e1, e2 = run(N, 12), run(N, 24)
+        rates = np.log2(e1[[0, 1, 2, 4]] / e2[[0, 1, 2, 4]])
+        print("vortex %s N=%d: errors %s, rates %s" % (precision, N, e2, rates))
+        assert (rates > bound).all(), (N, e1, e2, rates)
+
+
 @pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("dims", [(1, 1, 1), (1, 1, 3)])
 def test_residual_parity_fewer_elements_than_a_block(ch, oracle_mod, torch_dev, N, dims):
@@ -355,7 +494,7 @@ def test_residual_parity_fewer_elements_than_a_block(ch, oracle_mod, torch_dev, 
     assert_parity(Qd.cpu().numpy() - Q0, Qr - Q0, Qp - Q0, "rk3 E=%d N=%d" % (om.E, N))
 
 
-@pytest.mark.parametrize("rot", [0, 3, 7, 13, 22])
+@pytest.mark.parametrize("rot", range(24))
 def test_residual_parity_orientations(ch, oracle_mod, torch_dev, rot):
     m = two_element_mesh(rot)
     om = oracle_mod.OracleMesh(m, 3)
