@@ -90,7 +90,7 @@ typedef struct {
  * grad T; walls impermeable and stress-free (Section 5) with f.r_hat =
  * F_bottom at the inner wall and T = T_top at the outer wall (T_top <= 0:
  * interior temperature kept).  The radiative diffusivity may vary with
- * radius as in the solar benchmark (Section 7.3, a quadratic in r):
+ * radius as in the solar benchmark (Section 7.4, a quadratic in r):
  * kappa_r(r) = kappa_r + kappa_r1 r + kappa_r2 r^2, evaluated at the radius
  * of each flux point (kappa_r1 = kappa_r2 = 0: constant).  It must not be
  * negative anywhere on the mesh (CHORUS_EINVAL). */
@@ -176,6 +176,20 @@ typedef struct {
 } chorus_afb_desc;
 int chorus_init_afb(chorus_mesh_t mesh, const chorus_afb_desc *desc, double *Q_host, double pars[6]);
 
+/* Radiative diffusivity of the solar benchmark (Section 7.4, Table 2) in
+ * the units of chorus_init_polytrope (depth 1, rho = p = 1 at mid-layer):
+ * the printed quadratic lambda (c0 + c1 w + c2 w^2) in w = r / 1e10 cm,
+ * with r = r_unit * depth_cm (depth_cm <= 0: Table 2's shell depth,
+ * 1.74e10 cm), written as kappa_r(r) = out[0] + out[1] r + out[2] r^2 for
+ * chorus_physics (kappa_r, kappa_r1, kappa_r2).  lambda is set so that the
+ * polytrope's radiative flux -kappa_r rho c_p dT/dr carries L / (4 pi R_i^2)
+ * through the inner wall, which makes the almost-flux-balance entropy
+ * gradient (Section 4.3) vanish there, as the section describes for the
+ * solar run.  Host only; CHORUS_EINVAL for beta outside (0, 1), poly_n,
+ * R_gas <= 0, gamma <= 1, a negative luminosity or out == NULL. */
+int chorus_solar_kappa_r(double beta, double n_rho, double poly_n, double gamma, double R_gas,
+                         double luminosity, double depth_cm, double out[3]);
+
 /* Mixed mode: register the background state Q0 (device, [5][E N^3] FP64)
  * and compute, once, its complete FP64 residual R(Q0) and the background
  * arrays into the workspace.  Synchronises.  Q0 must be at rest (zero
@@ -201,8 +215,13 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
 int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev, double dt,
                    int32_t n_steps, void *ws, void *stream);
 
-/* sum over solution points of w w w |J| Q_v, fixed reduction order; the
- * 5 sums are returned on the host (synchronises). */
+/* Conserved totals (Section 6: the conservative form with interface fluxes
+ * shared by both sides conserves them discretely): the sum over solution
+ * points of w_i w_j w_k |J| Q_v for the 5 conserved variables, in a fixed
+ * reduction order (bitwise reproducible).  Q_dev: device [5][E N^3] FP64;
+ * the workspace holds the partial sums; the 5 sums are returned on the host
+ * (synchronises).  CHORUS_EINVAL for null pointers, CHORUS_ESTATE before
+ * chorus_mesh_upload. */
 int chorus_conserved_sums(chorus_mesh_t mesh, const double *Q_dev, double out_host[5], void *ws,
                           void *stream);
 

@@ -9,7 +9,7 @@ makes the diffusive flux f = -kappa rho T grad S - kappa_r rho c_p grad T of
 Section 2 carry the luminosity outward):
     Gamma = -(L / (4 pi r^2) + rho_a c_p kappa_r dT_a/dr) / (rho_a T_a kappa),
 with kappa_r(r) = kappa_r + kappa_r1 r + kappa_r2 r^2 (constant unless the
-quadratic terms are given: the solar case of Section 7.3).
+quadratic terms are given: the solar case of Section 7.4).
 State equations (Eq. state_equations), integrated from r_c (chi = 1) with
 rho0 = p0 = 1 by scipy's DOP853 at tight tolerances:
     Gamma / c_p = -(rho0'/rho0 + g rho0 / (gamma p0)),  p0' = -rho0 g,

@@ -23,7 +23,7 @@
  *     that -M reproduces rho g and rho u.g of Eqs. 2-3; Coriolis as printed.
  *   - energy component of F_v is u.tau - f (Eq. 3), f = -kappa rho T grad S
  *     - kappa_r rho c_p grad T; kappa_r may vary with radius as a quadratic
- *     in r (the solar case of Section 7.3), evaluated at the radius of each
+ *     in r (the solar case of Section 7.4), evaluated at the radius of each
  *     flux point given by the element map.
  *   - Rusanov wave speed max(|u_L.n| + c_L, |u_R.n| + c_R); one common flux
  *     per face point, shared by both sides.
@@ -611,7 +611,7 @@ static void stress(const ora_phys *ph, const prim_grad *pg, double tau[3][3])
 }
 
 /* radiative diffusivity at radius r: the constant, or the quadratic in r
- * of the solar case (Section 7.3) */
+ * of the solar case (Section 7.4) */
 static double kappa_r_at(const ora_phys *ph, double r)
 {
     return ph->kappa_r + ph->kappa_r1 * r + ph->kappa_r2 * r * r;

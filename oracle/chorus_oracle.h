@@ -30,7 +30,7 @@ typedef struct {
     double T_top;     /* outer-wall temperature; <= 0 keeps the interior p */
     double F_bottom;  /* prescribed f . r_hat at the inner wall            */
     double bc_state[5];
-    /* radius-dependent radiative diffusivity (Section 7.3, solar case):
+    /* radius-dependent radiative diffusivity (Section 7.4, solar case):
      * kappa_r(r) = kappa_r + kappa_r1 r + kappa_r2 r^2 at each flux point */
     double kappa_r1, kappa_r2;
 } ora_phys;

@@ -103,6 +103,7 @@ _SIGS = {
                               ctypes.c_double, _P, ctypes.c_double, _P, _P],
     "chorus_set_background": [_P, ctypes.POINTER(Physics), _P, _P, _P],
     "chorus_init_afb": [_P, ctypes.POINTER(AfbDesc), _P, _P],
+    "chorus_solar_kappa_r": [ctypes.c_double] * 7 + [_P],
     "chorus_sd_residual": [_P, ctypes.POINTER(Physics), _P, _P, _P, _P],
     "chorus_rk_step": [_P, ctypes.POINTER(Physics), _P, ctypes.c_double, ctypes.c_int32, _P, _P],
     "chorus_conserved_sums": [_P, _P, _P, _P, _P],
@@ -249,35 +250,14 @@ class Mesh:
         return torch.empty(b.value, dtype=torch.uint8, device=device)
 
 
-# radiative diffusivity of the solar benchmark (Section 7.3, Table 2):
-# lambda (c0 + c1 w + c2 w^2), w = r / 1e10 cm, over a shell of depth
-# d = 1.74e10 cm
-SOLAR_KAPPA_R_COEFFS = (1.5600975e8, -4.5631718e7, 3.3370368e6)
-SOLAR_DEPTH_CM = 1.74e10
-
-
-def solar_radiative_diffusivity(beta, n_rho, luminosity, poly_n=1.5, gamma=5.0 / 3.0, R_gas=1.0,
-                                depth_cm=SOLAR_DEPTH_CM):
+def solar_radiative_diffusivity(beta, n_rho, luminosity, poly_n=1.5, gamma=5.0 / 3.0, R_gas=1.0, depth_cm=0.0):
     """(kappa_r, kappa_r1, kappa_r2) of chorus_physics for the solar
-    benchmark's radiative diffusivity in the units of chorus_init_polytrope
-    (depth 1, rho = p = 1 at mid-layer): the printed quadratic in w = r / 1e10
-    cm with r = r_unit * depth_cm, scaled by lambda so that the radiative
-    flux -kappa_r rho c_p dT/dr of the polytrope carries L / (4 pi R_i^2)
-    through the inner wall (so the almost-flux-balance entropy gradient
-    vanishes there)."""
-    import math
-    c0, c1, c2 = SOLAR_KAPPA_R_COEFFS
-    s = depth_cm * 1e-10
-    chi_o = (beta + 1.0) / (beta * math.exp(n_rho / poly_n) + 1.0)
-    c = (2.0 * chi_o - beta - 1.0) / (1.0 - beta)
-    alpha = (1.0 + beta) * (1.0 - chi_o) / (1.0 - beta) ** 2
-    ri = beta / (1.0 - beta)
-    w = ri * s
-    rho_i = (c + alpha / ri) ** poly_n
-    cp = gamma * R_gas / (gamma - 1.0)
-    # -lambda poly(R_i) rho_a c_p T_a'(R_i) = L / (4 pi R_i^2), T_a' = -alpha / (R r^2)
-    lam = luminosity * R_gas / (4.0 * math.pi * (c0 + c1 * w + c2 * w * w) * rho_i * cp * alpha)
-    return lam * c0, lam * c1 * s, lam * c2 * s * s
+    benchmark's radiative diffusivity (chorus_solar_kappa_r; depth_cm <= 0:
+    the library's default shell depth)."""
+    out = (ctypes.c_double * 3)()
+    _check(_lib.chorus_solar_kappa_r(float(beta), float(n_rho), float(poly_n), float(gamma), float(R_gas),
+                                     float(luminosity), float(depth_cm), out), "chorus_solar_kappa_r")
+    return out[0], out[1], out[2]
 
 
 def chorus_mesh_create(panel_n, radial_n, order, r_inner, r_outer):

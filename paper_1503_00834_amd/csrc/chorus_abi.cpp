@@ -664,6 +664,37 @@ int chorus_init_afb(chorus_mesh_t mesh, const chorus_afb_desc *desc, double *Q_h
     return CHORUS_OK;
 }
 
+// the printed radiative-diffusivity polynomial of the solar benchmark
+// (Section 7.4): coefficients of w = r / 1e10 cm, and Table 2's shell depth
+static const double kSolarKr[3] = {1.5600975e8, -4.5631718e7, 3.3370368e6};
+static const double kSolarDepthCm = 1.74e10;
+
+int chorus_solar_kappa_r(double beta, double n_rho, double poly_n, double gamma, double R_gas, double luminosity,
+                         double depth_cm, double out[3]) {
+    if (!out || !(beta > 0.0 && beta < 1.0) || !(poly_n > 0.0) || !(gamma > 1.0) || !(R_gas > 0.0) ||
+        !(luminosity >= 0.0) || !std::isfinite(n_rho) || !std::isfinite(depth_cm)) {
+        set_error("solar_kappa_r: need 0 < beta < 1, poly_n > 0, gamma > 1, R_gas > 0, L >= 0, out");
+        return CHORUS_EINVAL;
+    }
+    const double s = (depth_cm > 0.0 ? depth_cm : kSolarDepthCm) * 1e-10;  // w per unit r
+    // the polytrope of Section 4.2 with depth 1, rho_c = p_c = 1
+    const double om = 1.0 - beta;
+    const double chi_o = (beta + 1.0) / (beta * std::exp(n_rho / poly_n) + 1.0);
+    const double c = (2.0 * chi_o - beta - 1.0) / om;
+    const double alpha = (1.0 + beta) * (1.0 - chi_o) / (om * om);
+    const double ri = beta / om, w = ri * s;
+    const double rho_i = std::pow(c + alpha / ri, poly_n);
+    const double cp = gamma * R_gas / (gamma - 1.0);
+    // -lambda poly(w_i) rho_a c_p dT_a/dr = L / (4 pi R_i^2) at the inner
+    // wall, with dT_a/dr = -alpha / (R_gas r^2)
+    const double poly = kSolarKr[0] + kSolarKr[1] * w + kSolarKr[2] * w * w;
+    const double lam = luminosity * R_gas / (4.0 * M_PI * poly * rho_i * cp * alpha);
+    out[0] = lam * kSolarKr[0];
+    out[1] = lam * kSolarKr[1] * s;
+    out[2] = lam * kSolarKr[2] * s * s;
+    return CHORUS_OK;
+}
+
 int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q0_dev, void *ws,
                           void *stream) {
     Mesh *m = reinterpret_cast<Mesh *>(mesh);
