@@ -215,6 +215,27 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
 int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev, double dt,
                    int32_t n_steps, void *ws, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * FP64 steps as chorus_rk_step (SSP-RK3 or SSPRK(5,4), in place on Q_dev,
+ * bitwise equal results) without a workspace argument.  The stage registers,
+ * mailboxes and flag live in a fixed device array of
+ * CHORUS_NOALLOC_SCRATCH_BYTES inside the library: one copy per GPU, held
+ * until the process ends, its address looked up on the first call on each
+ * device (the current device must be the stream's).  No allocator is
+ * called.  Limits: CHORUS_FP64 precision without the learned closure
+ * (CHORUS_ENOTSUP otherwise); the mesh must fit the array (about 6,500
+ * hexes at N = 4 with SSP-RK3, 4,300 with SSPRK(5,4)), else CHORUS_EINVAL
+ * before anything runs, with the bytes needed in chorus_last_error.  Every
+ * call on one GPU shares the array and leaves its contents behind (no
+ * kernel reads a value it did not write in the same call): calls that
+ * overlap on one GPU, from other streams or threads, race and must be
+ * serialised by the caller.  CHORUS_CHECK_FINITE synchronises, as in
+ * chorus_rk_step. */
+#define CHORUS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int chorus_rk_step_noalloc(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev, double dt,
+                           int32_t n_steps, void *stream);
+
 /* Conserved totals (Section 6: the conservative form with interface fluxes
  * shared by both sides conserves them discretely): the sum over solution
  * points of w_i w_j w_k |J| Q_v for the 5 conserved variables, in a fixed

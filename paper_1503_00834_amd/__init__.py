@@ -106,6 +106,7 @@ _SIGS = {
     "chorus_solar_kappa_r": [ctypes.c_double] * 7 + [_P],
     "chorus_sd_residual": [_P, ctypes.POINTER(Physics), _P, _P, _P, _P],
     "chorus_rk_step": [_P, ctypes.POINTER(Physics), _P, ctypes.c_double, ctypes.c_int32, _P, _P],
+    "chorus_rk_step_noalloc": [_P, ctypes.POINTER(Physics), _P, ctypes.c_double, ctypes.c_int32, _P],
     "chorus_conserved_sums": [_P, _P, _P, _P, _P],
     "chorus_stable_dt": [_P, ctypes.POINTER(Physics), _P, ctypes.c_double, _dp],
     "chorus_angular_momentum": [_P, _P, _P, _P, _P],
@@ -294,6 +295,14 @@ def chorus_rk_step(mesh, phys, Q, dt, n_steps, ws, stream=None):
     assert Q.is_contiguous() and Q.numel() == 5 * mesh.n_solpts
     _check(_lib.chorus_rk_step(mesh.handle, ctypes.byref(phys), _P(Q.data_ptr()), float(dt), int(n_steps),
                                _ws_ptr(ws), _P(_stream(stream))), "chorus_rk_step")
+
+
+def chorus_rk_step_noalloc(mesh, phys, Q, dt, n_steps, stream=None):
+    """chorus_rk_step without a workspace (FP64 only): the library's fixed
+    device scratch array holds the stage registers (no allocation)."""
+    assert Q.is_contiguous() and Q.numel() == 5 * mesh.n_solpts
+    _check(_lib.chorus_rk_step_noalloc(mesh.handle, ctypes.byref(phys), _P(Q.data_ptr()), float(dt),
+                                       int(n_steps), _P(_stream(stream))), "chorus_rk_step_noalloc")
 
 
 def chorus_conserved_sums(mesh, Q, ws, stream=None):

@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -227,9 +228,7 @@ static int check_ready(const Mesh *m) {
     return CHORUS_OK;
 }
 
-static int finite_check(const Mesh &m, const PhysParams &P, const double *Q, const WsLayout &w,
-                        unsigned char *ws, hipStream_t s) {
-    int *flag = (int *)(ws + w.flag);
+static int finite_check_flag(const Mesh &m, const PhysParams &P, const double *Q, int *flag, hipStream_t s) {
     hipError_t e = launch_check(Q, m.E * m.N * m.N * m.N, P.gamma - 1.0, flag, s);
     if (e != hipSuccess) return hip_fail(e, "finite check");
     int h = 0;
@@ -241,6 +240,11 @@ static int finite_check(const Mesh &m, const PhysParams &P, const double *Q, con
         return CHORUS_ENONFINITE;
     }
     return CHORUS_OK;
+}
+
+static int finite_check(const Mesh &m, const PhysParams &P, const double *Q, const WsLayout &w,
+                        unsigned char *ws, hipStream_t s) {
+    return finite_check_flag(m, P, Q, (int *)(ws + w.flag), s);
 }
 
 // ---------------------------------------------------------------------------
@@ -838,6 +842,45 @@ static const StagePlan kSSPRK54[5] = {
     {3, 0, 2, -1, -1, 1.0, kA54, kB54 / kA54, 0, 0, 0},
 };
 
+// buffers of the FP64 step: stage registers (Q itself is register 0),
+// the receiver-indexed trace and viscous mailboxes and the finite-check flag
+struct Fp64Bufs {
+    double *Qs, *Q2, *Q4;  // Q2, Q4: SSPRK(5,4) only
+    double *TQ, *TV;       // [E][6][5][N^2]
+    int *flag;
+};
+
+// n steps of the FP64 path on explicit buffers (no allocation); kernel
+// timing only when allowed and switched on
+static int rk_fp64(const Mesh &m, const chorus_physics *phys, const ClosureArgs &C, double *Q_dev, double dt,
+                   int32_t n_steps, const Fp64Bufs &b, hipStream_t s, bool allow_timing) {
+    const bool rk54 = phys->integrator == CHORUS_SSPRK54;
+    const StagePlan *plan = rk54 ? kSSPRK54 : kSSPRK3;
+    const int nst = rk54 ? 5 : 3;
+    const PhysParams P = params_of(phys);
+    double *reg[4] = {Q_dev, b.Qs, b.Q2, b.Q4};
+    // the flux pass reads the trace mailbox and writes the viscous one; the
+    // lift pass reads the viscous mailbox and rewrites the traces (kernel
+    // order separates every read from the next write)
+    const Geo G = geo_of(m, nullptr);
+    auto run = [&](int kind, auto &&launch) { return allow_timing ? timed(kind, s, launch) : launch(); };
+    hipError_t e = run(0, [&] { return launch_trace_push(m, G, Q_dev, b.TQ, s); });
+    for (int st = 0; st < n_steps && e == hipSuccess; ++st) {
+        for (int k = 0; k < nst && e == hipSuccess; ++k) {
+            const StagePlan &sp = plan[k];
+            const double *qin = reg[sp.in];
+            StageArgs sa{sp.a >= 0 ? reg[sp.a] : nullptr, reg[sp.out], b.TQ, sp.c0, sp.c1, sp.c2 * dt,
+                         sp.b >= 0 ? reg[sp.b] : nullptr, sp.tout >= 0 ? reg[sp.tout] : nullptr, sp.d0, sp.d1,
+                         sp.d2 * dt, 1};
+            e = run(1, [&] { return launch_flux64(m, G, P, qin, b.TQ, b.TV, sa, C, s); });
+            if (e == hipSuccess) e = run(2, [&] { return launch_lift64(m, G, b.TV, sa, s); });
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "rk_step");
+    if (phys->flags & CHORUS_CHECK_FINITE) return finite_check_flag(m, P, Q_dev, b.flag, s);
+    return CHORUS_OK;
+}
+
 int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev, double dt, int32_t n_steps,
                    void *ws, void *stream) {
     Mesh *m = reinterpret_cast<Mesh *>(mesh);
@@ -890,29 +933,89 @@ int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev
         if (phys->flags & CHORUS_CHECK_FINITE) return finite_check(*m, P, Q_dev, w, W, s);
         return CHORUS_OK;
     }
-    double *TV = (double *)(W + w.TV);
-    double *reg[4] = {Q_dev, (double *)(W + w.Qs), rk54 ? (double *)(W + w.Q2) : nullptr,
-                      rk54 ? (double *)(W + w.Q4) : nullptr};
-    // the flux pass reads the trace mailbox and writes the viscous one; the
-    // lift pass reads the viscous mailbox and rewrites the traces (kernel
-    // order separates every read from the next write)
-    double *TQ = (double *)(W + w.TQ0);
-    const Geo G = geo_of(*m, (unsigned char *)ws);
-    hipError_t e = timed(0, s, [&] { return launch_trace_push(*m, G, Q_dev, TQ, s); });
-    for (int st = 0; st < n_steps && e == hipSuccess; ++st) {
-        for (int k = 0; k < nst && e == hipSuccess; ++k) {
-            const StagePlan &sp = plan[k];
-            const double *qin = reg[sp.in];
-            StageArgs sa{sp.a >= 0 ? reg[sp.a] : nullptr, reg[sp.out], TQ, sp.c0, sp.c1, sp.c2 * dt,
-                         sp.b >= 0 ? reg[sp.b] : nullptr, sp.tout >= 0 ? reg[sp.tout] : nullptr, sp.d0, sp.d1,
-                         sp.d2 * dt, 1};
-            e = timed(1, s, [&] { return launch_flux64(*m, G, P, qin, TQ, TV, sa, C, s); });
-            if (e == hipSuccess) e = timed(2, s, [&] { return launch_lift64(*m, G, TV, sa, s); });
-        }
+    const Fp64Bufs b{(double *)(W + w.Qs), rk54 ? (double *)(W + w.Q2) : nullptr,
+                     rk54 ? (double *)(W + w.Q4) : nullptr, (double *)(W + w.TQ0), (double *)(W + w.TV),
+                     (int *)(W + w.flag)};
+    return rk_fp64(*m, phys, C, Q_dev, dt, n_steps, b, s, true);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 steps without a caller workspace: the stage registers, mailboxes and
+// flag live in a fixed device array (one copy per GPU, held until the
+// process ends).  Host code uses the address hipGetSymbolAddress returns on
+// each device, never the array's name (a host-side stand-in).
+// ---------------------------------------------------------------------------
+static constexpr size_t kStaticScratchBytes = CHORUS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[kMaxDevices];
+
+// the scratch address on the current device, looked up once per device
+static int scratch_address(unsigned char **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "rk_step_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("rk_step_noalloc: device index beyond the supported count");
+        return CHORUS_ENOTSUP;
     }
-    if (e != hipSuccess) return hip_fail(e, "rk_step");
-    if (phys->flags & CHORUS_CHECK_FINITE) return finite_check(*m, P, Q_dev, w, W, s);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "rk_step_noalloc: hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = (unsigned char *)p;
+    }
+    *out = g_scratch_ptr[dev];
     return CHORUS_OK;
+}
+
+int chorus_rk_step_noalloc(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev, double dt,
+                           int32_t n_steps, void *stream) {
+    Mesh *m = reinterpret_cast<Mesh *>(mesh);
+    int rc = check_ready(m);
+    if (rc) return rc;
+    rc = check_phys(phys);
+    if (rc) return rc;
+    rc = check_kappa_r(*m, phys);
+    if (rc) return rc;
+    if (!Q_dev || n_steps < 0 || !std::isfinite(dt)) {
+        set_error("rk_step_noalloc: null pointer, negative step count or non-finite dt");
+        return CHORUS_EINVAL;
+    }
+    if (phys->precision != CHORUS_FP64 || phys->closure != CHORUS_CLOSURE_NONE) {
+        set_error("rk_step_noalloc: FP64 precision without the learned closure only");
+        return CHORUS_ENOTSUP;
+    }
+    // compact layout: stage register, [two SSPRK(5,4) registers], trace and
+    // viscous mailboxes, flag
+    const int N = m->N, NP = N * N * N, NF2 = N * N;
+    const bool rk54 = phys->integrator == CHORUS_SSPRK54;
+    const size_t state = sizeof(double) * 5 * (size_t)m->E * NP;
+    const size_t mbox = sizeof(double) * (size_t)m->E * 6 * 5 * NF2;
+    size_t off = 0;
+    const size_t oQs = off;  off = align256(off + state);
+    const size_t oQ2 = off;  off = rk54 ? align256(off + state) : off;
+    const size_t oQ4 = off;  off = rk54 ? align256(off + state) : off;
+    const size_t oTQ = off;  off = align256(off + mbox);
+    const size_t oTV = off;  off = align256(off + mbox);
+    const size_t oFl = off;  off = align256(off + sizeof(int) * 4);
+    if (off > kStaticScratchBytes) {
+        set_error("rk_step_noalloc: this mesh and integrator need " + std::to_string(off) +
+                  " bytes of scratch; the fixed maximum is " + std::to_string(kStaticScratchBytes) +
+                  " (use chorus_rk_step with a workspace)");
+        return CHORUS_EINVAL;
+    }
+    if (n_steps == 0) return CHORUS_OK;
+    unsigned char *S = nullptr;
+    rc = scratch_address(&S);
+    if (rc) return rc;
+    const Fp64Bufs b{(double *)(S + oQs), rk54 ? (double *)(S + oQ2) : nullptr, rk54 ? (double *)(S + oQ4) : nullptr,
+                     (double *)(S + oTQ), (double *)(S + oTV), (int *)(S + oFl)};
+    const ClosureArgs C{nullptr, nullptr};
+    return rk_fp64(*m, phys, C, Q_dev, dt, n_steps, b, (hipStream_t)stream, false);
 }
 
 int chorus_conserved_sums(chorus_mesh_t mesh, const double *Q_dev, double out_host[5], void *ws, void *stream) {
