@@ -1,19 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark: SD DOF-updates/s of the SSP-RK3 spectral-difference solver on
-one MI355X, with the per-kernel HBM roofline and the CPU oracle beside it.
+one MI355X (mixed FP32/FP64 path, checked against the FP64 plain path on the
+same run), with the dominant kernel's HBM roofline and the CPU oracle beside
+it.
 
 One step = one full SSP-RK3 step (three residual evaluations with the fused
-stage update) over every solution point of the workload; DOFs = E N^3.
-Inputs are synthetic and seeded: a cubed-sphere shell, the polytropic
-background and a seeded entropy perturbation (see the design notes).
+stage update) over every solution point of the workload; DOFs = E N^3.  The
+default workload is the 331,776-hex N = 4 Sun-like shell (21.2M DOFs), the
+single-GPU stand-in at the paper's production scale.  Inputs are synthetic
+and seeded: a cubed-sphere shell, the polytropic background and a seeded
+entropy perturbation.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+Timing: W untimed warm-up steps, then R repeats of K timed steps, each
+bracketed by device synchronisation, with per-kernel event timing off; the
+value is the median repeat.  One further K-step run with per-launch HIP-event
+timing (on the launch stream) gives the kernels' average launch durations
+for the roofline; it is not part of the value.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--repeats R] [--workload NAME]
 
 Prints one JSON line.
 """
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -29,24 +40,24 @@ HBM_PEAK_GBS = 8000.0
 # is the FP64-rate 78.6); FP64 78.6 TFLOP/s
 ALU_PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}
 
+# Algorithmic HBM bytes per DOF-update (one SSP-RK3 step of one solution
+# point), the operation-count model of the hot path: 320 B of FP64 state
+# (5 reads + 3 writes of 40 B), the 20 node coordinates and the face
+# connectivity once per element and stage; the mixed path adds per stage the
+# FP32 background residual, rho0 and p0 at every point and the background
+# face jump with its wave speed at every face point.
+ALG_BYTES_PER_DOF_UPDATE = {"fp64": {3: 379.0, 4: 345.0, 6: 327.0},
+                            "mixed": {3: 472.0, 4: 445.0}}
+
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def alg_bytes_per_stage_point(N, precision):
-    """Algorithmic bytes per solution point and residual stage.
-
-    FP64 state: 5 reads + 3 writes of 40 B per point per SSP-RK3 step, i.e.
-    320/3 B per stage; geometry from the 20 element nodes (480 B) and the
-    face connectivity (48 B) once per element and stage."""
-    NP = N ** 3
-    per = 320.0 / 3.0 + (480.0 + 48.0) / NP
-    if precision == "mixed":
-        # FP32 background residual (20 B), rho0, p0 (8 B) per point, and the
-        # FP32 background face jump + wave speed (12 B per face point)
-        per += 28.0 + 12.0 * 6 * N * N / NP
-    return per
+    """Algorithmic bytes per solution point and residual stage (a third of
+    the per-DOF-update figure)."""
+    return ALG_BYTES_PER_DOF_UPDATE[precision][N] / 3.0
 
 
 def kernel_source_sha():
@@ -142,10 +153,9 @@ def closure_leg(panel_n=32, radial_n=16):
                          "peak": 157.3}}
 
 
-def large_leg(ch, workload="sun_332k_N4", steps=10):
-    """The mixed path on the largest shell (6 x 48 x 48 x 24 = 331,776 hexes,
-    N = 4, 21.2M DOFs, 849 MB per FP64 state copy), which no cache holds:
-    DOF-updates/s over a few SSP-RK3 steps after one warm-up step."""
+def workload_leg(ch, workload, steps=10):
+    """Both paths on another workload (DOF-updates/s over a few SSP-RK3
+    steps after two warm-up steps)."""
     import torch
     from chorus_inputs import CONFIGS, shell_params_from_config, uniform_noise
     cfg = CONFIGS[workload]
@@ -153,28 +163,30 @@ def large_leg(ch, workload="sun_332k_N4", steps=10):
     mesh = ch.chorus_mesh_create(cfg["panel_n"], cfg["radial_n"], cfg["order"], ri, ro).upload()
     Qh, pars = mesh.init_polytrope(cfg["beta"], cfg["n_rho"], poly_n=cfg["poly_n"],
                                    noise=uniform_noise(mesh.n_solpts, cfg["seed"]), amp=1e-4)
-    phys = ch.physics(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"],
-                      T_top=pars["chi_o"], precision=ch.CHORUS_MIXED)
-    dt = mesh.stable_dt(phys, Qh, cfg["cfl"])
-    ws = mesh.workspace(phys)
     Q0h, _ = mesh.init_polytrope(cfg["beta"], cfg["n_rho"], poly_n=cfg["poly_n"])
-    ch.chorus_set_background(mesh, phys, torch.from_numpy(Q0h).cuda(), ws)
-    del Q0h
-    Q = torch.from_numpy(Qh).cuda()
-    stream = torch.cuda.current_stream()
-    ch.chorus_rk_step(mesh, phys, Q, dt, 1, ws, stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ch.chorus_rk_step(mesh, phys, Q, dt, steps, ws, stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    if not bool(torch.isfinite(Q).all()):
-        raise RuntimeError("large workload state became non-finite")
-    value = mesh.n_solpts * steps / wall
+    out = {"workload": workload, "hexes": mesh.n_elems, "dofs": mesh.n_solpts, "steps": steps}
     N = cfg["order"]
-    return {"workload": workload, "hexes": mesh.n_elems, "dofs": mesh.n_solpts, "precision": "mixed",
-            "steps": steps, "value": value, "ms_per_step": wall / steps * 1e3,
-            "path_hbm_frac": value * alg_bytes_per_stage_point(N, "mixed") * 3.0 / (HBM_PEAK_GBS * 1e9)}
+    for name, prec in (("mixed", ch.CHORUS_MIXED), ("fp64", ch.CHORUS_FP64)):
+        phys = ch.physics(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"],
+                          T_top=pars["chi_o"], precision=prec)
+        dt = mesh.stable_dt(phys, Qh, cfg["cfl"])
+        ws = mesh.workspace(phys)
+        if prec == ch.CHORUS_MIXED:
+            ch.chorus_set_background(mesh, phys, torch.from_numpy(Q0h).cuda(), ws)
+        Q = torch.from_numpy(Qh).cuda()
+        ch.chorus_rk_step(mesh, phys, Q, dt, 2, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.chorus_rk_step(mesh, phys, Q, dt, steps, ws)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if not bool(torch.isfinite(Q).all()):
+            raise RuntimeError("%s state became non-finite" % workload)
+        value = mesh.n_solpts * steps / wall
+        out[name] = {"value": value, "ms_per_step": wall / steps * 1e3,
+                     "path_hbm_frac": value * ALG_BYTES_PER_DOF_UPDATE[name][N] / (HBM_PEAK_GBS * 1e9)}
+        del Q, ws
+    return out
 
 
 def next_rows_leg(ch, mesh, cfg, pars, Qh, Q0h, dt, ws, steps=10):
@@ -265,31 +277,69 @@ def uniform_noise_of(n):
     return uniform_noise(n, 0)
 
 
-def cpu_baseline(cfg, budget_s=15.0):
-    """The CPU oracle on the same workload for a bounded number of steps."""
+def cpu_baseline(sample="jupiter_41k_N4", all_steps=2, single_steps=1):
+    """The CPU oracle (FP64, plain C, OpenMP over elements) on a bounded
+    sample of the workload: the 41,472-hex N = 4 shell, one eighth of the
+    331,776-hex shell's elements (one GPU's share of it in an eight-way
+    lateral split) with the same order and per-element work, timed on all
+    the host cores of this process and on one thread.  The rate is per DOF,
+    so it carries over to the full workload's unit."""
     import oracle
-    from chorus_inputs import cubed_sphere_shell, shell_params_from_config, uniform_noise
+    from chorus_inputs import CONFIGS, cubed_sphere_shell, shell_params_from_config, uniform_noise
     oracle.build(force=False)
+    cfg = CONFIGS[sample]
     ri, ro = shell_params_from_config(cfg)
-    m = cubed_sphere_shell(cfg["panel_n"], cfg["radial_n"], ri, ro)
-    om = oracle.OracleMesh(m, cfg["order"])
+    om = oracle.OracleMesh(cubed_sphere_shell(cfg["panel_n"], cfg["radial_n"], ri, ro), cfg["order"])
     Q, pars = om.polytrope(cfg["beta"], cfg["n_rho"], poly_n=cfg["poly_n"],
                            noise=uniform_noise(om.n_solpts, cfg["seed"]), amp=1e-4)
     ph = oracle.phys(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"],
                      T_top=pars["chi_o"])
-    dt = 1e-3
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        Q = om.rk3(ph, Q, dt, 1)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 20:
-            break
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": om.n_solpts * steps / el, "unit": "DOF-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "%d SSP-RK3 step(s) of the full workload (%d hexes, N=%d), %.1f s" % (
-                steps, om.E, cfg["order"], el)}
+    try:
+        n_cpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n_cpu = os.cpu_count() or 1
+    threads_all = oracle.max_threads()
+
+    def timed(threads, steps):
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        om.rk3(ph, Q, 1e-3, steps)
+        return om.n_solpts * steps / (time.perf_counter() - t0)
+
+    v_all = timed(threads_all, all_steps)
+    v_one = timed(1, single_steps)
+    oracle.set_threads(threads_all)
+    return {"value": v_all, "unit": "DOF-updates/s", "cores": threads_all, "kind": "oracle",
+            "sample": "%d SSP-RK3 step(s) of the %d-hex N=%d shell (%s: 1/8 of the 331,776-hex "
+                      "workload's elements, same order and per-element work), %d OpenMP threads"
+                      % (all_steps, om.E, cfg["order"], sample, threads_all),
+            "single_thread": {"value": v_one, "steps": single_steps, "cores": 1},
+            "host_cpus": n_cpu}
+
+
+def run_path(ch, mesh, phys, Q, dt, ws, args, stream, label):
+    import torch
+    log("%s: warm-up %d steps" % (label, args.warmup))
+    ch.chorus_rk_step(mesh, phys, Q, dt, args.warmup, ws, stream)
+    torch.cuda.synchronize()
+    reps = []
+    for r in range(args.repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.chorus_rk_step(mesh, phys, Q, dt, args.steps, ws, stream)
+        torch.cuda.synchronize()
+        reps.append(time.perf_counter() - t0)
+        log("%s: repeat %d: %.3f ms/step" % (label, r, reps[-1] / args.steps * 1e3))
+    # the kernels' launch durations: one more K-step run with HIP events on
+    # the launch stream (not part of the value)
+    ch.chorus_kernel_timing(True)
+    torch.cuda.synchronize()
+    ch.chorus_rk_step(mesh, phys, Q, dt, args.steps, ws, stream)
+    torch.cuda.synchronize()
+    ch.chorus_kernel_timing(False)
+    kt = ch.chorus_kernel_times()
+    log("%s: kernel times %s" % (label, kt))
+    return statistics.median(reps), reps, kt
 
 
 def main():
@@ -297,15 +347,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="jupiter_41k_N4")
+    ap.add_argument("--repeats", type=int, default=5)
+    ap.add_argument("--workload", default="sun_332k_N4")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-plain comparison leg")
-    ap.add_argument("--no-large", action="store_true", help="skip the 331,776-hex shell leg")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-plain comparison on the same run")
+    ap.add_argument("--no-other", action="store_true", help="skip the 41,472-hex workload leg")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the leg of the five-stage integrator, radial kappa_r and angular-momentum correction")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--size-sweep", action="store_true",
                     help="only measure both paths on shells from 288 to 331,776 hexes (one JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -315,6 +365,9 @@ def main():
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.repeats < 1 or args.warmup < 0:
+        print("need --steps >= 1, --repeats >= 1, --warmup >= 0", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -345,43 +398,33 @@ def main():
     mesh = ch.chorus_mesh_create(cfg["panel_n"], cfg["radial_n"], N, ri, ro).upload()
     noise = uniform_noise(mesh.n_solpts, cfg["seed"])
     Qh, pars = mesh.init_polytrope(cfg["beta"], cfg["n_rho"], poly_n=cfg["poly_n"], noise=noise, amp=1e-4)
+    del noise
     prec = ch.CHORUS_MIXED if args.precision == "mixed" else ch.CHORUS_FP64
-    phys = ch.physics(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"],
-                      T_top=pars["chi_o"], precision=prec)
+    kw = dict(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"], T_top=pars["chi_o"])
+    phys = ch.physics(precision=prec, **kw)
     dt = mesh.stable_dt(phys, Qh, cfg["cfl"])
     Q = torch.from_numpy(Qh).cuda()
     ws = mesh.workspace(phys)
+    Q0h = None
     if prec == ch.CHORUS_MIXED:
         # background: the polytrope without the perturbation (at rest)
         Q0h, _ = mesh.init_polytrope(cfg["beta"], cfg["n_rho"], poly_n=cfg["poly_n"])
         ch.chorus_set_background(mesh, phys, torch.from_numpy(Q0h).cuda(), ws)
-    log("E=%d N=%d DOFs=%d dt=%.3e; warmup %d" % (mesh.n_elems, N, mesh.n_solpts, dt, args.warmup))
+    log("E=%d N=%d DOFs=%d dt=%.3e; warmup %d, %d x %d timed steps" % (
+        mesh.n_elems, N, mesh.n_solpts, dt, args.warmup, args.repeats, args.steps))
     stream = torch.cuda.current_stream()
-    ch.chorus_rk_step(mesh, phys, Q, dt, args.warmup, ws, stream)
-    torch.cuda.synchronize()
-
-    log("timing %d steps" % args.steps)
-    ch.chorus_kernel_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ch.chorus_rk_step(mesh, phys, Q, dt, args.steps, ws, stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ch.chorus_kernel_timing(False)
-    ktimes = ch.chorus_kernel_times()
-    log("kernel times: %s" % ktimes)
+    med, reps, ktimes = run_path(ch, mesh, phys, Q, dt, ws, args, stream, args.precision)
+    total_steps = args.warmup + (args.repeats + 1) * args.steps
 
     # sanity outside the timed region
-    Qc = Q.cpu().numpy()
-    if not np.isfinite(Qc).all() or (Qc[0] <= 0).any():
+    if not bool(torch.isfinite(Q).all()) or not bool((Q[0] > 0).all()):
         print("state became non-finite or non-positive", file=sys.stderr)
         sys.exit(3)
 
-    dof_updates = mesh.n_solpts * args.steps
-    value = dof_updates / wall
+    value = mesh.n_solpts * args.steps / med
     # dominant kernel: the pass with the longer average launch (the flux pass
     # of either path); it carries the line operators and pointwise fluxes, so
-    # the stage's algorithmic flops and bytes are set against its launch time
+    # the stage's algorithmic bytes (and flops) are set against its launch time
     per_launch = {k: ktimes[k][0] / max(ktimes[k][1], 1) for k in ("pass1", "pass2")}
     dom = max(per_launch, key=per_launch.get)
     kname = ch.KERNEL_NAMES[args.precision][dom]
@@ -391,6 +434,7 @@ def main():
     flops = alg_flops_per_stage_point(N) * mesh.n_solpts
     tflops = flops / avg_s / 1e12
     peak_alu = ALU_PEAK_TFLOPS[args.precision]
+    path_gbs = value * ALG_BYTES_PER_DOF_UPDATE[args.precision][N] / 1e9
     out = {
         "metric": METRIC,
         "value": value,
@@ -398,59 +442,66 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": med / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "hexes": mesh.n_elems, "order": N, "dofs": mesh.n_solpts,
-                   "precision": args.precision, "integrator": "SSP-RK3", "dt": dt},
-        "roofline": {"bound": "alu", "kernel": kname, "achieved": tflops, "peak": peak_alu,
-                     "unit": "TFLOP/s", "frac": tflops / peak_alu,
+                   "precision": args.precision, "integrator": "SSP-RK3", "dt": dt,
+                   "repeats": args.repeats, "timing": "median of the repeats, per-kernel events off"},
+        "repeats_ms_per_step": [r / args.steps * 1e3 for r in reps],
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload, args.precision, kname),
-                     "alg_flops_per_launch": flops, "avg_launch_ms": avg_s * 1e3,
-                     "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_launch": alg},
-                     "path_hbm_frac": value * alg_bytes_per_stage_point(N, args.precision) * 3.0
-                     / (HBM_PEAK_GBS * 1e9)},
+                     "alg_bytes_per_launch": alg, "avg_launch_ms": avg_s * 1e3,
+                     "alg_bytes_per_dof_update": ALG_BYTES_PER_DOF_UPDATE[args.precision][N],
+                     "path": {"achieved": path_gbs, "unit": "GB/s", "frac": path_gbs / HBM_PEAK_GBS,
+                              "note": "whole SSP-RK3 step: DOF-updates/s x algorithmic bytes per DOF-update"},
+                     "alu": {"achieved": tflops, "peak": peak_alu, "unit": "TFLOP/s", "frac": tflops / peak_alu,
+                             "alg_flops_per_launch": flops}},
         "kernels_ms_per_step": {ch.KERNEL_NAMES[args.precision][k]: v[0] / args.steps for k, v in ktimes.items()},
+        "kernels_avg_launch_ms": {ch.KERNEL_NAMES[args.precision][k]: v[0] / max(v[1], 1)
+                                  for k, v in ktimes.items()},
     }
     if prec == ch.CHORUS_MIXED and not args.no_fp64:
         # the FP64 plain path on the same workload, for the comparison the
-        # metric names: the same untimed and timed steps from the same
-        # state, so the two end states can be compared (outside the timing)
-        log("fp64 plain path")
-        p64 = ch.physics(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"],
-                         T_top=pars["chi_o"], precision=ch.CHORUS_FP64)
+        # metric names: the same warm-up and timed steps from the same state,
+        # so the two end states can be compared (outside the timing)
+        log("fp64 plain path on the same run")
+        p64 = ch.physics(precision=ch.CHORUS_FP64, **kw)
         Q64 = torch.from_numpy(Qh).cuda()
-        ch.chorus_rk_step(mesh, p64, Q64, dt, args.warmup, ws, stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ch.chorus_rk_step(mesh, p64, Q64, dt, args.steps, ws, stream)
-        torch.cuda.synchronize()
-        w64 = time.perf_counter() - t0
-        A = Q64.cpu().numpy().reshape(5, -1)
-        B = Qc.reshape(5, -1)
-        start = Qh.reshape(5, -1)
-        rel = [float(np.linalg.norm(B[v] - A[v]) / np.linalg.norm(A[v])) for v in range(5)]
-        rel_change = [float(np.linalg.norm(B[v] - A[v]) / max(np.linalg.norm(A[v] - start[v]), 1e-300))
-                      for v in (0, 4)]
-        out["fp64_plain"] = {"value": mesh.n_solpts * args.steps / w64, "ms_per_step": w64 / args.steps * 1e3,
-                             "speedup_mixed_over_fp64": w64 / wall,
-                             "mixed_vs_fp64": {"steps": args.warmup + args.steps, "rel_l2_per_variable": rel,
+        med64, reps64, kt64 = run_path(ch, mesh, p64, Q64, dt, ws, args, stream, "fp64")
+        Qs = torch.from_numpy(Qh).cuda()
+        rel, rel_change = [], []
+        for v in range(5):
+            d = torch.linalg.vector_norm(Q[v] - Q64[v]).item()
+            rel.append(d / torch.linalg.vector_norm(Q64[v]).item())
+            rel_change.append(d / max(torch.linalg.vector_norm(Q64[v] - Qs[v]).item(), 1e-300))
+        del Qs
+        v64 = mesh.n_solpts * args.steps / med64
+        out["fp64_plain"] = {"value": v64, "ms_per_step": med64 / args.steps * 1e3,
+                             "repeats_ms_per_step": [r / args.steps * 1e3 for r in reps64],
+                             "speedup_mixed_over_fp64": med64 / med,
+                             "kernels_avg_launch_ms": {ch.KERNEL_NAMES["fp64"][k]: t[0] / max(t[1], 1)
+                                                       for k, t in kt64.items()},
+                             "path_hbm_frac": v64 * ALG_BYTES_PER_DOF_UPDATE["fp64"][N] / (HBM_PEAK_GBS * 1e9),
+                             "mixed_vs_fp64": {"steps": total_steps, "rel_l2_per_variable": rel,
                                                "max_rel_l2": max(rel), "bound": 1e-6,
-                                               "rel_to_change_rho_E": rel_change}}
+                                               "rel_to_change_per_variable": rel_change}}
+        log("mixed vs fp64 after %d steps: %s" % (total_steps, rel))
         del Q64
     if prec == ch.CHORUS_MIXED and not args.no_next:
         log("five-stage integrator, radial kappa_r, angular-momentum leg")
         out["next_rows"] = next_rows_leg(ch, mesh, cfg, pars, Qh, Q0h, dt, ws)
         torch.cuda.synchronize()
-    if prec == ch.CHORUS_MIXED and not args.no_large:
-        log("large-shell leg")
-        del Q, ws
-        torch.cuda.empty_cache()
-        out["large"] = large_leg(ch)
+    del Q, ws
+    torch.cuda.empty_cache()
+    if not args.no_other:
+        other = "jupiter_41k_N4" if args.workload != "jupiter_41k_N4" else "sun_332k_N4"
+        log("%s leg" % other)
+        out["other_workload"] = workload_leg(ch, other)
         torch.cuda.synchronize()
     if not args.no_closure:
         log("closure leg")
@@ -458,7 +509,7 @@ def main():
         torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

@@ -69,6 +69,16 @@ def lib():
     return _lib
 
 
+def set_threads(n):
+    """OpenMP threads of the oracle's element loops (its results do not
+    depend on the count)."""
+    lib().omp_set_num_threads(int(n))
+
+
+def max_threads():
+    return int(lib().omp_get_max_threads())
+
+
 def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
