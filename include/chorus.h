@@ -59,7 +59,8 @@ enum {
 enum { CHORUS_FP64 = 0, CHORUS_MIXED = 1 };            /* chorus_physics.precision */
 enum { CHORUS_CLOSURE_NONE = 0, CHORUS_CLOSURE_MLP = 1 }; /* chorus_physics.closure */
 enum { CHORUS_SSPRK3 = 0, CHORUS_SSPRK54 = 1 };         /* chorus_physics.integrator */
-enum { CHORUS_CHECK_FINITE = 1 };                      /* chorus_physics.flags     */
+enum { CHORUS_CHECK_FINITE = 1,                       /* chorus_physics.flags     */
+       CHORUS_BALANCED = 2 };                          /* see chorus_set_background */
 enum { CHORUS_BC_INTERIOR = -1, CHORUS_BC_INNER = 1, CHORUS_BC_OUTER = 2,
        CHORUS_BC_STATE = 3 };
 
@@ -173,6 +174,10 @@ typedef struct {
     double luminosity;        /* L in the units of depth 1, rho_c = p_c = 1 */
     double kappa, kappa_r;
     double kappa_r1, kappa_r2;
+    const double *noise;      /* host [E N^3] or NULL: entropy perturbation
+                                 S' = amp c_p noise at fixed pressure, as in
+                                 chorus_init_polytrope                         */
+    double amp;
 } chorus_afb_desc;
 int chorus_init_afb(chorus_mesh_t mesh, const chorus_afb_desc *desc, double *Q_host, double pars[6]);
 
@@ -196,7 +201,18 @@ int chorus_solar_kappa_r(double beta, double n_rho, double poly_n, double gamma,
  * momentum; CHORUS_EINVAL otherwise); CHORUS_BC_STATE faces are not
  * supported (CHORUS_ENOTSUP).  A failed call leaves no background
  * registered: chorus_rk_step and chorus_sd_residual in mixed precision
- * then return CHORUS_ESTATE until a call succeeds. */
+ * then return CHORUS_ESTATE until a call succeeds.
+ * Balanced mode (phys->flags & CHORUS_BALANCED, set here and in every call
+ * that uses it): the residual becomes R(Q) - R(Q0) in both precisions, so
+ * the background is a discrete steady state (to rounding) and only its
+ * departure from one evolves.  The subtracted term is the discretisation's
+ * own imbalance of Q0, of the order of the truncation error (h^N); it lets
+ * a background built from the continuous equations, such as the
+ * almost-flux-balance state of Section 4.3, start convection from a seeded
+ * perturbation instead of adjustment flows.  FP64 calls with the flag need
+ * a background registered with this workspace and the same physics
+ * (CHORUS_ESTATE otherwise); mixed calls need a background registered with
+ * the flag. */
 int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const double *Q0_dev,
                           void *ws, void *stream);
 
@@ -223,8 +239,8 @@ int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev
  * CHORUS_NOALLOC_SCRATCH_BYTES inside the library: one copy per GPU, held
  * until the process ends, its address looked up on the first call on each
  * device (the current device must be the stream's).  No allocator is
- * called.  Limits: CHORUS_FP64 precision without the learned closure
- * (CHORUS_ENOTSUP otherwise); the mesh must fit the array (about 6,500
+ * called.  Limits: CHORUS_FP64 precision without the learned closure or
+ * CHORUS_BALANCED (CHORUS_ENOTSUP otherwise); the mesh must fit the array (about 6,500
  * hexes at N = 4 with SSP-RK3, 4,300 with SSPRK(5,4)), else CHORUS_EINVAL
  * before anything runs, with the bytes needed in chorus_last_error.  Every
  * call on one GPU shares the array and leaves its contents behind (no

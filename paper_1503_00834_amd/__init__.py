@@ -19,6 +19,7 @@ CHORUS_FP64, CHORUS_MIXED = 0, 1
 CHORUS_CLOSURE_NONE, CHORUS_CLOSURE_MLP = 0, 1
 CHORUS_SSPRK3, CHORUS_SSPRK54 = 0, 1
 CHORUS_CHECK_FINITE = 1
+CHORUS_BALANCED = 2
 CHORUS_MLP_IN, CHORUS_MLP_HIDDEN, CHORUS_MLP_OUT = 20, 64, 15
 CHORUS_MLP_NPARAM, CHORUS_MLP_NNORM = 6479, 70
 ERRORS = {-1: "EINVAL", -2: "EMESH", -3: "ENOTSUP", -4: "EHIP", -5: "ENONFINITE", -6: "ESTATE"}
@@ -26,6 +27,11 @@ ERRORS = {-1: "EINVAL", -2: "EMESH", -3: "ENOTSUP", -4: "EHIP", -5: "ENONFINITE"
 if not os.path.exists(LIB_PATH):
     raise ImportError("libchorus.so is not built; run __graft_entry__.build() or "
                       "python paper_1503_00834_amd/build.py")
+
+# PyTorch first: the library and PyTorch must share one HIP runtime, and the
+# one PyTorch brings has to be loaded before the library's dependency is
+# resolved
+import torch  # noqa: E402,F401
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -54,7 +60,8 @@ class AfbDesc(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("n_rho", ctypes.c_double), ("poly_n", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("R_gas", ctypes.c_double), ("luminosity", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("kappa_r", ctypes.c_double),
-                ("kappa_r1", ctypes.c_double), ("kappa_r2", ctypes.c_double)]
+                ("kappa_r1", ctypes.c_double), ("kappa_r2", ctypes.c_double),
+                ("noise", ctypes.c_void_p), ("amp", ctypes.c_double)]
 
 
 class Physics(ctypes.Structure):
@@ -216,12 +223,17 @@ class Mesh:
         return Q, dict(chi_o=pars[0], c=pars[1], alpha=pars[2], GM=pars[3])
 
     def init_afb(self, beta, n_rho, luminosity, kappa, kappa_r=0.0, poly_n=1.5, gamma=5.0 / 3.0, R_gas=1.0,
-                 kappa_r1=0.0, kappa_r2=0.0):
+                 kappa_r1=0.0, kappa_r2=0.0, noise=None, amp=0.0):
         """Almost-flux-balance background at rest (chorus_init_afb): (Q [5, n],
-        pars with GM, T_top (outer-wall temperature) and F_bottom)."""
+        pars with GM, T_top (outer-wall temperature) and F_bottom); noise and
+        amp: optional entropy perturbation at fixed pressure."""
         Q = np.zeros((5, self.n_solpts))
         pars = np.zeros(6)
-        d = AfbDesc(beta, n_rho, poly_n, gamma, R_gas, luminosity, kappa, kappa_r, kappa_r1, kappa_r2)
+        nz = None if noise is None else np.ascontiguousarray(noise, dtype=np.float64).reshape(-1)
+        if nz is not None:
+            assert nz.size == self.n_solpts
+        d = AfbDesc(beta, n_rho, poly_n, gamma, R_gas, luminosity, kappa, kappa_r, kappa_r1, kappa_r2,
+                    _ptr(nz), amp)
         _check(_lib.chorus_init_afb(self.handle, ctypes.byref(d), _ptr(Q), _ptr(pars)), "chorus_init_afb")
         return Q, dict(chi_o=pars[0], c=pars[1], alpha=pars[2], GM=pars[3], T_top=pars[4], F_bottom=pars[5])
 

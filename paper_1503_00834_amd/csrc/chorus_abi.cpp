@@ -33,6 +33,7 @@ struct WsLayout {
     // mixed-precision path
     size_t P0, P1, TQm, TVm, bg, dbg, gS0, R0, Q0, gbg;
     size_t P2, P4;  // SSPRK(5,4) on the perturbation
+    size_t R64;     // FP64 background residual R(Q0) (balanced mode)
     bool mixed;
     size_t total;
 };
@@ -69,6 +70,7 @@ static WsLayout ws_layout(const Mesh &m) {
     w.gbg = off;  off = align256(off + sizeof(float) * E * 3 * NP);
     w.R0 = off;   off = align256(off + sizeof(float) * 5 * E * NP);
     w.Q0 = off;   off = align256(off + state);
+    w.R64 = off;  off = align256(off + state);
     w.total = off;
     return w;
 }
@@ -164,8 +166,9 @@ static int check_mixed(const Mesh &m, const chorus_physics *p, const void *ws) {
     const chorus_physics &b = m.bg_phys;
     if (b.gamma != p->gamma || b.R_gas != p->R_gas || b.GM != p->GM || b.omega != p->omega || b.nu != p->nu ||
         b.kappa != p->kappa || b.kappa_r != p->kappa_r || b.kappa_r1 != p->kappa_r1 ||
-        b.kappa_r2 != p->kappa_r2 || b.T_top != p->T_top || b.F_bottom != p->F_bottom) {
-        set_error("mixed precision: the physics must match the one passed to chorus_set_background");
+        b.kappa_r2 != p->kappa_r2 || b.T_top != p->T_top || b.F_bottom != p->F_bottom ||
+        (b.flags & CHORUS_BALANCED) != (p->flags & CHORUS_BALANCED)) {
+        set_error("the physics (and the balanced flag) must match the one passed to chorus_set_background");
         return CHORUS_ESTATE;
     }
     return CHORUS_OK;
@@ -649,7 +652,8 @@ int chorus_init_afb(chorus_mesh_t mesh, const chorus_afb_desc *desc, double *Q_h
         // from rc down to ri)
         if (r >= rc) hermite(M, r_out, y_out, r, y);
         else hermite(M, r_in, y_in, r, y);
-        Q_host[g] = y[0];
+        // rho at fixed p for the entropy perturbation S' = amp c_p noise
+        Q_host[g] = d.noise ? y[0] * std::exp(-d.amp * d.noise[g]) : y[0];
         Q_host[n + g] = 0.0;
         Q_host[2 * n + g] = 0.0;
         Q_host[3 * n + g] = 0.0;
@@ -746,7 +750,13 @@ int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const 
     if (e == hipSuccess) e = launch_trace_push(*m, G, Q0, TQp, s);
     if (e == hipSuccess) e = launch_flux64(*m, G, P, Q0, TQp, TV, sa, C0, s);
     if (e == hipSuccess) e = launch_lift64(*m, G, TV, sa, s);
-    if (e == hipSuccess) e = launch_to_float(R0d, (float *)(W + w.R0), 5 * n, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(W + w.R64, R0d, sizeof(double) * 5 * n, hipMemcpyDeviceToDevice, s);
+    // the mixed path adds R0 to its FP32 perturbation residual; in balanced
+    // mode R(Q) - R(Q0) is the perturbation residual alone
+    if (e == hipSuccess) {
+        if (phys->flags & CHORUS_BALANCED) e = hipMemsetAsync(W + w.R0, 0, sizeof(float) * 5 * n, s);
+        else e = launch_to_float(R0d, (float *)(W + w.R0), 5 * n, s);
+    }
     int h = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -798,7 +808,12 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
     }
     double *TQ = (double *)(W + w.TQ0), *TV = (double *)(W + w.TV);
     const Geo G = geo_of(*m, (unsigned char *)ws);
-    StageArgs sa{nullptr, dQdt_dev, nullptr, 0.0, 1.0, 0.0, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
+    StageArgs sa{nullptr, dQdt_dev, nullptr, 0.0, 1.0, 0.0, nullptr, nullptr, 0.0, 0.0, 0.0, 0, nullptr};
+    if (phys->flags & CHORUS_BALANCED) {
+        rc = check_mixed(*m, phys, ws);
+        if (rc) return rc;
+        sa.R0 = (const double *)(W + w.R64);
+    }
     hipError_t e = timed(0, s, [&] { return launch_trace_push(*m, G, Q_dev, TQ, s); });
     if (e == hipSuccess) e = timed(1, s, [&] { return launch_flux64(*m, G, P, Q_dev, TQ, TV, sa, C, s); });
     if (e == hipSuccess) e = timed(2, s, [&] { return launch_lift64(*m, G, TV, sa, s); });
@@ -848,6 +863,7 @@ struct Fp64Bufs {
     double *Qs, *Q2, *Q4;  // Q2, Q4: SSPRK(5,4) only
     double *TQ, *TV;       // [E][6][5][N^2]
     int *flag;
+    const double *R0;      // subtracted background residual (balanced) or null
 };
 
 // n steps of the FP64 path on explicit buffers (no allocation); kernel
@@ -871,7 +887,7 @@ static int rk_fp64(const Mesh &m, const chorus_physics *phys, const ClosureArgs 
             const double *qin = reg[sp.in];
             StageArgs sa{sp.a >= 0 ? reg[sp.a] : nullptr, reg[sp.out], b.TQ, sp.c0, sp.c1, sp.c2 * dt,
                          sp.b >= 0 ? reg[sp.b] : nullptr, sp.tout >= 0 ? reg[sp.tout] : nullptr, sp.d0, sp.d1,
-                         sp.d2 * dt, 1};
+                         sp.d2 * dt, 1, b.R0};
             e = run(1, [&] { return launch_flux64(m, G, P, qin, b.TQ, b.TV, sa, C, s); });
             if (e == hipSuccess) e = run(2, [&] { return launch_lift64(m, G, b.TV, sa, s); });
         }
@@ -933,9 +949,15 @@ int chorus_rk_step(chorus_mesh_t mesh, const chorus_physics *phys, double *Q_dev
         if (phys->flags & CHORUS_CHECK_FINITE) return finite_check(*m, P, Q_dev, w, W, s);
         return CHORUS_OK;
     }
+    const double *R0 = nullptr;
+    if (phys->flags & CHORUS_BALANCED) {
+        rc = check_mixed(*m, phys, ws);
+        if (rc) return rc;
+        R0 = (const double *)(W + w.R64);
+    }
     const Fp64Bufs b{(double *)(W + w.Qs), rk54 ? (double *)(W + w.Q2) : nullptr,
                      rk54 ? (double *)(W + w.Q4) : nullptr, (double *)(W + w.TQ0), (double *)(W + w.TV),
-                     (int *)(W + w.flag)};
+                     (int *)(W + w.flag), R0};
     return rk_fp64(*m, phys, C, Q_dev, dt, n_steps, b, s, true);
 }
 
@@ -985,8 +1007,8 @@ int chorus_rk_step_noalloc(chorus_mesh_t mesh, const chorus_physics *phys, doubl
         set_error("rk_step_noalloc: null pointer, negative step count or non-finite dt");
         return CHORUS_EINVAL;
     }
-    if (phys->precision != CHORUS_FP64 || phys->closure != CHORUS_CLOSURE_NONE) {
-        set_error("rk_step_noalloc: FP64 precision without the learned closure only");
+    if (phys->precision != CHORUS_FP64 || phys->closure != CHORUS_CLOSURE_NONE || (phys->flags & CHORUS_BALANCED)) {
+        set_error("rk_step_noalloc: FP64 precision without the learned closure or the balanced mode only");
         return CHORUS_ENOTSUP;
     }
     // compact layout: stage register, [two SSPRK(5,4) registers], trace and
@@ -1013,7 +1035,7 @@ int chorus_rk_step_noalloc(chorus_mesh_t mesh, const chorus_physics *phys, doubl
     rc = scratch_address(&S);
     if (rc) return rc;
     const Fp64Bufs b{(double *)(S + oQs), rk54 ? (double *)(S + oQ2) : nullptr, rk54 ? (double *)(S + oQ4) : nullptr,
-                     (double *)(S + oTQ), (double *)(S + oTV), (int *)(S + oFl)};
+                     (double *)(S + oTQ), (double *)(S + oTV), (int *)(S + oFl), nullptr};
     const ClosureArgs C{nullptr, nullptr};
     return rk_fp64(*m, phys, C, Q_dev, dt, n_steps, b, (hipStream_t)stream, false);
 }

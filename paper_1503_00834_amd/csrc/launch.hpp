@@ -34,6 +34,8 @@ struct StageArgs {
     double *Tout;
     double d0, d1, d2;
     int mode;          // 0 residual, 1 RK stage
+    const double *R0;  // background residual subtracted from R (balanced
+                       // mode, added by the lift pass) or null
 };
 
 // learned subgrid closure (FP64 path, N = 3): model == null switches it off

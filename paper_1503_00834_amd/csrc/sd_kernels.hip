@@ -635,7 +635,8 @@ __global__ __launch_bounds__(NT) void k_lift64(Ops<N> opa, Geo G, const double *
         const bool ok = it < EPB * 30 * NF2 && e0 + it / (30 * NF2) < E;
         mb[k] = TV[ok ? e0 * 30 * NF2 + it : 0];
     }
-    double qo[IT_SOL][5], to[IT_SOL][5], iJ[IT_SOL];
+    double qo[IT_SOL][5], to[IT_SOL][5], iJ[IT_SOL], r0[IT_SOL][5];
+    const bool bal = S_.R0 != nullptr;
 #pragma unroll
     for (int k = 0; k < IT_SOL; ++k) {
         const int it = threadIdx.x + k * NT;
@@ -646,6 +647,7 @@ __global__ __launch_bounds__(NT) void k_lift64(Ops<N> opa, Geo G, const double *
             const int64_t gi = ((int64_t)v * E + e) * NP + p;
             qo[k][v] = S_.Qout[gi];
             to[k][v] = useT ? S_.Tout[gi] : 0.0;
+            r0[k][v] = bal ? S_.R0[gi] : 0.0;
         }
     }
     ops_to_lds(opa, op);
@@ -683,9 +685,11 @@ __global__ __launch_bounds__(NT) void k_lift64(Ops<N> opa, Geo G, const double *
         for (int v = 0; v < 5; ++v) {
             const int64_t gi = ((int64_t)v * E + e) * NP + p;
             const double x = -iJ[k] * corr[v];
-            const double qn = qo[k][v] + wP * x;
+            // balanced mode: the background residual leaves R after the
+            // lift (at Q = Q0 a residual call then gives exactly zero)
+            const double qn = bal ? (qo[k][v] + wP * x) - wP * r0[k][v] : qo[k][v] + wP * x;
             S_.Qout[gi] = qn;
-            if (useT) S_.Tout[gi] = to[k][v] + wT * x;
+            if (useT) S_.Tout[gi] = bal ? (to[k][v] + wT * x) - wT * r0[k][v] : to[k][v] + wT * x;
             sq[el][v][p] = qn;
         }
     }
