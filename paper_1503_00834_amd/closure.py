@@ -435,3 +435,215 @@ def cost_per_time(panel_n, radial_n, beta=0.7, order_fine=6, order_coarse=3, ste
         del Q, ws
     out["ratio_resolved_over_closure"] = out["resolved"]["seconds_per_time"] / out["closure"]["seconds_per_time"]
     return out
+
+
+# ---------------------------------------------------------------------------
+# the configured experiment: training data from a convecting resolved run on
+# the 12,288-hex shell, judged on the 98,304-hex shell
+# ---------------------------------------------------------------------------
+def _log(msg):
+    import sys
+    print("[closure] " + msg, file=sys.stderr, flush=True)
+
+
+def convecting_start(mesh, beta, n_rho, luminosity, nu, omega, seed, amp, gamma=5.0 / 3.0):
+    """Almost-flux-balance background (Section 4.3) at rest, Q0, and the
+    same state with a seeded entropy perturbation, Q (host arrays), with the
+    physics keywords (the balanced flag is added by the callers)."""
+    from chorus_inputs import uniform_noise
+    Q0h, pars = mesh.init_afb(beta, n_rho, luminosity, nu, gamma=gamma)
+    Qh, _ = mesh.init_afb(beta, n_rho, luminosity, nu, gamma=gamma, noise=uniform_noise(mesh.n_solpts, seed),
+                          amp=amp)
+    kw = dict(gamma=gamma, GM=pars["GM"], omega=omega, nu=nu, kappa=nu, T_top=pars["T_top"],
+              F_bottom=pars["F_bottom"])
+    return Q0h, Qh, kw
+
+
+def kinetic_energy(Q, wJ):
+    """Volume integral of rho |u|^2 / 2 (device state, device weights)."""
+    return float((0.5 * (Q[1:4] ** 2).sum(0) / Q[0] * wJ).sum())
+
+
+def balanced_run(mesh, kw, Q0, Q, t_end, cfl, precision, label, chunks=12):
+    """Advance Q (device) in balanced mode about Q0 to time t_end, the time
+    step recomputed from the state at every chunk; logs the kinetic energy.
+    Returns the time reached."""
+    from . import CHORUS_BALANCED, CHORUS_FP64, chorus_set_background
+    torch = _torch()
+    phys = physics(precision=precision, flags=CHORUS_BALANCED, **kw)
+    ws = mesh.workspace(phys)
+    chorus_set_background(mesh, phys, Q0, ws)
+    _, wJ = mesh.solpts()
+    wJd = torch.from_numpy(wJ).to(Q.device)
+    t = 0.0
+    while t < t_end * (1.0 - 1e-12):
+        dt = mesh.stable_dt(phys, Q.cpu().numpy(), cfl)
+        n = max(1, int(math.ceil(min(t_end / chunks, t_end - t) / dt)))
+        chorus_rk_step(mesh, phys, Q, dt, n, ws)
+        t += n * dt
+        ke = kinetic_energy(Q, wJd)
+        vmax = float((((Q[1:4] / Q[0]) ** 2).sum(0)).max().sqrt())
+        _log("%s: t = %.2f (dt %.2e), kinetic energy %.3e, max |u| %.3f" % (label, t, dt, ke, vmax))
+        if not math.isfinite(ke):
+            raise RuntimeError("%s became non-finite at t = %.2f" % (label, t))
+    del ws
+    return t
+
+
+def configured_experiment(beta=0.73, n_rho=3.0, omega=0.5, nu=5e-5, luminosity=1e-4, amp=1e-3,
+                          data_mesh=(16, 8), judge_mesh=(32, 16), order_fine=6, order_coarse=3,
+                          t_spin=24.0, n_snap=13, snap_every=0.8, iters=6000, batch=4096, lr=1e-3,
+                          coarse_steps=1000, n_ref=10, cfl=0.3, seed=1, gamma=5.0 / 3.0, spin_precision=None):
+    """The closure experiment at the configured sizes.
+
+    Data (12,288 hexes): a resolved order-6 run of the almost-flux-balance
+    background (Section 4.3; Sun-like: beta 0.73, 3 density scale heights,
+    Omega 0.5, nu = kappa = 5e-5, luminosity L) in balanced mode, from a
+    seeded entropy perturbation, spun up to t_spin (convecting), then n_snap
+    snapshots snap_every apart, each filtered to order 3 (331,776 samples
+    per snapshot); normalisation and mini-batch Adam.
+    Judged run (98,304 hexes): the same set-up at order 6 (another seed) spun
+    up to t_spin and filtered to order 3 as the common start; the resolved
+    run continues 2 coarse_steps steps (reference states filtered to order 3
+    every 2 coarse_steps / n_ref steps), the order-3 runs without and with
+    the closure take coarse_steps steps of twice the fine step; errors of
+    the kinetic-energy spectrum over the outer element layer and of the
+    mean radial profiles, time-averaged over the n_ref reference times;
+    cost per unit simulated time of the resolved and the closure runs.
+    Returns a JSON-ready report."""
+    import time
+    from chorus_inputs import mlp_init
+    from . import CHORUS_BALANCED, CHORUS_FP64, CHORUS_MIXED, chorus_mesh_create, chorus_set_background
+    torch = _torch()
+    spin_precision = CHORUS_MIXED if spin_precision is None else spin_precision
+    ri, ro = beta / (1.0 - beta), 1.0 / (1.0 - beta)
+    report = {"config": dict(beta=beta, n_rho=n_rho, omega=omega, nu=nu, luminosity=luminosity, amp=amp,
+                             data_mesh=data_mesh, judge_mesh=judge_mesh, t_spin=t_spin, n_snap=n_snap,
+                             snap_every=snap_every, iters=iters, batch=batch, coarse_steps=coarse_steps,
+                             n_ref=n_ref, cfl=cfl, seed=seed)}
+    t_start = time.perf_counter()
+    # ---- training data on the 12,288-hex shell
+    mf = chorus_mesh_create(data_mesh[0], data_mesh[1], order_fine, ri, ro).upload()
+    mc = chorus_mesh_create(data_mesh[0], data_mesh[1], order_coarse, ri, ro).upload()
+    Q0h, Qh, kw = convecting_start(mf, beta, n_rho, luminosity, nu, omega, seed, amp, gamma)
+    Q0 = torch.from_numpy(Q0h).cuda()
+    Q = torch.from_numpy(Qh).cuda()
+    _log("data run: %d hexes, order %d (%d points)" % (mf.n_elems, order_fine, mf.n_solpts))
+    balanced_run(mf, kw, Q0, Q, t_spin, cfl, spin_precision, "data spin-up")
+    p64 = physics(flags=CHORUS_BALANCED, **kw)
+    ws = mf.workspace(p64)
+    chorus_set_background(mf, p64, Q0, ws)
+    dt = mf.stable_dt(p64, Q.cpu().numpy(), cfl)
+    every = max(1, int(round(snap_every / dt)))
+    snaps = [Q.clone()]
+    for i in range(1, n_snap):
+        chorus_rk_step(mf, p64, Q, dt, every, ws)
+        snaps.append(Q.clone())
+    if not bool(torch.isfinite(Q).all()):
+        raise RuntimeError("data run became non-finite")
+    _log("data run: %d snapshots, %d steps of %.2e apart" % (n_snap, every, dt))
+    del ws
+    X, Y = samples(mf, mc, physics(**kw), snaps, gamma)
+    del snaps
+    norm = normalisation(X, Y)
+    t0 = time.perf_counter()
+    P, losses = train(X, Y, norm, mlp_init(seed), iters, batch, seed, lr=lr)
+    torch.cuda.synchronize()
+    report["training"] = {"samples": int(X.shape[0]), "seconds": time.perf_counter() - t0,
+                          "loss_start": float(losses[:20].mean()), "loss_end": float(losses[-50:].mean())}
+    _log("training: %d samples, loss %.3f -> %.3f" % (X.shape[0], report["training"]["loss_start"],
+                                                       report["training"]["loss_end"]))
+    del X, Y, mf, mc, Q, Q0
+    torch.cuda.empty_cache()
+    model = pack_or_none(P, norm)
+    # ---- judged runs on the 98,304-hex shell
+    mf = chorus_mesh_create(judge_mesh[0], judge_mesh[1], order_fine, ri, ro).upload()
+    mc = chorus_mesh_create(judge_mesh[0], judge_mesh[1], order_coarse, ri, ro).upload()
+    Q0h, Qh, kw = convecting_start(mf, beta, n_rho, luminosity, nu, omega, seed + 1, amp, gamma)
+    Q0 = torch.from_numpy(Q0h).cuda()
+    Q = torch.from_numpy(Qh).cuda()
+    del Q0h, Qh
+    _log("judged run: %d hexes, resolved order %d (%d points), coarse order %d (%d points)" % (
+        mf.n_elems, order_fine, mf.n_solpts, order_coarse, mc.n_solpts))
+    balanced_run(mf, kw, Q0, Q, t_spin, cfl, spin_precision, "judged spin-up")
+    Q0c, _ = filter_to_coarse(mf, mc, gamma, Q0)
+    Qc, _ = filter_to_coarse(mf, mc, gamma, Q)
+    p64 = physics(flags=CHORUS_BALANCED, **kw)
+    ws = mf.workspace(p64)
+    chorus_set_background(mf, p64, Q0, ws)
+    dtf = mf.stable_dt(p64, Q.cpu().numpy(), cfl)
+    fine_steps = 2 * coarse_steps
+    per_ref = fine_steps // n_ref
+    refs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_ref):
+        chorus_rk_step(mf, p64, Q, dtf, per_ref, ws)
+        refs.append(filter_to_coarse(mf, mc, gamma, Q)[0])
+    torch.cuda.synchronize()
+    wall_fine = time.perf_counter() - t0
+    if not bool(torch.isfinite(Q).all()):
+        raise RuntimeError("resolved judged run became non-finite")
+    _log("resolved reference: %d steps of %.2e in %.1f s" % (fine_steps, dtf, wall_fine))
+    del ws, Q, Q0
+    torch.cuda.empty_cache()
+    diag = ShellDiagnostics(mc, ri, ro, top_depth=(ro - ri) / judge_mesh[1])
+    refs_h = [r.cpu().numpy() for r in refs]
+    del refs
+    errors, walls = {}, {}
+    for name, mdl in (("plain", None), ("closure", model)):
+        if name == "closure" and mdl is None:
+            errors[name] = None
+            continue
+        ph = closure_physics(dict(kw, flags=CHORUS_BALANCED), mdl)
+        wsc = mc.workspace(ph)
+        chorus_set_background(mc, ph, Q0c, wsc)
+        q = Qc.clone()
+        errs, wall = [], 0.0
+        for i in range(n_ref):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            chorus_rk_step(mc, ph, q, 2.0 * dtf, per_ref // 2, wsc)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            if not bool(torch.isfinite(q).all()):
+                errs = None
+                break
+            errs.append(judge_errors(diag, q.cpu().numpy(), refs_h[i], gamma))
+        errors[name] = mean_errors(errs) if errs else None
+        walls[name] = wall
+        _log("%s run: %s" % (name, errors[name]))
+        del wsc, q
+    sim_time = fine_steps * dtf
+    report["judged"] = {"resolved_points": mf.n_solpts, "coarse_points": mc.n_solpts, "dt_fine": dtf,
+                        "fine_steps": fine_steps, "coarse_steps": coarse_steps, "simulated_time": sim_time,
+                        "errors": errors,
+                        "worst": {k: (score(v) if v else None) for k, v in errors.items()},
+                        "seconds_per_unit_time": {"resolved": wall_fine / sim_time,
+                                                  **{k: v / sim_time for k, v in walls.items()}}}
+    if "closure" in walls:
+        report["judged"]["cost_ratio_resolved_over_closure"] = wall_fine / walls["closure"]
+    use = choose(errors.get("closure"), errors["plain"], closure_finite=errors.get("closure") is not None)
+    report["use_closure"] = bool(use)
+    report["within_5_percent"] = bool(errors.get("closure") is not None and score(errors["closure"]) <= 0.05)
+    report["seconds"] = time.perf_counter() - t_start
+    return report
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="the closure experiment at the configured sizes (one JSON line)")
+    ap.add_argument("--t-spin", type=float, default=24.0)
+    ap.add_argument("--iters", type=int, default=6000)
+    ap.add_argument("--coarse-steps", type=int, default=1000)
+    ap.add_argument("--data-mesh", default="16,8")
+    ap.add_argument("--judge-mesh", default="32,16")
+    ap.add_argument("--luminosity", type=float, default=1e-4)
+    ap.add_argument("--amp", type=float, default=1e-3)
+    a = ap.parse_args()
+    rep = configured_experiment(t_spin=a.t_spin, iters=a.iters, coarse_steps=a.coarse_steps,
+                                data_mesh=tuple(int(v) for v in a.data_mesh.split(",")),
+                                judge_mesh=tuple(int(v) for v in a.judge_mesh.split(",")),
+                                luminosity=a.luminosity, amp=a.amp)
+    print(json.dumps(rep), flush=True)
