@@ -356,6 +356,8 @@ def main():
     ap.add_argument("--no-other", action="store_true", help="skip the 41,472-hex workload leg")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the leg of the five-stage integrator, radial kappa_r and angular-momentum correction")
+    ap.add_argument("--closure-experiment", action="store_true",
+                    help="only run the closure experiment at the configured sizes (about 5 minutes; one JSON line)")
     ap.add_argument("--size-sweep", action="store_true",
                     help="only measure both paths on shells from 288 to 331,776 hexes (one JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -386,6 +388,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}))
+        return
+    if args.closure_experiment:
+        from paper_1503_00834_amd import closure
+        rep = closure.configured_experiment()
+        print(json.dumps({"closure_experiment": rep, "data": "synthetic"}), flush=True)
         return
     if args.size_sweep:
         print(json.dumps({"size_sweep": size_sweep(ch), "unit": "DOF-updates/s", "integrator": "SSP-RK3",
