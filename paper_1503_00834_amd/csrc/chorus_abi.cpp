@@ -63,7 +63,7 @@ static WsLayout ws_layout(const Mesh &m) {
     w.P2 = off;   off = align256(off + state);
     w.P4 = off;   off = align256(off + state);
     w.TQm = off;  off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
-    w.TVm = off;  off = align256(off + sizeof(float) * E * 6 * 5 * NF2);
+    w.TVm = off;  off = align256(off + sizeof(float) * E * 6 * 4 * NF2);  // momentum and energy only
     w.bg = off;   off = align256(off + sizeof(float) * E * 2 * NP);
     w.dbg = off;  off = align256(off + sizeof(float) * E * 6 * 2 * NF2);
     w.gS0 = off;  off = align256(off + sizeof(float) * E * 3 * (N + 1) * NF2);

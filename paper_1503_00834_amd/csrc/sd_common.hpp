@@ -98,13 +98,14 @@ __device__ __forceinline__ void st_off(T *base, uint32_t i, T v) {
 
 // mailbox slot of face point pp of an element's face (nb, inf = the face's
 // neighbour element and info word): the receiving element's face and point
-// (the orientation map applied), variable 0; variable v is NF2 further on
-template <int N>
+// (the orientation map applied), first variable; the next is NF2 further on
+// (NV variables per face point)
+template <int N, int NV = 5>
 __device__ __forceinline__ int64_t mailbox_slot(int32_t nb, int32_t inf, int pp) {
     constexpr int NF2 = N * N;
     const int f2 = inf & 7, o = (inf >> 3) & 7;
     const int pn = map_face_point<N>(o, pp % N, pp / N);
-    return ((int64_t)nb * 6 + f2) * 5 * NF2 + pn;
+    return ((int64_t)nb * 6 + f2) * NV * NF2 + pn;
 }
 
 }  // namespace chorus

@@ -638,8 +638,9 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
         const float kr = kr_of<KR>(F, krf[k]);
         if (nb >= 0) {
             dflux_viscous<KR>(st, So, gSo, F, kr, 0, fv);
-            const int64_t slot = mailbox_slot<N>(nb, inf, pp);
-            for (int v = 0; v < 5; ++v) TV[slot + v * NF2] = fv[v];
+            // the viscous mass flux is zero: four components per point
+            const int64_t slot = mailbox_slot<N, 4>(nb, inf, pp);
+            for (int v = 1; v < 5; ++v) TV[slot + (v - 1) * NF2] = fv[v];
         }
         face_flux_own<KR>(st, R.nq[k], R.db[k], nb >= 0, ((inf >> 6) - 1) == CHORUS_BC_OUTER, So, gSo, kr, fv,
                           F, ffc[k]);
@@ -770,10 +771,10 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
 template <int N, int EPB, int NT>
 __global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> opa, GeoF G, const float *__restrict__ TV, MixedStage S_) {
     constexpr int NP = N * N * N, NF2 = N * N;
-    constexpr int IT_MB = (EPB * 30 * NF2 + NT - 1) / NT, IT_SOL = (EPB * NP + NT - 1) / NT;
+    constexpr int IT_MB = (EPB * 24 * NF2 + NT - 1) / NT, IT_SOL = (EPB * NP + NT - 1) / NT;
     __shared__ OpsF<N> op;
     ops_to_lds(opa, op);
-    __shared__ float nv[EPB][6][5][NF2];  // neighbours' viscous flux at own face points, 0 on boundary faces
+    __shared__ float nv[EPB][6][4][NF2];  // neighbours' viscous momentum and energy flux, 0 on boundary faces
     __shared__ float sp[EPB][5][NP];      // new perturbation (FP32) for the traces
     __shared__ int32_t lk[EPB][6], inf[EPB][6];
     // blocks walk the elements from the last to the first: the flux pass
@@ -798,8 +799,8 @@ __global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> opa, GeoF G, const fl
 #pragma unroll
     for (int k = 0; k < IT_MB; ++k) {
         const int it = threadIdx.x + k * NT;
-        const bool ok = it < EPB * 30 * NF2 && e0 + it / (30 * NF2) < G.E;
-        mb[k] = TV[ok ? e0 * 30 * NF2 + it : 0];
+        const bool ok = it < EPB * 24 * NF2 && e0 + it / (24 * NF2) < G.E;
+        mb[k] = TV[ok ? e0 * 24 * NF2 + it : 0];
     }
     double po[IT_SOL][5], to[IT_SOL][5];
     float iJ[IT_SOL];
@@ -825,8 +826,8 @@ __global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> opa, GeoF G, const fl
 #pragma unroll
     for (int k = 0; k < IT_MB; ++k) {
         const int it = threadIdx.x + k * NT;
-        if (it >= EPB * 30 * NF2) break;
-        const int el = it / (30 * NF2), r = it % (30 * NF2), f = r / (5 * NF2);
+        if (it >= EPB * 24 * NF2) break;
+        const int el = it / (24 * NF2), r = it % (24 * NF2), f = r / (4 * NF2);
         (&nv[el][0][0][0])[r] = (lk[el][f] >= 0) ? mb[k] : 0.0f;
     }
     __syncthreads();
@@ -846,7 +847,8 @@ __global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> opa, GeoF G, const fl
             const int pp = t1 + N * t2;
             const float wl = -0.5f * op.D[a][0], wu = 0.5f * op.D[a][N];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) corr[v] += wl * nv[el][2 * d][v][pp] + wu * nv[el][2 * d + 1][v][pp];
+            for (int v = 1; v < 5; ++v)
+                corr[v] += wl * nv[el][2 * d][v - 1][pp] + wu * nv[el][2 * d + 1][v - 1][pp];
         }
         for (int v = 0; v < 5; ++v) {
             const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
