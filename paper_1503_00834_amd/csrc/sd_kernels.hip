@@ -250,7 +250,7 @@ template <int N>
 struct Cfg64;
 template <> struct Cfg64<2> { static constexpr int EPB = 8, NT = 64, MINW = 1; };
 template <> struct Cfg64<3> { static constexpr int EPB = 2, NT = 64, MINW = 1; };
-template <> struct Cfg64<4> { static constexpr int EPB = 1, NT = 64, MINW = 1; };
+template <> struct Cfg64<4> { static constexpr int EPB = 1, NT = 64, MINW = 3; };
 template <> struct Cfg64<5> { static constexpr int EPB = 1, NT = 128, MINW = 1; };
 template <> struct Cfg64<6> { static constexpr int EPB = 1, NT = 256, MINW = 1; };
 
@@ -363,20 +363,21 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
         for (int c = 0; c < 3; ++c) Sf[k][c] = sg * G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
         krf[k] = RAD ? G.rflux[(e * 3 + d) * NFL + fl] : P.kappa_r;
     }
-    double Si[3][Sh::IT_INTD][3], kri[3][Sh::IT_INTD];
-    if constexpr (PART != 1) {
+    // interior flux-point metrics: one direction at a time, the next one
+    // issued while the current one is used (fewer registers in flight)
+    double Si[2][Sh::IT_INTD][3], kri[2][Sh::IT_INTD];
+    auto load_si = [&](int d, int slot) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-            for (int k = 0; k < Sh::IT_INTD; ++k) {
-                const int it = threadIdx.x + k * NT;
-                const int el = it / NINTD, q = it % NINTD;
-                const int fl = 1 + q % (N - 1) + (N + 1) * (q / (N - 1));
-                const int64_t e = (it < EPB * NINTD && e0 + el < E) ? e0 + el : 0;
-                for (int c = 0; c < 3; ++c) Si[d][k][c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
-                kri[d][k] = RAD ? G.rflux[(e * 3 + d) * NFL + fl] : P.kappa_r;
-            }
-    }
+        for (int k = 0; k < Sh::IT_INTD; ++k) {
+            const int it = threadIdx.x + k * NT;
+            const int el = it / NINTD, q = it % NINTD;
+            const int fl = 1 + q % (N - 1) + (N + 1) * (q / (N - 1));
+            const int64_t e = (it < EPB * NINTD && e0 + el < E) ? e0 + el : 0;
+            for (int c = 0; c < 3; ++c) Si[slot][k][c] = G.fluxgeo[((e * 3 + d) * 3 + c) * NFL + fl];
+            kri[slot][k] = RAD ? G.rflux[(e * 3 + d) * NFL + fl] : P.kappa_r;
+        }
+    };
+    if constexpr (PART != 1) load_si(0, 0);
     if constexpr (PART == 2) {
         for (int it = threadIdx.x; it < EPB * 15 * NP; it += NT) {
             const int el = it / (15 * NP), r = it % (15 * NP), k = r / NP, p = r % NP;
@@ -501,6 +502,8 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
         for (int v = 0; v < 5; ++v) div[k][v] = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
+        const int cur = d & 1;
+        if (d < 2) load_si(d + 1, cur ^ 1);
 #pragma unroll
         for (int k = 0; k < Sh::IT_INTD; ++k) {
             const int it = threadIdx.x + k * NT;
@@ -514,12 +517,12 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
                 qf[v] = line_interp<N>(op, sq[el][v], m, base, st);
                 for (int c = 0; c < 3; ++c) g[v][c] = line_interp<N>(op, sgr[el][v * 3 + c], m, base, st);
             }
-            flux_inviscid(qf, Si[d][k], gm1, fi);
-            flux_viscous(qf, g, Si[d][k], P, RAD ? kappa_r_at(P, kri[d][k]) : kri[d][k], fv);
+            flux_inviscid(qf, Si[cur][k], gm1, fi);
+            flux_viscous(qf, g, Si[cur][k], P, RAD ? kappa_r_at(P, kri[cur][k]) : kri[cur][k], fv);
             double ts[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
             if constexpr (CL) {
                 for (int v = 0; v < 5; ++v)
-                    for (int c = 0; c < 3; ++c) ts[v] += line_interp<N>(op, stau[el][v * 3 + c], m, base, st) * Si[d][k][c];
+                    for (int c = 0; c < 3; ++c) ts[v] += line_interp<N>(op, stau[el][v * 3 + c], m, base, st) * Si[cur][k][c];
             }
             const int fl = m + (N + 1) * tt;
             for (int v = 0; v < 5; ++v) U.sft[el][v][fl] = fi[v] - fv[v] + ts[v];
