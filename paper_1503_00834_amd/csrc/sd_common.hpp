@@ -96,6 +96,17 @@ __device__ __forceinline__ void st_off(T *base, uint32_t i, T v) {
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + i * (uint32_t)sizeof(T)) = v;
 }
 
+// access of data touched once per pass (mailboxes, geometry): the
+// non-temporal hint lets it leave the caches first
+template <typename T>
+__device__ __forceinline__ T ld_once(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void st_once(T *p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+
 // mailbox slot of face point pp of an element's face (nb, inf = the face's
 // neighbour element and info word): the receiving element's face and point
 // (the orientation map applied), first variable; the next is NF2 further on

@@ -271,7 +271,7 @@ __device__ __forceinline__ void push_traces64(const Ops<N> &op, const Geo &G, in
             double t = 0.0;
 #pragma unroll
             for (int b = 0; b < N; ++b) t += op.I[m][b] * sq[el][v][base + b * st];
-            out[v * NF2] = t;
+            st_once(&out[v * NF2], t);
         }
     }
 }
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
                     for (int c = 0; c < 3; ++c) fv[v] -= line_interp<N>(op, stau[el][v * 3 + c], m, base, st) * Sf[k][c];
             }
             double *tv = TV + mailbox_slot<N>(nb, inf[el][f], pp);
-            for (int v = 0; v < 5; ++v) tv[v * NF2] = fv[v];
+            for (int v = 0; v < 5; ++v) st_once(&tv[v * NF2], fv[v]);
             flux_rusanov(fo[k], nq[k], Sf[k], P, ffc[k]);
             for (int v = 0; v < 5; ++v) ffc[k][v] -= 0.5 * fv[v];
         } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
@@ -636,7 +636,7 @@ __global__ __launch_bounds__(NT) void k_lift64(Ops<N> opa, Geo G, const double *
     for (int k = 0; k < IT_MB; ++k) {
         const int it = threadIdx.x + k * NT;
         const bool ok = it < EPB * 30 * NF2 && e0 + it / (30 * NF2) < E;
-        mb[k] = TV[ok ? e0 * 30 * NF2 + it : 0];
+        mb[k] = ld_once(&TV[ok ? e0 * 30 * NF2 + it : 0]);
     }
     double qo[IT_SOL][5], to[IT_SOL][5], iJ[IT_SOL], r0[IT_SOL][5];
     const bool bal = S_.R0 != nullptr;
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(NT) void k_lift64(Ops<N> opa, Geo G, const double *
         const int it = threadIdx.x + k * NT;
         const int el = it / NP, p = it % NP;
         const int64_t e = (it < EPB * NP && e0 + el < E) ? e0 + el : 0;
-        iJ[k] = G.solgeo[(e * 13 + 9) * NP + p];
+        iJ[k] = ld_once(&G.solgeo[(e * 13 + 9) * NP + p]);
         for (int v = 0; v < 5; ++v) {
             const int64_t gi = ((int64_t)v * E + e) * NP + p;
             qo[k][v] = S_.Qout[gi];

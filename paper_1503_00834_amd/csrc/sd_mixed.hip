@@ -640,7 +640,7 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
             dflux_viscous<KR>(st, So, gSo, F, kr, 0, fv);
             // the viscous mass flux is zero: four components per point
             const int64_t slot = mailbox_slot<N, 4>(nb, inf, pp);
-            for (int v = 1; v < 5; ++v) TV[slot + (v - 1) * NF2] = fv[v];
+            for (int v = 1; v < 5; ++v) st_once(&TV[slot + (v - 1) * NF2], fv[v]);
         }
         face_flux_own<KR>(st, R.nq[k], R.db[k], nb >= 0, ((inf >> 6) - 1) == CHORUS_BC_OUTER, So, gSo, kr, fv,
                           F, ffc[k]);
@@ -800,7 +800,7 @@ __global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> opa, GeoF G, const fl
     for (int k = 0; k < IT_MB; ++k) {
         const int it = threadIdx.x + k * NT;
         const bool ok = it < EPB * 24 * NF2 && e0 + it / (24 * NF2) < G.E;
-        mb[k] = TV[ok ? e0 * 24 * NF2 + it : 0];
+        mb[k] = ld_once(&TV[ok ? e0 * 24 * NF2 + it : 0]);
     }
     double po[IT_SOL][5], to[IT_SOL][5];
     float iJ[IT_SOL];
@@ -809,7 +809,7 @@ __global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> opa, GeoF G, const fl
         const int it = threadIdx.x + k * NT;
         const int el = it / NP, p = it % NP;
         const int64_t e = (it < EPB * NP && e0 + el < G.E) ? e0 + el : 0;
-        iJ[k] = G.solgeo[(e * 13 + 9) * NP + p];
+        iJ[k] = ld_once(&G.solgeo[(e * 13 + 9) * NP + p]);
         for (int v = 0; v < 5; ++v) {
             const int64_t gi = ((int64_t)v * G.E + e) * NP + p;
             po[k][v] = S_.Pout[gi];
@@ -868,7 +868,7 @@ __global__ __launch_bounds__(NT) void k_lift_mixed(OpsF<N> opa, GeoF G, const fl
         if (e >= G.E || nb < 0) continue;
         float *out = S_.TQout + mailbox_slot<N>(nb, inf[el][f], pp);
         const int d = f >> 1, m = (f & 1) ? N : 0, base = sol_of<N>(d, 0, pp % N, pp / N), st = stride_of<N>(d);
-        for (int v = 0; v < 5; ++v) out[v * NF2] = line_val<N>(op, sp[el][v], m, base, st);
+        for (int v = 0; v < 5; ++v) st_once(&out[v * NF2], line_val<N>(op, sp[el][v], m, base, st));
     }
 }
 
