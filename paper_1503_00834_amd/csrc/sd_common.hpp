@@ -107,6 +107,26 @@ __device__ __forceinline__ void st_once(T *p, T v) {
     __builtin_nontemporal_store(v, p);
 }
 
+// LDS slot of solution point p in an element's FP64 field array.  A line
+// operator reads one lattice plane per instruction (the points of all lines
+// of one direction at one position along them); at order 4 the in-plane
+// index is XORed with 5 k (k the third lattice index), so that the 16
+// points of every plane occupy distinct 8-byte bank pairs modulo 16 and
+// modulo 32.  Other orders keep the natural index.
+template <int N>
+__device__ __forceinline__ int lds_sol(int p) {
+    if constexpr (N == 4) return p ^ ((p >> 4) * 5);
+    else return p;
+}
+// slot of point b of the line (base, st) (base at lattice index 0 along the
+// line): lds_sol is linear over XOR and base and b st share no set bit, so
+// the per-line part is computed once and the rest is a constant
+template <int N>
+__device__ __forceinline__ int lds_line(int base, int b, int st) {
+    if constexpr (N == 4) return lds_sol<N>(base) ^ lds_sol<N>(b * st);
+    else return base + b * st;
+}
+
 // mailbox slot of face point pp of an element's face (nb, inf = the face's
 // neighbour element and info word): the receiving element's face and point
 // (the orientation map applied), first variable; the next is NF2 further on

@@ -173,8 +173,8 @@ __device__ __forceinline__ void closure_tau(const ClosureArgs &C, int64_t E, int
         for (int i = 0; i < 8; ++i) {
             const int f = 8 * g + i;
             double raw = 0.0;
-            if (ok && f < 5) raw = sq[el][f][sp];
-            else if (ok && f < 20) raw = (double)sgr[el][f - 5][sp];
+            if (ok && f < 5) raw = sq[el][f][lds_sol<N>(sp)];
+            else if (ok && f < 20) raw = (double)sgr[el][f - 5][lds_sol<N>(sp)];
             x[i] = (ok && f < 20) ? mlp_norm_feature(C.model, f, raw) : 0.0f;
         }
         xb[pt] = u32x4_t{bf16_pair(x[0], x[1]), bf16_pair(x[2], x[3]), bf16_pair(x[4], x[5]), bf16_pair(x[6], x[7])};
@@ -255,7 +255,7 @@ template <> struct Cfg64<5> { static constexpr int EPB = 1, NT = 128, MINW = 1; 
 template <> struct Cfg64<6> { static constexpr int EPB = 1, NT = 256, MINW = 1; };
 
 // face traces of the element block's state (LDS) pushed to the neighbours
-template <int N, int EPB, int NT>
+template <int N, int EPB, int NT, bool SW = false>
 __device__ __forceinline__ void push_traces64(const Ops<N> &op, const Geo &G, int64_t e0, const int32_t (*lk)[6],
                                               const int32_t (*inf)[6], const double (*sq)[5][N * N * N],
                                               double *__restrict__ TQout) {
@@ -270,7 +270,7 @@ __device__ __forceinline__ void push_traces64(const Ops<N> &op, const Geo &G, in
         for (int v = 0; v < 5; ++v) {
             double t = 0.0;
 #pragma unroll
-            for (int b = 0; b < N; ++b) t += op.I[m][b] * sq[el][v][base + b * st];
+            for (int b = 0; b < N; ++b) t += op.I[m][b] * sq[el][v][SW ? lds_line<N>(base, b, st) : base + b * st];
             st_once(&out[v * NF2], t);
         }
     }
@@ -302,6 +302,14 @@ __device__ __forceinline__ double line_interp(const Ops<N> &op, const T *fld, in
     double t = 0.0;
 #pragma unroll
     for (int b = 0; b < N; ++b) t += op.I[m][b] * (double)fld[base + b * st];
+    return t;
+}
+// the same over a field stored in the lds_sol layout
+template <int N, typename T>
+__device__ __forceinline__ double line_interp_s(const Ops<N> &op, const T *fld, int m, int base, int st) {
+    double t = 0.0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) t += op.I[m][b] * (double)fld[lds_line<N>(base, b, st)];
     return t;
 }
 
@@ -398,12 +406,11 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
     for (int k = 0; k < Sh::IT_SOL; ++k) {
         const int it = threadIdx.x + k * NT;
         if (it >= EPB * NP) break;
-        for (int v = 0; v < 5; ++v) sq[it / NP][v][it % NP] = qv[k][v];
+        for (int v = 0; v < 5; ++v) sq[it / NP][v][lds_sol<N>(it % NP)] = qv[k][v];
     }
     __syncthreads();
-    // common interface solution; the own face values are kept for the
-    // face-flux phase
-    double fo[Sh::IT_FACE][5];
+    // common interface solution (the own face values are formed again in
+    // the face-flux phase: fewer registers live across the gradients)
 #pragma unroll
     for (int k = 0; k < Sh::IT_FACE; ++k) {
         const int it = threadIdx.x + k * NT;
@@ -412,16 +419,17 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
         if (e0 + el >= E) continue;
         const int d = f >> 1, m = (f & 1) ? N : 0;
         const int base = sol_of<N>(d, 0, pp % N, pp / N), st = stride_of<N>(d);
-        for (int v = 0; v < 5; ++v) fo[k][v] = line_interp<N>(op, sq[el][v], m, base, st);
+        double fo[5];
+        for (int v = 0; v < 5; ++v) fo[v] = line_interp_s<N>(op, sq[el][v], m, base, st);
         const int32_t nb = lk[el][f];
         const int bc = (inf[el][f] >> 6) - 1;
         double qs[5];
         if (nb >= 0) {
-            for (int v = 0; v < 5; ++v) qs[v] = 0.5 * (fo[k][v] + nq[k][v]);
+            for (int v = 0; v < 5; ++v) qs[v] = 0.5 * (fo[v] + nq[k][v]);
         } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
-            wall_state(fo[k], Sf[k], bc == CHORUS_BC_OUTER, P, qs);  // (the same along +-S)
+            wall_state(fo, Sf[k], bc == CHORUS_BC_OUTER, P, qs);  // (the same along +-S)
         } else {
-            for (int v = 0; v < 5; ++v) qs[v] = 0.5 * (fo[k][v] + P.bc_state[v]);
+            for (int v = 0; v < 5; ++v) qs[v] = 0.5 * (fo[v] + P.bc_state[v]);
         }
         for (int v = 0; v < 5; ++v) U.sqs[el][f][v][pp] = qs[v];
     }
@@ -441,14 +449,14 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
             for (int v = 0; v < 5; ++v) {
                 double t = op.D[a][0] * U.sqs[el][2 * d][v][pp] + op.D[a][N] * U.sqs[el][2 * d + 1][v][pp];
 #pragma unroll
-                for (int b = 0; b < N; ++b) t += op.B[a][b] * sq[el][v][base + b * st];
+                for (int b = 0; b < N; ++b) t += op.B[a][b] * sq[el][v][lds_line<N>(base, b, st)];
                 dq[d][v] = t;
             }
         }
         for (int v = 0; v < 5; ++v)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                sgr[el][v * 3 + c][p] = Gm[k][c] * dq[0][v] + Gm[k][3 + c] * dq[1][v] + Gm[k][6 + c] * dq[2][v];
+                sgr[el][v * 3 + c][lds_sol<N>(p)] = Gm[k][c] * dq[0][v] + Gm[k][3 + c] * dq[1][v] + Gm[k][6 + c] * dq[2][v];
     }
     __syncthreads();
     if constexpr (PART == 1) {
@@ -468,15 +476,17 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
         if (e0 + el >= E) continue;
         const int d = f >> 1, m = (f & 1) ? N : 0;
         const int base = sol_of<N>(d, 0, pp % N, pp / N), st = stride_of<N>(d);
-        double g[5][3];
-        for (int v = 0; v < 5; ++v)
-            for (int c = 0; c < 3; ++c) g[v][c] = line_interp<N>(op, sgr[el][v * 3 + c], m, base, st);
+        double fo[5], g[5][3];
+        for (int v = 0; v < 5; ++v) {
+            fo[v] = line_interp_s<N>(op, sq[el][v], m, base, st);
+            for (int c = 0; c < 3; ++c) g[v][c] = line_interp_s<N>(op, sgr[el][v * 3 + c], m, base, st);
+        }
         const int32_t nb = lk[el][f];
         const int bc = (inf[el][f] >> 6) - 1;
         const double kr = RAD ? kappa_r_at(P, krf[k]) : krf[k];
         double fv[5];
         if (nb >= 0) {
-            flux_viscous(fo[k], g, Sf[k], P, kr, fv);
+            flux_viscous(fo, g, Sf[k], P, kr, fv);
             if constexpr (CL) {
                 // the own-side subgrid flux enters the trace with the sign of -F_v
                 for (int v = 0; v < 5; ++v)
@@ -484,13 +494,13 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
             }
             double *tv = TV + mailbox_slot<N>(nb, inf[el][f], pp);
             for (int v = 0; v < 5; ++v) st_once(&tv[v * NF2], fv[v]);
-            flux_rusanov(fo[k], nq[k], Sf[k], P, ffc[k]);
+            flux_rusanov(fo, nq[k], Sf[k], P, ffc[k]);
             for (int v = 0; v < 5; ++v) ffc[k][v] -= 0.5 * fv[v];
         } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
-            flux_wall(fo[k], g, Sf[k], bc == CHORUS_BC_OUTER, P, kr, ffc[k]);
+            flux_wall(fo, g, Sf[k], bc == CHORUS_BC_OUTER, P, kr, ffc[k]);
         } else {
-            flux_viscous(fo[k], g, Sf[k], P, kr, fv);
-            flux_rusanov(fo[k], P.bc_state, Sf[k], P, ffc[k]);
+            flux_viscous(fo, g, Sf[k], P, kr, fv);
+            flux_rusanov(fo, P.bc_state, Sf[k], P, ffc[k]);
             for (int v = 0; v < 5; ++v) ffc[k][v] -= 0.5 * fv[v];
         }
     }
@@ -514,8 +524,8 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
             const int base = sol_of<N>(d, 0, tt % N, tt / N), st = stride_of<N>(d);
             double qf[5], g[5][3], fi[5], fv[5];
             for (int v = 0; v < 5; ++v) {
-                qf[v] = line_interp<N>(op, sq[el][v], m, base, st);
-                for (int c = 0; c < 3; ++c) g[v][c] = line_interp<N>(op, sgr[el][v * 3 + c], m, base, st);
+                qf[v] = line_interp_s<N>(op, sq[el][v], m, base, st);
+                for (int c = 0; c < 3; ++c) g[v][c] = line_interp_s<N>(op, sgr[el][v * 3 + c], m, base, st);
             }
             flux_inviscid(qf, Si[cur][k], gm1, fi);
             flux_viscous(qf, g, Si[cur][k], P, RAD ? kappa_r_at(P, kri[cur][k]) : kri[cur][k], fv);
@@ -582,7 +592,8 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
         if (e >= E) continue;
         const double iJ = gq[k][0];
         const double g0 = P.GM * gq[k][1], g1 = P.GM * gq[k][2], g2 = P.GM * gq[k][3];
-        const double rho = sq[el][0][p], mx = sq[el][1][p], my = sq[el][2][p], mz = sq[el][3][p];
+        const int ps = lds_sol<N>(p);
+        const double rho = sq[el][0][ps], mx = sq[el][1][ps], my = sq[el][2][ps], mz = sq[el][3][ps];
         double M[5];
         M[0] = 0.0;
         M[1] = rho * g0 - 2.0 * P.omega * my;
@@ -596,7 +607,7 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
                 S_.Qout[gi] = R;
                 continue;
             }
-            const double q = sq[el][v][p];
+            const double q = sq[el][v][ps];
             if (useT) S_.Tout[gi] = S_.d0 * bv[k][v] + S_.d1 * (q + S_.d2 * R);
             S_.Qout[gi] = S_.c0 * av[k][v] + S_.c1 * (q + S_.c2 * R);
         }
@@ -693,12 +704,12 @@ __global__ __launch_bounds__(NT) void k_lift64(Ops<N> opa, Geo G, const double *
             const double qn = bal ? (qo[k][v] + wP * x) - wP * r0[k][v] : qo[k][v] + wP * x;
             S_.Qout[gi] = qn;
             if (useT) S_.Tout[gi] = bal ? (to[k][v] + wT * x) - wT * r0[k][v] : to[k][v] + wT * x;
-            sq[el][v][p] = qn;
+            sq[el][v][lds_sol<N>(p)] = qn;
         }
     }
     if (S_.mode == 0 || S_.TQout == nullptr) return;
     __syncthreads();
-    push_traces64<N, EPB, NT>(op, G, e0, lk, inf, sq, S_.TQout);
+    push_traces64<N, EPB, NT, true>(op, G, e0, lk, inf, sq, S_.TQout);
 }
 
 // entropy gradient of a state at rest along the flux-point metric:
