@@ -199,6 +199,7 @@ template <int N>
 struct MixedLds {
     static constexpr int NP = N * N * N, NF2 = N * N, NFL = (N + 1) * N * N;
     float f[NFIELD][NP];          // perturbation + background fields
+    float plo[5][NP];             // FP64 perturbation minus its FP32 value f[0..4] (stage update)
     float g[NGRAD][NP];           // gradients
     union {
         float cs[5][6][NF2];       // common values of the perturbation
@@ -300,7 +301,11 @@ __device__ __forceinline__ void prologue_store(const Prologue<N, EPB, NT> &R, Mi
         const int it = threadIdx.x + k * NT;
         if (it >= EPB * NP) break;
         const int el = it / NP, p = it % NP;
-        for (int v = 0; v < 5; ++v) L[el].f[v][p] = (float)R.P[k][v];
+        for (int v = 0; v < 5; ++v) {
+            const float hi = (float)R.P[k][v];
+            L[el].f[v][p] = hi;
+            L[el].plo[v][p] = (float)(R.P[k][v] - (double)hi);
+        }
         L[el].f[F_R0][p] = R.bg[k][0];
         L[el].f[F_E0][p] = R.bg[k][1];
         for (int c = 0; c < 3; ++c) L[el].g[3 * F_R0 + c][p] = R.gb[k][c];
@@ -657,7 +662,7 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
     // a store would wait for it); block-uniform bases, per-lane offsets
     // clamped to the last element
     float r0v[Sh::IT_SOL][5], gq[Sh::IT_SOL][4];
-    double pin[Sh::IT_SOL][5], pst[Sh::IT_SOL][5], pb[Sh::IT_SOL][5];
+    double pst[Sh::IT_SOL][5], pb[Sh::IT_SOL][5];
     const bool rk = S_.mode != 0;
     const bool useA = rk && S_.c0 != 0.0, useT = rk && S_.Tout != nullptr, useB = useT && S_.d0 != 0.0;
     const int elmax = (G.E - 1 - e0 < EPB - 1) ? (int)(G.E - 1 - e0) : EPB - 1;
@@ -703,7 +708,6 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
                 for (int v = 0; v < 5; ++v) {
                     const int64_t vb = ((int64_t)v * G.E + e0) * NP;
                     r0v[k][v] = ld_off(B.R0 + vb, o);
-                    pin[k][v] = rk ? ld_off(Pq + vb, o) : 0.0;
                     pst[k][v] = useA ? ld_off(S_.A + vb, o) : 0.0;
                     pb[k][v] = useB ? ld_off(S_.B + vb, o) : 0.0;
                 }
@@ -755,8 +759,11 @@ __global__ __launch_bounds__(NT, MINW) void k_flux_mixed(OpsF<N> opa, GeoF G, Mi
                 st_off(S_.Pout + vb, o, Rv);
                 continue;
             }
-            if (useT) st_off(S_.Tout + vb, o, S_.d0 * pb[k][v] + S_.d1 * (pin[k][v] + S_.d2 * Rv));
-            st_off(S_.Pout + vb, o, S_.c0 * pst[k][v] + S_.c1 * (pin[k][v] + S_.c2 * Rv));
+            // the stage input from its FP32 value and FP32 remainder (48
+            // significant bits: 2^-48 relative, far below the FP32 residual)
+            const double pin = (double)l.f[v][p] + (double)l.plo[v][p];
+            if (useT) st_off(S_.Tout + vb, o, S_.d0 * pb[k][v] + S_.d1 * (pin + S_.d2 * Rv));
+            st_off(S_.Pout + vb, o, S_.c0 * pst[k][v] + S_.c1 * (pin + S_.c2 * Rv));
         }
     }
 }
@@ -945,9 +952,7 @@ template <> struct CfgM<6> { static constexpr int EPB = 1, NT = 256, MINW = 1; }
 // flux pass (elements per block, threads, minimum waves per SIMD) and lift
 // pass (elements per block, threads)
 template <int N> struct CfgF { static constexpr int EPB = CfgM<N>::EPB, NT = CfgM<N>::NT, MINW = CfgM<N>::MINW; };
-template <> struct CfgF<4> { static constexpr int EPB = 4, NT = 192, MINW = 3; };
 template <int N> struct CfgL { static constexpr int EPB = CfgM<N>::EPB, NT = CfgM<N>::NT; };
-template <> struct CfgL<4> { static constexpr int EPB = 1, NT = 64; };
 
 static GeoF geof_of(const GeoM &g) {
     GeoF o;
