@@ -131,27 +131,34 @@ __device__ __forceinline__ void dflux_inviscid(const PtState &s, const float S[3
 template <int KR>
 __device__ __forceinline__ void dflux_viscous(const PtState &s, const float S[3], float gS0S, const PhysF &F,
                                               float kr, int wall, float out[5]) {
+    // with mu = rho nu and du_a/dx_c = (dm_a/dx_c - u_a drho/dx_c) / rho, the
+    // stress along S needs the momentum gradient only through its
+    // contractions with S: Y_a = sum_c dm_a/dx_c S_c (also in grad p' . S)
+    // and Z_a = sum_b dm_b/dx_a S_b
     const float rho = s.r0 + s.rp, inv = rcp(rho);
     const float u[3] = {s.m[0] * inv, s.m[1] * inv, s.m[2] * inv};
-    float grho[3], du[3][3];
+    float grho[3];
     for (int c = 0; c < 3; ++c) grho[c] = s.gr0[c] + s.grp[c];
-    for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c) du[a][c] = (s.gm[a][c] - u[a] * grho[c]) * inv;
-    const float mu = rho * F.nu;
-    const float dv = du[0][0] + du[1][1] + du[2][2];
+    const float gr0S = s.gr0[0] * S[0] + s.gr0[1] * S[1] + s.gr0[2] * S[2];
+    const float grpS = s.grp[0] * S[0] + s.grp[1] * S[1] + s.grp[2] * S[2];
+    const float grhoS = gr0S + grpS;
+    const float uS = u[0] * S[0] + u[1] * S[1] + u[2] * S[2];
+    const float ug = u[0] * grho[0] + u[1] * grho[1] + u[2] * grho[2];
+    float Y[3];
+    for (int a = 0; a < 3; ++a) Y[a] = s.gm[a][0] * S[0] + s.gm[a][1] * S[1] + s.gm[a][2] * S[2];
+    // (2/3) rho div u
+    const float dv = (2.0f / 3.0f) * (s.gm[0][0] + s.gm[1][1] + s.gm[2][2] - ug);
     float tS[3];
     if (wall == 0) {
         for (int a = 0; a < 3; ++a) {
-            float t = 0.0f;
-            for (int b = 0; b < 3; ++b) t += (du[a][b] + du[b][a]) * S[b];
-            tS[a] = mu * (t - (2.0f / 3.0f) * dv * S[a]);
+            const float Za = s.gm[0][a] * S[0] + s.gm[1][a] * S[1] + s.gm[2][a] * S[2];
+            tS[a] = F.nu * (Y[a] + Za - u[a] * grhoS - uS * grho[a] - dv * S[a]);
         }
     } else {
+        // normal traction: n . tau . n = mu (2 S.grad u.S / |S|^2 - 2/3 div u)
         const float A2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
-        float ngn = 0.0f;
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) ngn += S[a] * du[a][b] * S[b];
-        const float tnn = mu * (2.0f * ngn * rcp(A2) - (2.0f / 3.0f) * dv);
+        const float SY = S[0] * Y[0] + S[1] * Y[1] + S[2] * Y[2];
+        const float tnn = F.nu * (2.0f * (SY - uS * grhoS) * rcp(A2) - dv);
         for (int a = 0; a < 3; ++a) tS[a] = tnn * S[a];
     }
     out[0] = 0.0f;
@@ -159,22 +166,15 @@ __device__ __forceinline__ void dflux_viscous(const PtState &s, const float S[3]
     out[2] = tS[1];
     out[3] = tS[2];
     if (wall == 1) {  // inner wall: stress free, no viscous work, energy flux in R0
-        out[1] = tS[0];
         out[4] = 0.0f;
         return;
     }
-    // p' and grad p' (m0 = 0, u0 = 0)
+    // p' and grad p' . S (m0 = 0, u0 = 0)
     const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const float pp = F.gm1 * (s.Ep - 0.5f * uu * rho);
     const float p0 = F.gm1 * s.E0, p = p0 + pp;
-    float gpS = 0.0f, grpS = 0.0f, gr0S = 0.0f;
-    for (int c = 0; c < 3; ++c) {
-        const float gp = F.gm1 * (s.gEp[c] - (u[0] * s.gm[0][c] + u[1] * s.gm[1][c] + u[2] * s.gm[2][c]) +
-                                  0.5f * uu * grho[c]);
-        gpS += gp * S[c];
-        grpS += s.grp[c] * S[c];
-        gr0S += s.gr0[c] * S[c];
-    }
+    const float gEpS = s.gEp[0] * S[0] + s.gEp[1] * S[1] + s.gEp[2] * S[2];
+    const float gpS = F.gm1 * (gEpS - (u[0] * Y[0] + u[1] * Y[1] + u[2] * Y[2]) + 0.5f * uu * grhoS);
     // (grad S - grad S0).S / c_p with grad p0 . S / p0 = gamma (gS0S / c_p
     // + grad rho0 . S / rho0), the background entropy gradient's definition
     const float igp = rcp(F.gam * p), ir0 = rcp(s.r0);
