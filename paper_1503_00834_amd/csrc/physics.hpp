@@ -74,28 +74,40 @@ __device__ __forceinline__ void prim_grad(const T q[5], const T g[5][3], const P
 
 // viscous flux along S: (0, tau.S, u.tau.S - f.S), tau = mu (grad u + grad u^T
 // - 2/3 div u I), mu = rho nu, -f = kappa rho T grad S + kr rho c_p grad T
-// (kr: the radiative diffusivity at the point)
+// (kr: the radiative diffusivity at the point).  With du_a/dx_c =
+// (dm_a/dx_c - u_a drho/dx_c) / rho the gradients enter only through their
+// contractions with S, gS_v = grad Q_v . S, and for the transposed stress
+// Z_a = sum_b dm_b/dx_a S_b; with S = c_p ln(p^(1/gamma) / rho) and
+// T = p / (rho R) the energy diffusion is (c_p / R) [kappa (grad p . S /
+// gamma - p grad rho . S / rho) + kr (grad p . S - p grad rho . S / rho)],
+// so 1/rho is the only reciprocal.
 template <typename T>
 __device__ __forceinline__ void flux_viscous(const T q[5], const T g[5][3], const T S[3],
                                              const PhysParams &P, T kr, T out[5]) {
-    PrimGrad<T> pg;
-    prim_grad(q, g, P, pg);
-    const T mu = pg.rho * T(P.nu);
-    const T div = pg.du[0][0] + pg.du[1][1] + pg.du[2][2];
+    const T gm1 = T(P.gamma - 1.0), nu = T(P.nu);
+    const T inv = T(1) / q[0];
+    const T u[3] = {q[1] * inv, q[2] * inv, q[3] * inv};
+    T gS[5];
+    for (int v = 0; v < 5; ++v) gS[v] = g[v][0] * S[0] + g[v][1] * S[1] + g[v][2] * S[2];
+    const T uS = u[0] * S[0] + u[1] * S[1] + u[2] * S[2];
+    const T ug = u[0] * g[0][0] + u[1] * g[0][1] + u[2] * g[0][2];
+    // (2/3) rho div u
+    const T dv = T(2.0 / 3.0) * (g[1][0] + g[2][1] + g[3][2] - ug);
     T tS[3];
     for (int a = 0; a < 3; ++a) {
-        T s = T(0);
-        for (int b = 0; b < 3; ++b) s += (pg.du[a][b] + pg.du[b][a]) * S[b];
-        tS[a] = mu * (s - T(2.0 / 3.0) * div * S[a]);
+        const T Za = g[1][a] * S[0] + g[2][a] * S[1] + g[3][a] * S[2];
+        tS[a] = nu * (gS[1 + a] + Za - u[a] * gS[0] - uS * g[0][a] - dv * S[a]);
     }
-    const T dSS = pg.dS[0] * S[0] + pg.dS[1] * S[1] + pg.dS[2] * S[2];
-    const T dTS = pg.dT[0] * S[0] + pg.dT[1] * S[1] + pg.dT[2] * S[2];
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T p = gm1 * (q[4] - T(0.5) * (q[1] * u[0] + q[2] * u[1] + q[3] * u[2]));
+    const T dpS = gm1 * (gS[4] - (u[0] * gS[1] + u[1] * gS[2] + u[2] * gS[3]) + T(0.5) * uu * gS[0]);
+    const T prS = p * inv * gS[0];
     out[0] = T(0);
     out[1] = tS[0];
     out[2] = tS[1];
     out[3] = tS[2];
-    out[4] = pg.u[0] * tS[0] + pg.u[1] * tS[1] + pg.u[2] * tS[2] +
-             T(P.kappa) * pg.rho * pg.Tmp * dSS + kr * pg.rho * T(P.cp) * dTS;
+    out[4] = u[0] * tS[0] + u[1] * tS[1] + u[2] * tS[2] +
+             T(P.cp / P.R_gas) * (T(P.kappa) * (dpS * T(1.0 / P.gamma) - prS) + kr * (dpS - prS));
 }
 
 // Rusanov common flux along S (outward from the qL side), wave speed
