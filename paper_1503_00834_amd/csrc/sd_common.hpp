@@ -40,19 +40,17 @@ inline OpsT<T, N> make_ops_t(const Basis1D &b) {
 
 // Copy the 1D operator tables into LDS.  Kernels index them with per-lane
 // indices, which on a by-value kernel argument compile to vector loads from
-// the argument segment on every line operation.  Thread 0 copies with
-// constant indices (scalar-register sources); the caller's first barrier
-// publishes the tables.
+// the argument segment on every line operation.  Each lane copies one word
+// (one vector load from the argument segment per lane, once per block: a
+// copy by one lane from scalar registers issues one vector instruction per
+// word); the caller's first barrier publishes the tables.
 template <typename T, int N>
 __device__ __forceinline__ void ops_to_lds(const OpsT<T, N> &src, OpsT<T, N> &dst) {
-    constexpr int NW = (int)(sizeof(OpsT<T, N>) / sizeof(T));
-    static_assert(sizeof(OpsT<T, N>) % sizeof(T) == 0, "tables of T");
-    const T *s = reinterpret_cast<const T *>(&src);
-    T *d = reinterpret_cast<T *>(&dst);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < NW; ++i) d[i] = s[i];
-    }
+    constexpr int NW = (int)(sizeof(OpsT<T, N>) / sizeof(uint32_t));
+    static_assert(sizeof(OpsT<T, N>) % sizeof(uint32_t) == 0, "tables of words");
+    const uint32_t *s = reinterpret_cast<const uint32_t *>(&src);
+    uint32_t *d = reinterpret_cast<uint32_t *>(&dst);
+    for (int i = threadIdx.x; i < NW; i += blockDim.x) d[i] = s[i];
 }
 
 // line through solution point (a along d; t1 < t2 the tangential indices).
