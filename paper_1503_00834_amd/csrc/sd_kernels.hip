@@ -155,10 +155,11 @@ __global__ __launch_bounds__(NT) void k_trace(Ops<N> opa, Geo G, const double *_
 
 // learned subgrid flux at the solution points of the block's elements (one
 // wave, all points in 16-point tiles): features (Q, grad Q) -> network ->
-// tau[k][E][NP] (global)
+// tau[k][E][NP] (global), or into the block's LDS copy stau when given
 template <int N, int EPB, int NT, typename GT>
 __device__ __forceinline__ void closure_tau(const ClosureArgs &C, int64_t E, int64_t e0,
-                                            double (*sq)[5][N * N * N], GT (*sgr)[15][N * N * N]) {
+                                            double (*sq)[5][N * N * N], GT (*sgr)[15][N * N * N],
+                                            float (*stau)[15][N * N * N] = nullptr) {
     constexpr int NP = N * N * N, NPTS = EPB * NP, NPT = (NPTS + 15) / 16;
     static_assert(NT == 64, "the closure runs one wave per block");
     const int lane = threadIdx.x, g = lane >> 4;
@@ -190,7 +191,8 @@ __device__ __forceinline__ void closure_tau(const ClosureArgs &C, int64_t E, int
         for (int i = 0; i < 4; ++i) {
             const int k = 4 * g + i;
             if (k >= kMlpOut) continue;
-            C.tau[((int64_t)k * E + e0 + el) * NP + sp] = out[pt][i];
+            if (stau) stau[el][k][sp] = out[pt][i];
+            else C.tau[((int64_t)k * E + e0 + el) * NP + sp] = out[pt][i];
         }
     }
 }
@@ -315,8 +317,8 @@ __device__ __forceinline__ double line_interp_s(const Ops<N> &op, const T *fld, 
 
 // PART 0: the flux pass; PART 1: only the learned subgrid flux (common
 // solution, gradients, network -> C.tau); PART 2: the flux pass with the
-// subgrid flux of a preceding PART-1 launch read from C.tau (the network's
-// registers stay out of the flux pass)
+// learned subgrid flux evaluated in the pass (network on the gradients in
+// LDS, its output kept in LDS)
 // RAD: radiative diffusivity varying with radius (radius of each flux point
 // read with its geometry), else the constant P.kappa_r
 template <int N, int EPB, int NT, int PART, bool RAD>
@@ -337,7 +339,7 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
         double sqs[EPB][6][5][NF2];
         double sft[EPB][5][NFL];
     } U;
-    __shared__ float stau[PART == 2 ? EPB : 1][15][PART == 2 ? NP : 1];  // subgrid flux read back (PART 2)
+    __shared__ float stau[PART == 2 ? EPB : 1][15][PART == 2 ? NP : 1];  // subgrid flux (PART 2)
     __shared__ int32_t lk[EPB][6], inf[EPB][6];
     __shared__ Ops<N> op;
     // the network's pass walks the elements from the last to the first, so
@@ -386,13 +388,6 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
         }
     };
     if constexpr (PART != 1) load_si(0, 0);
-    if constexpr (PART == 2) {
-        for (int it = threadIdx.x; it < EPB * 15 * NP; it += NT) {
-            const int el = it / (15 * NP), r = it % (15 * NP), k = r / NP, p = r % NP;
-            const int64_t e = (e0 + el < E) ? e0 + el : 0;
-            stau[el][k][p] = C.tau[((int64_t)k * E + e) * NP + p];
-        }
-    }
     {
         const bool okl = (int)threadIdx.x < EPB * 6 && e0 + threadIdx.x / 6 < E;
         const int32_t l = G.link[okl ? e0 * 6 + threadIdx.x : 0], i = G.info[okl ? e0 * 6 + threadIdx.x : 0];
@@ -463,6 +458,11 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
         // subgrid flux at the solution points -> C.tau
         closure_tau<N, EPB, NT>(C, E, e0, sq, sgr);
         return;
+    }
+    if constexpr (PART == 2) {
+        // subgrid flux at the solution points -> LDS
+        closure_tau<N, EPB, NT>(C, E, e0, sq, sgr, stau);
+        __syncthreads();
     }
     // face points: own viscous flux to the neighbour, own-side common flux
     // kept in registers for the divergence
@@ -926,12 +926,8 @@ static hipError_t launch_flux64_t(const Mesh &m, const Geo &G, const PhysParams 
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
     const bool rad = P.kappa_r1 != 0.0 || P.kappa_r2 != 0.0;
     if (C.model) {
-        // the network's pass, then the flux pass reading its subgrid flux
+        // the flux pass with the network inside
         if constexpr (N == 3) {
-            hipLaunchKernelGGL((k_flux64<N, EPB, NT, 1, false>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G,
-                               P, Q, TQ, TV, sa, C);
-            const hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
             if (rad)
                 hipLaunchKernelGGL((k_flux64<N, EPB, NT, 2, true>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis),
                                    G, P, Q, TQ, TV, sa, C);
