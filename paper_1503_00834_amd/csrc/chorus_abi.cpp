@@ -749,7 +749,7 @@ int chorus_set_background(chorus_mesh_t mesh, const chorus_physics *phys, const 
     StageArgs sa{nullptr, R0d, nullptr, 0.0, 1.0, 0.0, nullptr, nullptr, 0.0, 0.0, 0.0, 0};
     if (e == hipSuccess) e = launch_trace_push(*m, G, Q0, TQp, s);
     if (e == hipSuccess) e = launch_flux64(*m, G, P, Q0, TQp, TV, sa, C0, s);
-    if (e == hipSuccess) e = launch_lift64(*m, G, TV, sa, s);
+    if (e == hipSuccess) e = launch_lift64(*m, G, TV, sa, false, s);
     if (e == hipSuccess) e = hipMemcpyAsync(W + w.R64, R0d, sizeof(double) * 5 * n, hipMemcpyDeviceToDevice, s);
     // the mixed path adds R0 to its FP32 perturbation residual; in balanced
     // mode R(Q) - R(Q0) is the perturbation residual alone
@@ -816,7 +816,7 @@ int chorus_sd_residual(chorus_mesh_t mesh, const chorus_physics *phys, const dou
     }
     hipError_t e = timed(0, s, [&] { return launch_trace_push(*m, G, Q_dev, TQ, s); });
     if (e == hipSuccess) e = timed(1, s, [&] { return launch_flux64(*m, G, P, Q_dev, TQ, TV, sa, C, s); });
-    if (e == hipSuccess) e = timed(2, s, [&] { return launch_lift64(*m, G, TV, sa, s); });
+    if (e == hipSuccess) e = timed(2, s, [&] { return launch_lift64(*m, G, TV, sa, C.model != nullptr, s); });
     if (e != hipSuccess) return hip_fail(e, "sd_residual");
     if (phys->flags & CHORUS_CHECK_FINITE) return finite_check(*m, P, Q_dev, w, W, s);
     return CHORUS_OK;
@@ -889,7 +889,7 @@ static int rk_fp64(const Mesh &m, const chorus_physics *phys, const ClosureArgs 
                          sp.b >= 0 ? reg[sp.b] : nullptr, sp.tout >= 0 ? reg[sp.tout] : nullptr, sp.d0, sp.d1,
                          sp.d2 * dt, 1, b.R0};
             e = run(1, [&] { return launch_flux64(m, G, P, qin, b.TQ, b.TV, sa, C, s); });
-            if (e == hipSuccess) e = run(2, [&] { return launch_lift64(m, G, b.TV, sa, s); });
+            if (e == hipSuccess) e = run(2, [&] { return launch_lift64(m, G, b.TV, sa, C.model != nullptr, s); });
         }
     }
     if (e != hipSuccess) return hip_fail(e, "rk_step");

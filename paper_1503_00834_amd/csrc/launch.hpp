@@ -62,7 +62,10 @@ hipError_t launch_features(const Mesh &m, const Geo &G, const PhysParams &P, con
 hipError_t launch_trace_push(const Mesh &m, const Geo &G, const double *Q, double *TQ, hipStream_t s);
 hipError_t launch_flux64(const Mesh &m, const Geo &G, const PhysParams &P, const double *Q, const double *TQ,
                          double *TV, const StageArgs &sa, const ClosureArgs &C, hipStream_t s);
-hipError_t launch_lift64(const Mesh &m, const Geo &G, const double *TV, const StageArgs &sa, hipStream_t s);
+// closure: the flux pass ran with the learned subgrid flux (five mailbox
+// components per point instead of four)
+hipError_t launch_lift64(const Mesh &m, const Geo &G, const double *TV, const StageArgs &sa, bool closure,
+                         hipStream_t s);
 
 // closure training buffers for a mini-batch of nb samples (rows of 64 or 16)
 struct TrainBufs {

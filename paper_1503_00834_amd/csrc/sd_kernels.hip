@@ -492,8 +492,11 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
                 for (int v = 0; v < 5; ++v)
                     for (int c = 0; c < 3; ++c) fv[v] -= line_interp<N>(op, stau[el][v * 3 + c], m, base, st) * Sf[k][c];
             }
-            double *tv = TV + mailbox_slot<N>(nb, inf[el][f], pp);
-            for (int v = 0; v < 5; ++v) st_once(&tv[v * NF2], fv[v]);
+            // the viscous mass flux is zero: four components per point
+            // unless the subgrid flux (with a mass part) rides along
+            constexpr int NV = CL ? 5 : 4;
+            double *tv = TV + mailbox_slot<N, NV>(nb, inf[el][f], pp);
+            for (int v = 5 - NV; v < 5; ++v) st_once(&tv[(v - (5 - NV)) * NF2], fv[v]);
             flux_rusanov(fo, nq[k], Sf[k], P, ffc[k]);
             for (int v = 0; v < 5; ++v) ffc[k][v] -= 0.5 * fv[v];
         } else if (bc == CHORUS_BC_INNER || bc == CHORUS_BC_OUTER) {
@@ -619,11 +622,13 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
 // -(1/|J|) times that lift is added in place to the flux pass's outputs
 // with their stage weights (Qout: c1 c2, Tout: d1 d2; residual mode: 1);
 // the face traces of the new state are pushed to the neighbours.
-template <int N, int EPB, int NT>
+// NV: components per mailbox point (4: momentum and energy; 5 with the
+// subgrid flux, whose mass part need not vanish)
+template <int N, int EPB, int NT, int NV>
 __global__ __launch_bounds__(NT) void k_lift64(Ops<N> opa, Geo G, const double *__restrict__ TV, StageArgs S_) {
-    constexpr int NP = N * N * N, NF2 = N * N;
-    constexpr int IT_MB = (EPB * 30 * NF2 + NT - 1) / NT, IT_SOL = (EPB * NP + NT - 1) / NT;
-    __shared__ double nv[EPB][6][5][NF2];  // neighbours' viscous flux at own face points, 0 off interfaces
+    constexpr int NP = N * N * N, NF2 = N * N, MBE = 6 * NV * NF2;
+    constexpr int IT_MB = (EPB * MBE + NT - 1) / NT, IT_SOL = (EPB * NP + NT - 1) / NT;
+    __shared__ double nv[EPB][6][NV][NF2];  // neighbours' viscous flux at own face points, 0 off interfaces
     __shared__ double sq[EPB][5][NP];      // the new state, for the traces
     __shared__ int32_t lk[EPB][6], inf[EPB][6];
     __shared__ Ops<N> op;
@@ -646,8 +651,8 @@ __global__ __launch_bounds__(NT) void k_lift64(Ops<N> opa, Geo G, const double *
 #pragma unroll
     for (int k = 0; k < IT_MB; ++k) {
         const int it = threadIdx.x + k * NT;
-        const bool ok = it < EPB * 30 * NF2 && e0 + it / (30 * NF2) < E;
-        mb[k] = ld_once(&TV[ok ? e0 * 30 * NF2 + it : 0]);
+        const bool ok = it < EPB * MBE && e0 + it / MBE < E;
+        mb[k] = ld_once(&TV[ok ? e0 * MBE + it : 0]);
     }
     double qo[IT_SOL][5], to[IT_SOL][5], iJ[IT_SOL], r0[IT_SOL][5];
     const bool bal = S_.R0 != nullptr;
@@ -673,8 +678,8 @@ __global__ __launch_bounds__(NT) void k_lift64(Ops<N> opa, Geo G, const double *
 #pragma unroll
     for (int k = 0; k < IT_MB; ++k) {
         const int it = threadIdx.x + k * NT;
-        if (it >= EPB * 30 * NF2) break;
-        const int el = it / (30 * NF2), r = it % (30 * NF2), f = r / (5 * NF2);
+        if (it >= EPB * MBE) break;
+        const int el = it / MBE, r = it % MBE, f = r / (NV * NF2);
         (&nv[el][0][0][0])[r] = (lk[el][f] >= 0) ? mb[k] : 0.0;
     }
     __syncthreads();
@@ -694,7 +699,8 @@ __global__ __launch_bounds__(NT) void k_lift64(Ops<N> opa, Geo G, const double *
             const int pp = t1 + N * t2;
             const double wl = -0.5 * op.D[a][0], wu = 0.5 * op.D[a][N];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) corr[v] += wl * nv[el][2 * d][v][pp] + wu * nv[el][2 * d + 1][v][pp];
+            for (int v = 0; v < NV; ++v)
+                corr[v + 5 - NV] += wl * nv[el][2 * d][v][pp] + wu * nv[el][2 * d + 1][v][pp];
         }
         for (int v = 0; v < 5; ++v) {
             const int64_t gi = ((int64_t)v * E + e) * NP + p;
@@ -948,10 +954,14 @@ static hipError_t launch_flux64_t(const Mesh &m, const Geo &G, const PhysParams 
 }
 
 template <int N>
-static hipError_t launch_lift64_t(const Mesh &m, const Geo &G, const double *TV, const StageArgs &sa, hipStream_t s) {
+static hipError_t launch_lift64_t(const Mesh &m, const Geo &G, const double *TV, const StageArgs &sa, bool closure,
+                                  hipStream_t s) {
     constexpr int EPB = Cfg64<N>::EPB, NT = Cfg64<N>::NT;
     const unsigned nb = (unsigned)((m.E + EPB - 1) / EPB);
-    hipLaunchKernelGGL((k_lift64<N, EPB, NT>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, TV, sa);
+    if (closure)
+        hipLaunchKernelGGL((k_lift64<N, EPB, NT, 5>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, TV, sa);
+    else
+        hipLaunchKernelGGL((k_lift64<N, EPB, NT, 4>), dim3(nb), dim3(NT), 0, s, make_ops<N>(m.basis), G, TV, sa);
     return hipGetLastError();
 }
 
@@ -1012,8 +1022,9 @@ hipError_t launch_flux64(const Mesh &m, const Geo &G, const PhysParams &P, const
     CHORUS_DISPATCH(m.N, C_)
 #undef C_
 }
-hipError_t launch_lift64(const Mesh &m, const Geo &G, const double *TV, const StageArgs &sa, hipStream_t s) {
-#define C_(n) launch_lift64_t<n>(m, G, TV, sa, s)
+hipError_t launch_lift64(const Mesh &m, const Geo &G, const double *TV, const StageArgs &sa, bool closure,
+                         hipStream_t s) {
+#define C_(n) launch_lift64_t<n>(m, G, TV, sa, closure, s)
     CHORUS_DISPATCH(m.N, C_)
 #undef C_
 }
