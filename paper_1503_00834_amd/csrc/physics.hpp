@@ -111,7 +111,8 @@ __device__ __forceinline__ void flux_viscous(const T q[5], const T g[5][3], cons
 }
 
 // Rusanov common flux along S (outward from the qL side), wave speed
-// max(|u_L.n| + c_L, |u_R.n| + c_R)
+// max(|u_L.n| + c_L, |u_R.n| + c_R), formed as max(|u_L.S| + c_L |S|, ...)
+// (two square roots, no division by |S|)
 template <typename T>
 __device__ __forceinline__ void flux_rusanov(const T qL[5], const T qR[5], const T S[3],
                                              const PhysParams &P, T out[5]) {
@@ -119,16 +120,15 @@ __device__ __forceinline__ void flux_rusanov(const T qL[5], const T qR[5], const
     T fL[5], fR[5];
     flux_inviscid(qL, S, gm1, fL);
     flux_inviscid(qR, S, gm1, fR);
-    const T A = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
-    const T iA = T(1) / A;
+    const T A2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
     const T iL = T(1) / qL[0], iR = T(1) / qR[0];
-    const T unL = fabs((qL[1] * S[0] + qL[2] * S[1] + qL[3] * S[2]) * iA * iL);
-    const T unR = fabs((qR[1] * S[0] + qR[2] * S[1] + qR[3] * S[2]) * iA * iR);
+    const T unL = fabs((qL[1] * S[0] + qL[2] * S[1] + qL[3] * S[2]) * iL);
+    const T unR = fabs((qR[1] * S[0] + qR[2] * S[1] + qR[3] * S[2]) * iR);
     const T pL = gm1 * (qL[4] - T(0.5) * (qL[1] * qL[1] + qL[2] * qL[2] + qL[3] * qL[3]) * iL);
     const T pR = gm1 * (qR[4] - T(0.5) * (qR[1] * qR[1] + qR[2] * qR[2] + qR[3] * qR[3]) * iR);
-    const T cL = sqrt(gam * pL * iL);
-    const T cR = sqrt(gam * pR * iR);
-    const T lamA = T(0.5) * fmax(unL + cL, unR + cR) * A;
+    const T cAL = sqrt(gam * pL * iL * A2);
+    const T cAR = sqrt(gam * pR * iR * A2);
+    const T lamA = T(0.5) * fmax(unL + cAL, unR + cAR);
     for (int v = 0; v < 5; ++v) out[v] = T(0.5) * (fL[v] + fR[v]) - lamA * (qR[v] - qL[v]);
 }
 
