@@ -198,13 +198,13 @@ class OracleMesh:
         return G
 
     def rk3(self, ph, Q, dt, nsteps):
-        Q = np.array(Q, dtype=np.float64, copy=True).reshape(5, self.E, self.np)
+        Q = np.array(Q, dtype=np.float64, order="C", copy=True).reshape(5, self.E, self.np)
         lib().ora_rk3(self._h, ctypes.byref(ph), _dp(Q), float(dt), int(nsteps))
         return Q
 
     def ssp54(self, ph, Q, dt, nsteps):
         """nsteps of the five-stage fourth-order SSP Runge-Kutta method."""
-        Q = np.array(Q, dtype=np.float64, copy=True).reshape(5, self.E, self.np)
+        Q = np.array(Q, dtype=np.float64, order="C", copy=True).reshape(5, self.E, self.np)
         lib().ora_ssp54(self._h, ctypes.byref(ph), _dp(Q), float(dt), int(nsteps))
         return Q
 
@@ -223,7 +223,7 @@ class OracleMesh:
 
     def am_correct(self, Q):
         """(corrected copy of Q, applied dOmega [3])."""
-        Q = np.array(Q, dtype=np.float64, copy=True)
+        Q = np.array(Q, dtype=np.float64, order="C", copy=True)
         dO = np.zeros(3)
         lib().ora_am_correct(self._h, _dp(Q), _dp(dO))
         return Q, dO

@@ -924,3 +924,22 @@ def test_afb_flux_balance_and_state_equations(oracle_mod):
     np.testing.assert_allclose((pp - pm) / (2 * h), -rho * GM / r ** 2, rtol=1e-7)
     S = lambda rr, pr: 2.5 * np.log(pr ** 0.6 / rr)   # c_p ln(p^(1/gamma) / rho)
     np.testing.assert_allclose((S(rp, pp) - S(rm, pm)) / (2 * h), G, rtol=1e-6, atol=1e-9)
+
+
+def test_oracle_wrappers_take_any_memory_layout(oracle_mod):
+    """The ctypes wrappers hand C-ordered buffers to the oracle whatever the
+    layout of the array given (a fancy-indexed element subset is not
+    C-contiguous): the time steppers and the correction agree with the same
+    call on a C-ordered copy."""
+    m = cubed_sphere_shell(2, 2, 7.0 / 3.0, 10.0 / 3.0)
+    om = oracle_mod.OracleMesh(m, 3)
+    Q, pars = om.polytrope(0.7, 1.0, noise=uniform_noise(om.n_solpts, 4), amp=1e-2)
+    Qe = Q.reshape(5, om.E, om.np)
+    view = np.concatenate([Qe, Qe], axis=1)[:, np.arange(om.E)]
+    assert np.array_equal(view, Qe) and not view.flags["C_CONTIGUOUS"]
+    ph = oracle_mod.phys(GM=pars["GM"], omega=1.0, nu=1e-3, kappa=1e-3)
+    ref = np.ascontiguousarray(view)
+    assert np.array_equal(om.rk3(ph, view, 0.01, 1), om.rk3(ph, ref, 0.01, 1))
+    assert np.array_equal(om.ssp54(ph, view, 0.01, 1), om.ssp54(ph, ref, 0.01, 1))
+    assert np.array_equal(om.residual(ph, view), om.residual(ph, ref))
+    assert np.array_equal(om.am_correct(view)[0], om.am_correct(ref)[0])
