@@ -358,6 +358,9 @@ def main():
                     help="skip the leg of the five-stage integrator, radial kappa_r and angular-momentum correction")
     ap.add_argument("--closure-experiment", action="store_true",
                     help="only run the closure experiment at the configured sizes (about 5 minutes; one JSON line)")
+    ap.add_argument("--closure-cost", action="store_true",
+                    help="only time the resolved, plain and closure runs on the closure-run shell "
+                         "(98,304 hexes; one JSON line; for profiling the order-3 passes)")
     ap.add_argument("--size-sweep", action="store_true",
                     help="only measure both paths on shells from 288 to 331,776 hexes (one JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -393,6 +396,11 @@ def main():
         from paper_1503_00834_amd import closure
         rep = closure.configured_experiment()
         print(json.dumps({"closure_experiment": rep, "data": "synthetic"}), flush=True)
+        return
+    if args.closure_cost:
+        from paper_1503_00834_amd import closure
+        c = closure.cost_per_time(32, 16, steps=1)
+        print(json.dumps({"closure_cost": c, "data": "synthetic"}), flush=True)
         return
     if args.size_sweep:
         print(json.dumps({"size_sweep": size_sweep(ch), "unit": "DOF-updates/s", "integrator": "SSP-RK3",
