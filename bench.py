@@ -153,9 +153,9 @@ def closure_leg(panel_n=32, radial_n=16):
                          "peak": 157.3}}
 
 
-def workload_leg(ch, workload, steps=10):
-    """Both paths on another workload (DOF-updates/s over a few SSP-RK3
-    steps after two warm-up steps)."""
+def workload_leg(ch, workload, steps=20, repeats=3):
+    """Both paths on another workload (DOF-updates/s: median of `repeats`
+    timed calls of `steps` SSP-RK3 steps after two warm-up steps)."""
     import torch
     from chorus_inputs import CONFIGS, shell_params_from_config, uniform_noise
     cfg = CONFIGS[workload]
@@ -164,7 +164,7 @@ def workload_leg(ch, workload, steps=10):
     Qh, pars = mesh.init_polytrope(cfg["beta"], cfg["n_rho"], poly_n=cfg["poly_n"],
                                    noise=uniform_noise(mesh.n_solpts, cfg["seed"]), amp=1e-4)
     Q0h, _ = mesh.init_polytrope(cfg["beta"], cfg["n_rho"], poly_n=cfg["poly_n"])
-    out = {"workload": workload, "hexes": mesh.n_elems, "dofs": mesh.n_solpts, "steps": steps}
+    out = {"workload": workload, "hexes": mesh.n_elems, "dofs": mesh.n_solpts, "steps": steps, "repeats": repeats}
     N = cfg["order"]
     for name, prec in (("mixed", ch.CHORUS_MIXED), ("fp64", ch.CHORUS_FP64)):
         phys = ch.physics(GM=pars["GM"], omega=cfg["omega"], nu=cfg["nu"], kappa=cfg["kappa"],
@@ -176,10 +176,13 @@ def workload_leg(ch, workload, steps=10):
         Q = torch.from_numpy(Qh).cuda()
         ch.chorus_rk_step(mesh, phys, Q, dt, 2, ws)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ch.chorus_rk_step(mesh, phys, Q, dt, steps, ws)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        walls = []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            ch.chorus_rk_step(mesh, phys, Q, dt, steps, ws)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+        wall = statistics.median(walls)
         if not bool(torch.isfinite(Q).all()):
             raise RuntimeError("%s state became non-finite" % workload)
         value = mesh.n_solpts * steps / wall

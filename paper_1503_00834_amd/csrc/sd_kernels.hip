@@ -316,9 +316,9 @@ __device__ __forceinline__ double line_interp_s(const Ops<N> &op, const T *fld, 
 }
 
 // PART 0: the flux pass; PART 1: only the learned subgrid flux (common
-// solution, gradients, network -> C.tau); PART 2: the flux pass with the
-// learned subgrid flux evaluated in the pass (network on the gradients in
-// LDS, its output kept in LDS)
+// solution, gradients, network -> C.tau: chorus_closure_infer); PART 2: the
+// flux pass with the learned subgrid flux evaluated in the pass (network on
+// the gradients in LDS, its output kept in LDS)
 // RAD: radiative diffusivity varying with radius (radius of each flux point
 // read with its geometry), else the constant P.kappa_r
 template <int N, int EPB, int NT, int PART, bool RAD>
@@ -342,11 +342,7 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
     __shared__ float stau[PART == 2 ? EPB : 1][15][PART == 2 ? NP : 1];  // subgrid flux (PART 2)
     __shared__ int32_t lk[EPB][6], inf[EPB][6];
     __shared__ Ops<N> op;
-    // the network's pass walks the elements from the last to the first, so
-    // the flux pass after it begins with the elements whose subgrid flux,
-    // state, traces and metrics the network's pass touched last (still in
-    // the memory-side cache); the lift pass then runs from the last again
-    const int64_t e0 = (int64_t)(PART == 1 ? gridDim.x - 1 - blockIdx.x : blockIdx.x) * EPB, E = G.E;
+    const int64_t e0 = (int64_t)blockIdx.x * EPB, E = G.E;
     const double gm1 = P.gamma - 1.0;
     // every global input of the element block before the first wait;
     // unpredicated loads through clamped indices (items past the end read
