@@ -313,8 +313,8 @@ int chorus_kernel_times(double ms[3], int64_t counts[3]);
  * y_mean[15], y_std[15]; network input x = (feature - x_mean) x_inv_std,
  * output tau = y_mean + y_std y.
  * Inference runs on bfloat16 matrix cores with FP32 accumulation (inputs,
- * weights and hidden activations rounded to bfloat16, nearest-even);
- * training runs in FP32.
+ * weights and hidden activations rounded to bfloat16, nearest-even), inside
+ * the order-3 flux pass of a solve; training runs in FP32.
  * ---------------------------------------------------------------------- */
 enum { CHORUS_MLP_IN = 20, CHORUS_MLP_HIDDEN = 64, CHORUS_MLP_OUT = 15, CHORUS_MLP_NPARAM = 6479,
        CHORUS_MLP_NNORM = 70 };
