@@ -161,38 +161,44 @@ __device__ __forceinline__ void closure_tau(const ClosureArgs &C, int64_t E, int
                                             double (*sq)[5][N * N * N], GT (*sgr)[15][N * N * N],
                                             float (*stau)[15][N * N * N] = nullptr) {
     constexpr int NP = N * N * N, NPTS = EPB * NP, NPT = (NPTS + 15) / 16;
+    // point tiles evaluated together (fewer live accumulators than all of
+    // the block's tiles at once)
+    constexpr int TB = NPT < 2 ? NPT : 2;
     static_assert(NT == 64, "the closure runs one wave per block");
     const int lane = threadIdx.x, g = lane >> 4;
-    u32x4_t xb[NPT];
 #pragma unroll
-    for (int pt = 0; pt < NPT; ++pt) {
-        const int pidx = 16 * pt + (lane & 15);
-        const int el = pidx / NP, sp = pidx % NP;
-        const bool ok = pidx < NPTS && e0 + el < E;
-        float x[8];
+    for (int t0 = 0; t0 < NPT; t0 += TB) {
+        u32x4_t xb[TB];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int f = 8 * g + i;
-            double raw = 0.0;
-            if (ok && f < 5) raw = sq[el][f][lds_sol<N>(sp)];
-            else if (ok && f < 20) raw = (double)sgr[el][f - 5][lds_sol<N>(sp)];
-            x[i] = (ok && f < 20) ? mlp_norm_feature(C.model, f, raw) : 0.0f;
+        for (int j = 0; j < TB; ++j) {
+            const int pidx = 16 * (t0 + j) + (lane & 15);
+            const int el = pidx / NP, sp = pidx % NP;
+            const bool ok = pidx < NPTS && e0 + el < E;
+            float x[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int f = 8 * g + i;
+                double raw = 0.0;
+                if (ok && f < 5) raw = sq[el][f][lds_sol<N>(sp)];
+                else if (ok && f < 20) raw = (double)sgr[el][f - 5][lds_sol<N>(sp)];
+                x[i] = (ok && f < 20) ? mlp_norm_feature(C.model, f, raw) : 0.0f;
+            }
+            xb[j] = u32x4_t{bf16_pair(x[0], x[1]), bf16_pair(x[2], x[3]), bf16_pair(x[4], x[5]), bf16_pair(x[6], x[7])};
         }
-        xb[pt] = u32x4_t{bf16_pair(x[0], x[1]), bf16_pair(x[2], x[3]), bf16_pair(x[4], x[5]), bf16_pair(x[6], x[7])};
-    }
-    f32x4_t out[NPT];
-    mlp_eval<NPT>(C.model, xb, out);
+        f32x4_t out[TB];
+        mlp_eval<TB>(C.model, xb, out);
 #pragma unroll
-    for (int pt = 0; pt < NPT; ++pt) {
-        const int pidx = 16 * pt + (lane & 15);
-        const int el = pidx / NP, sp = pidx % NP;
-        if (pidx >= NPTS || e0 + el >= E) continue;
+        for (int j = 0; j < TB; ++j) {
+            const int pidx = 16 * (t0 + j) + (lane & 15);
+            const int el = pidx / NP, sp = pidx % NP;
+            if (pidx >= NPTS || e0 + el >= E) continue;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int k = 4 * g + i;
-            if (k >= kMlpOut) continue;
-            if (stau) stau[el][k][sp] = out[pt][i];
-            else C.tau[((int64_t)k * E + e0 + el) * NP + sp] = out[pt][i];
+            for (int i = 0; i < 4; ++i) {
+                const int k = 4 * g + i;
+                if (k >= kMlpOut) continue;
+                if (stau) stau[el][k][sp] = out[j][i];
+                else C.tau[((int64_t)k * E + e0 + el) * NP + sp] = out[j][i];
+            }
         }
     }
 }
@@ -333,13 +339,16 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
     // FP32: they are network inputs, rounded to bfloat16 after
     // normalisation)
     __shared__ std::conditional_t<PART == 1, float, double> sgr[EPB][15][NP];
-    // the common solution is consumed by the gradients before the first
-    // direction's fluxes are written
+    // the common solution is consumed by the gradients before the subgrid
+    // flux (PART 2) and the first direction's fluxes are written
     __shared__ union {
         double sqs[EPB][6][5][NF2];
-        double sft[EPB][5][NFL];
+        struct {
+            double sft[EPB][5][NFL];
+            float stau[PART == 2 ? EPB : 1][15][PART == 2 ? NP : 1];  // subgrid flux (PART 2)
+        } F;
     } U;
-    __shared__ float stau[PART == 2 ? EPB : 1][15][PART == 2 ? NP : 1];  // subgrid flux (PART 2)
+    auto &stau = U.F.stau;
     __shared__ int32_t lk[EPB][6], inf[EPB][6];
     __shared__ Ops<N> op;
     const int64_t e0 = (int64_t)blockIdx.x * EPB, E = G.E;
@@ -534,7 +543,7 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
                     for (int c = 0; c < 3; ++c) ts[v] += line_interp<N>(op, stau[el][v * 3 + c], m, base, st) * Si[cur][k][c];
             }
             const int fl = m + (N + 1) * tt;
-            for (int v = 0; v < 5; ++v) U.sft[el][v][fl] = fi[v] - fv[v] + ts[v];
+            for (int v = 0; v < 5; ++v) U.F.sft[el][v][fl] = fi[v] - fv[v] + ts[v];
         }
 #pragma unroll
         for (int k = 0; k < Sh::IT_FACE; ++k) {
@@ -544,7 +553,7 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
             if ((f >> 1) != d || e0 + el >= E) continue;
             const double sg = (f & 1) ? 1.0 : -1.0;
             const int fl = ((f & 1) ? N : 0) + (N + 1) * pp;
-            for (int v = 0; v < 5; ++v) U.sft[el][v][fl] = sg * ffc[k][v];
+            for (int v = 0; v < 5; ++v) U.F.sft[el][v][fl] = sg * ffc[k][v];
         }
         __syncthreads();
 #pragma unroll
@@ -559,7 +568,7 @@ __global__ __launch_bounds__(NT, Cfg64<N>::MINW) void k_flux64(Ops<N> opa, Geo G
             for (int v = 0; v < 5; ++v) {
                 double t = 0.0;
 #pragma unroll
-                for (int mm = 0; mm <= N; ++mm) t += op.D[a][mm] * U.sft[el][v][fb + mm];
+                for (int mm = 0; mm <= N; ++mm) t += op.D[a][mm] * U.F.sft[el][v][fb + mm];
                 div[k][v] += t;
             }
         }
