@@ -1268,7 +1268,7 @@ int chorus_closure_infer(chorus_mesh_t mesh, const chorus_physics *phys, const d
 }
 
 struct TrainLayout {
-    size_t H1, G1, H2, G2, dZ1, dZ2, dY, lossv, part, grad, total;
+    size_t H1, H2, dZ1, dZ2, dY, lossv, part, total;
 };
 
 static TrainLayout train_layout(int64_t B) {
@@ -1276,15 +1276,12 @@ static TrainLayout train_layout(int64_t B) {
     size_t off = 0;
     const size_t row = sizeof(float) * 64 * (size_t)B;
     L.H1 = off;  off = align256(off + row);
-    L.G1 = off;  off = align256(off + row);
     L.H2 = off;  off = align256(off + row);
-    L.G2 = off;  off = align256(off + row);
     L.dZ1 = off; off = align256(off + row);
     L.dZ2 = off; off = align256(off + row);
     L.dY = off;  off = align256(off + sizeof(float) * 16 * (size_t)B);
     L.lossv = off; off = align256(off + sizeof(float) * (size_t)B);
     L.part = off;  off = align256(off + sizeof(float) * (kMlpParams + 1) * (size_t)((B + 63) / 64));
-    L.grad = off;  off = align256(off + sizeof(float) * kMlpParams);
     L.total = off;
     return L;
 }
@@ -1292,9 +1289,7 @@ static TrainLayout train_layout(int64_t B) {
 static TrainBufs train_bufs(const TrainLayout &L, unsigned char *W, int64_t n_mean) {
     TrainBufs T;
     T.H1 = (float *)(W + L.H1);
-    T.G1 = (float *)(W + L.G1);
     T.H2 = (float *)(W + L.H2);
-    T.G2 = (float *)(W + L.G2);
     T.dZ1 = (float *)(W + L.dZ1);
     T.dZ2 = (float *)(W + L.dZ2);
     T.dY = (float *)(W + L.dY);
@@ -1367,11 +1362,7 @@ int chorus_closure_train(const float *X_dev, const float *Y_dev, int64_t n, cons
     const TrainLayout L = train_layout(batch);
     unsigned char *W = (unsigned char *)ws;
     const TrainBufs T = train_bufs(L, W, batch);
-    float *grad = (float *)(W + L.grad);
     for (int32_t it = 0; it < iters && e == hipSuccess; ++it) {
-        e = launch_train_grad(X_dev, Y_dev, idx_dev, (int64_t)it * batch, batch, params_dev, T, grad,
-                              loss_dev + it, s);
-        if (e != hipSuccess) break;
         const double t = (double)(step0 + it + 1);
         AdamArgs a;
         a.lr = (float)lr;
@@ -1380,7 +1371,8 @@ int chorus_closure_train(const float *X_dev, const float *Y_dev, int64_t n, cons
         a.eps = (float)eps;
         a.inv_bc1 = (float)(1.0 / (1.0 - std::pow(b1, t)));
         a.inv_bc2 = (float)(1.0 / (1.0 - std::pow(b2, t)));
-        e = launch_adam(params_dev, adam_m_dev, adam_v_dev, grad, a, s);
+        e = launch_train_step(X_dev, Y_dev, idx_dev, (int64_t)it * batch, batch, params_dev, adam_m_dev, adam_v_dev,
+                              T, a, loss_dev + it, s);
     }
     if (e != hipSuccess) return hip_fail(e, "closure_train");
     return CHORUS_OK;

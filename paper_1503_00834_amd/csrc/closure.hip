@@ -9,13 +9,14 @@
 //   k_fwd_bwd    a block of eight waves per 64 samples (lane = sample, wave
 //                = an eighth of the hidden units of every layer): forward
 //                pass, loss terms, and the pre-activation gradients dZ1,
-//                dZ2, dY (activations and GELU derivatives kept per sample,
-//                [t][64] rows)
+//                dZ2, dY (activations and gradients kept per sample, [t][64]
+//                rows; the GELU derivatives stay in registers)
 //   k_wgrad      one thread per (parameter or loss, chunk of 64 samples):
 //                partial sums of the outer products and of the losses
-//   k_wgrad_sum  chunk partials summed
+//   k_wgrad_sum  chunk partials summed (the gradient alone)
+//   k_wgrad_sum_adam  chunk partials summed and the Adam update (Kingma &
+//                Ba 2015, with bias correction) applied at once (training)
 // (every sum in a fixed order: four interleaved running sums, then pairwise)
-//   k_adam       Adam update (Kingma & Ba 2015) with bias correction
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -99,8 +100,7 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_fwd_bwd(const float *__res
     float x[kMlpIn];
 #pragma unroll
     for (int i = 0; i < kMlpIn; ++i) x[i] = X[s * kMlpIn + i];
-    float *H1 = T.H1 + (int64_t)t * 64, *G1 = T.G1 + (int64_t)t * 64;
-    float *H2 = T.H2 + (int64_t)t * 64, *G2 = T.G2 + (int64_t)t * 64;
+    float *H1 = T.H1 + (int64_t)t * 64, *H2 = T.H2 + (int64_t)t * 64;
     // layer 1, this wave's units
     float g1[QU];
 #pragma unroll
@@ -112,10 +112,7 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_fwd_bwd(const float *__res
         const float h = gelu_f(z);
         g1[jj] = gelu_prime_f(z);
         sh1[j][lane] = h;
-        if (ok) {
-            H1[j] = h;
-            G1[j] = g1[jj];
-        }
+        if (ok) H1[j] = h;
     }
     __syncthreads();
     // layer 2, this wave's units, and their share of layer 3
@@ -130,10 +127,7 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_fwd_bwd(const float *__res
         for (int k = 0; k < kMlpHid; ++k) z += W[kW2 + j * kMlpHid + k] * sh1[k][lane];
         const float h = gelu_f(z);
         g2[jj] = gelu_prime_f(z);
-        if (ok) {
-            H2[j] = h;
-            G2[j] = g2[jj];
-        }
+        if (ok) H2[j] = h;
 #pragma unroll
         for (int k = 0; k < kMlpOut; ++k) yq[k] += W[kW3 + k * kMlpHid + j] * h;
     }
@@ -250,16 +244,23 @@ __global__ __launch_bounds__(64) void k_wgrad_sum(int nchunk, const float *__res
     else loss[0] = s / ((float)n_mean * (float)kMlpOut);
 }
 
-__global__ __launch_bounds__(64) void k_adam(float *__restrict__ W, float *__restrict__ m, float *__restrict__ v,
-                                             const float *__restrict__ grad, AdamArgs a) {
-    const int q = blockIdx.x * 64 + threadIdx.x;
-    if (q >= kMlpParams) return;
-    const float g = grad[q];
+__device__ __forceinline__ void adam_update(float *__restrict__ W, float *__restrict__ m, float *__restrict__ v,
+                                            float g, const AdamArgs &a, int q) {
     const float mq = a.b1 * m[q] + (1.0f - a.b1) * g;
     const float vq = a.b2 * v[q] + (1.0f - a.b2) * g * g;
     m[q] = mq;
     v[q] = vq;
     W[q] -= a.lr * (mq * a.inv_bc1) / (sqrtf(vq * a.inv_bc2) + a.eps);
+}
+
+__global__ __launch_bounds__(64) void k_wgrad_sum_adam(int nchunk, const float *__restrict__ part, int64_t n_mean,
+                                                       float *__restrict__ W, float *__restrict__ m,
+                                                       float *__restrict__ v, AdamArgs a, float *__restrict__ loss) {
+    const int q = blockIdx.x * 64 + threadIdx.x;
+    if (q > kMlpParams) return;
+    const float s = fixed_sum(0, nchunk, [&](int c) { return part[(int64_t)c * (kMlpParams + 1) + q]; });
+    if (q < kMlpParams) adam_update(W, m, v, s, a, q);
+    else loss[0] = s / ((float)n_mean * (float)kMlpOut);
 }
 
 // ---------------------------------------------------------------------------
@@ -336,22 +337,32 @@ hipError_t launch_pack(const float *W, const float *norm, unsigned char *model, 
     return hipGetLastError();
 }
 
-hipError_t launch_train_grad(const float *X, const float *Y, const int32_t *idx, int64_t base, int nb,
-                             const float *W, const TrainBufs &T, float *grad, float *loss, hipStream_t s) {
+// forward/backward and the chunk partials of the gradient and the loss
+static hipError_t launch_train_partials(const float *X, const float *Y, const int32_t *idx, int64_t base, int nb,
+                                        const float *W, const TrainBufs &T, hipStream_t s) {
     const int nchunk = (nb + 63) / 64;
     hipLaunchKernelGGL(k_fwd_bwd, dim3(nchunk), dim3(64 * kTrainWaves), 0, s, X, Y, idx, base, nb, W, T);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_wgrad, dim3((kMlpParams + 1 + 63) / 64, nchunk), dim3(64), 0, s, X, idx, base, nb, T);
-    e = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t launch_train_grad(const float *X, const float *Y, const int32_t *idx, int64_t base, int nb,
+                             const float *W, const TrainBufs &T, float *grad, float *loss, hipStream_t s) {
+    hipError_t e = launch_train_partials(X, Y, idx, base, nb, W, T, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad_sum, dim3((kMlpParams + 1 + 63) / 64), dim3(64), 0, s, nchunk,
+    hipLaunchKernelGGL(k_wgrad_sum, dim3((kMlpParams + 1 + 63) / 64), dim3(64), 0, s, (nb + 63) / 64,
                        (const float *)T.part, T.n_mean, grad, loss);
     return hipGetLastError();
 }
 
-hipError_t launch_adam(float *W, float *m, float *v, const float *grad, const AdamArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_adam, dim3((kMlpParams + 63) / 64), dim3(64), 0, s, W, m, v, grad, a);
+hipError_t launch_train_step(const float *X, const float *Y, const int32_t *idx, int64_t base, int nb, float *W,
+                             float *m, float *v, const TrainBufs &T, const AdamArgs &a, float *loss, hipStream_t s) {
+    hipError_t e = launch_train_partials(X, Y, idx, base, nb, W, T, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wgrad_sum_adam, dim3((kMlpParams + 1 + 63) / 64), dim3(64), 0, s, (nb + 63) / 64,
+                       (const float *)T.part, T.n_mean, W, m, v, a, loss);
     return hipGetLastError();
 }
 

@@ -69,11 +69,11 @@ hipError_t launch_lift64(const Mesh &m, const Geo &G, const double *TV, const St
 
 // closure training buffers for a mini-batch of nb samples (rows of 64 or 16)
 struct TrainBufs {
-    float *H1, *G1, *H2, *G2, *dZ1, *dZ2;  // [nb][64]: activations, GELU derivatives, gradients
-    float *dY;                             // [nb][16]
-    float *lossv;                          // [nb]
-    float *part;                           // [ceil(nb/64)][6480] chunk partial gradients and losses
-    int64_t n_mean;                        // samples the loss is averaged over
+    float *H1, *H2, *dZ1, *dZ2;  // [nb][64]: activations and pre-activation gradients
+    float *dY;                   // [nb][16]
+    float *lossv;                // [nb]
+    float *part;                 // [ceil(nb/64)][6480] chunk partial gradients and losses
+    int64_t n_mean;              // samples the loss is averaged over
 };
 
 struct AdamArgs {
@@ -96,7 +96,10 @@ struct FilterArgs {
 hipError_t launch_pack(const float *W, const float *norm, unsigned char *model, hipStream_t s);
 hipError_t launch_train_grad(const float *X, const float *Y, const int32_t *idx, int64_t base, int nb,
                              const float *W, const TrainBufs &T, float *grad, float *loss, hipStream_t s);
-hipError_t launch_adam(float *W, float *m, float *v, const float *grad, const AdamArgs &a, hipStream_t s);
+// one training iteration: gradient of the mini-batch (as launch_train_grad)
+// and the Adam update of the parameters
+hipError_t launch_train_step(const float *X, const float *Y, const int32_t *idx, int64_t base, int nb, float *W,
+                             float *m, float *v, const TrainBufs &T, const AdamArgs &a, float *loss, hipStream_t s);
 hipError_t launch_filter(const FilterArgs &A, hipStream_t s);
 
 hipError_t launch_sums(const double *Q, const double *solw, int64_t n, double *part, int nblocks, double *out,
