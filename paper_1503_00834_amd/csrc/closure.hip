@@ -6,17 +6,19 @@
 //
 // Training is a sequence of small fixed-order kernels (no atomics), so a
 // run is bitwise reproducible:
-//   k_fwd_bwd    a block of eight waves per 64 samples (lane = sample, wave
-//                = an eighth of the hidden units of every layer): forward
-//                pass, loss terms, and the pre-activation gradients dZ1,
-//                dZ2, dY (activations and gradients kept per sample, [t][64]
-//                rows; the GELU derivatives stay in registers)
-//   k_wgrad      one thread per (parameter or loss, chunk of 64 samples):
-//                partial sums of the outer products and of the losses
+//   k_fwd_bwd    one wave per 16 samples, every layer on the FP32 matrix
+//                cores: forward pass, loss terms, and the pre-activation
+//                gradients dZ1, dZ2, dY (activations and gradients kept per
+//                sample, [t][64] rows; the GELU derivatives stay in
+//                registers)
+//   k_wgrad      one block per chunk of 64 samples: the chunk's partial
+//                weight gradients as matrix-core products, bias gradients
+//                and loss as fixed-order sums
 //   k_wgrad_sum  chunk partials summed (the gradient alone)
 //   k_wgrad_sum_adam  chunk partials summed and the Adam update (Kingma &
 //                Ba 2015, with bias correction) applied at once (training)
-// (every sum in a fixed order: four interleaved running sums, then pairwise)
+// (every sum in a fixed order: the matrix-core products in their instruction
+// order, the other sums as four interleaved running sums, then pairwise)
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -82,164 +84,307 @@ __device__ __forceinline__ float gelu_prime_f(float z) {
     return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
-constexpr int kTrainWaves = 8;  // waves per 64 samples in the forward/backward pass
-
-__global__ __launch_bounds__(64 * kTrainWaves) void k_fwd_bwd(const float *__restrict__ X, const float *__restrict__ Y,
-                                                 const int32_t *__restrict__ idx, int64_t base, int nb,
-                                                 const float *__restrict__ W, TrainBufs T) {
-    constexpr int NW = kTrainWaves, QU = kMlpHid / NW;  // hidden units per wave
-    __shared__ float sh1[kMlpHid][64];              // h1[unit][sample]
-    __shared__ float syq[NW][kMlpOut][64];          // layer-3 sums over each wave's units
-    __shared__ float sdz2[kMlpHid][64];             // dz2[unit][sample]
-    const int lane = threadIdx.x & 63;
-    const int q = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-    const int t = blockIdx.x * 64 + lane;
+// One wave per 16 samples: every layer as FP32 matrix-core products
+// (v_mfma_f32_16x16x4f32) with hidden units as rows and the wave's samples as
+// columns.  Operand layout of the instruction (A 16 x 4, B 4 x 16, C 16 x
+// 16): lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and C[4 (l / 16) +
+// i][l % 16], i = 0..3.  A layer's accumulator (lane l: units 16 mt + 4 (l /
+// 16) + i of sample l % 16) serves as the next product's B operand when the
+// K steps run over (mt, i): the step (mt, i) takes unit 16 mt + 4 (l / 16) + i
+// from lane group l / 16, and the weight operand is read at the same unit,
+// so no data moves between lanes.
+__global__ __launch_bounds__(64) void k_fwd_bwd(const float *__restrict__ X, const float *__restrict__ Y,
+                                                const int32_t *__restrict__ idx, int64_t base, int nb,
+                                                const float *__restrict__ W, TrainBufs T) {
+    const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
+    const int t = blockIdx.x * 16 + c;  // this lane's sample (column)
     const bool ok = t < nb;
     // lanes past the batch compute on its first sample and store nothing
     const int64_t s = idx ? (int64_t)idx[base + (ok ? t : 0)] : base + (ok ? t : 0);
-    float x[kMlpIn];
+    // layer 1: z1[mt][i] = unit 16 mt + 4 g + i; K = the 20 features
+    f32x4_t h1[4], gp1[4];
 #pragma unroll
-    for (int i = 0; i < kMlpIn; ++i) x[i] = X[s * kMlpIn + i];
-    float *H1 = T.H1 + (int64_t)t * 64, *H2 = T.H2 + (int64_t)t * 64;
-    // layer 1, this wave's units
-    float g1[QU];
+    for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-    for (int jj = 0; jj < QU; ++jj) {
-        const int j = QU * q + jj;
-        float z = W[kB1 + j];
+        for (int i = 0; i < 4; ++i) h1[mt][i] = W[kB1 + 16 * mt + 4 * g + i];
 #pragma unroll
-        for (int i = 0; i < kMlpIn; ++i) z += W[kW1 + j * kMlpIn + i] * x[i];
-        const float h = gelu_f(z);
-        g1[jj] = gelu_prime_f(z);
-        sh1[j][lane] = h;
-        if (ok) H1[j] = h;
-    }
-    __syncthreads();
-    // layer 2, this wave's units, and their share of layer 3
-    float g2[QU], yq[kMlpOut];
+    for (int ks = 0; ks < kMlpIn / 4; ++ks) {
+        const float b = X[s * kMlpIn + 4 * ks + g];
 #pragma unroll
-    for (int k = 0; k < kMlpOut; ++k) yq[k] = 0.0f;
-#pragma unroll 4
-    for (int jj = 0; jj < QU; ++jj) {
-        const int j = QU * q + jj;
-        float z = W[kB2 + j];
-#pragma unroll
-        for (int k = 0; k < kMlpHid; ++k) z += W[kW2 + j * kMlpHid + k] * sh1[k][lane];
-        const float h = gelu_f(z);
-        g2[jj] = gelu_prime_f(z);
-        if (ok) H2[j] = h;
-#pragma unroll
-        for (int k = 0; k < kMlpOut; ++k) yq[k] += W[kW3 + k * kMlpHid + j] * h;
+        for (int mt = 0; mt < 4; ++mt)
+            h1[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(W[kW1 + (16 * mt + c) * kMlpIn + 4 * ks + g], b, h1[mt],
+                                                        0, 0, 0);
     }
 #pragma unroll
-    for (int k = 0; k < kMlpOut; ++k) syq[q][k][lane] = yq[k];
-    __syncthreads();
-    // outputs, loss and dY (every wave forms them for its own backward pass)
-    float l = 0.0f, dy[kMlpOut];
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float z = h1[mt][i];
+            h1[mt][i] = gelu_f(z);
+            gp1[mt][i] = gelu_prime_f(z);
+        }
+    // layer 2: K steps over the layer-1 units
+    f32x4_t h2[4], gp2[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h2[mt][i] = W[kB2 + 16 * mt + 4 * g + i];
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+        for (int ki = 0; ki < 4; ++ki) {
+            const int k = 16 * kt + 4 * g + ki;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                h2[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(W[kW2 + (16 * mt + c) * kMlpHid + k], h1[kt][ki], h2[mt],
+                                                            0, 0, 0);
+        }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float z = h2[mt][i];
+            h2[mt][i] = gelu_f(z);
+            gp2[mt][i] = gelu_prime_f(z);
+        }
+    // layer 3: outputs 4 g + i (row 15 padding)
+    f32x4_t y;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[i] = (4 * g + i < kMlpOut) ? W[kB3 + 4 * g + i] : 0.0f;
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+        for (int ki = 0; ki < 4; ++ki) {
+            const int k = 16 * kt + 4 * g + ki;
+            const float a = (c < kMlpOut) ? W[kW3 + c * kMlpHid + k] : 0.0f;
+            y = __builtin_amdgcn_mfma_f32_16x16x4f32(a, h2[kt][ki], y, 0, 0, 0);
+        }
+    // loss terms and dY
     const float sc = 2.0f / ((float)T.n_mean * (float)kMlpOut);
+    f32x4_t dy;
+    float l = 0.0f;
 #pragma unroll
-    for (int k = 0; k < kMlpOut; ++k) {
-        float p[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) p[w] = syq[w][k][lane];
-#pragma unroll
-        for (int h = NW / 2; h > 0; h /= 2)  // pairwise, fixed order
-#pragma unroll
-            for (int w = 0; w < h; ++w) p[w] += p[w + h];
-        const float y = W[kB3 + k] + p[0];
-        const float e = y - Y[s * kMlpOut + k];
+    for (int i = 0; i < 4; ++i) {
+        const int k = 4 * g + i;
+        const float e = (k < kMlpOut) ? y[i] - Y[s * kMlpOut + (k < kMlpOut ? k : 0)] : 0.0f;
         l += e * e;
-        dy[k] = sc * e;
+        dy[i] = sc * e;
     }
-    if (q == 0 && ok) {
+    // the sample's loss: the four lane groups summed in a fixed order
+    const float l1 = __shfl_xor(l, 16), l2 = __shfl_xor(l, 32), l3 = __shfl_xor(l, 48);
+    const float lsum = (g == 0) ? (l + l1) + (l2 + l3) : 0.0f;
+    // back through layer 3: dH2 = W3^T dY, K = the 16 (15 + padding) outputs
+    f32x4_t dz2[4];
 #pragma unroll
-        for (int k = 0; k < kMlpOut; ++k) T.dY[(int64_t)t * 16 + k] = dy[k];
-        T.lossv[t] = l;
-    }
-    // back through layer 3 to this wave's layer-2 units:
-    // dZ2_j = (sum_k W3[k][j] dY_k) gelu'(z2_j)
-    float *dZ2 = T.dZ2 + (int64_t)t * 64, *dZ1 = T.dZ1 + (int64_t)t * 64;
+    for (int mt = 0; mt < 4; ++mt) dz2[mt] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int jj = 0; jj < QU; ++jj) {
-        const int j = QU * q + jj;
-        float a = 0.0f;
+    for (int ki = 0; ki < 4; ++ki) {
+        const int k = 4 * g + ki;
 #pragma unroll
-        for (int k = 0; k < kMlpOut; ++k) a += W[kW3 + k * kMlpHid + j] * dy[k];
-        const float dz = a * g2[jj];
-        sdz2[j][lane] = dz;
-        if (ok) dZ2[j] = dz;
+        for (int mt = 0; mt < 4; ++mt) {
+            const float a = (k < kMlpOut) ? W[kW3 + (k < kMlpOut ? k : 0) * kMlpHid + 16 * mt + c] : 0.0f;
+            dz2[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, dy[ki], dz2[mt], 0, 0, 0);
+        }
     }
-    __syncthreads();
-    // back through layer 2 to this wave's layer-1 units:
-    // dZ1_k = (sum_j W2[j][k] dZ2_j) gelu'(z1_k)
-#pragma unroll 4
-    for (int kk = 0; kk < QU; ++kk) {
-        const int k = QU * q + kk;
-        float dh = 0.0f;
 #pragma unroll
-        for (int j = 0; j < kMlpHid; ++j) dh += W[kW2 + j * kMlpHid + k] * sdz2[j][lane];
-        if (ok) dZ1[k] = dh * g1[kk];
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dz2[mt][i] *= gp2[mt][i];
+    // back through layer 2: dH1 = W2^T dZ2
+    f32x4_t dz1[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) dz1[mt] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+        for (int ki = 0; ki < 4; ++ki) {
+            const int k = 16 * kt + 4 * g + ki;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                dz1[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(W[kW2 + k * kMlpHid + 16 * mt + c], dz2[kt][ki], dz1[mt],
+                                                             0, 0, 0);
+        }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dz1[mt][i] *= gp1[mt][i];
+    if (!ok) return;
+    // [t][64] rows: four consecutive units per lane and row tile
+    const int64_t r64 = (int64_t)t * 64 + 4 * g;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        *reinterpret_cast<f32x4_t *>(T.H1 + r64 + 16 * mt) = h1[mt];
+        *reinterpret_cast<f32x4_t *>(T.H2 + r64 + 16 * mt) = h2[mt];
+        *reinterpret_cast<f32x4_t *>(T.dZ1 + r64 + 16 * mt) = dz1[mt];
+        *reinterpret_cast<f32x4_t *>(T.dZ2 + r64 + 16 * mt) = dz2[mt];
     }
-}
-
-// sum of f(t) for t0 <= t < t1 in a fixed order: four interleaved running
-// sums (t = t0 + 4u + r in sum r), combined pairwise
-template <typename Fn>
-__device__ __forceinline__ float fixed_sum(int t0, int t1, Fn f) {
-    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-    int t = t0;
-    for (; t + 3 < t1; t += 4) {
-        a0 += f(t);
-        a1 += f(t + 1);
-        a2 += f(t + 2);
-        a3 += f(t + 3);
-    }
-    if (t < t1) a0 += f(t);
-    if (t + 1 < t1) a1 += f(t + 1);
-    if (t + 2 < t1) a2 += f(t + 2);
-    return (a0 + a1) + (a2 + a3);
+    *reinterpret_cast<f32x4_t *>(T.dY + (int64_t)t * 16 + 4 * g) = dy;
+    if (g == 0) T.lossv[t] = lsum;
 }
 
 // partial sums over chunk c (samples 64c .. 64c+63) of each parameter's
-// gradient and (q = kMlpParams) of the losses: part[c][q]
-__global__ __launch_bounds__(64) void k_wgrad(const float *__restrict__ X, const int32_t *__restrict__ idx,
-                                              int64_t base, int nb, TrainBufs T) {
-    const int q = blockIdx.x * 64 + threadIdx.x, c = blockIdx.y;
-    if (q > kMlpParams) return;
+// gradient and (q = kMlpParams) of the losses: part[c][q].  The weight
+// gradients are products over the chunk's samples on the FP32 matrix cores
+// (operand layout as in k_fwd_bwd; K = the samples, 16 steps of 4): dW2 =
+// dZ2^T H1 (waves 0 and 1, 8 tiles each), dW1 = dZ1^T X (wave 2, features
+// padded to 32), dW3 = dY^T H2 (wave 3, outputs padded to 16).  The bias
+// gradients are the same products with a column of ones (feature 20 of the
+// padded X; one more column tile for dW2 and dW3), and the loss rides in
+// the padding row 15 of dY^T.  Samples past the batch enter as zeros.
+__global__ __launch_bounds__(256) void k_wgrad(const float *__restrict__ X, const int32_t *__restrict__ idx,
+                                               int64_t base, int nb, TrainBufs T) {
+    const int c = blockIdx.x, w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
     const int t0 = 64 * c, t1 = min(nb, t0 + 64);
-    float s;
-    if (q == kMlpParams) {
-        s = fixed_sum(t0, t1, [&](int t) { return T.lossv[t]; });
-    } else if (q < kB1) {
-        const int j = q / kMlpIn, i = q % kMlpIn;
-        s = fixed_sum(t0, t1, [&](int t) {
-            const int64_t smp = idx ? (int64_t)idx[base + t] : base + t;
-            return T.dZ1[(int64_t)t * 64 + j] * X[smp * kMlpIn + i];
-        });
-    } else if (q < kW2) {
-        const int j = q - kB1;
-        s = fixed_sum(t0, t1, [&](int t) { return T.dZ1[(int64_t)t * 64 + j]; });
-    } else if (q < kB2) {
-        const int j = (q - kW2) / kMlpHid, k = (q - kW2) % kMlpHid;
-        s = fixed_sum(t0, t1, [&](int t) { return T.dZ2[(int64_t)t * 64 + j] * T.H1[(int64_t)t * 64 + k]; });
-    } else if (q < kW3) {
-        const int j = q - kB2;
-        s = fixed_sum(t0, t1, [&](int t) { return T.dZ2[(int64_t)t * 64 + j]; });
-    } else if (q < kB3) {
-        const int k = (q - kW3) / kMlpHid, j = (q - kW3) % kMlpHid;
-        s = fixed_sum(t0, t1, [&](int t) { return T.dY[(int64_t)t * 16 + k] * T.H2[(int64_t)t * 64 + j]; });
+    float *part = T.part + (int64_t)c * (kMlpParams + 1);
+    // operand of sample t0 + 4 ks + g: row t of a [t][ld] array at column col
+    auto opnd = [&](const float *A, int ld, int ks, int col) {
+        const int t = t0 + 4 * ks + g;
+        return (t < t1) ? A[(int64_t)t * ld + col] : 0.0f;
+    };
+    if (w < 2) {
+        // dW2[j][k] = sum_t dZ2[t][j] H1[t][k], rows j in tiles 2w, 2w + 1;
+        // column tile 4: a column of ones (db2)
+        f32x4_t acc[2][5];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int nt = 0; nt < 5; ++nt) acc[a][nt] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        // every operand of the chunk first (one wait), then the products
+        float av[16][2], bv[16][4];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[ks][a] = opnd(T.dZ2, 64, ks, 16 * (2 * w + a) + r);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) bv[ks][nt] = opnd(T.H1, 64, ks, 16 * nt + r);
+        }
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const float one = (r == 0 && t0 + 4 * ks + g < t1) ? 1.0f : 0.0f;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[a][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][a], bv[ks][nt], acc[a][nt], 0, 0, 0);
+                acc[a][4] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][a], one, acc[a][4], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = 16 * (2 * w + a) + 4 * g + i;
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) part[kW2 + j * kMlpHid + 16 * nt + r] = acc[a][nt][i];
+                if (r == 0) part[kB2 + j] = acc[a][4][i];
+            }
+    } else if (w == 2) {
+        // dW1[j][i] = sum_t dZ1[t][j] X[s_t][i]
+        f32x4_t acc[4][2];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        // every operand of the chunk first (sample indices, then the rest)
+        int64_t smp[16];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const int t = t0 + 4 * ks + g;
+            const int tc = (t < t1) ? t : t0;
+            smp[ks] = idx ? (int64_t)idx[base + tc] : base + tc;
+        }
+        float av[16][4], bv[16][2];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const bool in = t0 + 4 * ks + g < t1;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) av[ks][mt] = opnd(T.dZ1, 64, ks, 16 * mt + r);
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const int f = 16 * nt + r;
+                bv[ks][nt] = !in ? 0.0f : (f < kMlpIn) ? X[smp[ks] * kMlpIn + f] : (f == kMlpIn) ? 1.0f : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][mt], bv[ks][nt], acc[mt][nt], 0, 0, 0);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int f = 16 * nt + r, j = 16 * mt + 4 * g + i;
+                    if (f < kMlpIn) part[kW1 + j * kMlpIn + f] = acc[mt][nt][i];
+                    else if (f == kMlpIn) part[kB1 + j] = acc[mt][nt][i];
+                }
     } else {
-        const int k = q - kB3;
-        s = fixed_sum(t0, t1, [&](int t) { return T.dY[(int64_t)t * 16 + k]; });
+        // dW3[k][j] = sum_t dY[t][k] H2[t][j]; row 15 carries the sample
+        // losses, column tile 4 a column of ones (db3 and the loss)
+        f32x4_t acc[5];
+#pragma unroll
+        for (int nt = 0; nt < 5; ++nt) acc[nt] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        float av[16], bv[16][4];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            av[ks] = (r < kMlpOut) ? opnd(T.dY, 16, ks, r) : opnd(T.lossv, 1, ks, 0);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) bv[ks][nt] = opnd(T.H2, 64, ks, 16 * nt + r);
+        }
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks], bv[ks][nt], acc[nt], 0, 0, 0);
+            const float one = (r == 0 && t0 + 4 * ks + g < t1) ? 1.0f : 0.0f;
+            acc[4] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks], one, acc[4], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * g + i;
+            if (k < kMlpOut) {
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) part[kW3 + k * kMlpHid + 16 * nt + r] = acc[nt][i];
+                if (r == 0) part[kB3 + k] = acc[4][i];
+            } else if (r == 0) {
+                part[kMlpParams] = acc[4][i];
+            }
+        }
     }
-    T.part[(int64_t)c * (kMlpParams + 1) + q] = s;
 }
 
+// sum over the chunks of quantity q in a fixed order: four running sums on
+// four lanes (lane 4 q' + r sums chunks r, r + 4, ... in turn), combined
+// pairwise as (s0 + s1) + (s2 + s3)
+__device__ __forceinline__ float chunk_sum(int nchunk, const float *__restrict__ part, int q) {
+    const int r = threadIdx.x & 3;
+    float a = 0.0f;
+    // 16 chunks per lane and round, every load of a round issued first
+    for (int c0 = r; c0 < nchunk; c0 += 64) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int c = c0 + 4 * u;
+            v[u] = part[(int64_t)(c < nchunk ? c : r) * (kMlpParams + 1) + q];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (c0 + 4 * u < nchunk) a += v[u];
+    }
+    const float p = a + __shfl_xor(a, 1);
+    return p + __shfl_xor(p, 2);
+}
+
+// four lanes per quantity (parameter, or the loss for q = kMlpParams)
 __global__ __launch_bounds__(64) void k_wgrad_sum(int nchunk, const float *__restrict__ part, int64_t n_mean,
                                                   float *__restrict__ grad, float *__restrict__ loss) {
-    const int q = blockIdx.x * 64 + threadIdx.x;
-    if (q > kMlpParams) return;
-    const float s = fixed_sum(0, nchunk, [&](int c) { return part[(int64_t)c * (kMlpParams + 1) + q]; });
+    const int qq = (blockIdx.x * 64 + (int)threadIdx.x) >> 2, q = qq <= kMlpParams ? qq : kMlpParams;
+    const float s = chunk_sum(nchunk, part, q);
+    if ((threadIdx.x & 3) != 0 || qq > kMlpParams) return;
     if (q < kMlpParams) grad[q] = s;
     else loss[0] = s / ((float)n_mean * (float)kMlpOut);
 }
@@ -256,9 +401,9 @@ __device__ __forceinline__ void adam_update(float *__restrict__ W, float *__rest
 __global__ __launch_bounds__(64) void k_wgrad_sum_adam(int nchunk, const float *__restrict__ part, int64_t n_mean,
                                                        float *__restrict__ W, float *__restrict__ m,
                                                        float *__restrict__ v, AdamArgs a, float *__restrict__ loss) {
-    const int q = blockIdx.x * 64 + threadIdx.x;
-    if (q > kMlpParams) return;
-    const float s = fixed_sum(0, nchunk, [&](int c) { return part[(int64_t)c * (kMlpParams + 1) + q]; });
+    const int qq = (blockIdx.x * 64 + (int)threadIdx.x) >> 2, q = qq <= kMlpParams ? qq : kMlpParams;
+    const float s = chunk_sum(nchunk, part, q);
+    if ((threadIdx.x & 3) != 0 || qq > kMlpParams) return;
     if (q < kMlpParams) adam_update(W, m, v, s, a, q);
     else loss[0] = s / ((float)n_mean * (float)kMlpOut);
 }
@@ -341,10 +486,10 @@ hipError_t launch_pack(const float *W, const float *norm, unsigned char *model, 
 static hipError_t launch_train_partials(const float *X, const float *Y, const int32_t *idx, int64_t base, int nb,
                                         const float *W, const TrainBufs &T, hipStream_t s) {
     const int nchunk = (nb + 63) / 64;
-    hipLaunchKernelGGL(k_fwd_bwd, dim3(nchunk), dim3(64 * kTrainWaves), 0, s, X, Y, idx, base, nb, W, T);
+    hipLaunchKernelGGL(k_fwd_bwd, dim3((nb + 15) / 16), dim3(64), 0, s, X, Y, idx, base, nb, W, T);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad, dim3((kMlpParams + 1 + 63) / 64, nchunk), dim3(64), 0, s, X, idx, base, nb, T);
+    hipLaunchKernelGGL(k_wgrad, dim3(nchunk), dim3(256), 0, s, X, idx, base, nb, T);
     return hipGetLastError();
 }
 
@@ -352,7 +497,7 @@ hipError_t launch_train_grad(const float *X, const float *Y, const int32_t *idx,
                              const float *W, const TrainBufs &T, float *grad, float *loss, hipStream_t s) {
     hipError_t e = launch_train_partials(X, Y, idx, base, nb, W, T, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad_sum, dim3((kMlpParams + 1 + 63) / 64), dim3(64), 0, s, (nb + 63) / 64,
+    hipLaunchKernelGGL(k_wgrad_sum, dim3((4 * (kMlpParams + 1) + 63) / 64), dim3(64), 0, s, (nb + 63) / 64,
                        (const float *)T.part, T.n_mean, grad, loss);
     return hipGetLastError();
 }
@@ -361,7 +506,7 @@ hipError_t launch_train_step(const float *X, const float *Y, const int32_t *idx,
                              float *m, float *v, const TrainBufs &T, const AdamArgs &a, float *loss, hipStream_t s) {
     hipError_t e = launch_train_partials(X, Y, idx, base, nb, W, T, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad_sum_adam, dim3((kMlpParams + 1 + 63) / 64), dim3(64), 0, s, (nb + 63) / 64,
+    hipLaunchKernelGGL(k_wgrad_sum_adam, dim3((4 * (kMlpParams + 1) + 63) / 64), dim3(64), 0, s, (nb + 63) / 64,
                        (const float *)T.part, T.n_mean, W, m, v, a, loss);
     return hipGetLastError();
 }
