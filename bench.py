@@ -114,7 +114,7 @@ def closure_leg(panel_n=32, radial_n=16):
     from paper_1503_00834_amd import closure
     from chorus_inputs import mlp_init
     c = closure.cost_per_time(panel_n, radial_n, kernel_times=True)
-    # training (FP32, one thread per sample): Adam iterations on synthetic
+    # training (FP32 matrix-core products): Adam iterations on synthetic
     # normalised samples, batch 4,096; about 3 x 12,672 flops per sample
     # (forward, and a backward twice its size)
     n, batch, iters = 1 << 20, 4096, 200
@@ -149,7 +149,7 @@ def closure_leg(panel_n=32, radial_n=16):
                     "note": "network time = the network pass plus the order-3 flux pass, minus the plain "
                             "order-3 flux pass"},
             "training": {"samples_per_s": train_sps, "batch": batch, "iters": iters,
-                         "achieved": train_sps * 3 * 12672.0 / 1e12, "unit": "TFLOP/s (FP32 vector)",
+                         "achieved": train_sps * 3 * 12672.0 / 1e12, "unit": "TFLOP/s (FP32 matrix)",
                          "peak": 157.3}}
 
 
