@@ -1268,7 +1268,7 @@ int chorus_closure_infer(chorus_mesh_t mesh, const chorus_physics *phys, const d
 }
 
 struct TrainLayout {
-    size_t H1, H2, dZ1, dZ2, dY, lossv, part, total;
+    size_t H1, H2, dZ1, dZ2, dY, lossv, part, flag, total;
 };
 
 static TrainLayout train_layout(int64_t B) {
@@ -1282,6 +1282,7 @@ static TrainLayout train_layout(int64_t B) {
     L.dY = off;  off = align256(off + sizeof(float) * 16 * (size_t)B);
     L.lossv = off; off = align256(off + sizeof(float) * (size_t)B);
     L.part = off;  off = align256(off + sizeof(float) * (kMlpParams + 1) * (size_t)((B + 63) / 64));
+    L.flag = off;  off = align256(off + sizeof(int));
     L.total = off;
     return L;
 }
@@ -1349,19 +1350,20 @@ int chorus_closure_train(const float *X_dev, const float *Y_dev, int64_t n, cons
     }
     if (iters == 0) return CHORUS_OK;
     hipStream_t s = (hipStream_t)stream;
-    // every sample index must address a row of X and Y
-    std::vector<int32_t> hidx((size_t)iters * batch);
-    hipError_t e = hipMemcpyAsync(hidx.data(), idx_dev, sizeof(int32_t) * hidx.size(), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "closure_train");
-    for (int32_t v : hidx)
-        if (v < 0 || v >= n) {
-            set_error("closure_train: sample index out of range");
-            return CHORUS_EINVAL;
-        }
     const TrainLayout L = train_layout(batch);
     unsigned char *W = (unsigned char *)ws;
     const TrainBufs T = train_bufs(L, W, batch);
+    // every sample index must address a row of X and Y (checked on the
+    // device, before any training kernel reads through the indices)
+    int *flag = (int *)(W + L.flag), bad = 0;
+    hipError_t e = launch_check_idx(idx_dev, (int64_t)iters * batch, n, flag, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "closure_train");
+    if (bad) {
+        set_error("closure_train: sample index out of range");
+        return CHORUS_EINVAL;
+    }
     for (int32_t it = 0; it < iters && e == hipSuccess; ++it) {
         const double t = (double)(step0 + it + 1);
         AdamArgs a;

@@ -511,6 +511,22 @@ hipError_t launch_train_step(const float *X, const float *Y, const int32_t *idx,
     return hipGetLastError();
 }
 
+// flag[0] = 1 if a sample index lies outside [0, n) (flag cleared first)
+__global__ __launch_bounds__(256) void k_check_idx(const int32_t *__restrict__ idx, int64_t count, int64_t n,
+                                                   int *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const int32_t v = idx[i];
+    if (v < 0 || v >= n) flag[0] = 1;
+}
+
+hipError_t launch_check_idx(const int32_t *idx, int64_t count, int64_t n, int *flag, hipStream_t s) {
+    hipError_t e = launch_clear_flag(flag, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_check_idx, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, idx, count, n, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_filter(const FilterArgs &A, hipStream_t s) {
     hipLaunchKernelGGL(k_filter, dim3((unsigned)A.E), dim3(64), 0, s, A);
     return hipGetLastError();

@@ -101,6 +101,8 @@ hipError_t launch_train_grad(const float *X, const float *Y, const int32_t *idx,
 hipError_t launch_train_step(const float *X, const float *Y, const int32_t *idx, int64_t base, int nb, float *W,
                              float *m, float *v, const TrainBufs &T, const AdamArgs &a, float *loss, hipStream_t s);
 hipError_t launch_filter(const FilterArgs &A, hipStream_t s);
+// flag[0] = 1 if any of idx[0 .. count) lies outside [0, n)
+hipError_t launch_check_idx(const int32_t *idx, int64_t count, int64_t n, int *flag, hipStream_t s);
 
 hipError_t launch_sums(const double *Q, const double *solw, int64_t n, double *part, int nblocks, double *out,
                        hipStream_t s);

@@ -326,6 +326,35 @@ def test_train_matches_oracle_and_is_deterministic(ch, cl, torch_dev):
     assert np.linalg.norm(got - want) <= 2e-3 * np.linalg.norm(dW)
 
 
+def test_train_rejects_out_of_range_indices(ch, torch_dev):
+    """A sample index outside [0, n) is an argument error, found before any
+    training kernel reads through the indices; the parameters stay as
+    they were."""
+    torch = torch_dev
+    n, batch, iters = 200, 64, 3
+    rng = np.random.default_rng(41)
+    X = torch.from_numpy(rng.normal(size=(n, 20)).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.normal(size=(n, 15)).astype(np.float32)).cuda()
+    P = torch.as_tensor(mlp_init(3), dtype=torch.float32).cuda()
+    P0 = P.clone()
+    M, V = torch.zeros_like(P), torch.zeros_like(P)
+    L = torch.zeros(iters, dtype=torch.float32, device="cuda")
+    ws = ch.closure_train_workspace(batch)
+    for bad in (n, -1):
+        idx = torch.zeros(batch * iters, dtype=torch.int32, device="cuda")
+        idx[batch * iters - 1] = bad
+        with pytest.raises(ch.ChorusError) as ei:
+            ch.chorus_closure_train(X, T, idx, batch, iters, P, M, V, 0, (1e-3, 0.9, 0.999, 1e-8), L, ws)
+        assert ei.value.status == -1
+        torch.cuda.synchronize()
+        assert torch.equal(P, P0)
+    # in range: trains
+    idx = torch.from_numpy(rng.integers(0, n, batch * iters).astype(np.int32)).cuda()
+    ch.chorus_closure_train(X, T, idx, batch, iters, P, M, V, 0, (1e-3, 0.9, 0.999, 1e-8), L, ws)
+    torch.cuda.synchronize()
+    assert not torch.equal(P, P0)
+
+
 def test_pack_rejects_nonfinite(ch, torch_dev):
     torch = torch_dev
     params = mlp_init(17).astype(np.float32)
