@@ -80,8 +80,25 @@ __global__ __launch_bounds__(64) void k_pack(const float *__restrict__ W, const 
 // ---------------------------------------------------------------------------
 // training
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float gelu_prime_f(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+// GELU h = z Phi(z) and its derivative Phi(z) + z phi(z) in FP32, with
+// erf by the rational approximation 7.1.26 of Abramowitz and Stegun (as in
+// the inference; |error| <= 1.5e-7, the size of an FP32 rounding at these
+// magnitudes; hardware reciprocal and exponential): with x = |z| / sqrt 2,
+// 1 - erf(x) = t (a1 + ... + a5 t^4)
+// exp(-x^2), t = 1 / (1 + p x), and exp(-x^2) = exp(-z^2 / 2) is also the
+// normal density's factor, so one exponential serves both
+__device__ __forceinline__ void gelu_and_prime(float z, float &h, float &gp) {
+    const float az = fabsf(z);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, az, 1.0f));
+    float q = fmaf(1.061405429f, t, -1.453152027f);
+    q = fmaf(q, t, 1.421413741f);
+    q = fmaf(q, t, -0.284496736f);
+    q = fmaf(q, t, 0.254829592f);
+    const float e = __builtin_amdgcn_exp2f(z * z * (-0.5f * 1.4426950408889634f));
+    const float tail = 0.5f * q * t * e;            // Phi(-|z|)
+    const float Phi = (z >= 0.0f) ? 1.0f - tail : tail;
+    h = z * Phi;
+    gp = fmaf(z * 0.39894228040143268f, e, Phi);
 }
 
 // One wave per 16 samples: every layer as FP32 matrix-core products
@@ -119,9 +136,10 @@ __global__ __launch_bounds__(64) void k_fwd_bwd(const float *__restrict__ X, con
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const float z = h1[mt][i];
-            h1[mt][i] = gelu_f(z);
-            gp1[mt][i] = gelu_prime_f(z);
+            float h, gp;
+            gelu_and_prime(h1[mt][i], h, gp);
+            h1[mt][i] = h;
+            gp1[mt][i] = gp;
         }
     // layer 2: K steps over the layer-1 units
     f32x4_t h2[4], gp2[4];
@@ -143,9 +161,10 @@ __global__ __launch_bounds__(64) void k_fwd_bwd(const float *__restrict__ X, con
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const float z = h2[mt][i];
-            h2[mt][i] = gelu_f(z);
-            gp2[mt][i] = gelu_prime_f(z);
+            float h, gp;
+            gelu_and_prime(h2[mt][i], h, gp);
+            h2[mt][i] = h;
+            gp2[mt][i] = gp;
         }
     // layer 3: outputs 4 g + i (row 15 padding)
     f32x4_t y;

@@ -49,13 +49,8 @@ __device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
 }
 
-// GELU z Phi(z), Phi(z) = (1 + erf(z / sqrt 2)) / 2: FP32 with the library
-// erf (training).
-__device__ __forceinline__ float gelu_f(float z) {
-    return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
-}
-
-// The same for the bfloat16 inference, with erf by the rational
+// GELU z Phi(z), Phi(z) = (1 + erf(z / sqrt 2)) / 2, for the bfloat16
+// inference, with erf by the rational
 // approximation 7.1.26 of Abramowitz and Stegun (Handbook of Mathematical
 // Functions, 1964): erf(x) = 1 - q, q = t (a1 + t (a2 + t (a3 + t (a4 +
 // t a5)))) exp(-x^2), t = 1 / (1 + p x) for x >= 0 (odd extension),
