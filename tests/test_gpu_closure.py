@@ -269,7 +269,7 @@ def test_closure_ssp54_step_matches_oracle(ch, cl, oracle_mod, torch_dev):
         assert np.linalg.norm(got[v] - q[v]) <= 2e-3 * dq + 1e-13 * np.linalg.norm(q[v]), v
 
 
-@pytest.mark.parametrize("n", [64, 300])
+@pytest.mark.parametrize("n", [1, 17, 64, 300])
 def test_grad_matches_oracle(ch, cl, torch_dev, n):
     torch = torch_dev
     rng = np.random.default_rng(21 + n)
