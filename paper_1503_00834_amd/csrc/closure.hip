@@ -12,8 +12,8 @@
 //                sample, [t][64] rows; the GELU derivatives stay in
 //                registers)
 //   k_wgrad      one block per chunk of 64 samples: the chunk's partial
-//                weight gradients as matrix-core products, bias gradients
-//                and loss as fixed-order sums
+//                weight and bias gradients and its loss as matrix-core
+//                products over the chunk's samples
 //   k_wgrad_sum  chunk partials summed (the gradient alone)
 //   k_wgrad_sum_adam  chunk partials summed and the Adam update (Kingma &
 //                Ba 2015, with bias correction) applied at once (training)
@@ -84,9 +84,9 @@ __global__ __launch_bounds__(64) void k_pack(const float *__restrict__ W, const 
 // erf by the rational approximation 7.1.26 of Abramowitz and Stegun (as in
 // the inference; |error| <= 1.5e-7, the size of an FP32 rounding at these
 // magnitudes; hardware reciprocal and exponential): with x = |z| / sqrt 2,
-// 1 - erf(x) = t (a1 + ... + a5 t^4)
-// exp(-x^2), t = 1 / (1 + p x), and exp(-x^2) = exp(-z^2 / 2) is also the
-// normal density's factor, so one exponential serves both
+// 1 - erf(x) = t (a1 + a2 t + ... + a5 t^4) exp(-x^2), t = 1 / (1 + p x);
+// exp(-x^2) = exp(-z^2 / 2) is also the normal density's factor, so one
+// exponential serves both
 __device__ __forceinline__ void gelu_and_prime(float z, float &h, float &gp) {
     const float az = fabsf(z);
     const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, az, 1.0f));
