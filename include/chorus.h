@@ -347,7 +347,9 @@ int chorus_closure_grad(const float *X_dev, const float *Y_dev, int64_t n, const
  * caller draws them).  params/adam_m/adam_v [CHORUS_MLP_NPARAM] FP32 are
  * updated in place; the bias correction uses step step0 + i + 1;
  * hyper = (lr, beta1, beta2, eps); loss_dev [iters] receives the loss of
- * each mini-batch before its update. */
+ * each mini-batch before its update.  Every index is checked on the device
+ * first: one outside [0, n) returns CHORUS_EINVAL with the parameters
+ * untouched (the call waits for the stream once, to read that check). */
 int chorus_closure_train(const float *X_dev, const float *Y_dev, int64_t n, const int32_t *idx_dev,
                          int32_t batch, int32_t iters, float *params_dev, float *adam_m_dev, float *adam_v_dev,
                          int64_t step0, const double hyper[4], float *loss_dev, void *ws, size_t ws_bytes,
