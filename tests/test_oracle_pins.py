@@ -30,7 +30,10 @@ def test_points_closed_forms(oracle_mod, N):
     assert xf[0] == 0.0 and xf[-1] == 1.0
 
 
-def test_points_survey_values(oracle_mod):
+def test_points_closed_form_values(oracle_mod):
+    """Solution points (1 - cos((2s + 1) pi / (2N))) / 2 and flux points
+    (the end points and the N - 1 Legendre-Gauss points on [0, 1]), printed
+    to seven digits."""
     xs, xf, *_ = oracle_mod.basis(3)
     np.testing.assert_allclose(xs, [0.0669873, 0.5, 0.9330127], atol=1e-7)
     np.testing.assert_allclose(xf, [0, 0.2113249, 0.7886751, 1], atol=1e-7)
