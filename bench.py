@@ -110,14 +110,31 @@ def closure_leg(panel_n=32, radial_n=16):
     simulated time.  The network's matrix-core rate is its algorithmic
     flops (2 (20*64 + 64*64 + 64*15) = 12,672 per point) over the extra
     time its pass adds to the first pass of a stage."""
-    import torch
     from paper_1503_00834_amd import closure
-    from chorus_inputs import mlp_init
     c = closure.cost_per_time(panel_n, radial_n, kernel_times=True)
-    # training (FP32 matrix-core products): Adam iterations on synthetic
-    # normalised samples, batch 4,096; about 3 x 12,672 flops per sample
-    # (forward, and a backward twice its size)
-    n, batch, iters = 1 << 20, 4096, 200
+    g_cl = c["closure"]["kernel_ms_per_launch"]["pass1"]
+    g_pl = c["plain"]["kernel_ms_per_launch"]["pass1"]
+    flops = 12672.0 * c["closure"]["points"]
+    dt_mlp = max(g_cl - g_pl, 1e-6) * 1e-3
+    return {"workload": "closure_98k_N3", "hexes": 6 * panel_n * panel_n * radial_n,
+            "dof_updates_per_s": {k: c[k]["dof_updates_per_s"] for k in ("closure", "plain", "resolved")},
+            "seconds_per_unit_time": {k: c[k]["seconds_per_time"] for k in ("closure", "plain", "resolved")},
+            "cost_ratio_resolved_over_closure": c["ratio_resolved_over_closure"],
+            "grad_kernel_ms": {"closure": g_cl, "plain": g_pl},
+            "mlp": {"bound": "mfma", "achieved": flops / dt_mlp / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                    "frac": flops / dt_mlp / 1e12 / 2500.0, "alg_flops_per_launch": flops,
+                    "note": "network time = the network pass plus the order-3 flux pass, minus the plain "
+                            "order-3 flux pass"},
+            "training": training_leg()}
+
+
+def training_leg(iters=200):
+    """Closure training (FP32 matrix-core products): Adam iterations on
+    synthetic normalised samples, batch 4,096; about 3 x 12,672 flops per
+    sample (forward, and a backward twice its size)."""
+    import torch
+    from chorus_inputs import mlp_init
+    n, batch = 1 << 20, 4096
     gen = torch.Generator(device="cuda").manual_seed(0)
     X = torch.randn((n, 20), generator=gen, device="cuda", dtype=torch.float32)
     Y = torch.randn((n, 15), generator=gen, device="cuda", dtype=torch.float32)
@@ -135,22 +152,8 @@ def closure_leg(panel_n=32, radial_n=16):
     wt = time.perf_counter() - t0
     train_sps = iters * batch / wt
     del X, Y, idx, ws
-    g_cl = c["closure"]["kernel_ms_per_launch"]["pass1"]
-    g_pl = c["plain"]["kernel_ms_per_launch"]["pass1"]
-    flops = 12672.0 * c["closure"]["points"]
-    dt_mlp = max(g_cl - g_pl, 1e-6) * 1e-3
-    return {"workload": "closure_98k_N3", "hexes": 6 * panel_n * panel_n * radial_n,
-            "dof_updates_per_s": {k: c[k]["dof_updates_per_s"] for k in ("closure", "plain", "resolved")},
-            "seconds_per_unit_time": {k: c[k]["seconds_per_time"] for k in ("closure", "plain", "resolved")},
-            "cost_ratio_resolved_over_closure": c["ratio_resolved_over_closure"],
-            "grad_kernel_ms": {"closure": g_cl, "plain": g_pl},
-            "mlp": {"bound": "mfma", "achieved": flops / dt_mlp / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
-                    "frac": flops / dt_mlp / 1e12 / 2500.0, "alg_flops_per_launch": flops,
-                    "note": "network time = the network pass plus the order-3 flux pass, minus the plain "
-                            "order-3 flux pass"},
-            "training": {"samples_per_s": train_sps, "batch": batch, "iters": iters,
-                         "achieved": train_sps * 3 * 12672.0 / 1e12, "unit": "TFLOP/s (FP32 matrix)",
-                         "peak": 157.3}}
+    return {"samples_per_s": train_sps, "batch": batch, "iters": iters,
+            "achieved": train_sps * 3 * 12672.0 / 1e12, "unit": "TFLOP/s (FP32 matrix)", "peak": 157.3}
 
 
 def workload_leg(ch, workload, steps=20, repeats=3):
@@ -364,6 +367,9 @@ def main():
     ap.add_argument("--closure-cost", action="store_true",
                     help="only time the resolved, plain and closure runs on the closure-run shell "
                          "(98,304 hexes; one JSON line; for profiling the order-3 passes)")
+    ap.add_argument("--closure-training", type=int, default=0, metavar="ITERS",
+                    help="only time this many closure training iterations (batch 4,096; one JSON line; for "
+                         "profiling the training kernels)")
     ap.add_argument("--size-sweep", action="store_true",
                     help="only measure both paths on shells from 288 to 331,776 hexes (one JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -404,6 +410,10 @@ def main():
         from paper_1503_00834_amd import closure
         c = closure.cost_per_time(32, 16, steps=1)
         print(json.dumps({"closure_cost": c, "data": "synthetic"}), flush=True)
+        return
+    if args.closure_training:
+        print(json.dumps({"closure_training": training_leg(args.closure_training), "data": "synthetic"}),
+              flush=True)
         return
     if args.size_sweep:
         print(json.dumps({"size_sweep": size_sweep(ch), "unit": "DOF-updates/s", "integrator": "SSP-RK3",
